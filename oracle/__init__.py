@@ -1,0 +1,324 @@
+"""FP64 CPU oracle for APCG with total (TRKS) and selective (SRKS) Krylov reuse.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the library package imports this
+module; only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg
+of ``bench.py`` use it.  The inner solver is plain C (``oracle.c``, built
+with gcc); the sequence logic below (Lanczos tridiagonal, Ritz selection,
+basis update) is plain numpy following the paper step by step.
+
+Paper: Gosselet, Rey, Pebrel, arXiv 1301.7530.
+  * Algorithm 1 / Section 2.1: APCG with the pair (x0, P).
+  * Algorithm 2 / Section 3: TRKS, concatenation of all search directions.
+  * Section 4.1: Ritz values/vectors from the CG coefficients.
+  * Section 4.4 / Algorithm 3: SRKS stagnation test and concatenation.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import math
+
+import numpy as np
+
+from .build import ensure_built
+
+ORC_OK, ORC_MAXIT, ORC_BREAKDOWN, ORC_INVALID, ORC_NOMEM = range(5)
+PRECOND = {"none": 0, "jacobi": 1, "block3": 3}
+
+_lib = None
+_D = ctypes.POINTER(ctypes.c_double)
+_I64 = ctypes.POINTER(ctypes.c_int64)
+_I32 = ctypes.POINTER(ctypes.c_int32)
+_INT = ctypes.POINTER(ctypes.c_int)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        L = ctypes.CDLL(ensure_built())
+        L.orc_apcg.restype = ctypes.c_int
+        L.orc_apcg.argtypes = [ctypes.c_int64, _I64, _I32, _D, ctypes.c_int, _D, ctypes.c_int, ctypes.c_int64,
+                               _D, ctypes.c_double, ctypes.c_int, ctypes.c_double, _D, _D, _D, _D, _D,
+                               _D, ctypes.c_int64, _D, ctypes.c_int64, _INT, _INT, _D]
+        L.orc_apcg_alg1.restype = ctypes.c_int
+        L.orc_apcg_alg1.argtypes = [ctypes.c_int64, _I64, _I32, _D, ctypes.c_int, _D, ctypes.c_int, ctypes.c_int64,
+                                    _D, ctypes.c_int, ctypes.c_double, _D, _D, _D]
+        L.orc_spmv.restype = None
+        L.orc_spmv.argtypes = [ctypes.c_int64, _I64, _I32, _D, _D, _D]
+        L.orc_ldl_count.restype = ctypes.c_int
+        L.orc_ldl_count.argtypes = [ctypes.c_int, _D, _D, ctypes.c_double]
+        L.orc_ldl_eigvals.restype = None
+        L.orc_ldl_eigvals.argtypes = [ctypes.c_int, _D, _D, _D]
+        L.orc_tridiag_eigvec.restype = None
+        L.orc_tridiag_eigvec.argtypes = [ctypes.c_int, _D, _D, ctypes.c_double, _D]
+        L.orc_jacobi_eigvals.restype = None
+        L.orc_jacobi_eigvals.argtypes = [ctypes.c_int, _D, _D]
+        L.orc_dense_cholesky_solve.restype = ctypes.c_int
+        L.orc_dense_cholesky_solve.argtypes = [ctypes.c_int, _D, _D, _D]
+        _lib = L
+    return _lib
+
+
+def _p(a, t=_D):
+    return None if a is None else a.ctypes.data_as(t)
+
+
+def _csr(row_ptr, col_idx, values):
+    return (np.ascontiguousarray(row_ptr, dtype=np.int64), np.ascontiguousarray(col_idx, dtype=np.int32),
+            np.ascontiguousarray(values, dtype=np.float64))
+
+
+# ----------------------------------------------------------------- kernels
+
+def spmv(row_ptr, col_idx, values, x):
+    rp, ci, v = _csr(row_ptr, col_idx, values)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.empty(len(rp) - 1)
+    lib().orc_spmv(len(y), _p(rp, _I64), _p(ci, _I32), _p(v), _p(x), _p(y))
+    return y
+
+
+def apcg(row_ptr, col_idx, values, b, precond="jacobi", C=None, tol=1e-8, max_iter=None, guard=1e-12,
+         record_z=False, record_w=False):
+    """One APCG(A, M, C, b) solve (Algorithm 1, standard form; see oracle.c).
+
+    Returns a dict with x, m, status, alpha[m], gamma[m], rho[m] (rho_0..rho_{m-1}),
+    resnorm[m+1], relres_true, kept (bool per column of C), and Z / W
+    (n x m, when requested).
+    """
+    rp, ci, v = _csr(row_ptr, col_idx, values)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    n = len(b)
+    if max_iter is None:
+        max_iter = max(10, 4 * n)
+    if C is None or C.shape[1] == 0:
+        Cf, nc, ldc = None, 0, n
+    else:
+        Cf = np.asfortranarray(C, dtype=np.float64)
+        nc, ldc = Cf.shape[1], n
+    x = np.zeros(n)
+    alpha = np.zeros(max_iter + 1)
+    rho = np.zeros(max_iter + 1)
+    gamma = np.zeros(max_iter + 1)
+    resn = np.zeros(max_iter + 2)
+    Z = np.empty((n, max_iter), order="F") if record_z else None
+    W = np.empty((n, max_iter), order="F") if record_w else None
+    kept = np.ones(max(nc, 1), dtype=np.intc)
+    m = ctypes.c_int(0)
+    rel = ctypes.c_double(0.0)
+    st = lib().orc_apcg(n, _p(rp, _I64), _p(ci, _I32), _p(v), PRECOND[precond], _p(Cf), nc, ldc, _p(b), tol,
+                        max_iter, guard, _p(x), _p(alpha), _p(rho), _p(gamma), _p(resn), _p(Z), n, _p(W), n,
+                        _p(kept, _INT), ctypes.byref(m), ctypes.byref(rel))
+    if st in (ORC_INVALID, ORC_NOMEM):
+        raise ValueError(f"oracle apcg failed with status {st}")
+    m = m.value
+    out = dict(x=x, m=m, status=st, alpha=alpha[:m].copy(), gamma=gamma[:m].copy(), rho=rho[:m].copy(),
+               resnorm=resn[: m + 1].copy(), relres_true=rel.value, kept=kept[:nc].astype(bool))
+    if record_z:
+        out["Z"] = Z[:, :m]
+    if record_w:
+        out["W"] = W[:, :m]
+    return out
+
+
+def apcg_alg1(row_ptr, col_idx, values, b, iters, precond="jacobi", C=None, guard=1e-12):
+    """Algorithm 1 in its printed Gram-Schmidt form; returns (x, alpha, bgs)."""
+    rp, ci, v = _csr(row_ptr, col_idx, values)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    n = len(b)
+    if C is None or C.shape[1] == 0:
+        Cf, nc = None, 0
+    else:
+        Cf = np.asfortranarray(C, dtype=np.float64)
+        nc = Cf.shape[1]
+    x = np.zeros(n)
+    alpha = np.zeros(iters)
+    bgs = np.zeros(max(iters, 1))
+    st = lib().orc_apcg_alg1(n, _p(rp, _I64), _p(ci, _I32), _p(v), PRECOND[precond], _p(Cf), nc, n, _p(b),
+                             iters, guard, _p(x), _p(alpha), _p(bgs))
+    if st != ORC_OK:
+        raise ValueError(f"oracle apcg_alg1 failed with status {st}")
+    return x, alpha, bgs
+
+
+# ------------------------------------------------------ Ritz (Section 4.1)
+
+def lanczos_factors(alpha, rho):
+    """H_m = L D L^T: d_j = 1/alpha_j, l_j^2 = beta_{j+1} = rho_{j+1}/rho_j."""
+    alpha = np.asarray(alpha, dtype=np.float64)
+    rho = np.asarray(rho, dtype=np.float64)
+    m = len(alpha)
+    d = 1.0 / alpha
+    l2 = rho[1:m] / rho[: m - 1] if m > 1 else np.zeros(0)
+    return d, l2
+
+
+def lanczos_tridiag(alpha, rho):
+    """Explicit H_m of Section 4.1: diagonal delta_j and off-diagonal eta_j.
+
+    delta_0 = 1/alpha_0, delta_j = 1/alpha_j + beta_j/alpha_{j-1},
+    eta_j = sqrt(beta_{j+1})/alpha_j, with beta_j = rho_j/rho_{j-1}.
+    """
+    alpha = np.asarray(alpha, dtype=np.float64)
+    rho = np.asarray(rho, dtype=np.float64)
+    m = len(alpha)
+    beta = np.zeros(m)
+    beta[1:] = rho[1:m] / rho[: m - 1]
+    delta = 1.0 / alpha
+    delta[1:] += beta[1:] / alpha[:-1]
+    eta = np.sqrt(beta[1:]) / alpha[:-1]
+    return delta, eta
+
+
+def ldl_eigvals(d, l2):
+    """Eigenvalues of L D L^T, descending, by bisection (oracle.c)."""
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    l2 = np.ascontiguousarray(l2 if len(l2) else np.zeros(1), dtype=np.float64)
+    m = len(d)
+    th = np.zeros(m)
+    if m:
+        lib().orc_ldl_eigvals(m, _p(d), _p(l2), _p(th))
+    return th
+
+
+def ritz_values(alpha, rho):
+    """(Theta_m, Theta_{m-1}) in descending order (Algorithm 3)."""
+    d, l2 = lanczos_factors(alpha, rho)
+    m = len(d)
+    th_m = ldl_eigvals(d, l2)
+    th_m1 = ldl_eigvals(d[: m - 1], l2[: max(m - 2, 0)]) if m > 1 else np.zeros(0)
+    return th_m, th_m1
+
+
+def tridiag_eigvec(delta, eta, theta):
+    delta = np.ascontiguousarray(delta, dtype=np.float64)
+    eta = np.ascontiguousarray(eta if len(eta) else np.zeros(1), dtype=np.float64)
+    v = np.zeros(len(delta))
+    lib().orc_tridiag_eigvec(len(delta), _p(delta), _p(eta), float(theta), _p(v))
+    return v
+
+
+def jacobi_eigvals(A):
+    a = np.asfortranarray(A, dtype=np.float64).copy(order="F")
+    ev = np.zeros(a.shape[0])
+    lib().orc_jacobi_eigvals(a.shape[0], _p(a), _p(ev))
+    return ev
+
+
+def dense_cholesky_solve(A, b):
+    a = np.asfortranarray(A, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.zeros_like(b)
+    st = lib().orc_dense_cholesky_solve(a.shape[0], _p(a), _p(b), _p(x))
+    if st != ORC_OK:
+        raise ValueError("matrix not SPD")
+    return x
+
+
+def srks_select(th_m, th_m1, eps):
+    """Indices (0-based, ascending) of converged Ritz values (Section 4.4).
+
+    For j = 0..m-2 (the paper's 1..m-1): theta_m[j] has converged if
+    |theta_m[j] - theta_{m-1}[j]| <= eps |theta_m[j]|, and theta_m[j+1] if
+    |theta_m[j+1] - theta_{m-1}[j]| <= eps |theta_m[j+1]|.  An index found
+    twice is taken once.
+    """
+    sel = set()
+    for j in range(len(th_m1)):
+        if abs(th_m[j] - th_m1[j]) <= eps * abs(th_m[j]):
+            sel.add(j)
+        if abs(th_m[j + 1] - th_m1[j]) <= eps * abs(th_m[j + 1]):
+            sel.add(j + 1)
+    return sorted(sel)
+
+
+def ritz_block(Z, alpha, rho, idx, th_m):
+    """Columns y^i / sqrt(|theta^i|) for i in idx (Algorithm 3).
+
+    y^i = V_m q^i with V_m = [(-1)^j z_j / sqrt(rho_j)] and q^i the unit
+    eigenvector of H_m for theta^i.
+    """
+    m = len(alpha)
+    if not len(idx):
+        return np.zeros((Z.shape[0], 0))
+    delta, eta = lanczos_tridiag(alpha, rho)
+    Q = np.stack([tridiag_eigvec(delta, eta, th_m[i]) for i in idx], axis=1)
+    sgn = np.where(np.arange(m) % 2 == 0, 1.0, -1.0)
+    F = (sgn / np.sqrt(rho[:m]))[:, None] * Q / np.sqrt(np.abs(th_m[idx]))[None, :]
+    return Z[:, :m] @ F
+
+
+def trks_block(W, gamma):
+    """All search directions w_j, scaled by 1/sqrt((w_j, A w_j)) (Algorithm 2)."""
+    return W / np.sqrt(gamma)[None, :]
+
+
+def freeze_pick(idx, th_m, room):
+    """Cap policy 'freeze': keep at most `room` indices, smallest Ritz values first."""
+    if room <= 0:
+        return []
+    if len(idx) <= room:
+        return list(idx)
+    order = sorted(idx, key=lambda i: (th_m[i], i))
+    return sorted(order[:room])
+
+
+def solve_sequence(seq, n_systems=None, reuse="srks", precond=None, tol=1e-8, eps=1e-14, cap=0,
+                   cap_policy="freeze", C0=None, max_iter=None, guard=1e-12, keep_x=False):
+    """Run TRKS / SRKS / plain PCG over systems 0..n_systems-1 of ``seq``.
+
+    ``reuse``: 'none' (PCG), 'trks' (Algorithm 2) or 'srks' (Algorithm 3).
+    ``cap`` (n_c_lim, 0 = none) with ``cap_policy`` 'restart' (reset the
+    basis to C0 once its size reaches the cap, Algorithm 3) or 'freeze'
+    (append only while below the cap, smallest Ritz values first).
+    Returns one record per system.
+    """
+    n_systems = seq.n_systems if n_systems is None else n_systems
+    if precond is None:
+        precond = "block3" if getattr(seq, "block", 1) == 3 else "jacobi"
+    n = seq.n
+    C_init = np.zeros((n, 0)) if C0 is None else np.asarray(C0, dtype=np.float64)
+    C = C_init.copy()
+    recs = []
+    for k in range(n_systems):
+        rp, ci, v, b = seq.csr(k)
+        res = apcg(rp, ci, v, b, precond, C, tol, max_iter, guard, record_z=(reuse == "srks"),
+                   record_w=(reuse == "trks"))
+        nc_in = C.shape[1]
+        if nc_in:
+            C = C[:, res["kept"]]
+        rec = dict(k=k, m=res["m"], nc=C.shape[1], nc_in=nc_in, dropped=nc_in - C.shape[1], status=res["status"],
+                   relres_true=res["relres_true"], alpha=res["alpha"], rho=res["rho"], gamma=res["gamma"],
+                   resnorm=res["resnorm"])
+        if keep_x:
+            rec["x"] = res["x"]
+        m = res["m"]
+        new = np.zeros((n, 0))
+        if reuse == "trks" and m > 0:
+            cols = list(range(m))
+            if cap and cap_policy == "freeze":
+                cols = cols[: max(cap - C.shape[1], 0)]
+            new = trks_block(res["W"][:, cols], res["gamma"][cols])
+        elif reuse == "srks" and m > 1:
+            th_m, th_m1 = ritz_values(res["alpha"], res["rho"])
+            sel = srks_select(th_m, th_m1, eps)
+            rec["theta"] = th_m
+            rec["selected_all"] = list(sel)
+            if cap and cap_policy == "freeze":
+                sel = freeze_pick(sel, th_m, cap - C.shape[1])
+            rec["selected"] = list(sel)
+            new = ritz_block(res["Z"], res["alpha"], res["rho"], sel, th_m)
+        rec["added"] = new.shape[1]
+        C = np.concatenate([C, new], axis=1) if new.shape[1] else C
+        if cap and cap_policy == "restart" and C.shape[1] >= cap:
+            C = C_init.copy()
+            rec["restarted"] = True
+        rec["nc_next"] = C.shape[1]
+        recs.append(rec)
+    return recs, C
+
+
+def cg_iteration_bound(kappa, eps):
+    """n_eps = ln(eps/2)/ln(sigma), sigma = (sqrt(kappa)-1)/(sqrt(kappa)+1) (Section 4, CG bound)."""
+    s = (math.sqrt(kappa) - 1.0) / (math.sqrt(kappa) + 1.0)
+    return math.log(eps / 2.0) / math.log(s)
