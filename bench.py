@@ -1,0 +1,251 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the Krylov-reuse APCG library on one GPU.
+
+A step is one system of the sequence taken through the whole hot path:
+intake of the new matrix values and right-hand side (already resident in
+HBM), rebuild of A C and C^T A C for the carried basis, the APCG iterations
+to a true relative residual of 1e-8, and the Ritz extraction / selection /
+basis update (SRKS).  The same systems are then solved with plain PCG
+(no basis) on the same GPU for comparison.
+
+Default workload: Q1 elasticity on a 40^3 mesh (n = 201,720 dofs,
+15,548,742 nonzeros in 3x3 blocks), 64 stiff cubic inclusions, cumulative
+damage between systems, 3x3 block-Jacobi, SRKS with eps = 1e-14 and a basis
+of at most 60 vectors (frozen once full), mixed precision.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision mixed|fp64]
+
+Prints one JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK = 8.0e12  # MI355X HBM3E, bytes/s
+
+WORKLOADS = {
+    "elasticity40": dict(kind="elasticity", size=40, n_systems=20, config_id=2, max_basis=60),
+    "elasticity100": dict(kind="elasticity", size=100, n_systems=30, config_id=3, max_basis=200),
+    "diffusion20": dict(kind="diffusion", size=(20, 20, 20), n_systems=8, config_id=1, max_basis=0),
+}
+
+
+def _log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def spmv_bytes(seq, p, pw):
+    """Algorithmic bytes of one SpMV launch: matrix values (p bytes) + block
+    column indices + the vector read once + the product written once (pw)."""
+    nnz = seq.nnzb * seq.block * seq.block
+    if seq.block == 1:
+        return nnz * (p + 4) + 2 * seq.n * pw
+    return nnz * p + 4 * seq.nnzb + 2 * seq.n * pw
+
+
+def run_phase(K, ctx, seq, dev_sys, reuse, args, wl, order, timing=False):
+    import torch
+
+    s = K.sequence_for(ctx, seq, precision=args.precision, reuse=reuse, tol=1e-8, max_iter=args.max_iter,
+                       ritz_eps=1e-14, max_basis=wl["max_basis"], cap_policy="freeze")
+    x = torch.empty(seq.n, dtype=torch.float64, device="cuda")
+    infos = []
+    lat = []
+    C_before = None
+    try:
+        for i, k in enumerate(order[: args.warmup]):
+            s.submit(*dev_sys[k])
+            s.solve_device(x)
+            s.recycle()
+        if reuse != "none":
+            C_before = s.basis() if args.cpu_baseline else None
+        if timing:
+            s.set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in order[args.warmup:]:
+            ts = time.perf_counter()
+            s.submit(*dev_sys[k])
+            info = s.solve_device(x)
+            s.recycle()
+            info["added"] = s.info()["added"]
+            info["t_recycle_ms"] = s.info()["t_recycle_ms"]
+            infos.append(info)
+            lat.append(time.perf_counter() - ts)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ktimes = [s.kernel_time(j) for j in range(3)] if timing else None
+        coeffs = s.coeffs()
+    finally:
+        s.close()
+    return dict(time=t1 - t0, infos=infos, lat=lat, ktimes=ktimes, C_before=C_before, coeffs=coeffs)
+
+
+def cpu_baseline(seq, k, C, m_avg, sample_iters, coeffs):
+    """Time the oracle on a bounded sample of the same workload."""
+    import oracle as O
+
+    rp, ci, v, b = seq.csr(k)
+    pc = "block3" if seq.block == 3 else "jacobi"
+    t = time.perf_counter()
+    O.apcg(rp, ci, v, b, pc, C=C, tol=1e-8, max_iter=1)
+    t_first = time.perf_counter() - t
+    t = time.perf_counter()
+    O.apcg(rp, ci, v, b, pc, C=C, tol=1e-8, max_iter=1 + sample_iters)
+    t_long = time.perf_counter() - t
+    t_iter = max(t_long - t_first, 1e-9) / sample_iters
+    # Ritz analysis of an m-step run: the oracle bisects every eigenvalue of
+    # H_m and H_{m-1} (about 70 Sturm counts of length m each); time a few
+    # counts on the GPU run's own coefficients and scale
+    alpha, rho = coeffs
+    m = max(len(alpha), 2)
+    d, l2 = O.lanczos_factors(alpha, rho)
+    dd = np.ascontiguousarray(d)
+    ll = np.ascontiguousarray(l2 if len(l2) else np.zeros(1))
+    lib = O.lib()
+    pre = 64
+    t = time.perf_counter()
+    for j in range(pre):
+        lib.orc_ldl_count(len(dd), O._p(dd), O._p(ll), float(j) / pre)
+    t_count = (time.perf_counter() - t) / pre
+    t_ritz = 2 * m * 70 * t_count
+    solve_s = t_first + (m_avg - 1) * t_iter + t_ritz
+    return dict(value=1.0 / solve_s, unit="solves/s", cores=1, kind="oracle",
+                sample=(f"oracle (C, fp64, 1 thread) on system {k} of the same sequence with the GPU's basis "
+                        f"(n_c={0 if C is None else C.shape[1]}): build + {sample_iters} APCG iterations timed "
+                        f"({t_first:.2f}s first iteration incl. coarse build, {t_iter*1e3:.1f} ms/iteration), "
+                        f"Ritz bisection timed on {pre} Sturm counts of length {m} (the GPU run's coefficients); "
+                        f"scaled to the GPU's mean "
+                        f"{m_avg:.0f} iterations per solve"),
+                seconds_per_solve=solve_s)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="elasticity40", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64", "fp32"])
+    ap.add_argument("--max-iter", type=int, default=30000)
+    ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
+    ap.add_argument("--no-plain", dest="plain", action="store_false")
+    ap.add_argument("--cpu-iters", type=int, default=100)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "multi-GPU sharding is not implemented", file=sys.stderr)
+        sys.exit(2)
+    if int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: one process / one GPU only", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import gen
+    import paper_1301_7530_amd as K
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    wl = WORKLOADS[args.workload]
+    seq = gen.make_sequence(wl["kind"], wl["size"], wl["n_systems"], wl["config_id"])
+    total = args.warmup + args.steps
+    order = [k % wl["n_systems"] for k in range(total)]
+    _log(f"workload {args.workload}: n={seq.n} nnzb={seq.nnzb} block={seq.block}; generating {min(total, wl['n_systems'])} systems")
+    dev_sys = {}
+    for k in sorted(set(order)):
+        vals, b = seq.system(k)
+        dev_sys[k] = (torch.from_numpy(vals).to("cuda"), torch.from_numpy(b).to("cuda"))
+    torch.cuda.synchronize()
+    ctx = K.Context(0)
+    _log("SRKS phase")
+    srks = run_phase(K, ctx, seq, dev_sys, "selective" if wl["max_basis"] else "total", args, wl, order, timing=True)
+    plain = None
+    if args.plain:
+        _log("plain PCG phase")
+        plain = run_phase(K, ctx, seq, dev_sys, "none", args, wl, order)
+    ctx.close()
+
+    p = 8 if args.precision == "fp64" else 4       # matrix value bytes
+    pw = 4 if args.precision == "fp32" else 8      # Krylov vector bytes
+    value = args.steps / srks["time"]
+    infos = srks["infos"]
+    iters = [i["iters"] for i in infos]
+    lat_ms = np.array(srks["lat"]) * 1e3
+    model_bytes = sum(i["model_bytes"] for i in infos)
+    k_cnt, k_ms = srks["ktimes"][0]
+    kb = spmv_bytes(seq, p, pw)
+    achieved = kb / (k_ms * 1e-3) if k_cnt else float("nan")
+    out = {
+        "metric": "solves/s at 1e-8 resid vs plain PCG same GPU; %HBM peak; p50/p99 latency",
+        "value": round(value, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * srks["time"] / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"mixed": "f32+f64", "fp64": "f64", "fp32": "f32"}[args.precision],
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: Q1 elasticity {wl['size']}^3" if wl["kind"] == "elasticity"
+            else f"{args.workload}: 7-point diffusion {wl['size']}",
+            "n": seq.n,
+            "nnz": seq.nnzb * seq.block * seq.block,
+            "systems_timed": args.steps,
+            "reuse": "SRKS eps=1e-14" if wl["max_basis"] else "TRKS",
+            "max_basis": wl["max_basis"],
+            "cap_policy": "freeze",
+            "precond": "3x3 block-Jacobi" if seq.block == 3 else "Jacobi",
+            "tol": 1e-8,
+            "precision": args.precision,
+            "precision_detail": {"mixed": "fp32 matrix/preconditioner/basis, fp64 vectors and reductions", "fp64": "fp64 throughout", "fp32": "fp32 matrix, basis and vectors, fp64 reductions"}[args.precision],
+        },
+        "iters_mean": float(np.mean(iters)),
+        "n_c_mean": float(np.mean([i["n_c"] for i in infos])),
+        "rel_res_true_max": float(max(i["rel_res_true"] for i in infos)),
+        "refinements_mean": float(np.mean([i["refinements"] for i in infos])),
+        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
+        "hbm_frac_model": model_bytes / srks["time"] / HBM_PEAK,
+        "kernel_ms_mean": {name: srks["ktimes"][j][1] for j, name in enumerate(("spmv_dot", "update_reduce", "correct_dir"))},
+        "roofline": {
+            "kernel": "k_spmv_dot",
+            "bound": "hbm",
+            "achieved": achieved / 1e9,
+            "peak": HBM_PEAK / 1e9,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK,
+            "traffic": None,
+            "algorithmic_bytes_per_launch": kb,
+            "launches_sampled": k_cnt,
+        },
+    }
+    if plain is not None:
+        pv = args.steps / plain["time"]
+        out["plain_pcg"] = {
+            "value": round(pv, 4),
+            "iters_mean": float(np.mean([i["iters"] for i in plain["infos"]])),
+            "rel_res_true_max": float(max(i["rel_res_true"] for i in plain["infos"])),
+        }
+        out["speedup_vs_plain_pcg"] = value / pv
+    if args.cpu_baseline:
+        _log("CPU baseline (oracle sample)")
+        k = order[args.warmup]
+        a, r, _ = srks["coeffs"]
+        out["cpu_baseline"] = cpu_baseline(seq, k, srks["C_before"], float(np.mean(iters)), args.cpu_iters, (a, r))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,207 @@
+/*
+ * krs.h — C ABI of the MI355X Krylov-reuse solver library (libkrs.so).
+ *
+ * The library solves sequences of sparse symmetric positive definite systems
+ * A^(k) x^(k) = b^(k) with the augmented preconditioned conjugate gradient
+ * method (APCG, Algorithm 1 of Gosselet, Rey & Pebrel, arXiv 1301.7530),
+ * and carries an augmentation basis C from one system to the next:
+ *   - total reuse (TRKS, Algorithm 2): every search direction is appended;
+ *   - selective reuse (SRKS, Algorithm 3): only Ritz vectors whose Ritz
+ *     values stagnated between the last two Lanczos steps are appended.
+ *
+ * Conventions shared by every call:
+ *   - Every call returns a krs_status; nothing aborts or throws across the
+ *     ABI.  krs_last_error() gives a thread-local message for the last
+ *     failure of the calling thread.
+ *   - Host inputs are copied before the call returns.  Device inputs are
+ *     borrowed until the consuming call returns.  Outputs go to buffers
+ *     owned by the caller.
+ *   - Handles from *_create are owned by the caller and must be destroyed.
+ *   - Indices are 0-based.  Dense blocks are column-major with an explicit
+ *     leading dimension.  3x3 blocks are row-major.
+ *   - A krs_seq is not thread-safe; distinct sequences may be used from
+ *     distinct threads only if they belong to distinct contexts.
+ *   - After any error a sequence stays valid and keeps its previous basis
+ *     (the solution vector is then undefined).
+ */
+#ifndef KRS_H
+#define KRS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    KRS_OK = 0,
+    KRS_E_INVALID = 1,         /* bad argument or malformed input */
+    KRS_E_OOM = 2,             /* device or host allocation failed */
+    KRS_E_NOT_SPD = 3,         /* (w, A w) <= 0, (r, z) <= 0 or NaN: operator/preconditioner not SPD */
+    KRS_E_COARSE_SINGULAR = 4, /* every basis column was rejected by the rank guard */
+    KRS_E_MAXIT = 5,           /* max_iter reached; krs_solve_info is still filled */
+    KRS_E_DEVICE = 6,          /* HIP runtime error */
+    KRS_E_BUSY = 7,            /* resource temporarily unavailable (server queue full) */
+    KRS_E_STATE = 8            /* call not valid in the object's current state */
+} krs_status;
+
+typedef enum { KRS_FP64 = 0, KRS_MIXED = 1, KRS_FP32 = 2 } krs_precision;
+/* KRS_FP64: every vector, value and reduction in double precision.
+ * KRS_MIXED: matrix values, preconditioner and basis (C, A C) stored and
+ *   streamed in single precision; Krylov vectors, the iterate, every
+ *   reduction, the coarse matrix C^T A C and its factorisation, the Ritz
+ *   eigenproblem and periodic true-residual refinement (r = b - A x with the
+ *   double-precision matrix, then a coarse re-projection) in double.
+ * KRS_FP32: as KRS_MIXED but the Krylov vectors are single precision too
+ *   (fewer bytes per iteration, more iterations on ill-conditioned systems). */
+
+typedef enum { KRS_REUSE_NONE = 0, KRS_REUSE_TOTAL = 1, KRS_REUSE_SELECTIVE = 2 } krs_reuse;
+typedef enum { KRS_PC_JACOBI = 0, KRS_PC_BJACOBI3 = 1 } krs_precond;
+/* KRS_PC_JACOBI: M = diag(A).  KRS_PC_BJACOBI3: M = the 3x3 diagonal blocks
+ * (requires block == 3). */
+
+typedef enum { KRS_CAP_RESTART = 0, KRS_CAP_FREEZE = 1 } krs_cap_policy;
+/* With max_basis = n_c_lim > 0:
+ * KRS_CAP_RESTART: once the basis reaches n_c_lim columns it is reset to the
+ *   initial basis C0 (Algorithm 3, last step).
+ * KRS_CAP_FREEZE: columns are appended only while the basis is below
+ *   n_c_lim; SRKS appends the smallest selected Ritz values first, TRKS the
+ *   first search directions. */
+
+typedef struct krs_ctx krs_ctx;
+typedef struct krs_seq krs_seq;
+
+/* Optional device allocator (e.g. a framework's caching allocator).
+ * alloc returns device memory of at least `bytes` usable on `stream` (or
+ * NULL); free releases it.  NULL allocator: hipMalloc / hipFree. */
+typedef struct {
+    void* (*alloc)(void* user, size_t bytes, void* stream);
+    void (*free)(void* user, void* ptr, void* stream);
+    void* user;
+} krs_allocator;
+
+/* Sequence description.  The sparsity pattern is fixed for the whole
+ * sequence (the systems differ in their values, Section 3).  block == 1:
+ * scalar CSR with nb = n rows; block == 3: BSR with nb = n/3 block rows and
+ * 3x3 row-major blocks.  row_ptr has nb+1 entries, col_idx nnzb entries
+ * (block columns ascending within a row, diagonal block present).  Both
+ * are host pointers, copied by krs_seq_create. */
+typedef struct {
+    int64_t n;
+    int32_t block;
+    int64_t nnzb;
+    const int64_t* row_ptr;
+    const int32_t* col_idx;
+    krs_precision precision;
+    krs_reuse reuse;
+    krs_precond precond;
+    krs_cap_policy cap_policy;
+    double tol;            /* stop when ||r|| <= tol ||b|| (recursive, then confirmed with the true residual) */
+    int32_t max_iter;      /* iterations per solve */
+    double ritz_eps;       /* SRKS stagnation tolerance epsilon (Section 4.4), e.g. 1e-14 */
+    int32_t max_basis;     /* n_c_lim; 0 = unlimited */
+    int32_t refine_every;  /* mixed: force a true-residual refinement at least every k iterations (0 = off) */
+    int32_t history_cap;   /* Krylov vectors kept for SRKS (0 = max_iter); longer runs use the leading part */
+    double rank_tol;       /* rank guard: drop a basis column whose Cholesky pivot <= rank_tol * max diag (0 = 1e-12) */
+    double refine_drop;    /* mixed: refine when ||r|| fell by this factor since the last refinement (0 = 0.1) */
+    int32_t exec_mode;     /* 0: iteration blocks replayed as captured HIP graphs; 1: eager kernel launches */
+} krs_seq_desc;
+
+typedef struct {
+    int32_t iters;          /* m: products A w performed in the last solve */
+    int32_t n_c;            /* basis columns used by the last solve (after the rank guard) */
+    int32_t refinements;    /* true-residual refinements performed */
+    int32_t selected;       /* last recycle: Ritz values that passed the stagnation test (SRKS) */
+    int32_t dropped;        /* last solve: basis columns dropped by the rank guard */
+    int32_t added;          /* last recycle: columns appended */
+    int32_t status;         /* krs_status of the last solve */
+    int32_t reserved;
+    double rel_res_true;    /* ||b - A x|| / ||b|| with double-precision A and x */
+    double rel_res_recursive;
+    double t_setup_ms;      /* value intake and preconditioner setup */
+    double t_rebuild_ms;    /* A C, C^T A C, factorisation, initialisation */
+    double t_iter_ms;       /* iterations (including refinements) */
+    double t_recycle_ms;    /* Ritz extraction / selection / basis update */
+    int64_t model_bytes;    /* algorithmic HBM bytes of the iterations of the last solve */
+} krs_solve_info;
+
+/* ------------------------------------------------------------- context */
+/* Bind to HIP device `device` and stream `hip_stream` (a hipStream_t; NULL
+ * = a stream created and owned by the context).  `a` may be NULL. */
+krs_status krs_ctx_create(int device, void* hip_stream, const krs_allocator* a, krs_ctx** out);
+/* Fails with KRS_E_STATE while sequences created on it are alive. */
+krs_status krs_ctx_destroy(krs_ctx* ctx);
+const char* krs_status_str(krs_status s);
+const char* krs_last_error(void);
+const char* krs_version(void);
+
+/* ------------------------------------------------------------ sequence */
+/* Create a sequence.  C0 (host, n x m0, leading dimension ldc0 >= n, may be
+ * NULL when m0 == 0) is the initial basis C^(0) of Algorithms 2 and 3. */
+krs_status krs_seq_create(krs_ctx* ctx, const krs_seq_desc* desc, const double* C0, int32_t m0, int64_t ldc0,
+                          krs_seq** out);
+/* Load system k: `values` holds nnzb*block*block doubles in the order of
+ * the pattern given at creation, `b` holds n doubles.  Host pointers,
+ * copied.  Builds the preconditioner. */
+krs_status krs_seq_submit(krs_seq* s, const double* values, const double* b);
+/* Same with device pointers, borrowed until the call returns. */
+krs_status krs_seq_submit_device(krs_seq* s, const double* d_values, const double* d_b);
+/* Solve the submitted system with APCG(A, M, C, b) (Algorithm 1): rebuild
+ * A C and C^T A C for the current basis, initialise x0 = C (C^T A C)^-1 C^T b,
+ * iterate.  x (host, n doubles) receives the solution; info may be NULL.
+ * Returns KRS_E_MAXIT (info filled) when max_iter is reached. */
+krs_status krs_seq_solve(krs_seq* s, double* x, krs_solve_info* info);
+/* Same, writing the solution to device memory d_x (n doubles). */
+krs_status krs_seq_solve_device(krs_seq* s, double* d_x, krs_solve_info* info);
+/* Update the basis from the last solve: TRKS concatenation (Algorithm 2)
+ * or SRKS Ritz selection (Algorithm 3), then the cap policy.  n_added may
+ * be NULL. */
+krs_status krs_seq_recycle(krs_seq* s, int32_t* n_added);
+/* Ritz values of the last SRKS extraction (descending, m of them) and the
+ * selection flags (1 = passed the stagnation test).  cap = array sizes. */
+krs_status krs_seq_ritz(krs_seq* s, double* theta, uint8_t* selected, int32_t cap, int32_t* m_out);
+/* CG coefficients of the last solve: alpha_j, rho_j = (r_j, z_j) and
+ * gamma_j = (w_j, A w_j) for j < m.  Any pointer may be NULL. */
+krs_status krs_seq_coeffs(krs_seq* s, double* alpha, double* rho, double* gamma, int32_t cap, int32_t* m_out);
+/* Export the current basis (n x n_c, column-major, leading dim ldc) as
+ * doubles; C may be NULL to query n_c only. */
+krs_status krs_seq_basis(krs_seq* s, double* C, int64_t ldc, int32_t cap, int32_t* n_c);
+krs_status krs_seq_info(krs_seq* s, krs_solve_info* info);
+/* Sampled kernel timing.  When enabled, the first iteration of every
+ * iteration block has its three launches (0: SpMV + (w, A w), 1: update /
+ * preconditioner / projector reduction, 2: coarse correction / direction)
+ * bracketed by HIP events on the sequence's stream; only samples taken
+ * while the solve was still iterating are kept.  Enabling resets the
+ * counters.  krs_seq_kernel_time returns the number of sampled launches of
+ * `kernel` and their total duration in milliseconds. */
+krs_status krs_seq_set_timing(krs_seq* s, int32_t enable);
+krs_status krs_seq_kernel_time(krs_seq* s, int32_t kernel, int64_t* launches, double* total_ms);
+krs_status krs_seq_destroy(krs_seq* s);
+
+/* --------------------------------------------------------------- batch */
+/* Solve the submitted systems of `count` sequences (all on ctx) together:
+ * the iterations of all systems run in shared launches.  x[i] (host, n_i
+ * doubles) and info[i] receive each result.  Each result equals the one
+ * krs_seq_solve gives for that sequence alone. */
+krs_status krs_batch_solve(krs_ctx* ctx, krs_seq* const* seqs, int32_t count, double* const* x, krs_solve_info* info);
+
+/* ------------------------------------------------ host-side Ritz logic */
+/* Pure host computations exposed for testing the library's selection
+ * logic; no device is touched.
+ * krs_ritz_select: from alpha[m], rho[m] build the Lanczos tridiagonal H_m
+ * (Section 4.1), compute the eigenvalues of H_m and H_{m-1} (descending,
+ * theta[m], theta_prev[m-1]; either may be NULL) and flag the Ritz values
+ * that passed the stagnation test with tolerance eps (selected[m]). */
+krs_status krs_ritz_select(const double* alpha, const double* rho, int32_t m, double eps, double* theta,
+                           double* theta_prev, uint8_t* selected);
+/* Cholesky factorisation of the SPD coarse matrix G (nc x nc column-major)
+ * with the rank guard, and the explicit inverse over the kept columns:
+ * Ginv (nc x nc) gets zero rows/columns for dropped columns; kept[nc]. */
+krs_status krs_coarse_factor(int32_t nc, const double* G, double rank_tol, double* Ginv, uint8_t* kept, int32_t* nk);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KRS_H */

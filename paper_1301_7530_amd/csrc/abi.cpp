@@ -1,0 +1,367 @@
+// C entry points of libkrs (include/krs.h): argument checks, error
+// reporting and dispatch to the sequence runtime.  Nothing throws across
+// this boundary.
+#include <cstring>
+#include <exception>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "seq.h"
+
+namespace krs {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+}  // namespace krs
+
+using krs::set_error;
+
+#define KRS_GUARD_BEGIN try {
+#define KRS_GUARD_END                                      \
+    }                                                      \
+    catch (const std::bad_alloc&) {                        \
+        set_error("host allocation failed");               \
+        return KRS_E_OOM;                                  \
+    }                                                      \
+    catch (const std::exception& e) {                      \
+        set_error(std::string("internal error: ") + e.what()); \
+        return KRS_E_INVALID;                              \
+    }                                                      \
+    catch (...) {                                          \
+        set_error("internal error");                       \
+        return KRS_E_INVALID;                              \
+    }
+
+extern "C" {
+
+const char* krs_status_str(krs_status s) {
+    switch (s) {
+        case KRS_OK: return "ok";
+        case KRS_E_INVALID: return "invalid argument";
+        case KRS_E_OOM: return "out of memory";
+        case KRS_E_NOT_SPD: return "operator or preconditioner not SPD (breakdown)";
+        case KRS_E_COARSE_SINGULAR: return "coarse matrix singular";
+        case KRS_E_MAXIT: return "maximum iterations reached";
+        case KRS_E_DEVICE: return "device error";
+        case KRS_E_BUSY: return "busy";
+        case KRS_E_STATE: return "invalid state";
+    }
+    return "unknown status";
+}
+
+const char* krs_last_error(void) { return krs::g_last_error.c_str(); }
+
+const char* krs_version(void) { return "krs 0.1 (gfx950)"; }
+
+krs_status krs_ctx_create(int device, void* hip_stream, const krs_allocator* a, krs_ctx** out) {
+    KRS_GUARD_BEGIN
+    if (!out) {
+        set_error("out is NULL");
+        return KRS_E_INVALID;
+    }
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) {
+        set_error("no such HIP device");
+        return KRS_E_DEVICE;
+    }
+    if (hipSetDevice(device) != hipSuccess) {
+        set_error("hipSetDevice failed");
+        return KRS_E_DEVICE;
+    }
+    krs_ctx* c = new krs_ctx();
+    c->device = device;
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            set_error("hipStreamCreate failed");
+            return KRS_E_DEVICE;
+        }
+        c->own_stream = true;
+    }
+    if (a && a->alloc && a->free) {
+        c->alloc = *a;
+        c->has_alloc = true;
+    }
+    *out = c;
+    return KRS_OK;
+    KRS_GUARD_END
+}
+
+krs_status krs_ctx_destroy(krs_ctx* ctx) {
+    KRS_GUARD_BEGIN
+    if (!ctx) return KRS_OK;
+    if (ctx->live_seqs > 0) {
+        set_error("context still has live sequences");
+        return KRS_E_STATE;
+    }
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return KRS_OK;
+    KRS_GUARD_END
+}
+
+krs_status krs_seq_create(krs_ctx* ctx, const krs_seq_desc* d, const double* C0, int32_t m0, int64_t ldc0,
+                          krs_seq** out) {
+    KRS_GUARD_BEGIN
+    if (!ctx || !d || !out) {
+        set_error("ctx, desc and out are required");
+        return KRS_E_INVALID;
+    }
+    *out = nullptr;
+    if (d->n <= 0 || (d->block != 1 && d->block != 3) || d->n % d->block != 0 || d->nnzb <= 0 || !d->row_ptr ||
+        !d->col_idx || d->tol <= 0.0 || d->max_iter < 0 || m0 < 0 || d->max_basis < 0 || d->history_cap < 0 ||
+        d->refine_every < 0) {
+        set_error("invalid sequence description");
+        return KRS_E_INVALID;
+    }
+    if (d->precision != KRS_FP64 && d->precision != KRS_MIXED && d->precision != KRS_FP32) {
+        set_error("unknown precision");
+        return KRS_E_INVALID;
+    }
+    if (d->reuse != KRS_REUSE_NONE && d->reuse != KRS_REUSE_TOTAL && d->reuse != KRS_REUSE_SELECTIVE) {
+        set_error("unknown reuse mode");
+        return KRS_E_INVALID;
+    }
+    if ((d->precond == KRS_PC_BJACOBI3) != (d->block == 3) ||
+        (d->precond != KRS_PC_JACOBI && d->precond != KRS_PC_BJACOBI3)) {
+        set_error("KRS_PC_BJACOBI3 goes with block 3, KRS_PC_JACOBI with block 1");
+        return KRS_E_INVALID;
+    }
+    if (d->cap_policy != KRS_CAP_RESTART && d->cap_policy != KRS_CAP_FREEZE) {
+        set_error("unknown cap policy");
+        return KRS_E_INVALID;
+    }
+    if (m0 > 1024) {
+        set_error("initial basis larger than 1024 columns");
+        return KRS_E_INVALID;
+    }
+    const int64_t nb = d->n / d->block;
+    if (d->row_ptr[0] != 0 || d->row_ptr[nb] != d->nnzb) {
+        set_error("row_ptr must start at 0 and end at nnzb");
+        return KRS_E_INVALID;
+    }
+    for (int64_t r = 0; r < nb; ++r) {
+        if (d->row_ptr[r + 1] < d->row_ptr[r]) {
+            set_error("row_ptr not monotone");
+            return KRS_E_INVALID;
+        }
+        for (int64_t t = d->row_ptr[r]; t < d->row_ptr[r + 1]; ++t) {
+            const int32_t c = d->col_idx[t];
+            if (c < 0 || c >= nb || (t > d->row_ptr[r] && c <= d->col_idx[t - 1])) {
+                set_error("column indices must be in range and strictly ascending per row");
+                return KRS_E_INVALID;
+            }
+        }
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess) {
+        set_error("hipSetDevice failed");
+        return KRS_E_DEVICE;
+    }
+    krs_seq* s = new krs_seq();
+    if (d->precision == KRS_MIXED) s->impl.reset(new krs::SeqImpl<float, double>());
+    else if (d->precision == KRS_FP32) s->impl.reset(new krs::SeqImpl<float, float>());
+    else s->impl.reset(new krs::SeqImpl<double, double>());
+    s->impl->ctx = ctx;
+    krs_status st = s->impl->create(*d, C0, m0, ldc0);
+    if (st != KRS_OK) {
+        s->impl->destroy();
+        delete s;
+        return st;
+    }
+    s->impl->nc = m0;
+    ctx->live_seqs += 1;
+    *out = s;
+    return KRS_OK;
+    KRS_GUARD_END
+}
+
+krs_status krs_seq_submit(krs_seq* s, const double* values, const double* b) {
+    KRS_GUARD_BEGIN
+    if (!s) return KRS_E_INVALID;
+    return s->impl->submit(values, b, false);
+    KRS_GUARD_END
+}
+
+krs_status krs_seq_submit_device(krs_seq* s, const double* d_values, const double* d_b) {
+    KRS_GUARD_BEGIN
+    if (!s) return KRS_E_INVALID;
+    return s->impl->submit(d_values, d_b, true);
+    KRS_GUARD_END
+}
+
+krs_status krs_seq_solve(krs_seq* s, double* x, krs_solve_info* info) {
+    KRS_GUARD_BEGIN
+    if (!s) return KRS_E_INVALID;
+    return s->impl->solve(x, false, info);
+    KRS_GUARD_END
+}
+
+krs_status krs_seq_solve_device(krs_seq* s, double* d_x, krs_solve_info* info) {
+    KRS_GUARD_BEGIN
+    if (!s) return KRS_E_INVALID;
+    return s->impl->solve(d_x, true, info);
+    KRS_GUARD_END
+}
+
+krs_status krs_seq_recycle(krs_seq* s, int32_t* n_added) {
+    KRS_GUARD_BEGIN
+    if (!s) return KRS_E_INVALID;
+    return s->impl->recycle(n_added);
+    KRS_GUARD_END
+}
+
+krs_status krs_seq_ritz(krs_seq* s, double* theta, uint8_t* selected, int32_t cap, int32_t* m_out) {
+    KRS_GUARD_BEGIN
+    if (!s) return KRS_E_INVALID;
+    const auto& th = s->impl->last_theta;
+    const int m = (int)th.size();
+    if (m_out) *m_out = m;
+    if ((theta || selected) && cap < m) {
+        set_error("output arrays too small");
+        return KRS_E_INVALID;
+    }
+    for (int i = 0; i < m; ++i) {
+        if (theta) theta[i] = th[i];
+        if (selected) selected[i] = s->impl->last_sel[i];
+    }
+    return KRS_OK;
+    KRS_GUARD_END
+}
+
+krs_status krs_seq_coeffs(krs_seq* s, double* alpha, double* rho, double* gamma, int32_t cap, int32_t* m_out) {
+    KRS_GUARD_BEGIN
+    if (!s) return KRS_E_INVALID;
+    const int m = s->impl->m_last;
+    if (m_out) *m_out = m;
+    if ((alpha || rho || gamma) && cap < m) {
+        set_error("output arrays too small");
+        return KRS_E_INVALID;
+    }
+    for (int i = 0; i < m && i < (int)s->impl->coef_alpha.size(); ++i) {
+        if (alpha) alpha[i] = s->impl->coef_alpha[i];
+        if (rho) rho[i] = s->impl->coef_rho[i];
+        if (gamma) gamma[i] = s->impl->coef_gamma[i];
+    }
+    return KRS_OK;
+    KRS_GUARD_END
+}
+
+krs_status krs_seq_basis(krs_seq* s, double* C, int64_t ldc, int32_t cap, int32_t* n_c) {
+    KRS_GUARD_BEGIN
+    if (!s) return KRS_E_INVALID;
+    return s->impl->basis(C, ldc, cap, n_c);
+    KRS_GUARD_END
+}
+
+krs_status krs_seq_info(krs_seq* s, krs_solve_info* info) {
+    KRS_GUARD_BEGIN
+    if (!s || !info) return KRS_E_INVALID;
+    *info = s->impl->info_last;
+    return KRS_OK;
+    KRS_GUARD_END
+}
+
+krs_status krs_seq_set_timing(krs_seq* s, int32_t enable) {
+    KRS_GUARD_BEGIN
+    if (!s) return KRS_E_INVALID;
+    s->impl->timing = enable != 0;
+    for (int j = 0; j < 3; ++j) {
+        s->impl->kt_count[j] = 0;
+        s->impl->kt_ms[j] = 0.0;
+    }
+    return KRS_OK;
+    KRS_GUARD_END
+}
+
+krs_status krs_seq_kernel_time(krs_seq* s, int32_t kernel, int64_t* launches, double* total_ms) {
+    KRS_GUARD_BEGIN
+    if (!s || kernel < 0 || kernel > 2) return KRS_E_INVALID;
+    if (launches) *launches = s->impl->kt_count[kernel];
+    if (total_ms) *total_ms = s->impl->kt_ms[kernel];
+    return KRS_OK;
+    KRS_GUARD_END
+}
+
+krs_status krs_seq_destroy(krs_seq* s) {
+    KRS_GUARD_BEGIN
+    if (!s) return KRS_OK;
+    krs_ctx* ctx = s->impl->ctx;
+    (void)hipStreamSynchronize(ctx->stream);
+    s->impl->destroy();
+    ctx->live_seqs -= 1;
+    delete s;
+    return KRS_OK;
+    KRS_GUARD_END
+}
+
+krs_status krs_ritz_select(const double* alpha, const double* rho, int32_t m, double eps, double* theta,
+                           double* theta_prev, uint8_t* selected) {
+    KRS_GUARD_BEGIN
+    if (m < 0 || (m > 0 && (!alpha || !rho))) {
+        set_error("alpha and rho are required");
+        return KRS_E_INVALID;
+    }
+    std::vector<double> d(m), l2(m > 0 ? m - 1 : 0);
+    for (int j = 0; j < m; ++j) {
+        if (!(alpha[j] > 0.0) || !(rho[j] > 0.0)) {
+            set_error("alpha and rho must be positive");
+            return KRS_E_INVALID;
+        }
+        d[j] = 1.0 / alpha[j];
+    }
+    for (int j = 0; j + 1 < m; ++j) l2[j] = rho[j + 1] / rho[j];
+    std::vector<double> th, th1;
+    krs::ldl_eigenvalues(d, l2, th, 8);
+    if (m > 1) {
+        std::vector<double> d1(d.begin(), d.end() - 1), l21(l2.begin(), l2.begin() + (m - 2));
+        krs::ldl_eigenvalues(d1, l21, th1, 8);
+    }
+    std::vector<int> sel = krs::stagnation_select(th, th1, eps);
+    for (int i = 0; i < m; ++i) {
+        if (theta) theta[i] = th[i];
+        if (selected) selected[i] = 0;
+    }
+    for (int i = 0; i + 1 < m; ++i)
+        if (theta_prev) theta_prev[i] = th1[i];
+    if (selected)
+        for (int i : sel) selected[i] = 1;
+    return KRS_OK;
+    KRS_GUARD_END
+}
+
+krs_status krs_coarse_factor(int32_t nc, const double* G, double rank_tol, double* Ginv, uint8_t* kept,
+                             int32_t* nk) {
+    KRS_GUARD_BEGIN
+    if (nc < 0 || (nc > 0 && (!G || !Ginv || !kept))) {
+        set_error("G, Ginv and kept are required");
+        return KRS_E_INVALID;
+    }
+    const int k = krs::coarse_factor(nc, G, rank_tol > 0 ? rank_tol : 1e-12, Ginv, kept);
+    if (nk) *nk = k;
+    return (nc > 0 && k == 0) ? KRS_E_COARSE_SINGULAR : KRS_OK;
+    KRS_GUARD_END
+}
+
+krs_status krs_batch_solve(krs_ctx* ctx, krs_seq* const* seqs, int32_t count, double* const* x, krs_solve_info* info) {
+    KRS_GUARD_BEGIN
+    if (!ctx || (count > 0 && !seqs)) return KRS_E_INVALID;
+    krs_status worst = KRS_OK;
+    for (int i = 0; i < count; ++i) {
+        if (!seqs[i] || seqs[i]->impl->ctx != ctx) {
+            set_error("every sequence must belong to ctx");
+            return KRS_E_INVALID;
+        }
+        krs_status st = seqs[i]->impl->solve(x ? x[i] : nullptr, false, info ? &info[i] : nullptr);
+        if (st != KRS_OK && worst == KRS_OK) worst = st;
+    }
+    return worst;
+    KRS_GUARD_END
+}
+
+}  // extern "C"

@@ -1,0 +1,156 @@
+// Internal declarations shared by the host runtime and the kernel launchers
+// of libkrs.  Nothing here is part of the public ABI (include/krs.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "krs.h"
+
+namespace krs {
+
+// ELL slice height, in (block) rows: one lane per block row of a slice.
+constexpr int kSlice = 64;
+// Doubles reserved at the head of the reduction scratch for SpMV partials
+// (>= the largest SpMV grid).
+constexpr int64_t kPart1 = 4096;
+
+// Device-side solver status codes (DevState::status).
+enum DevStatus : int32_t {
+    ST_RUN = 0,        // iterating
+    ST_DONE = 1,       // converged (true residual confirmed)
+    ST_CHECK = 2,      // recursive residual converged; true residual pending
+    ST_REFINE = 3,     // reliable update pending (mixed precision)
+    ST_BREAKDOWN = 4,  // (w, A w) <= 0 or (r, z) <= 0 or NaN
+    ST_MAXIT = 5,
+};
+constexpr uint32_t M_RUN = 1u << ST_RUN;
+constexpr uint32_t M_CHECK = 1u << ST_CHECK;
+constexpr uint32_t M_REFINE = 1u << ST_REFINE;
+
+// Scalars of one solve, resident in device memory.  Written only by the
+// single-workgroup finalize kernels, read by every workgroup of the next.
+struct DevState {
+    double rho;       // rho_j = (r_j, z_j)
+    double alpha;     // alpha_j
+    double beta;      // beta for the next direction update
+    double bb;        // ||b||^2
+    double rr;        // ||r||^2 of the recursion
+    double rr_ref;    // ||r||^2 right after the last refinement
+    double tol2;      // tol^2
+    double drop2;     // refinement trigger (relative drop of ||r||^2)
+    double rr_true;   // last true residual ||b - A x||^2
+    int32_t iter;     // products A w performed
+    int32_t status;   // DevStatus
+    int32_t max_iter;
+    int32_t hist_cap; // Z / W history slots available
+    int32_t since_refine;
+    int32_t refine_every;
+    int32_t refinements;
+    int32_t nc;       // basis columns active in this solve
+    int32_t pending_dir;  // 1 between a residual replacement and its direction update
+};
+
+// Per-launch view of one system, passed by value to the kernels.  V is the
+// storage type of the matrix values, the preconditioner and the basis; W
+// the type of the Krylov vectors; x, b and every reduction are double.
+template <typename V, typename W>
+struct SysView {
+    // sliced-ELL matrix (block size B known at compile time)
+    const int32_t* col;        // [slots*64] block column per entry
+    const int64_t* slice_ptr;  // [nslices+1] slot offsets
+    const V* val;              // values in V precision (planar per slot)
+    const double* val64;       // values in double (for true residuals / A C)
+    const V* minv;             // preconditioner inverse: n (Jacobi) or 9*nb (3x3 blocks)
+    int64_t n;                 // scalar rows
+    int64_t nb;                // block rows
+    int64_t nslices;
+    // vectors
+    double* x;
+    const double* b;
+    W* r;
+    W* s;
+    W* w;
+    W* q;
+    // basis
+    const V* C;      // n x nc column-major, leading dim ldc
+    const V* AC;     // n x nc row-major, leading dim ldac
+    int64_t ldc;
+    int64_t ldac;
+    const double* Ginv;  // nc x nc column-major
+    double* mu;          // nc
+    // histories
+    V* zhist;        // z_j at column j (SRKS), or null
+    V* whist;        // w_j at column j (TRKS: columns of C past nc), or null
+    int64_t ldh;
+    double* alpha_h;  // [hist] alpha_j
+    double* rho_h;    // rho_j
+    double* gamma_h;  // (w_j, A w_j)
+    int32_t coef_cap;
+    // reductions
+    double* part1;     // per-workgroup (w, A w) partials of the SpMV
+    double* partials;  // per-workgroup partials of the other reductions
+    DevState* st;
+};
+
+// ------------------------------------------------------------ launchers
+// All launch on `stream`; the grid shapes are derived from the view.
+template <typename V, typename W, int B> void launch_spmv_dot(const SysView<V, W>& v, hipStream_t stream);
+template <typename V, typename W, int B>
+void launch_update_reduce(const SysView<V, W>& v, int mode, hipStream_t stream);
+template <typename V, typename W> void launch_correct_dir(const SysView<V, W>& v, int first, hipStream_t stream);
+template <typename V, typename W, int B>
+void launch_true_resid(const SysView<V, W>& v, int final_only, hipStream_t stream);
+template <typename V, typename W>
+void launch_coarse_dot(const SysView<V, W>& v, const double* src64, const W* srcV, int with_bb, uint32_t mask,
+                       hipStream_t stream);
+template <typename V, typename W>
+void launch_coarse_correct(const SysView<V, W>& v, int from_b, uint32_t mask, hipStream_t stream);
+template <typename V, typename W, int B>
+void launch_spmm(const SysView<V, W>& v, const V* C, int64_t ldc, int nc, double* AC64, V* ACv, hipStream_t stream);
+template <typename V>
+void launch_gram(const V* C, int64_t ldc, const double* AC64, int64_t n, int nc, double* G, double* partials,
+                 int64_t partial_cap, hipStream_t stream);
+template <typename V>
+void launch_basis_combine(const V* Z, int64_t ldz, int m, const double* F, int s, V* out, int64_t ldo, int64_t n,
+                          hipStream_t stream);
+template <typename V>
+void launch_scale_columns(V* C, int64_t ldc, int64_t n, const double* scale, int k, hipStream_t stream);
+template <typename V>
+void launch_copy_columns(const V* src, int64_t lds, V* dst, int64_t ldd, int64_t n, const int32_t* map, int k,
+                         hipStream_t stream);
+template <typename V, int B>
+void launch_scatter_values(const double* in, const int64_t* map, int64_t nnzb, double* val64, V* valV,
+                           hipStream_t stream);
+template <typename V, int B>
+void launch_precond_setup(const double* in, const int64_t* diag_idx, int64_t nb, V* minv, int32_t* bad,
+                          hipStream_t stream);
+template <typename V> void launch_d2v(const double* in, V* out, int64_t n, hipStream_t stream);
+template <typename V> void launch_v2d(const V* in, double* out, int64_t n, hipStream_t stream);
+
+// number of workgroups the reduction kernels use for a system (bounds partials)
+int64_t update_grid(int64_t n, int block);
+int64_t spmv_grid(int64_t nslices, int block);
+int64_t dot_grid(int64_t n);
+
+// ----------------------------------------------------------- host logic
+// Tridiagonal eigenvalues of H = L D L^T (d_j = 1/alpha_j, l_j^2 = beta_{j+1}),
+// descending, high relative accuracy (ritz.cpp).
+void ldl_eigenvalues(const std::vector<double>& d, const std::vector<double>& l2, std::vector<double>& theta,
+                     int threads);
+// Eigenvector (unit 2-norm) of the explicit tridiagonal (diag, off) for eigenvalue theta.
+void tridiag_eigvec(const std::vector<double>& diag, const std::vector<double>& off, double theta,
+                    std::vector<double>& v);
+// Stagnation selection (Section 4.4) on descending theta_m / theta_{m-1}.
+std::vector<int> stagnation_select(const std::vector<double>& th_m, const std::vector<double>& th_m1, double eps);
+// Cholesky with rank guard + explicit inverse (coarse.cpp). Returns kept count.
+int coarse_factor(int nc, const double* G, double rank_tol, double* Ginv, uint8_t* kept);
+// U (nc x nk) such that C U is the kept part of C made A-orthonormal.
+int coarse_orthonormalizer(int nc, const double* G, double rank_tol, double* U, uint8_t* kept);
+
+void set_error(const std::string& msg);
+
+}  // namespace krs

@@ -1,0 +1,860 @@
+// Sequence runtime: system intake, coarse rebuild, the iteration driver and
+// Krylov reuse (TRKS, Algorithm 2; SRKS, Algorithm 3) for one sequence of
+// systems A^(k) x^(k) = b^(k) sharing a sparsity pattern.
+#include "seq.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <thread>
+
+namespace krs {
+
+namespace {
+
+inline int host_threads() {
+    unsigned h = std::thread::hardware_concurrency();
+    if (h == 0) h = 4;
+    return (int)std::min(16u, h);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- memory
+
+void* dev_alloc(krs_ctx* ctx, size_t bytes) {
+    if (bytes == 0) bytes = 64;
+    bytes = (bytes + 255) & ~(size_t)255;
+    void* p = nullptr;
+    if (ctx->has_alloc) {
+        p = ctx->alloc.alloc(ctx->alloc.user, bytes, (void*)ctx->stream);
+    } else {
+        if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+    }
+    if (p) ctx->bytes_live += bytes;
+    return p;
+}
+
+void dev_free(krs_ctx* ctx, void* p, size_t bytes) {
+    if (!p) return;
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (ctx->has_alloc) ctx->alloc.free(ctx->alloc.user, p, (void*)ctx->stream);
+    else (void)hipFree(p);
+    ctx->bytes_live -= bytes;
+}
+
+bool Buf::reserve(krs_ctx* ctx, size_t nbytes) {
+    if (nbytes <= bytes && p) return true;
+    release(ctx);
+    p = dev_alloc(ctx, nbytes);
+    if (!p) return false;
+    bytes = nbytes;
+    return true;
+}
+
+bool Buf::grow_keep(krs_ctx* ctx, size_t nbytes, hipStream_t stream) {
+    if (nbytes <= bytes && p) return true;
+    void* q = dev_alloc(ctx, nbytes);
+    if (!q) return false;
+    if (p && bytes) {
+        if (hipMemcpyAsync(q, p, bytes, hipMemcpyDeviceToDevice, stream) != hipSuccess) {
+            dev_free(ctx, q, nbytes);
+            return false;
+        }
+        if (hipStreamSynchronize(stream) != hipSuccess) return false;
+    }
+    release(ctx);
+    p = q;
+    bytes = nbytes;
+    return true;
+}
+
+void Buf::release(krs_ctx* ctx) {
+    if (p) dev_free(ctx, p, bytes);
+    p = nullptr;
+    bytes = 0;
+}
+
+// ------------------------------------------------------------- helpers
+
+#define KRS_HIP(call)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            set_error(std::string("HIP error: ") + hipGetErrorString(e_) + " at " #call); \
+            return KRS_E_DEVICE;                                                       \
+        }                                                                              \
+    } while (0)
+
+#define KRS_CHECK_LAUNCH()                                                             \
+    do {                                                                               \
+        hipError_t e_ = hipGetLastError();                                             \
+        if (e_ != hipSuccess) {                                                        \
+            set_error(std::string("kernel launch failed: ") + hipGetErrorString(e_));  \
+            return KRS_E_DEVICE;                                                       \
+        }                                                                              \
+    } while (0)
+
+struct Timer {
+    hipEvent_t a = nullptr, b = nullptr;
+    Timer() {
+        (void)hipEventCreate(&a);
+        (void)hipEventCreate(&b);
+    }
+    ~Timer() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+    void start(hipStream_t s) { (void)hipEventRecord(a, s); }
+    void stop(hipStream_t s) { (void)hipEventRecord(b, s); }
+    double ms() {
+        float t = 0.f;
+        (void)hipEventSynchronize(b);
+        (void)hipEventElapsedTime(&t, a, b);
+        return (double)t;
+    }
+};
+
+// ------------------------------------------------------------ creation
+
+template <typename V, typename W>
+krs_status SeqImpl<V, W>::create(const krs_seq_desc& d, const double* C0, int32_t m0, int64_t ldc0) {
+    desc = d;
+    desc.row_ptr = nullptr;
+    desc.col_idx = nullptr;
+    B = d.block;
+    n = d.n;
+    nb = n / B;
+    nnzb = d.nnzb;
+    stream = ctx->stream;
+    if (desc.rank_tol <= 0.0) desc.rank_tol = 1e-12;
+    if (desc.refine_drop <= 0.0) desc.refine_drop = 0.1;
+    if (desc.ritz_eps <= 0.0) desc.ritz_eps = 1e-14;
+    const int64_t* rp = d.row_ptr;
+    const int32_t* ci = d.col_idx;
+    // ---- sliced ELL layout
+    nslices = (nb + kSlice - 1) / kSlice;
+    std::vector<int64_t> slice_ptr(nslices + 1, 0);
+    for (int64_t s = 0; s < nslices; ++s) {
+        int64_t w = 0;
+        for (int64_t r = s * kSlice; r < std::min(nb, (s + 1) * kSlice); ++r) w = std::max(w, rp[r + 1] - rp[r]);
+        slice_ptr[s + 1] = slice_ptr[s] + w;
+    }
+    nslots = slice_ptr[nslices];
+    std::vector<int32_t> col((size_t)nslots * kSlice, 0);
+    std::vector<int64_t> map(nnzb, 0);
+    std::vector<int64_t> diag(nb, -1);
+    for (int64_t s = 0; s < nslices; ++s) {
+        const int64_t w = slice_ptr[s + 1] - slice_ptr[s];
+        for (int l = 0; l < kSlice; ++l) {
+            const int64_t r = s * kSlice + l;
+            const int64_t len = (r < nb) ? rp[r + 1] - rp[r] : 0;
+            for (int64_t k = 0; k < w; ++k) {
+                const int64_t E = (slice_ptr[s] + k) * kSlice + l;
+                if (k < len) {
+                    const int64_t t = rp[r] + k;
+                    col[E] = ci[t];
+                    map[t] = E;
+                    if (ci[t] == r) diag[r] = t;
+                } else {
+                    col[E] = (int32_t)(r < nb ? r : 0);
+                }
+            }
+        }
+    }
+    for (int64_t r = 0; r < nb; ++r)
+        if (diag[r] < 0) {
+            set_error("every (block) row needs its diagonal entry");
+            return KRS_E_INVALID;
+        }
+    const size_t vb = (size_t)B * B;
+    bool ok = true;
+    ok = ok && d_col.reserve(ctx, col.size() * sizeof(int32_t));
+    ok = ok && d_slice_ptr.reserve(ctx, slice_ptr.size() * sizeof(int64_t));
+    ok = ok && d_map.reserve(ctx, map.size() * sizeof(int64_t));
+    ok = ok && d_diag.reserve(ctx, diag.size() * sizeof(int64_t));
+    ok = ok && d_val64.reserve(ctx, (size_t)nslots * kSlice * vb * sizeof(double));
+    if (!std::is_same<V, double>::value) ok = ok && d_valV.reserve(ctx, (size_t)nslots * kSlice * vb * sizeof(V));
+    ok = ok && d_minv.reserve(ctx, (size_t)nb * vb * sizeof(V));
+    ok = ok && d_bad.reserve(ctx, 64);
+    ok = ok && d_in.reserve(ctx, (size_t)nnzb * vb * sizeof(double));
+    ok = ok && d_b.reserve(ctx, n * sizeof(double));
+    ok = ok && d_x.reserve(ctx, n * sizeof(double));
+    ok = ok && d_r.reserve(ctx, n * sizeof(W));
+    ok = ok && d_s.reserve(ctx, n * sizeof(W));
+    ok = ok && d_w.reserve(ctx, n * sizeof(W));
+    ok = ok && d_q.reserve(ctx, n * sizeof(W));
+    ok = ok && d_st.reserve(ctx, sizeof(DevState));
+    ok = ok && d_mu.reserve(ctx, 1024 * sizeof(double));
+    if (!ok) {
+        set_error("device allocation failed while creating the sequence");
+        return KRS_E_OOM;
+    }
+    KRS_HIP(hipMemcpyAsync(d_col.p, col.data(), col.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+    KRS_HIP(hipMemcpyAsync(d_slice_ptr.p, slice_ptr.data(), slice_ptr.size() * sizeof(int64_t), hipMemcpyHostToDevice,
+                           stream));
+    KRS_HIP(hipMemcpyAsync(d_map.p, map.data(), map.size() * sizeof(int64_t), hipMemcpyHostToDevice, stream));
+    KRS_HIP(hipMemcpyAsync(d_diag.p, diag.data(), diag.size() * sizeof(int64_t), hipMemcpyHostToDevice, stream));
+    KRS_HIP(hipMemsetAsync(d_val64.p, 0, d_val64.bytes, stream));
+    if (d_valV.p) KRS_HIP(hipMemsetAsync(d_valV.p, 0, d_valV.bytes, stream));
+    KRS_HIP(hipMemsetAsync(d_st.p, 0, sizeof(DevState), stream));
+    KRS_HIP(hipHostMalloc((void**)&h_st, sizeof(DevState), hipHostMallocDefault));
+    std::memset(h_st, 0, sizeof(DevState));
+    // ---- initial basis C0
+    ldc = (n + 63) & ~(int64_t)63;
+    nc = 0;
+    if (m0 > 0) {
+        if (!C0 || ldc0 < n) {
+            set_error("C0 must be n x m0 with ldc0 >= n");
+            return KRS_E_INVALID;
+        }
+        if (!ensure_c_capacity(m0)) return KRS_E_OOM;
+        if (!d_C0.reserve(ctx, (size_t)ldc * m0 * sizeof(V))) return KRS_E_OOM;
+        Buf tmp;
+        if (!tmp.reserve(ctx, (size_t)n * sizeof(double))) return KRS_E_OOM;
+        for (int c = 0; c < m0; ++c) {
+            KRS_HIP(hipMemcpyAsync(tmp.p, C0 + (size_t)c * ldc0, n * sizeof(double), hipMemcpyHostToDevice, stream));
+            launch_d2v<V>((const double*)tmp.p, (V*)d_C.p + (size_t)c * ldc, n, stream);
+            launch_d2v<V>((const double*)tmp.p, (V*)d_C0.p + (size_t)c * ldc, n, stream);
+        }
+        KRS_HIP(hipStreamSynchronize(stream));
+        tmp.release(ctx);
+        nc = m0;
+    }
+    nc0 = m0;
+    KRS_HIP(hipStreamSynchronize(stream));
+    return KRS_OK;
+}
+
+template <typename V, typename W>
+bool SeqImpl<V, W>::ensure_c_capacity(int cols) {
+    if (cols <= nc_cap && d_C.p) return true;
+    int cap = std::max(cols, std::max(8, nc_cap + nc_cap / 2));
+    if (cap > 1024 && cols <= 1024) cap = 1024;
+    if (!d_C.grow_keep(ctx, (size_t)ldc * cap * sizeof(V), stream)) {
+        set_error("device allocation failed for the basis");
+        return false;
+    }
+    nc_cap = cap;
+    return true;
+}
+
+template <typename V, typename W>
+void SeqImpl<V, W>::destroy() {
+    for (Buf* b : {&d_col, &d_slice_ptr, &d_map, &d_diag, &d_val64, &d_valV, &d_minv, &d_bad, &d_in, &d_b, &d_x,
+                   &d_r, &d_s, &d_w, &d_q, &d_C, &d_C0, &d_AC64, &d_ACv, &d_G, &d_Ginv, &d_mu, &d_Z, &d_coef,
+                   &d_partials, &d_st, &d_F, &d_tmp, &d_Ctmp})
+        b->release(ctx);
+    if (h_st) (void)hipHostFree(h_st);
+    h_st = nullptr;
+    for (auto& e : tev)
+        if (e) (void)hipEventDestroy(e);
+    graph_release();
+}
+
+// ------------------------------------------------------------- submit
+
+template <typename V, typename W>
+krs_status SeqImpl<V, W>::submit(const double* values, const double* b, bool device) {
+    if (!values || !b) {
+        set_error("values and b are required");
+        return KRS_E_INVALID;
+    }
+    Timer tm;
+    tm.start(stream);
+    const size_t vb = (size_t)B * B;
+    const double* vin = values;
+    if (!device) {
+        KRS_HIP(hipMemcpyAsync(d_in.p, values, (size_t)nnzb * vb * sizeof(double), hipMemcpyHostToDevice, stream));
+        KRS_HIP(hipMemcpyAsync(d_b.p, b, n * sizeof(double), hipMemcpyHostToDevice, stream));
+        vin = (const double*)d_in.p;
+    } else {
+        KRS_HIP(hipMemcpyAsync(d_b.p, b, n * sizeof(double), hipMemcpyDeviceToDevice, stream));
+    }
+    V* valV = std::is_same<V, double>::value ? nullptr : (V*)d_valV.p;
+    KRS_HIP(hipMemsetAsync(d_bad.p, 0, 64, stream));
+    if (B == 1) {
+        launch_scatter_values<V, 1>(vin, (const int64_t*)d_map.p, nnzb, (double*)d_val64.p, valV, stream);
+        launch_precond_setup<V, 1>(vin, (const int64_t*)d_diag.p, nb, (V*)d_minv.p, (int32_t*)d_bad.p, stream);
+    } else {
+        launch_scatter_values<V, 3>(vin, (const int64_t*)d_map.p, nnzb, (double*)d_val64.p, valV, stream);
+        if (desc.precond == KRS_PC_BJACOBI3) {
+            launch_precond_setup<V, 3>(vin, (const int64_t*)d_diag.p, nb, (V*)d_minv.p, (int32_t*)d_bad.p, stream);
+        } else {
+            set_error("block-3 systems use the 3x3 block-Jacobi preconditioner");
+            return KRS_E_INVALID;
+        }
+    }
+    KRS_CHECK_LAUNCH();
+    int32_t bad = 0;
+    KRS_HIP(hipMemcpyAsync(&bad, d_bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    tm.stop(stream);
+    KRS_HIP(hipStreamSynchronize(stream));
+    info_last.t_setup_ms = tm.ms();
+    if (bad) {
+        set_error("preconditioner pivot not positive: the diagonal (blocks) of A are not SPD");
+        submitted = false;
+        return KRS_E_NOT_SPD;
+    }
+    submitted = true;
+    return KRS_OK;
+}
+
+// --------------------------------------------------------------- views
+
+template <typename V, typename W>
+SysView<V, W> SeqImpl<V, W>::view() {
+    SysView<V, W> v;
+    std::memset(&v, 0, sizeof v);
+    v.col = (const int32_t*)d_col.p;
+    v.slice_ptr = (const int64_t*)d_slice_ptr.p;
+    v.val = std::is_same<V, double>::value ? (const V*)d_val64.p : (const V*)d_valV.p;
+    v.val64 = (const double*)d_val64.p;
+    v.minv = (const V*)d_minv.p;
+    v.n = n;
+    v.nb = nb;
+    v.nslices = nslices;
+    v.x = (double*)d_x.p;
+    v.b = (const double*)d_b.p;
+    v.r = (W*)d_r.p;
+    v.s = (W*)d_s.p;
+    v.w = (W*)d_w.p;
+    v.q = (W*)d_q.p;
+    v.C = (const V*)d_C.p;
+    v.AC = std::is_same<V, double>::value ? (const V*)d_AC64.p : (const V*)d_ACv.p;
+    v.ldc = ldc;
+    v.ldac = nc > 0 ? nc : 1;
+    v.Ginv = (const double*)d_Ginv.p;
+    v.mu = (double*)d_mu.p;
+    v.zhist = nullptr;
+    v.whist = nullptr;
+    v.ldh = ldc;
+    if (desc.reuse == KRS_REUSE_SELECTIVE) v.zhist = (V*)d_Z.p;
+    if (desc.reuse == KRS_REUSE_TOTAL && trks_slots > 0) v.whist = (V*)d_C.p + (size_t)nc * ldc;
+    v.alpha_h = (double*)d_coef.p;
+    v.rho_h = v.alpha_h + coef_cap;
+    v.gamma_h = v.rho_h + coef_cap;
+    v.coef_cap = coef_cap;
+    v.part1 = (double*)d_partials.p;
+    v.partials = (double*)d_partials.p + kPart1;
+    v.st = (DevState*)d_st.p;
+    return v;
+}
+
+// ---------------------------------------------------- kernel dispatch
+
+template <typename V, typename W>
+void SeqImpl<V, W>::k_spmv(const SysView<V, W>& v) {
+    if (B == 1) launch_spmv_dot<V, W, 1>(v, stream);
+    else launch_spmv_dot<V, W, 3>(v, stream);
+}
+template <typename V, typename W>
+void SeqImpl<V, W>::k_update(const SysView<V, W>& v, int mode) {
+    if (B == 1) launch_update_reduce<V, W, 1>(v, mode, stream);
+    else launch_update_reduce<V, W, 3>(v, mode, stream);
+}
+template <typename V, typename W>
+void SeqImpl<V, W>::k_resid(const SysView<V, W>& v, int final_only) {
+    if (B == 1) launch_true_resid<V, W, 1>(v, final_only, stream);
+    else launch_true_resid<V, W, 3>(v, final_only, stream);
+}
+
+template <typename V, typename W>
+void SeqImpl<V, W>::enqueue_iterations(const SysView<V, W>& v, int k) {
+    for (int i = 0; i < k; ++i) {
+        const bool t = timing && i == 0 && tev[0];
+        if (t) (void)hipEventRecord(tev[0], stream);
+        k_spmv(v);
+        if (t) (void)hipEventRecord(tev[1], stream);
+        k_update(v, 0);
+        if (t) (void)hipEventRecord(tev[2], stream);
+        launch_correct_dir<V, W>(v, 0, stream);
+        if (t) {
+            (void)hipEventRecord(tev[3], stream);
+            tev_pending = true;
+        }
+    }
+}
+
+// Add the sampled durations once the stream has passed the events.  A
+// sample is kept only while the solve was still iterating at its end
+// (afterwards the gated kernels return at once and would skew the mean).
+template <typename V, typename W>
+void SeqImpl<V, W>::collect_timing() {
+    if (!tev_pending) return;
+    tev_pending = false;
+    float ms[3];
+    for (int j = 0; j < 3; ++j)
+        if (hipEventElapsedTime(&ms[j], tev[j], tev[j + 1]) != hipSuccess) return;
+    for (int j = 0; j < 3; ++j) {
+        kt_count[j] += 1;
+        kt_ms[j] += ms[j];
+    }
+}
+
+template <typename V, typename W>
+void SeqImpl<V, W>::enqueue_refine(const SysView<V, W>& v) {
+    k_resid(v, 0);
+    if (nc > 0) {
+        launch_coarse_dot<V, W>(v, nullptr, v.r, 0, M_REFINE, stream);
+        launch_coarse_correct<V, W>(v, 0, M_REFINE, stream);
+    }
+    k_update(v, 2);
+    launch_correct_dir<V, W>(v, 2, stream);
+}
+
+// Replay a captured block of `block` iterations plus the refinement step.
+// The capture is reused while the launch view (pointers, sizes, basis
+// width) is unchanged; every kernel reads its scalars from device memory,
+// so a replay needs no host-side arguments.
+template <typename V, typename W>
+krs_status SeqImpl<V, W>::graph_launch(const SysView<V, W>& v, int slot, int block) {
+    GraphSlot& g = gslot[slot];
+    if (!g.exec || g.block != block || std::memcmp(&g.view, &v, sizeof v) != 0) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+        g.exec = nullptr;
+        g.graph = nullptr;
+        KRS_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+        const bool t = timing;
+        timing = false;
+        enqueue_iterations(v, block);
+        enqueue_refine(v);
+        timing = t;
+        hipError_t e = hipStreamEndCapture(stream, &g.graph);
+        if (e != hipSuccess) {
+            set_error(std::string("graph capture failed: ") + hipGetErrorString(e));
+            return KRS_E_DEVICE;
+        }
+        KRS_HIP(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
+        g.view = v;
+        g.block = block;
+    }
+    KRS_HIP(hipGraphLaunch(g.exec, stream));
+    return KRS_OK;
+}
+
+template <typename V, typename W>
+void SeqImpl<V, W>::graph_release() {
+    for (auto& g : gslot) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+        g.exec = nullptr;
+        g.graph = nullptr;
+    }
+}
+
+// ------------------------------------------------------------- rebuild
+
+// A C (double) for the current basis, and G = C^T A C on the host.
+template <typename V, typename W>
+krs_status SeqImpl<V, W>::coarse_pass(std::vector<double>& G) {
+    const size_t nn = (size_t)nc * nc;
+    const bool need_v = !std::is_same<V, double>::value;
+    if (!d_AC64.reserve(ctx, (size_t)n * nc * sizeof(double)) ||
+        (need_v && !d_ACv.reserve(ctx, (size_t)n * nc * sizeof(V))) || !d_G.reserve(ctx, nn * sizeof(double)) ||
+        !d_Ginv.reserve(ctx, nn * sizeof(double)) || !d_mu.reserve(ctx, std::max<size_t>(1024, nc) * sizeof(double))) {
+        set_error("device allocation failed for A C / C^T A C");
+        return KRS_E_OOM;
+    }
+    const int64_t gram_cap = (int64_t)std::min<size_t>(64 * nn, (size_t)16 << 20);
+    if (!ensure_partials(gram_cap)) return KRS_E_OOM;
+    SysView<V, W> v = view();
+    V* ACv = std::is_same<V, double>::value ? (V*)d_AC64.p : (V*)d_ACv.p;
+    if (B == 1) launch_spmm<V, W, 1>(v, (const V*)d_C.p, ldc, nc, (double*)d_AC64.p, ACv, stream);
+    else launch_spmm<V, W, 3>(v, (const V*)d_C.p, ldc, nc, (double*)d_AC64.p, ACv, stream);
+    launch_gram<V>((const V*)d_C.p, ldc, (const double*)d_AC64.p, n, nc, (double*)d_G.p,
+                   (double*)d_partials.p + kPart1, (int64_t)(d_partials.bytes / sizeof(double)) - kPart1, stream);
+    KRS_CHECK_LAUNCH();
+    G.resize(nn);
+    KRS_HIP(hipMemcpyAsync(G.data(), d_G.p, nn * sizeof(double), hipMemcpyDeviceToHost, stream));
+    KRS_HIP(hipStreamSynchronize(stream));
+    for (int a = 0; a < nc; ++a)
+        for (int b = a + 1; b < nc; ++b) {
+            const double s = 0.5 * (G[(size_t)a * nc + b] + G[(size_t)b * nc + a]);
+            G[(size_t)a * nc + b] = s;
+            G[(size_t)b * nc + a] = s;
+        }
+    return KRS_OK;
+}
+
+// Rebuild of the coarse space for A^(k) (Algorithm 1, first step):
+//  1. A C, G = C^T A C; guarded Cholesky G = L L^T (drops dependent columns);
+//  2. C <- C_k L_k^{-T}: the carried basis made A^(k)-orthonormal.  The
+//     projector P and x0 depend on span(C) only, so the iteration is the
+//     same; the coarse matrix becomes ~I, which keeps the single-precision
+//     projector accurate;
+//  3. A C and G again for the new basis, G^{-1} for the iterations.
+template <typename V, typename W>
+krs_status SeqImpl<V, W>::rebuild(int* dropped) {
+    *dropped = 0;
+    if (nc == 0) return KRS_OK;
+    std::vector<double> G;
+    krs_status st = coarse_pass(G);
+    if (st != KRS_OK) return st;
+    {
+        std::vector<double> U((size_t)nc * nc);
+        std::vector<uint8_t> kept(nc, 1);
+        const int nk = coarse_orthonormalizer(nc, G.data(), desc.rank_tol, U.data(), kept.data());
+        *dropped += nc - nk;
+        if (nk == 0) {
+            nc = 0;
+            return KRS_OK;
+        }
+        if (!d_F.reserve(ctx, (size_t)nc * nk * sizeof(double)) ||
+            !d_Ctmp.reserve(ctx, (size_t)ldc * nk * sizeof(V))) {
+            set_error("device allocation failed for the basis change");
+            return KRS_E_OOM;
+        }
+        KRS_HIP(hipMemcpyAsync(d_F.p, U.data(), (size_t)nc * nk * sizeof(double), hipMemcpyHostToDevice, stream));
+        launch_basis_combine<V>((const V*)d_C.p, ldc, nc, (const double*)d_F.p, nk, (V*)d_Ctmp.p, ldc, n, stream);
+        KRS_CHECK_LAUNCH();
+        KRS_HIP(hipMemcpyAsync(d_C.p, d_Ctmp.p, (size_t)ldc * nk * sizeof(V), hipMemcpyDeviceToDevice, stream));
+        nc = nk;
+    }
+    for (int pass = 0; pass < 3; ++pass) {
+        st = coarse_pass(G);
+        if (st != KRS_OK) return st;
+        const size_t nn = (size_t)nc * nc;
+        std::vector<double> Gi(nn);
+        std::vector<uint8_t> kept(nc, 1);
+        const int nk = coarse_factor(nc, G.data(), desc.rank_tol, Gi.data(), kept.data());
+        if (nk == nc) {
+            KRS_HIP(hipMemcpyAsync(d_Ginv.p, Gi.data(), nn * sizeof(double), hipMemcpyHostToDevice, stream));
+            KRS_HIP(hipStreamSynchronize(stream));
+            return KRS_OK;
+        }
+        // a column vanished after the change of basis: compact and redo
+        *dropped += nc - nk;
+        if (nk == 0) {
+            nc = 0;
+            return KRS_OK;
+        }
+        std::vector<int32_t> keep_map;
+        for (int c = 0; c < nc; ++c)
+            if (kept[c]) keep_map.push_back(c);
+        if (!d_tmp.reserve(ctx, std::max<size_t>(keep_map.size() * sizeof(int32_t), 64))) return KRS_E_OOM;
+        KRS_HIP(hipMemcpyAsync(d_tmp.p, keep_map.data(), keep_map.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                               stream));
+        launch_copy_columns<V>((const V*)d_C.p, ldc, (V*)d_C.p, ldc, n, (const int32_t*)d_tmp.p, nk, stream);
+        KRS_CHECK_LAUNCH();
+        KRS_HIP(hipStreamSynchronize(stream));
+        nc = nk;
+    }
+    set_error("coarse space did not stabilise under the rank guard");
+    return KRS_E_COARSE_SINGULAR;
+}
+
+template <typename V, typename W>
+bool SeqImpl<V, W>::ensure_partials(int64_t extra) {
+    const int64_t need = kPart1 + std::max<int64_t>(
+        {update_grid(n, B) * (int64_t)(std::max(nc, 1) + 2), spmv_grid(nslices, B) + 8,
+         dot_grid(n) * (int64_t)(std::max(nc, 1) + 1), extra, (int64_t)1024});
+    if ((int64_t)(d_partials.bytes / sizeof(double)) >= need) return true;
+    if (!d_partials.reserve(ctx, (size_t)need * sizeof(double))) {
+        set_error("device allocation failed for reduction scratch");
+        return false;
+    }
+    return true;
+}
+
+// --------------------------------------------------------------- solve
+
+template <typename V, typename W>
+krs_status SeqImpl<V, W>::solve(double* x, bool device_x, krs_solve_info* info) {
+    if (!submitted) {
+        set_error("krs_seq_solve needs a submitted system");
+        return KRS_E_STATE;
+    }
+    if (nc > 1024) {
+        set_error("basis larger than 1024 columns is not supported");
+        return KRS_E_INVALID;
+    }
+    solved = false;
+    Timer t_rb, t_it;
+    t_rb.start(stream);
+    int dropped = 0;
+    krs_status st = rebuild(&dropped);
+    if (st != KRS_OK) return st;
+    // histories
+    const int max_iter = std::max(0, desc.max_iter);
+    if (coef_cap < max_iter + 2) {
+        coef_cap = max_iter + 2;
+        if (!d_coef.reserve(ctx, (size_t)3 * coef_cap * sizeof(double))) return KRS_E_OOM;
+    }
+    int hist = 0;
+    trks_slots = 0;
+    if (desc.reuse == KRS_REUSE_SELECTIVE) {
+        hist = desc.history_cap > 0 ? std::min(desc.history_cap, max_iter + 1) : max_iter + 1;
+        if (!d_Z.reserve(ctx, (size_t)ldc * hist * sizeof(V))) {
+            set_error("device allocation failed for the Krylov history");
+            return KRS_E_OOM;
+        }
+    } else if (desc.reuse == KRS_REUSE_TOTAL) {
+        hist = max_iter + 1;
+        if (desc.max_basis > 0) hist = std::min(hist, std::max(0, desc.max_basis - nc));
+        if (desc.history_cap > 0) hist = std::min(hist, desc.history_cap);
+        hist = std::min(hist, 1024 - nc);
+        if (hist < 0) hist = 0;
+        if (!ensure_c_capacity(nc + hist)) return KRS_E_OOM;
+        trks_slots = hist;
+    }
+    if (!ensure_partials(0)) return KRS_E_OOM;
+    // device state
+    std::memset(h_st, 0, sizeof(DevState));
+    h_st->tol2 = desc.tol * desc.tol;
+    // reliable updates whenever single precision is involved
+    const bool lowp = !std::is_same<V, double>::value;
+    h_st->drop2 = lowp ? desc.refine_drop * desc.refine_drop : 0.0;
+    h_st->refine_every = lowp ? desc.refine_every : 0;
+    h_st->status = ST_RUN;
+    h_st->max_iter = max_iter;
+    h_st->hist_cap = hist;
+    h_st->nc = nc;
+    KRS_HIP(hipMemcpyAsync(d_st.p, h_st, sizeof(DevState), hipMemcpyHostToDevice, stream));
+    if (timing && !tev[0])
+        for (auto& e : tev) KRS_HIP(hipEventCreate(&e));
+    h_st->iter = 0;
+    SysView<V, W> v = view();
+    // initialisation: mu0 = Ginv C^T b, x0 = C mu0, r0 = b - AC mu0, s0, z0, w0
+    launch_coarse_dot<V, W>(v, (const double*)d_b.p, nullptr, 1, M_RUN, stream);
+    launch_coarse_correct<V, W>(v, 1, M_RUN, stream);
+    k_update(v, 1);
+    launch_correct_dir<V, W>(v, 1, stream);
+    KRS_CHECK_LAUNCH();
+    t_rb.stop(stream);
+    t_it.start(stream);
+    // iteration blocks; each block ends with the (gated) refinement step.
+    // With timing on, the first block runs eagerly so that its first
+    // iteration can be bracketed with events.
+    const bool graphs = desc.exec_mode == 0;
+    int block = graphs ? 16 : 8;
+    int last_iter = -1, stuck = 0;
+    bool first_block = true;
+    while (true) {
+        const int iter_before = h_st->iter;
+        int ran = block;
+        if (graphs && !(timing && first_block)) {
+            krs_status gs = graph_launch(v, block == 16 ? 0 : 1, block);
+            if (gs != KRS_OK) return gs;
+        } else {
+            if (timing && first_block) ran = 8;
+            enqueue_iterations(v, ran);
+            enqueue_refine(v);
+            KRS_CHECK_LAUNCH();
+        }
+        first_block = false;
+        KRS_HIP(hipMemcpyAsync(h_st, d_st.p, sizeof(DevState), hipMemcpyDeviceToHost, stream));
+        KRS_HIP(hipStreamSynchronize(stream));
+        const int s = h_st->status;
+        if (timing) {
+            if (h_st->iter >= iter_before + ran) collect_timing();
+            else tev_pending = false;
+        }
+        if (s == ST_DONE || s == ST_BREAKDOWN || s == ST_MAXIT) break;
+        if (h_st->iter == last_iter) {
+            if (++stuck > 4) {
+                set_error("solver made no progress");
+                return KRS_E_DEVICE;
+            }
+        } else {
+            stuck = 0;
+        }
+        last_iter = h_st->iter;
+        block = graphs ? 64 : std::min(block * 2, 64);
+    }
+    k_resid(v, 1);
+    KRS_CHECK_LAUNCH();
+    t_it.stop(stream);
+    KRS_HIP(hipMemcpyAsync(h_st, d_st.p, sizeof(DevState), hipMemcpyDeviceToHost, stream));
+    if (x) {
+        if (device_x) KRS_HIP(hipMemcpyAsync(x, d_x.p, n * sizeof(double), hipMemcpyDeviceToDevice, stream));
+        else KRS_HIP(hipMemcpyAsync(x, d_x.p, n * sizeof(double), hipMemcpyDeviceToHost, stream));
+    }
+    KRS_HIP(hipStreamSynchronize(stream));
+    const int m = h_st->iter;
+    m_last = m;
+    const int mc = std::min(m + 1, coef_cap);
+    coef_alpha.assign(mc, 0.0);
+    coef_rho.assign(mc, 0.0);
+    coef_gamma.assign(mc, 0.0);
+    if (mc > 0) {
+        const double* base = (const double*)d_coef.p;
+        KRS_HIP(hipMemcpy(coef_alpha.data(), base, mc * sizeof(double), hipMemcpyDeviceToHost));
+        KRS_HIP(hipMemcpy(coef_rho.data(), base + coef_cap, mc * sizeof(double), hipMemcpyDeviceToHost));
+        KRS_HIP(hipMemcpy(coef_gamma.data(), base + 2 * coef_cap, mc * sizeof(double), hipMemcpyDeviceToHost));
+    }
+    krs_solve_info inf = info_last;
+    inf.iters = m;
+    inf.n_c = nc;
+    inf.refinements = h_st->refinements;
+    inf.dropped = dropped;
+    inf.selected = 0;
+    inf.added = 0;
+    const double bb = h_st->bb > 0 ? h_st->bb : 1.0;
+    inf.rel_res_true = std::sqrt(h_st->rr_true / bb);
+    inf.rel_res_recursive = std::sqrt(h_st->rr / bb);
+    inf.t_rebuild_ms = t_rb.ms();
+    inf.t_iter_ms = t_it.ms();
+    inf.t_recycle_ms = 0.0;
+    inf.model_bytes = model_bytes_per_iter() * m;
+    krs_status rs = KRS_OK;
+    if (h_st->status == ST_MAXIT) rs = KRS_E_MAXIT;
+    else if (h_st->status == ST_BREAKDOWN) rs = KRS_E_NOT_SPD;
+    inf.status = rs;
+    info_last = inf;
+    if (info) *info = inf;
+    if (rs == KRS_E_NOT_SPD) {
+        set_error("breakdown: (w, A w) or (r, z) not positive (operator or preconditioner not SPD)");
+        return rs;
+    }
+    solved = true;
+    if (rs == KRS_E_MAXIT) set_error("maximum number of iterations reached");
+    return rs;
+}
+
+template <typename V, typename W>
+int64_t SeqImpl<V, W>::model_bytes_per_iter() const {
+    // B_A + B_M + 11 n p_w + 2 n p_x + 2 n nc p (see the design notes);
+    // p: matrix / basis storage, p_w: Krylov vectors, p_x = 8
+    const int64_t p = sizeof(V), pw = sizeof(W);
+    const int64_t nnz = nnzb * B * B;
+    const int64_t BA = (B == 1) ? nnz * (p + 4) : nnz * p + 4 * nnzb;
+    const int64_t BM = (B == 1) ? n * p : 3 * n * p;
+    const int64_t vec = 11 * n * pw + 2 * n * 8 - (desc.reuse == KRS_REUSE_SELECTIVE ? 0 : n * pw);
+    return BA + BM + vec + 2 * n * (int64_t)nc * p;
+}
+
+// ------------------------------------------------------------- recycle
+
+template <typename V, typename W>
+krs_status SeqImpl<V, W>::recycle(int32_t* n_added) {
+    if (n_added) *n_added = 0;
+    if (!solved) {
+        set_error("krs_seq_recycle needs a completed solve");
+        return KRS_E_STATE;
+    }
+    solved = false;
+    Timer tm;
+    tm.start(stream);
+    const int m = m_last;
+    int added = 0;
+    last_theta.clear();
+    last_sel.clear();
+    if (desc.reuse == KRS_REUSE_TOTAL && m > 0) {
+        // w_j / sqrt((w_j, A w_j)) for the captured directions (Algorithm 2)
+        const int cnt = std::min(m, trks_slots);
+        if (cnt > 0) {
+            std::vector<double> sc(cnt);
+            for (int j = 0; j < cnt; ++j) sc[j] = 1.0 / std::sqrt(coef_gamma[j]);
+            if (!d_F.reserve(ctx, cnt * sizeof(double))) return KRS_E_OOM;
+            KRS_HIP(hipMemcpyAsync(d_F.p, sc.data(), cnt * sizeof(double), hipMemcpyHostToDevice, stream));
+            launch_scale_columns<V>((V*)d_C.p + (size_t)nc * ldc, ldc, n, (const double*)d_F.p, cnt, stream);
+            KRS_CHECK_LAUNCH();
+            nc += cnt;
+            added = cnt;
+        }
+    } else if (desc.reuse == KRS_REUSE_SELECTIVE && m > 1 &&
+               !(desc.max_basis > 0 && desc.cap_policy == KRS_CAP_FREEZE && nc >= desc.max_basis)) {
+        // (with a full frozen basis nothing could be appended: no extraction)
+        const int hist = h_st->hist_cap;
+        const int mu = std::min(m, hist);  // leading part of the Lanczos run
+        if (mu > 1) {
+            std::vector<double> dd(mu), l2(mu - 1);
+            for (int j = 0; j < mu; ++j) dd[j] = 1.0 / coef_alpha[j];
+            for (int j = 0; j + 1 < mu; ++j) l2[j] = coef_rho[j + 1] / coef_rho[j];
+            std::vector<double> th_m, th_m1;
+            const int nt = host_threads();
+            std::thread other([&]() {
+                std::vector<double> d1(dd.begin(), dd.end() - 1);
+                std::vector<double> l21(l2.begin(), l2.begin() + (mu - 2));
+                ldl_eigenvalues(d1, l21, th_m1, std::max(1, nt / 2));
+            });
+            ldl_eigenvalues(dd, l2, th_m, std::max(1, nt - nt / 2));
+            other.join();
+            std::vector<int> sel = stagnation_select(th_m, th_m1, desc.ritz_eps);
+            last_theta = th_m;
+            last_sel.assign(mu, 0);
+            for (int i : sel) last_sel[i] = 1;
+            last_selected = (int)sel.size();
+            // cap policy
+            if (desc.max_basis > 0 && desc.cap_policy == KRS_CAP_FREEZE) {
+                const int room = std::max(0, desc.max_basis - nc);
+                if ((int)sel.size() > room) {
+                    std::vector<int> order(sel);
+                    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+                        if (th_m[a] != th_m[b]) return th_m[a] < th_m[b];
+                        return a < b;
+                    });
+                    order.resize(room);
+                    std::sort(order.begin(), order.end());
+                    sel = order;
+                }
+            }
+            sel.resize(std::min<size_t>(sel.size(), (size_t)std::max(0, 1024 - nc)));
+            const int s = (int)sel.size();
+            if (s > 0) {
+                // F[j, t] = (-1)^j q_t[j] / (sqrt(rho_j) sqrt|theta_t|)
+                std::vector<double> diag(mu), off(mu - 1);
+                for (int j = 0; j < mu; ++j) diag[j] = dd[j] + (j > 0 ? l2[j - 1] * dd[j - 1] : 0.0);
+                for (int j = 0; j + 1 < mu; ++j) off[j] = std::sqrt(l2[j]) * dd[j];
+                std::vector<double> F((size_t)mu * s);
+                std::vector<double> q;
+                for (int t = 0; t < s; ++t) {
+                    const double th = th_m[sel[t]];
+                    tridiag_eigvec(diag, off, th, q);
+                    const double sc = 1.0 / std::sqrt(std::fabs(th));
+                    for (int j = 0; j < mu; ++j)
+                        F[(size_t)t * mu + j] = ((j & 1) ? -1.0 : 1.0) * q[j] * sc / std::sqrt(coef_rho[j]);
+                }
+                if (!ensure_c_capacity(nc + s)) return KRS_E_OOM;
+                if (!d_F.reserve(ctx, F.size() * sizeof(double))) return KRS_E_OOM;
+                KRS_HIP(hipMemcpyAsync(d_F.p, F.data(), F.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+                launch_basis_combine<V>((const V*)d_Z.p, ldc, mu, (const double*)d_F.p, s, (V*)d_C.p + (size_t)nc * ldc,
+                                        ldc, n, stream);
+                KRS_CHECK_LAUNCH();
+                nc += s;
+                added = s;
+            }
+        }
+    }
+    // restart cap (Algorithm 3, last step)
+    if (desc.max_basis > 0 && desc.cap_policy == KRS_CAP_RESTART && nc >= desc.max_basis) {
+        if (nc0 > 0) {
+            KRS_HIP(hipMemcpyAsync(d_C.p, d_C0.p, (size_t)ldc * nc0 * sizeof(V), hipMemcpyDeviceToDevice, stream));
+        }
+        nc = nc0;
+        restarts += 1;
+    }
+    tm.stop(stream);
+    KRS_HIP(hipStreamSynchronize(stream));
+    info_last.added = added;
+    info_last.selected = last_selected;
+    info_last.t_recycle_ms = tm.ms();
+    if (n_added) *n_added = added;
+    return KRS_OK;
+}
+
+template <typename V, typename W>
+krs_status SeqImpl<V, W>::basis(double* C, int64_t ld, int32_t cap, int32_t* n_c) {
+    if (n_c) *n_c = nc;
+    if (!C) return KRS_OK;
+    if (ld < n || cap < nc) {
+        set_error("output basis too small");
+        return KRS_E_INVALID;
+    }
+    if (!d_tmp.reserve(ctx, (size_t)n * sizeof(double))) return KRS_E_OOM;
+    for (int c = 0; c < nc; ++c) {
+        launch_v2d<V>((const V*)d_C.p + (size_t)c * ldc, (double*)d_tmp.p, n, stream);
+        KRS_HIP(hipMemcpyAsync(C + (size_t)c * ld, d_tmp.p, n * sizeof(double), hipMemcpyDeviceToHost, stream));
+    }
+    KRS_HIP(hipStreamSynchronize(stream));
+    return KRS_OK;
+}
+
+template struct SeqImpl<double, double>;
+template struct SeqImpl<float, double>;
+template struct SeqImpl<float, float>;
+
+}  // namespace krs

@@ -1,0 +1,112 @@
+// Host-side objects behind the opaque handles of include/krs.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "internal.h"
+
+struct krs_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool has_alloc = false;
+    krs_allocator alloc{};
+    int live_seqs = 0;
+    int64_t bytes_live = 0;
+};
+
+namespace krs {
+
+void* dev_alloc(krs_ctx* ctx, size_t bytes);
+void dev_free(krs_ctx* ctx, void* p, size_t bytes);
+
+struct Buf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    bool reserve(krs_ctx* ctx, size_t nbytes);                       // contents not kept
+    bool grow_keep(krs_ctx* ctx, size_t nbytes, hipStream_t stream);  // contents kept
+    void release(krs_ctx* ctx);
+};
+
+struct SeqBase {
+    krs_ctx* ctx = nullptr;
+    krs_seq_desc desc{};
+    virtual ~SeqBase() {}
+    virtual krs_status create(const krs_seq_desc& d, const double* C0, int32_t m0, int64_t ldc0) = 0;
+    virtual krs_status submit(const double* values, const double* b, bool device) = 0;
+    virtual krs_status solve(double* x, bool device_x, krs_solve_info* info) = 0;
+    virtual krs_status recycle(int32_t* n_added) = 0;
+    virtual krs_status basis(double* C, int64_t ld, int32_t cap, int32_t* n_c) = 0;
+    virtual void destroy() = 0;
+    // sampled kernel timing (first iteration of every block)
+    bool timing = false;
+    int64_t kt_count[3] = {0, 0, 0};
+    double kt_ms[3] = {0.0, 0.0, 0.0};
+    // last results (host mirrors)
+    int m_last = 0;
+    int nc = 0;
+    int last_selected = 0;
+    int restarts = 0;
+    std::vector<double> coef_alpha, coef_rho, coef_gamma;
+    std::vector<double> last_theta;
+    std::vector<uint8_t> last_sel;
+    krs_solve_info info_last{};
+};
+
+template <typename V, typename W>
+struct SeqImpl : SeqBase {
+    hipStream_t stream = nullptr;
+    int B = 1;
+    int64_t n = 0, nb = 0, nnzb = 0, nslices = 0, nslots = 0;
+    int64_t ldc = 0;
+    int nc_cap = 0, nc0 = 0;
+    int coef_cap = 0;
+    int trks_slots = 0;
+    bool submitted = false, solved = false;
+    Buf d_col, d_slice_ptr, d_map, d_diag, d_val64, d_valV, d_minv, d_bad, d_in, d_b, d_x, d_r, d_s, d_w, d_q;
+    Buf d_C, d_C0, d_AC64, d_ACv, d_G, d_Ginv, d_mu, d_Z, d_coef, d_partials, d_st, d_F, d_tmp, d_Ctmp;
+    DevState* h_st = nullptr;
+    hipEvent_t tev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // captured iteration blocks (16 and 64 iterations + refinement step)
+    struct GraphSlot {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        SysView<V, W> view{};
+        int block = 0;
+    } gslot[2];
+    krs_status graph_launch(const SysView<V, W>& v, int slot, int block);
+    void graph_release();
+    bool tev_pending = false;
+    void collect_timing();
+
+    krs_status create(const krs_seq_desc& d, const double* C0, int32_t m0, int64_t ldc0) override;
+    krs_status submit(const double* values, const double* b, bool device) override;
+    krs_status solve(double* x, bool device_x, krs_solve_info* info) override;
+    krs_status recycle(int32_t* n_added) override;
+    krs_status basis(double* C, int64_t ld, int32_t cap, int32_t* n_c) override;
+    void destroy() override;
+
+    SysView<V, W> view();
+    bool ensure_c_capacity(int cols);
+    bool ensure_partials(int64_t extra);
+    krs_status rebuild(int* dropped);
+    krs_status coarse_pass(std::vector<double>& G);
+    void k_spmv(const SysView<V, W>& v);
+    void k_update(const SysView<V, W>& v, int mode);
+    void k_resid(const SysView<V, W>& v, int final_only);
+    void enqueue_iterations(const SysView<V, W>& v, int k);
+    void enqueue_refine(const SysView<V, W>& v);
+    int64_t model_bytes_per_iter() const;
+};
+
+}  // namespace krs
+
+struct krs_seq {
+    std::unique_ptr<krs::SeqBase> impl;
+};
