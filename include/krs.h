@@ -103,7 +103,7 @@ typedef struct {
     int32_t max_basis;     /* n_c_lim; 0 = unlimited */
     int32_t refine_every;  /* mixed: force a true-residual refinement at least every k iterations (0 = off) */
     int32_t history_cap;   /* Krylov vectors kept for SRKS (0 = max_iter); longer runs use the leading part */
-    double rank_tol;       /* rank guard: drop a basis column whose Cholesky pivot <= rank_tol * max diag (0 = 1e-12) */
+    double rank_tol;       /* rank guard: drop a basis column whose Cholesky pivot <= rank_tol * max diag (0 = 1e-6) */
     double refine_drop;    /* mixed: refine when ||r|| fell by this factor since the last refinement (0 = 0.1) */
     int32_t exec_mode;     /* 0: iteration blocks replayed as captured HIP graphs; 1: eager kernel launches */
 } krs_seq_desc;

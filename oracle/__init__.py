@@ -78,7 +78,7 @@ def spmv(row_ptr, col_idx, values, x):
     return y
 
 
-def apcg(row_ptr, col_idx, values, b, precond="jacobi", C=None, tol=1e-8, max_iter=None, guard=1e-12,
+def apcg(row_ptr, col_idx, values, b, precond="jacobi", C=None, tol=1e-8, max_iter=None, guard=1e-6,
          record_z=False, record_w=False):
     """One APCG(A, M, C, b) solve (Algorithm 1, standard form; see oracle.c).
 
@@ -121,7 +121,7 @@ def apcg(row_ptr, col_idx, values, b, precond="jacobi", C=None, tol=1e-8, max_it
     return out
 
 
-def apcg_alg1(row_ptr, col_idx, values, b, iters, precond="jacobi", C=None, guard=1e-12):
+def apcg_alg1(row_ptr, col_idx, values, b, iters, precond="jacobi", C=None, guard=1e-6):
     """Algorithm 1 in its printed Gram-Schmidt form; returns (x, alpha, bgs)."""
     rp, ci, v = _csr(row_ptr, col_idx, values)
     b = np.ascontiguousarray(b, dtype=np.float64)
@@ -264,7 +264,7 @@ def freeze_pick(idx, th_m, room):
 
 
 def solve_sequence(seq, n_systems=None, reuse="srks", precond=None, tol=1e-8, eps=1e-14, cap=0,
-                   cap_policy="freeze", C0=None, max_iter=None, guard=1e-12, keep_x=False):
+                   cap_policy="freeze", C0=None, max_iter=None, guard=1e-6, keep_x=False):
     """Run TRKS / SRKS / plain PCG over systems 0..n_systems-1 of ``seq``.
 
     ``reuse``: 'none' (PCG), 'trks' (Algorithm 2) or 'srks' (Algorithm 3).

@@ -137,7 +137,10 @@ static void prec_free(orc_prec* P) { free(P->f); P->f = NULL; }
  * factor is computed column by column; a column whose pivot falls to
  * guard * max_i G_ii or below is declared dependent and dropped (the paper
  * leaves the full-rank check open, Section 2.3; this rule is the reading
- * adopted here).  Only the kept columns take part in the projector.
+ * adopted here, with guard = 1e-6 by default: the kept coarse matrix then
+ * has a condition number of at most about 1e6, so the double-precision
+ * projector stays accurate well below a 1e-8 tolerance).  Only the kept
+ * columns take part in the projector.
  */
 typedef struct {
     int nc, nk;

@@ -172,7 +172,7 @@ def ritz_select(alpha, rho, eps):
     return th[:m], th1[: max(m - 1, 0)], sel[:m].astype(bool)
 
 
-def coarse_factor(G, rank_tol=1e-12):
+def coarse_factor(G, rank_tol=1e-6):
     """Library's guarded Cholesky + inverse of a coarse matrix (no device used)."""
     G = np.asfortranarray(G, dtype=np.float64)
     nc = G.shape[0]

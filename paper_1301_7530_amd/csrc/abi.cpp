@@ -342,7 +342,7 @@ krs_status krs_coarse_factor(int32_t nc, const double* G, double rank_tol, doubl
         set_error("G, Ginv and kept are required");
         return KRS_E_INVALID;
     }
-    const int k = krs::coarse_factor(nc, G, rank_tol > 0 ? rank_tol : 1e-12, Ginv, kept);
+    const int k = krs::coarse_factor(nc, G, rank_tol > 0 ? rank_tol : 1e-6, Ginv, kept);
     if (nk) *nk = k;
     return (nc > 0 && k == 0) ? KRS_E_COARSE_SINGULAR : KRS_OK;
     KRS_GUARD_END

@@ -141,6 +141,9 @@ int64_t dot_grid(int64_t n);
 // descending, high relative accuracy (ritz.cpp).
 void ldl_eigenvalues(const std::vector<double>& d, const std::vector<double>& l2, std::vector<double>& theta,
                      int threads);
+// Ascending eigenvalues k0..k1-1 (0 = smallest) of L D L^T into asc[k].
+void ldl_eigenvalues_range(const std::vector<double>& d, const std::vector<double>& l2, int k0, int k1,
+                           double* asc, int threads);
 // Eigenvector (unit 2-norm) of the explicit tridiagonal (diag, off) for eigenvalue theta.
 void tridiag_eigvec(const std::vector<double>& diag, const std::vector<double>& off, double theta,
                     std::vector<double>& v);

@@ -48,15 +48,12 @@ void bisect_range(int m, const double* d, const double* l2d, double lo, double h
 
 }  // namespace
 
-void ldl_eigenvalues(const std::vector<double>& d, const std::vector<double>& l2, std::vector<double>& theta,
-                     int threads) {
+// Gershgorin interval of the explicit tridiagonal of L D L^T.
+static void ldl_bounds(const std::vector<double>& d, const std::vector<double>& l2, const std::vector<double>& l2d,
+                       double& lo, double& hi) {
     const int m = (int)d.size();
-    theta.assign(m, 0.0);
-    if (m == 0) return;
-    std::vector<double> l2d(m, 0.0);
-    for (int i = 0; i + 1 < m; ++i) l2d[i] = l2[i] * d[i];
-    // Gershgorin bounds of the explicit tridiagonal
-    double lo = 0.0, hi = 0.0;
+    lo = 0.0;
+    hi = 0.0;
     for (int i = 0; i < m; ++i) {
         const double diag = d[i] + (i > 0 ? l2d[i - 1] : 0.0);
         double off = 0.0;
@@ -67,18 +64,38 @@ void ldl_eigenvalues(const std::vector<double>& d, const std::vector<double>& l2
     }
     lo = std::min(lo, 0.0);
     hi = hi * (1.0 + 4.0 * DBL_EPSILON) + DBL_MIN;
-    std::vector<double> asc(m);
-    int nt = std::max(1, std::min(threads, m / 32 + 1));
+}
+
+void ldl_eigenvalues_range(const std::vector<double>& d, const std::vector<double>& l2, int k0, int k1,
+                           double* asc, int threads) {
+    const int m = (int)d.size();
+    if (k1 > m) k1 = m;
+    if (k0 >= k1) return;
+    std::vector<double> l2d(m, 0.0);
+    for (int i = 0; i + 1 < m; ++i) l2d[i] = l2[i] * d[i];
+    double lo, hi;
+    ldl_bounds(d, l2, l2d, lo, hi);
+    const int cnt = k1 - k0;
+    const int nt = std::max(1, std::min(threads, cnt / 4 + 1));
     if (nt == 1) {
-        bisect_range(m, d.data(), l2d.data(), lo, hi, 0, m, asc.data());
-    } else {
-        std::vector<std::thread> pool;
-        for (int t = 0; t < nt; ++t) {
-            const int k0 = (int)((int64_t)m * t / nt), k1 = (int)((int64_t)m * (t + 1) / nt);
-            pool.emplace_back(bisect_range, m, d.data(), l2d.data(), lo, hi, k0, k1, asc.data());
-        }
-        for (auto& th : pool) th.join();
+        bisect_range(m, d.data(), l2d.data(), lo, hi, k0, k1, asc);
+        return;
     }
+    std::vector<std::thread> pool;
+    for (int t = 0; t < nt; ++t) {
+        const int a = k0 + (int)((int64_t)cnt * t / nt), b = k0 + (int)((int64_t)cnt * (t + 1) / nt);
+        pool.emplace_back(bisect_range, m, d.data(), l2d.data(), lo, hi, a, b, asc);
+    }
+    for (auto& th : pool) th.join();
+}
+
+void ldl_eigenvalues(const std::vector<double>& d, const std::vector<double>& l2, std::vector<double>& theta,
+                     int threads) {
+    const int m = (int)d.size();
+    theta.assign(m, 0.0);
+    if (m == 0) return;
+    std::vector<double> asc(m);
+    ldl_eigenvalues_range(d, l2, 0, m, asc.data(), threads);
     for (int k = 0; k < m; ++k) theta[m - 1 - k] = asc[k];
 }
 

@@ -128,7 +128,7 @@ krs_status SeqImpl<V, W>::create(const krs_seq_desc& d, const double* C0, int32_
     nb = n / B;
     nnzb = d.nnzb;
     stream = ctx->stream;
-    if (desc.rank_tol <= 0.0) desc.rank_tol = 1e-12;
+    if (desc.rank_tol <= 0.0) desc.rank_tol = 1e-6;
     if (desc.refine_drop <= 0.0) desc.refine_drop = 0.1;
     if (desc.ritz_eps <= 0.0) desc.ritz_eps = 1e-14;
     const int64_t* rp = d.row_ptr;
@@ -764,33 +764,77 @@ krs_status SeqImpl<V, W>::recycle(int32_t* n_added) {
             std::vector<double> dd(mu), l2(mu - 1);
             for (int j = 0; j < mu; ++j) dd[j] = 1.0 / coef_alpha[j];
             for (int j = 0; j + 1 < mu; ++j) l2[j] = coef_rho[j + 1] / coef_rho[j];
-            std::vector<double> th_m, th_m1;
+            std::vector<double> d1(dd.begin(), dd.end() - 1);
+            std::vector<double> l21(l2.begin(), l2.begin() + (mu - 2));
             const int nt = host_threads();
-            std::thread other([&]() {
-                std::vector<double> d1(dd.begin(), dd.end() - 1);
-                std::vector<double> l21(l2.begin(), l2.begin() + (mu - 2));
-                ldl_eigenvalues(d1, l21, th_m1, std::max(1, nt / 2));
-            });
-            ldl_eigenvalues(dd, l2, th_m, std::max(1, nt - nt / 2));
-            other.join();
-            std::vector<int> sel = stagnation_select(th_m, th_m1, desc.ritz_eps);
-            last_theta = th_m;
-            last_sel.assign(mu, 0);
-            for (int i : sel) last_sel[i] = 1;
-            last_selected = (int)sel.size();
-            // cap policy
-            if (desc.max_basis > 0 && desc.cap_policy == KRS_CAP_FREEZE) {
+            const bool frozen = desc.max_basis > 0 && desc.cap_policy == KRS_CAP_FREEZE;
+            std::vector<double> th_m(mu, 0.0);  // descending (Algorithm 3 order)
+            std::vector<int> sel;               // descending indices, ascending order
+            if (!frozen) {
+                std::vector<double> th_m1;
+                ldl_eigenvalues(dd, l2, th_m, nt);
+                ldl_eigenvalues(d1, l21, th_m1, nt);
+                sel = stagnation_select(th_m, th_m1, desc.ritz_eps);
+                last_theta = th_m;
+                last_sel.assign(mu, 0);
+                for (int i : sel) last_sel[i] = 1;
+                last_selected = (int)sel.size();
+            } else {
+                // Smallest Ritz values first (the order in which a frozen
+                // basis is filled): a_k, b_k are the k-th smallest
+                // eigenvalues of H_m, H_{m-1}; a_k passed the stagnation test
+                // iff it is within eps of one of its interlacing neighbours
+                // b_{k-1} <= a_k <= b_k.  Stop once the room is filled (and
+                // any exact ties of the last value are seen).
                 const int room = std::max(0, desc.max_basis - nc);
-                if ((int)sel.size() > room) {
-                    std::vector<int> order(sel);
-                    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-                        if (th_m[a] != th_m[b]) return th_m[a] < th_m[b];
-                        return a < b;
-                    });
-                    order.resize(room);
-                    std::sort(order.begin(), order.end());
-                    sel = order;
+                std::vector<double> a(mu), bv(mu);
+                std::vector<int> sel_asc;
+                bool have_cut = false, stop = false;
+                double cut = 0.0;
+                int k = 0, done = 0;
+                const int CH = 128;
+                while (k < mu && !stop) {
+                    const int k1 = std::min(mu, k + CH);
+                    ldl_eigenvalues_range(dd, l2, k, k1, a.data(), nt);
+                    ldl_eigenvalues_range(d1, l21, k, std::min(k1, mu - 1), bv.data(), nt);
+                    for (int kk = k; kk < k1; ++kk) {
+                        if (have_cut && a[kk] > cut) {
+                            stop = true;
+                            break;
+                        }
+                        const double e = desc.ritz_eps * std::fabs(a[kk]);
+                        const bool s1 = kk >= 1 && std::fabs(a[kk] - bv[kk - 1]) <= e;
+                        const bool s2 = kk <= mu - 2 && std::fabs(a[kk] - bv[kk]) <= e;
+                        if (s1 || s2) {
+                            sel_asc.push_back(kk);
+                            if (!have_cut && (int)sel_asc.size() >= room) {
+                                have_cut = true;
+                                cut = a[kk];
+                            }
+                        }
+                        done = kk + 1;
+                    }
+                    k = k1;
                 }
+                // same order as the full rule: theta ascending, then the
+                // descending index ascending
+                std::vector<int> cand;
+                for (int kk : sel_asc) cand.push_back(mu - 1 - kk);
+                std::stable_sort(cand.begin(), cand.end(), [&](int i, int j) {
+                    const double ti = a[mu - 1 - i], tj = a[mu - 1 - j];
+                    if (ti != tj) return ti < tj;
+                    return i < j;
+                });
+                if ((int)cand.size() > room) cand.resize(room);
+                std::sort(cand.begin(), cand.end());
+                sel = cand;
+                last_selected = (int)sel_asc.size();
+                // report the computed part, descending
+                last_theta.assign(done, 0.0);
+                last_sel.assign(done, 0);
+                for (int kk = 0; kk < done; ++kk) last_theta[done - 1 - kk] = a[kk];
+                for (int kk : sel_asc) last_sel[done - 1 - kk] = 1;
+                for (int kk = 0; kk < done; ++kk) th_m[mu - 1 - kk] = a[kk];
             }
             sel.resize(std::min<size_t>(sel.size(), (size_t)std::max(0, 1024 - nc)));
             const int s = (int)sel.size();

@@ -105,14 +105,28 @@ def test_srks_elasticity_sequence_fp64(gpu):
             ref = O.apcg(rp, ci, v, b, "block3", C=C_in, tol=1e-8, max_iter=4000, record_z=True)
             assert info["status"] == 0
             assert _relres(seq.csr(k), x) <= 1e-8
-            assert abs(info["iters"] - ref["m"]) <= 2, (k, info["iters"], ref["m"])
+            # The augmented iteration count is not unique in finite precision:
+            # the oracle itself varies under an equivalent basis C Q (Q
+            # orthogonal, same span).  Require +-2 around that range.
+            ms = [ref["m"]]
+            if C_in.shape[1] > 1:
+                rng = np.random.default_rng(k)
+                for _ in range(3):
+                    Q, _r = np.linalg.qr(rng.standard_normal((C_in.shape[1], C_in.shape[1])))
+                    ms.append(O.apcg(rp, ci, v, b, "block3", C=C_in @ Q, tol=1e-8, max_iter=4000)["m"])
+            assert min(ms) - 2 <= info["iters"] <= max(ms) + 2, (k, info["iters"], ms)
             assert info["n_c"] == int(ref["kept"].sum()) if C_in.shape[1] else info["n_c"] == 0
             added = s.recycle()
             th_gpu, sel_gpu = s.ritz()
             if len(th_gpu):  # no extraction once a frozen basis is full
+                # with a frozen cap only the smallest Ritz values needed to
+                # fill it are computed: compare that (descending) tail
                 th_o, th_o1 = O.ritz_values(alpha, rho)
-                assert np.array_equal(th_gpu, th_o)
-                assert list(np.nonzero(sel_gpu)[0]) == O.srks_select(th_o, th_o1, eps)
+                L = len(th_gpu)
+                assert np.array_equal(th_gpu, th_o[len(th_o) - L:])
+                sel_o = np.zeros(len(th_o), dtype=bool)
+                sel_o[O.srks_select(th_o, th_o1, eps)] = True
+                assert np.array_equal(sel_gpu, sel_o[len(th_o) - L:])
             if added:
                 C_out = s.basis()
                 new_gpu = C_out[:, C_out.shape[1] - added:]
