@@ -55,7 +55,8 @@ def run_phase(K, ctx, seq, dev_sys, reuse, args, wl, order, timing=False):
     import torch
 
     s = K.sequence_for(ctx, seq, precision=args.precision, reuse=reuse, tol=1e-8, max_iter=args.max_iter,
-                       ritz_eps=args.eps if args.eps else wl["eps"], max_basis=wl["max_basis"], cap_policy="freeze")
+                       ritz_eps=args.eps if args.eps else wl["eps"], max_basis=wl["max_basis"], cap_policy="freeze",
+                       refine_drop=args.refine_drop)
     x = torch.empty(seq.n, dtype=torch.float64, device="cuda")
     infos = []
     lat = []
@@ -140,6 +141,7 @@ def main():
     ap.add_argument("--no-plain", dest="plain", action="store_false")
     ap.add_argument("--cpu-iters", type=int, default=100)
     ap.add_argument("--eps", type=float, default=0.0, help="SRKS stagnation tolerance (default: per workload)")
+    ap.add_argument("--refine-drop", type=float, default=0.0, help="mixed: refinement trigger (0 = library default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "

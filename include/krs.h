@@ -104,7 +104,9 @@ typedef struct {
     int32_t refine_every;  /* mixed: force a true-residual refinement at least every k iterations (0 = off) */
     int32_t history_cap;   /* Krylov vectors kept for SRKS (0 = max_iter); longer runs use the leading part */
     double rank_tol;       /* rank guard: drop a basis column whose Cholesky pivot <= rank_tol * max diag (0 = 1e-6) */
-    double refine_drop;    /* mixed: refine when ||r|| fell by this factor since the last refinement (0 = 0.1) */
+    double refine_drop;    /* mixed: refine when ||r|| fell by this factor since the last refinement
+                              (0 = 0.1; negative: only when the recursion has converged).  A
+                              replacement that more than doubles ||r|| restarts the direction. */
     int32_t exec_mode;     /* 0: iteration blocks replayed as captured HIP graphs; 1: eager kernel launches */
 } krs_seq_desc;
 
@@ -168,13 +170,13 @@ krs_status krs_seq_coeffs(krs_seq* s, double* alpha, double* rho, double* gamma,
  * doubles; C may be NULL to query n_c only. */
 krs_status krs_seq_basis(krs_seq* s, double* C, int64_t ldc, int32_t cap, int32_t* n_c);
 krs_status krs_seq_info(krs_seq* s, krs_solve_info* info);
-/* Sampled kernel timing.  When enabled, the first iteration of every
- * iteration block has its three launches (0: SpMV + (w, A w), 1: update /
- * preconditioner / projector reduction, 2: coarse correction / direction)
- * bracketed by HIP events on the sequence's stream; only samples taken
- * while the solve was still iterating are kept.  Enabling resets the
- * counters.  krs_seq_kernel_time returns the number of sampled launches of
- * `kernel` and their total duration in milliseconds. */
+/* Live kernel timing.  When enabled, every 32nd iteration the SpMV + (w, A w)
+ * kernel (0), the update / preconditioner / projector-reduction kernel (1)
+ * and the coarse-correction / direction kernel (2) record the span from
+ * their first workgroup's start to their last workgroup's end with the
+ * device wall clock, during the normal (graph-replayed) iterations.
+ * Enabling resets the sums.  krs_seq_kernel_time returns the number of
+ * sampled launches of `kernel` and their total duration in milliseconds. */
 krs_status krs_seq_set_timing(krs_seq* s, int32_t enable);
 krs_status krs_seq_kernel_time(krs_seq* s, int32_t kernel, int64_t* launches, double* total_ms);
 krs_status krs_seq_destroy(krs_seq* s);

@@ -52,6 +52,14 @@ struct DevState {
     int32_t refinements;
     int32_t nc;       // basis columns active in this solve
     int32_t pending_dir;  // 1 between a residual replacement and its direction update
+    int32_t first_restart;  // iteration of the first direction restart (Lanczos run ends there)
+    int32_t restarts;
+    // live kernel timing (device wall clock): summed spans of sampled
+    // launches of the SpMV, update and direction kernels
+    int32_t ktime_on;
+    int32_t ktime_pad;
+    unsigned long long ksum[3];
+    unsigned long long kcnt[3];
 };
 
 // Per-launch view of one system, passed by value to the kernels.  V is the
@@ -81,7 +89,9 @@ struct SysView {
     int64_t ldc;
     int64_t ldac;
     const double* Ginv;  // nc x nc column-major
-    double* mu;          // nc
+    double* mu;          // nc: G^-1 (AC)^T s of the current step
+    double* u;           // nc: C^T r, tracked by recurrence (zero in exact arithmetic)
+    double* mu2;         // nc: mu + beta G^-1 (AC)^T w_old, for the projected direction
     // histories
     V* zhist;        // z_j at column j (SRKS), or null
     V* whist;        // w_j at column j (TRKS: columns of C past nc), or null
@@ -94,6 +104,7 @@ struct SysView {
     double* part1;     // per-workgroup (w, A w) partials of the SpMV
     double* partials;  // per-workgroup partials of the other reductions
     DevState* st;
+    unsigned long long* kslots;  // per-workgroup start / end stamps of timed launches
 };
 
 // ------------------------------------------------------------ launchers
@@ -135,6 +146,7 @@ template <typename V> void launch_v2d(const V* in, double* out, int64_t n, hipSt
 int64_t update_grid(int64_t n, int block);
 int64_t spmv_grid(int64_t nslices, int block);
 int64_t dot_grid(int64_t n);
+int64_t correct_grid(int64_t n);
 
 // ----------------------------------------------------------- host logic
 // Tridiagonal eigenvalues of H = L D L^T (d_j = 1/alpha_j, l_j^2 = beta_{j+1}),

@@ -64,14 +64,21 @@ __device__ void reduce_partials(const double* partials, int64_t np, int nv, int 
         const int p = threadIdx.x % tpv;
         double acc = 0.0;
         if (k < nv && threadIdx.x / tpv < T / tpv) {
+            // up to 32 independent loads in flight per thread
             int64_t i = p;
-            for (; i + 4 * tpv <= np; i += 4 * tpv) {
-                const double a0 = partials[i * stride + k], a1 = partials[(i + tpv) * stride + k];
-                const double a2 = partials[(i + 2 * tpv) * stride + k], a3 = partials[(i + 3 * tpv) * stride + k];
-                acc += a0;
-                acc += a1;
-                acc += a2;
-                acc += a3;
+            for (; i + 32 * tpv <= np; i += 32 * tpv) {
+                double t[32];
+#pragma unroll
+                for (int u = 0; u < 32; ++u) t[u] = partials[(i + u * tpv) * stride + k];
+#pragma unroll
+                for (int u = 0; u < 32; ++u) acc += t[u];
+            }
+            for (; i + 8 * tpv <= np; i += 8 * tpv) {
+                double t[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) t[u] = partials[(i + u * tpv) * stride + k];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) acc += t[u];
             }
             for (; i < np; i += tpv) acc += partials[i * stride + k];
         }
@@ -129,6 +136,64 @@ __device__ void ginv_matvec(const double* __restrict__ Ginv, int nc, const doubl
         }
         __syncthreads();
     }
+}
+
+// Live kernel timing: iteration j is sampled when j % 32 == 1 (K1, K3) and
+// its direction update (K5, which already sees j + 1) likewise.  Every
+// workgroup of a sampled launch stores its start and end wall-clock stamps
+// in its own slot (plain stores, no contention); the finalize kernel adds
+// max(end) - min(start) to the running sums.
+constexpr int kSlotStride = 2 * 4096;
+__device__ __forceinline__ bool ktime_sample(const DevState* st, int which) {
+    return st->ktime_on && (st->iter & 31) == (which == 2 ? 2 : 1);
+}
+__device__ __forceinline__ void ktime_begin(unsigned long long* slots, int which, bool on) {
+    if (on && threadIdx.x == 0) slots[which * kSlotStride + 2 * blockIdx.x] = (unsigned long long)wall_clock64();
+}
+__device__ __forceinline__ void ktime_end(unsigned long long* slots, int which, bool on) {
+    if (on) {
+        __syncthreads();
+        if (threadIdx.x == 0) slots[which * kSlotStride + 2 * blockIdx.x + 1] = (unsigned long long)wall_clock64();
+    }
+}
+// All threads: span of kernel `which` over np workgroup slots, added to
+// the sums by thread 0.  lds: 2 * blockDim.x entries.
+__device__ void ktime_collect(DevState* st, const unsigned long long* slots, int which, int64_t np,
+                              unsigned long long* lds) {
+    unsigned long long lo = ~0ull, hi = 0ull;
+    for (int64_t i = threadIdx.x; i < np; i += blockDim.x) {
+        const unsigned long long s0 = slots[which * kSlotStride + 2 * i], s1 = slots[which * kSlotStride + 2 * i + 1];
+        lo = s0 < lo ? s0 : lo;
+        hi = s1 > hi ? s1 : hi;
+    }
+    lds[threadIdx.x] = lo;
+    lds[blockDim.x + threadIdx.x] = hi;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int t = 1; t < (int)blockDim.x; ++t) {
+            lo = lds[t] < lo ? lds[t] : lo;
+            hi = lds[blockDim.x + t] > hi ? lds[blockDim.x + t] : hi;
+        }
+        if (hi > lo) {
+            st->ksum[which] += hi - lo;
+            st->kcnt[which] += 1;
+        }
+    }
+    __syncthreads();
+}
+
+// Fixed-order sum of one value per thread, returned to every thread.
+__device__ double sum_all_reg(double a, double* lds) {
+    a = wave_sum(a);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) lds[wave] = a;
+    __syncthreads();
+    double t = 0.0;
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int i = 0; i < nw; ++i) t += lds[i];
+    __syncthreads();
+    return t;
 }
 
 __device__ __forceinline__ bool gate(const DevState* st, uint32_t mask) {
@@ -213,6 +278,8 @@ __device__ __forceinline__ X ell_row3(const V* __restrict__ val, const int32_t* 
 template <typename V, typename W, int B>
 __global__ __launch_bounds__(256) void k_spmv_dot(SysView<V, W> v) {
     if (!gate(v.st, M_RUN)) return;
+    const bool tm = ktime_sample(v.st, 0);
+    ktime_begin(v.kslots, 0, tm);
     __shared__ double lds[8];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double part = 0.0;
@@ -242,47 +309,62 @@ __global__ __launch_bounds__(256) void k_spmv_dot(SysView<V, W> v) {
     }
     const double bs = block_sum(part, lds);
     if (threadIdx.x == 0) v.part1[blockIdx.x] = bs;
+    ktime_end(v.kslots, 0, tm);
 }
 
 // ------------------------------------------------------------------ K3
 // mode 0: x += alpha w, r -= alpha q (the regular step)
 // mode 1: initial step (r0 given), no update
 // mode 2: after a true-residual replacement, no update
-// then s = M^-1 r and per-workgroup partials [||r||^2, (r, s), (AC)^T s]
-// in partials[blockIdx.x * (nc + 2) + ...].  Tiles of TR rows (block
-// aligned); the projector part reads the tile's rows of AC (row-major)
-// with one lane per column (CW lanes, RW rows per wave step).
+// then s = M^-1 r and per-workgroup partials, stride 2 nc + 2:
+//   [ ||r||^2, (r, s), t = (AC)^T s (nc), v = (AC)^T w (nc, modes 0 and 2) ]
+// v measures the A-component of w along C, which is zero in exact
+// arithmetic; it drives the recurrence for u = C^T r used to form
+// rho = (r, z) = (r, s) - (C^T r)^T mu exactly.  Tiles of TR rows (block
+// aligned); the projector part reads the tile's rows of AC (row-major) once
+// with one lane per column (CW lanes, RW rows per wave step) and
+// accumulates both sums per column in LDS.
 template <typename V, typename W, int B>
 __global__ __launch_bounds__(1024) void k_update_reduce(SysView<V, W> v, int mode, int np1) {
     DevState* st = v.st;
     const uint32_t mask = (mode == 2) ? M_REFINE : M_RUN;
     if (!gate(st, mask)) return;
+    const bool tm = mode == 0 && ktime_sample(st, 1);
+    ktime_begin(v.kslots, 1, tm);
     constexpr int TR = (B == 1) ? 1024 : 768;  // rows per tile == threads
     __shared__ double ss[TR];
+    __shared__ double ws[TR];
     __shared__ double red[1024];
+    __shared__ double red2[1024];
+    __shared__ double tacc[1024];
+    __shared__ double vacc[1024];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     constexpr int nwaves = TR / 64;
     const int nc = st->nc;
     double a = 0.0;
     if (mode == 0) a = st->rho / sum_all(v.part1, np1, red);
+    for (int c = tid; c < nc; c += TR) {
+        tacc[c] = 0.0;
+        vacc[c] = 0.0;
+    }
     // projector reduction geometry
     int CW = 64;
     if (nc <= 32) CW = nc <= 1 ? 1 : (nc <= 2 ? 2 : (nc <= 4 ? 4 : (nc <= 8 ? 8 : (nc <= 16 ? 16 : 32))));
     const int RW = 64 / CW;
     const int nch = (nc + 63) / 64;
     const int c0 = lane % CW, rsub = lane / CW;
-    double acc[kMaxChunks];
-#pragma unroll
-    for (int i = 0; i < kMaxChunks; ++i) acc[i] = 0.0;
+    const int G = nwaves * RW;
+    const int g0 = wave * RW + rsub;
     double rr = 0.0, rs = 0.0;
     const int64_t ntiles = (v.n + TR - 1) / TR;
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t i = tile * TR + tid;
-        double ri = 0.0;
+        double ri = 0.0, wi = 0.0;
         if (i < v.n) {
             W rv = v.r[i];
+            if (mode != 1) wi = (double)v.w[i];
             if (mode == 0) {
-                v.x[i] += a * (double)v.w[i];
+                v.x[i] += a * wi;
                 rv = (W)((double)rv - a * (double)v.q[i]);
                 v.r[i] = rv;
             }
@@ -311,39 +393,52 @@ __global__ __launch_bounds__(1024) void k_update_reduce(SysView<V, W> v, int mod
         if (nc > 0) {
             __syncthreads();
             ss[tid] = (i < v.n) ? si : 0.0;
+            ws[tid] = (i < v.n) ? wi : 0.0;
             __syncthreads();
             const int rows = (int)((v.n - tile * TR) < TR ? (v.n - tile * TR) : TR);
             const V* ACt = v.AC + tile * TR * v.ldac;
-            const int G = nwaves * RW;
-            const int g0 = wave * RW + rsub;
             constexpr int UR = 8;
-#pragma unroll
-            for (int ch = 0; ch < kMaxChunks; ++ch) {
+            for (int ch = 0; ch < nch; ++ch) {
                 const int c = ch * 64 + c0;
-                if (ch < nch && c < nc) {
-                    double a2 = 0.0;
+                double a2 = 0.0, b2 = 0.0;
+                if (c < nc) {
                     for (int r = g0; r < rows; r += G * UR) {
                         // rows past the tile end are clamped (weight 0) so
                         // every load of the group is issued unconditionally
                         V av[UR];
 #pragma unroll
                         for (int u = 0; u < UR; ++u) {
-                            const int rr = min(r + u * G, rows - 1);
-                            av[u] = ACt[(int64_t)rr * v.ldac + c];
+                            const int r2 = min(r + u * G, rows - 1);
+                            av[u] = ACt[(int64_t)r2 * v.ldac + c];
                         }
 #pragma unroll
                         for (int u = 0; u < UR; ++u) {
-                            const int rr = r + u * G;
-                            a2 += (double)av[u] * (rr < rows ? ss[rr] : 0.0);
+                            const int r2 = r + u * G;
+                            const bool ok = r2 < rows;
+                            a2 += (double)av[u] * (ok ? ss[r2] : 0.0);
+                            b2 += (double)av[u] * (ok ? ws[r2] : 0.0);
                         }
                     }
-                    acc[ch] += a2;
+                }
+                // combine the G row groups of this chunk (fixed order)
+                __syncthreads();
+                red[g0 * CW + c0] = a2;
+                red2[g0 * CW + c0] = b2;
+                __syncthreads();
+                if (tid < CW && ch * 64 + tid < nc) {
+                    double t = 0.0, u2 = 0.0;
+                    for (int gg = 0; gg < G; ++gg) {
+                        t += red[gg * CW + tid];
+                        u2 += red2[gg * CW + tid];
+                    }
+                    tacc[ch * 64 + tid] += t;
+                    vacc[ch * 64 + tid] += u2;
                 }
             }
         }
     }
-    // workgroup partials: [rr, rs, t_0 .. t_{nc-1}]
-    const int stride = nc + 2;
+    // workgroup partials
+    const int stride = 2 * nc + 2;
     double* myp = v.partials + (int64_t)blockIdx.x * stride;
     {
         const double brr = block_sum(rr, red);
@@ -351,50 +446,107 @@ __global__ __launch_bounds__(1024) void k_update_reduce(SysView<V, W> v, int mod
         const double brs = block_sum(rs, red);
         if (tid == 0) myp[1] = brs;
     }
-    if (nc > 0) {
-        // combine the row groups: group g = wave*RW + rsub holds columns
-        // c0 (+ 64*ch); G*CW == nwaves*64 <= 1024 doubles of LDS per chunk
-        const int G = nwaves * RW;
-        const int g = wave * RW + rsub;
-        for (int ch = 0; ch < nch; ++ch) {
-            __syncthreads();
-            red[g * CW + c0] = acc[ch];
-            __syncthreads();
-            const int c = ch * 64 + tid;
-            if (tid < CW && c < nc) {
-                double t = 0.0;
-                for (int gg = 0; gg < G; ++gg) t += red[gg * CW + tid];
-                myp[2 + c] = t;
-            }
-        }
+    __syncthreads();
+    for (int c = tid; c < nc; c += TR) {
+        myp[2 + c] = tacc[c];
+        myp[2 + nc + c] = vacc[c];
     }
+    ktime_end(v.kslots, 1, tm);
 }
 
 // F3: one workgroup.  Reduces the partials of K1 (mode 0) and K3, records
 // alpha_j, gamma_j, rho_{j+1}, decides convergence / refinement / breakdown
-// and forms beta and mu = G^-1 t for the direction update.
+// and forms beta, mu = G^-1 t, mu2 and u = C^T r for the direction update.
+// Being a single workgroup it is latency bound: every independent load
+// (K3 partials, K1 partials, G^-1, state) is issued before the first wait.
 template <typename V, typename W>
-__global__ __launch_bounds__(1024) void k_finalize_update(SysView<V, W> v, int mode, int np1, int np3) {
+__global__ __launch_bounds__(1024) void k_finalize_update(SysView<V, W> v, int mode, int np1, int np3, int np5) {
     DevState* st = v.st;
     const uint32_t mask = (mode == 2) ? M_REFINE : M_RUN;
     if (!gate(st, mask)) return;
     __shared__ double red[1024];
-    __shared__ double fin[1024 + 4];
-    __shared__ int next;
+    __shared__ double fin[2048 + 4];
+    __shared__ double muL[1024];
+    __shared__ double gvL[1024];
+    __shared__ double Gl[4096];
+    __shared__ double beta_s;
     const int tid = threadIdx.x;
+    const int T = blockDim.x;
     const int nc = st->nc;
-    const int stride = nc + 2;
-    double g = 0.0;
-    if (mode == 0) g = sum_all(v.part1, np1, red);
-    reduce_partials(v.partials, np3, stride, stride, fin, red);
-    __syncthreads();
+    const int nv = 2 * nc + 2;
+    const int stride = nv;
+    // ---- issue loads: K3 partials (fast path: <= 32 per thread)
+    int tpv = T / nv;
+    if (tpv < 1) tpv = 1;
+    if (tpv > 64) tpv = 64;
+    const int per = (np3 + tpv - 1) / tpv;
+    const bool fast = nv <= T && per <= 32;
+    const int kv = tid / tpv, pv = tid % tpv;
+    const bool act = fast && kv < nv && kv < T / tpv;
+    double vals[32];
+#pragma unroll
+    for (int u = 0; u < 32; ++u) {
+        const int idx = pv + u * tpv;
+        vals[u] = (act && idx < np3) ? v.partials[(int64_t)idx * stride + kv] : 0.0;
+    }
+    double p1 = 0.0;
+    if (mode == 0)
+        for (int64_t i = tid; i < np1; i += T) p1 += v.part1[i];
+    const bool gsmall = nc <= 64;
+    if (gsmall)
+        for (int e = tid; e < nc * nc; e += T) Gl[e] = v.Ginv[e];
+    // ---- combine
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < 32; ++u) acc += vals[u];
+    const double g = (mode == 0) ? sum_all_reg(p1, red) : 0.0;
+    if (fast) {
+        red[tid] = acc;
+        __syncthreads();
+        if (act && pv == 0) {
+            double t = 0.0;
+            for (int j = 0; j < tpv; ++j) t += red[tid + j];
+            fin[kv] = t;
+        }
+        __syncthreads();
+    } else {
+        reduce_partials(v.partials, np3, nv, stride, fin, red);
+        __syncthreads();
+    }
+    const double a = (mode == 0) ? st->rho / g : 0.0;
+    double du = 0.0;
+    if (nc > 0) {
+        const double* Gi = gsmall ? Gl : v.Ginv;
+        ginv_matvec(Gi, nc, fin + 2, muL, red);
+        ginv_matvec(Gi, nc, fin + 2 + nc, gvL, red);
+        __syncthreads();
+        // u = C^T r: recurrence u -= alpha (AC)^T w; zero after (re)projection
+        double p = 0.0;
+        for (int c = tid; c < nc; c += T) {
+            const double uc = (mode == 0) ? v.u[c] - a * fin[2 + nc + c] : 0.0;
+            v.u[c] = uc;
+            v.mu[c] = muL[c];
+            p += uc * muL[c];
+        }
+        du = sum_all_reg(p, red);
+    }
+    const int j0 = st->iter;
+    if (mode == 0 && st->ktime_on) {
+        unsigned long long* tl = reinterpret_cast<unsigned long long*>(Gl);
+        if ((j0 & 31) == 1) {
+            ktime_collect(st, v.kslots, 0, np1, tl);
+            ktime_collect(st, v.kslots, 1, np3, tl);
+        } else if ((j0 & 31) == 2) {
+            ktime_collect(st, v.kslots, 2, np5, tl);
+        }
+    }
     if (tid == 0) {
         const double rrn = fin[0];
-        const double rho_new = fin[1];
-        const int j = st->iter;
+        const double rho_new = fin[1] - du;  // (r, z) = (r, s) - (C^T r)^T mu
+        const double rr_before = st->rr;
+        const int j = j0;
         int stn = ST_RUN;
         if (mode == 0) {
-            const double a = st->rho / g;
             if (j < v.coef_cap) {
                 v.gamma_h[j] = g;
                 v.alpha_h[j] = a;
@@ -431,51 +583,84 @@ __global__ __launch_bounds__(1024) void k_finalize_update(SysView<V, W> v, int m
                 stn = ST_BREAKDOWN;
             } else {
                 const int it = st->iter;
-                st->beta = (mode == 1) ? 0.0 : rho_new / st->rho;
+                double beta = (mode == 1) ? 0.0 : rho_new / st->rho;
+                // A replacement that more than doubles the residual (the
+                // single-precision operator's floor reached) voids the
+                // conjugacy with the old direction: restart from z.
+                if (mode == 2 && rrn > 4.0 * rr_before) {
+                    beta = 0.0;
+                    st->restarts += 1;
+                    if (it < st->first_restart) st->first_restart = it;
+                }
+                st->beta = beta;
                 st->rho = rho_new;
                 if (it < v.coef_cap) v.rho_h[it] = rho_new;
             }
         }
         st->status = stn;
-        next = stn;
+        beta_s = (stn == ST_RUN) ? st->beta : 0.0;
     }
     __syncthreads();
-    if (next == ST_RUN && nc > 0) ginv_matvec(v.Ginv, nc, fin + 2, v.mu, red);
+    // the new direction is projected as a whole: w = P (z + beta w_old)
+    // = s + beta w_old - C (mu + beta G^-1 (AC)^T w_old)
+    const double bt = beta_s;
+    for (int c = tid; c < nc; c += T) v.mu2[c] = muL[c] + bt * gvL[c];
 }
 
 // ------------------------------------------------------------------ K5
-// z = s - C mu, w = z + beta w.  first = 1: initial direction w = z;
-// first = 2: the update that follows a residual replacement (runs only
-// when one is pending).  Records z_j / w_j.
+// z = s - C mu (recorded for SRKS) and the new direction
+// w = s - C mu2 + beta w_old with mu2 = mu + beta G^-1 (AC)^T w_old, i.e.
+// w = P (z + beta w_old): the whole direction is kept A-orthogonal to C
+// (in exact arithmetic (AC)^T w_old = 0 and mu2 = mu).  first = 1: initial
+// direction w = z; first = 2: the update that follows a residual
+// replacement (runs only when one is pending).
+template <typename V, typename W>
+__device__ __forceinline__ void correct_row(const SysView<V, W>& v, int64_t i, int nc, const double* mu,
+                                            const double* mu2, double beta, int first, int j, int hist_cap) {
+    const double s = (double)v.s[i];
+    double cz = 0.0, cw = 0.0;
+    const V* Ci = v.C + i;
+    int c = 0;
+    for (; c + 4 <= nc; c += 4) {
+        const double c0 = (double)Ci[(int64_t)c * v.ldc], c1 = (double)Ci[(int64_t)(c + 1) * v.ldc];
+        const double c2 = (double)Ci[(int64_t)(c + 2) * v.ldc], c3 = (double)Ci[(int64_t)(c + 3) * v.ldc];
+        cz += c0 * mu[c] + c1 * mu[c + 1] + c2 * mu[c + 2] + c3 * mu[c + 3];
+        cw += c0 * mu2[c] + c1 * mu2[c + 1] + c2 * mu2[c + 2] + c3 * mu2[c + 3];
+    }
+    for (; c < nc; ++c) {
+        const double cc = (double)Ci[(int64_t)c * v.ldc];
+        cz += cc * mu[c];
+        cw += cc * mu2[c];
+    }
+    const W zv = (W)(s - cz);
+    const W wv = (first == 1) ? zv : (W)(s - cw + beta * (double)v.w[i]);
+    v.w[i] = wv;
+    if (j < hist_cap) {
+        if (v.zhist) v.zhist[(int64_t)j * v.ldh + i] = (V)zv;
+        if (v.whist) v.whist[(int64_t)j * v.ldh + i] = (V)wv;
+    }
+}
+
 template <typename V, typename W>
 __global__ __launch_bounds__(256) void k_correct_dir(SysView<V, W> v, int first) {
     DevState* st = v.st;
     if (!gate(st, M_RUN)) return;
     if (first == 2 && st->pending_dir == 0) return;
     __shared__ double mu[1024];
+    __shared__ double mu2[1024];
     const int nc = st->nc;
-    for (int c = threadIdx.x; c < nc; c += blockDim.x) mu[c] = v.mu[c];
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+        mu[c] = v.mu[c];
+        mu2[c] = (first == 1) ? v.mu[c] : v.mu2[c];
+    }
     __syncthreads();
     const double beta = (first == 1) ? 0.0 : st->beta;
     const int j = st->iter;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= v.n) return;
-    double z = (double)v.s[i];
-    const V* Ci = v.C + i;
-    int c = 0;
-    for (; c + 4 <= nc; c += 4) {
-        const double c0 = (double)Ci[(int64_t)c * v.ldc], c1 = (double)Ci[(int64_t)(c + 1) * v.ldc];
-        const double c2 = (double)Ci[(int64_t)(c + 2) * v.ldc], c3 = (double)Ci[(int64_t)(c + 3) * v.ldc];
-        z -= c0 * mu[c] + c1 * mu[c + 1] + c2 * mu[c + 2] + c3 * mu[c + 3];
-    }
-    for (; c < nc; ++c) z -= (double)Ci[(int64_t)c * v.ldc] * mu[c];
-    const W zv = (W)z;
-    const W wv = (first == 1) ? zv : (W)((double)zv + beta * (double)v.w[i]);
-    v.w[i] = wv;
-    if (j < st->hist_cap) {
-        if (v.zhist) v.zhist[(int64_t)j * v.ldh + i] = (V)zv;
-        if (v.whist) v.whist[(int64_t)j * v.ldh + i] = (V)wv;
-    }
+    const bool tm = first == 0 && ktime_sample(st, 2);
+    ktime_begin(v.kslots, 2, tm);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < v.n; i += (int64_t)gridDim.x * blockDim.x)
+        correct_row(v, i, nc, mu, mu2, beta, first, j, st->hist_cap);
+    ktime_end(v.kslots, 2, tm);
 }
 
 // ----------------------------------------------------------------- K11
@@ -870,6 +1055,12 @@ int64_t update_grid(int64_t n, int block) {
     return g < 1 ? 1 : g;
 }
 
+int64_t correct_grid(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    if (g > 4096) g = 4096;
+    return g < 1 ? 1 : g;
+}
+
 int64_t dot_grid(int64_t n) {
     int64_t g = (n + kTpb - 1) / kTpb;
     if (g > 256) g = 256;
@@ -888,12 +1079,13 @@ void launch_update_reduce(const SysView<V, W>& v, int mode, hipStream_t stream) 
     const int np1 = (int)spmv_grid(v.nslices, B);
     const int np3 = (int)update_grid(v.n, B);
     hipLaunchKernelGGL((k_update_reduce<V, W, B>), dim3((unsigned)np3), dim3(threads), 0, stream, v, mode, np1);
-    hipLaunchKernelGGL((k_finalize_update<V, W>), dim3(1), dim3(1024), 0, stream, v, mode, np1, np3);
+    hipLaunchKernelGGL((k_finalize_update<V, W>), dim3(1), dim3(1024), 0, stream, v, mode, np1, np3,
+                       (int)correct_grid(v.n));
 }
 
 template <typename V, typename W>
 void launch_correct_dir(const SysView<V, W>& v, int first, hipStream_t stream) {
-    hipLaunchKernelGGL((k_correct_dir<V, W>), dim3(cdiv(v.n, 256)), dim3(256), 0, stream, v, first);
+    hipLaunchKernelGGL((k_correct_dir<V, W>), dim3((unsigned)correct_grid(v.n)), dim3(256), 0, stream, v, first);
 }
 
 template <typename V, typename W, int B>

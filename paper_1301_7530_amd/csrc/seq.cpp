@@ -129,7 +129,7 @@ krs_status SeqImpl<V, W>::create(const krs_seq_desc& d, const double* C0, int32_
     nnzb = d.nnzb;
     stream = ctx->stream;
     if (desc.rank_tol <= 0.0) desc.rank_tol = 1e-6;
-    if (desc.refine_drop <= 0.0) desc.refine_drop = 0.1;
+    if (desc.refine_drop == 0.0) desc.refine_drop = 0.1;
     if (desc.ritz_eps <= 0.0) desc.ritz_eps = 1e-14;
     const int64_t* rp = d.row_ptr;
     const int32_t* ci = d.col_idx;
@@ -186,7 +186,7 @@ krs_status SeqImpl<V, W>::create(const krs_seq_desc& d, const double* C0, int32_
     ok = ok && d_w.reserve(ctx, n * sizeof(W));
     ok = ok && d_q.reserve(ctx, n * sizeof(W));
     ok = ok && d_st.reserve(ctx, sizeof(DevState));
-    ok = ok && d_mu.reserve(ctx, 1024 * sizeof(double));
+    ok = ok && d_mu.reserve(ctx, 3072 * sizeof(double));
     if (!ok) {
         set_error("device allocation failed while creating the sequence");
         return KRS_E_OOM;
@@ -244,12 +244,10 @@ template <typename V, typename W>
 void SeqImpl<V, W>::destroy() {
     for (Buf* b : {&d_col, &d_slice_ptr, &d_map, &d_diag, &d_val64, &d_valV, &d_minv, &d_bad, &d_in, &d_b, &d_x,
                    &d_r, &d_s, &d_w, &d_q, &d_C, &d_C0, &d_AC64, &d_ACv, &d_G, &d_Ginv, &d_mu, &d_Z, &d_coef,
-                   &d_partials, &d_st, &d_F, &d_tmp, &d_Ctmp})
+                   &d_partials, &d_st, &d_F, &d_tmp, &d_Ctmp, &d_kslots})
         b->release(ctx);
     if (h_st) (void)hipHostFree(h_st);
     h_st = nullptr;
-    for (auto& e : tev)
-        if (e) (void)hipEventDestroy(e);
     graph_release();
 }
 
@@ -327,6 +325,8 @@ SysView<V, W> SeqImpl<V, W>::view() {
     v.ldac = nc > 0 ? nc : 1;
     v.Ginv = (const double*)d_Ginv.p;
     v.mu = (double*)d_mu.p;
+    v.u = (double*)d_mu.p + 1024;
+    v.mu2 = (double*)d_mu.p + 2048;
     v.zhist = nullptr;
     v.whist = nullptr;
     v.ldh = ldc;
@@ -339,6 +339,7 @@ SysView<V, W> SeqImpl<V, W>::view() {
     v.part1 = (double*)d_partials.p;
     v.partials = (double*)d_partials.p + kPart1;
     v.st = (DevState*)d_st.p;
+    v.kslots = (unsigned long long*)d_kslots.p;
     return v;
 }
 
@@ -363,33 +364,9 @@ void SeqImpl<V, W>::k_resid(const SysView<V, W>& v, int final_only) {
 template <typename V, typename W>
 void SeqImpl<V, W>::enqueue_iterations(const SysView<V, W>& v, int k) {
     for (int i = 0; i < k; ++i) {
-        const bool t = timing && i == 0 && tev[0];
-        if (t) (void)hipEventRecord(tev[0], stream);
         k_spmv(v);
-        if (t) (void)hipEventRecord(tev[1], stream);
         k_update(v, 0);
-        if (t) (void)hipEventRecord(tev[2], stream);
         launch_correct_dir<V, W>(v, 0, stream);
-        if (t) {
-            (void)hipEventRecord(tev[3], stream);
-            tev_pending = true;
-        }
-    }
-}
-
-// Add the sampled durations once the stream has passed the events.  A
-// sample is kept only while the solve was still iterating at its end
-// (afterwards the gated kernels return at once and would skew the mean).
-template <typename V, typename W>
-void SeqImpl<V, W>::collect_timing() {
-    if (!tev_pending) return;
-    tev_pending = false;
-    float ms[3];
-    for (int j = 0; j < 3; ++j)
-        if (hipEventElapsedTime(&ms[j], tev[j], tev[j + 1]) != hipSuccess) return;
-    for (int j = 0; j < 3; ++j) {
-        kt_count[j] += 1;
-        kt_ms[j] += ms[j];
     }
 }
 
@@ -417,11 +394,8 @@ krs_status SeqImpl<V, W>::graph_launch(const SysView<V, W>& v, int slot, int blo
         g.exec = nullptr;
         g.graph = nullptr;
         KRS_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-        const bool t = timing;
-        timing = false;
         enqueue_iterations(v, block);
         enqueue_refine(v);
-        timing = t;
         hipError_t e = hipStreamEndCapture(stream, &g.graph);
         if (e != hipSuccess) {
             set_error(std::string("graph capture failed: ") + hipGetErrorString(e));
@@ -454,7 +428,7 @@ krs_status SeqImpl<V, W>::coarse_pass(std::vector<double>& G) {
     const bool need_v = !std::is_same<V, double>::value;
     if (!d_AC64.reserve(ctx, (size_t)n * nc * sizeof(double)) ||
         (need_v && !d_ACv.reserve(ctx, (size_t)n * nc * sizeof(V))) || !d_G.reserve(ctx, nn * sizeof(double)) ||
-        !d_Ginv.reserve(ctx, nn * sizeof(double)) || !d_mu.reserve(ctx, std::max<size_t>(1024, nc) * sizeof(double))) {
+        !d_Ginv.reserve(ctx, nn * sizeof(double)) || !d_mu.reserve(ctx, 3072 * sizeof(double))) {
         set_error("device allocation failed for A C / C^T A C");
         return KRS_E_OOM;
     }
@@ -549,7 +523,7 @@ krs_status SeqImpl<V, W>::rebuild(int* dropped) {
 template <typename V, typename W>
 bool SeqImpl<V, W>::ensure_partials(int64_t extra) {
     const int64_t need = kPart1 + std::max<int64_t>(
-        {update_grid(n, B) * (int64_t)(std::max(nc, 1) + 2), spmv_grid(nslices, B) + 8,
+        {update_grid(n, B) * (int64_t)(2 * std::max(nc, 1) + 2), spmv_grid(nslices, B) + 8,
          dot_grid(n) * (int64_t)(std::max(nc, 1) + 1), extra, (int64_t)1024});
     if ((int64_t)(d_partials.bytes / sizeof(double)) >= need) return true;
     if (!d_partials.reserve(ctx, (size_t)need * sizeof(double))) {
@@ -606,15 +580,16 @@ krs_status SeqImpl<V, W>::solve(double* x, bool device_x, krs_solve_info* info) 
     h_st->tol2 = desc.tol * desc.tol;
     // reliable updates whenever single precision is involved
     const bool lowp = !std::is_same<V, double>::value;
-    h_st->drop2 = lowp ? desc.refine_drop * desc.refine_drop : 0.0;
+    h_st->drop2 = (lowp && desc.refine_drop > 0.0) ? desc.refine_drop * desc.refine_drop : 0.0;
     h_st->refine_every = lowp ? desc.refine_every : 0;
     h_st->status = ST_RUN;
+    h_st->first_restart = max_iter + 1;
     h_st->max_iter = max_iter;
     h_st->hist_cap = hist;
     h_st->nc = nc;
     KRS_HIP(hipMemcpyAsync(d_st.p, h_st, sizeof(DevState), hipMemcpyHostToDevice, stream));
-    if (timing && !tev[0])
-        for (auto& e : tev) KRS_HIP(hipEventCreate(&e));
+    h_st->ktime_on = timing ? 1 : 0;
+    if (timing && !d_kslots.reserve(ctx, (size_t)3 * 2 * 4096 * sizeof(unsigned long long))) return KRS_E_OOM;
     h_st->iter = 0;
     SysView<V, W> v = view();
     // initialisation: mu0 = Ginv C^T b, x0 = C mu0, r0 = b - AC mu0, s0, z0, w0
@@ -625,33 +600,22 @@ krs_status SeqImpl<V, W>::solve(double* x, bool device_x, krs_solve_info* info) 
     KRS_CHECK_LAUNCH();
     t_rb.stop(stream);
     t_it.start(stream);
-    // iteration blocks; each block ends with the (gated) refinement step.
-    // With timing on, the first block runs eagerly so that its first
-    // iteration can be bracketed with events.
+    // iteration blocks; each block ends with the (gated) refinement step
     const bool graphs = desc.exec_mode == 0;
     int block = graphs ? 16 : 8;
     int last_iter = -1, stuck = 0;
-    bool first_block = true;
     while (true) {
-        const int iter_before = h_st->iter;
-        int ran = block;
-        if (graphs && !(timing && first_block)) {
+        if (graphs) {
             krs_status gs = graph_launch(v, block == 16 ? 0 : 1, block);
             if (gs != KRS_OK) return gs;
         } else {
-            if (timing && first_block) ran = 8;
-            enqueue_iterations(v, ran);
+            enqueue_iterations(v, block);
             enqueue_refine(v);
             KRS_CHECK_LAUNCH();
         }
-        first_block = false;
         KRS_HIP(hipMemcpyAsync(h_st, d_st.p, sizeof(DevState), hipMemcpyDeviceToHost, stream));
         KRS_HIP(hipStreamSynchronize(stream));
         const int s = h_st->status;
-        if (timing) {
-            if (h_st->iter >= iter_before + ran) collect_timing();
-            else tev_pending = false;
-        }
         if (s == ST_DONE || s == ST_BREAKDOWN || s == ST_MAXIT) break;
         if (h_st->iter == last_iter) {
             if (++stuck > 4) {
@@ -673,6 +637,15 @@ krs_status SeqImpl<V, W>::solve(double* x, bool device_x, krs_solve_info* info) 
         else KRS_HIP(hipMemcpyAsync(x, d_x.p, n * sizeof(double), hipMemcpyDeviceToHost, stream));
     }
     KRS_HIP(hipStreamSynchronize(stream));
+    if (timing) {
+        int khz = 0;
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx->device) != hipSuccess || khz <= 0)
+            khz = 100000;
+        for (int j = 0; j < 3; ++j) {
+            kt_count[j] += (int64_t)h_st->kcnt[j];
+            kt_ms[j] += (double)h_st->ksum[j] / (double)khz;
+        }
+    }
     const int m = h_st->iter;
     m_last = m;
     const int mc = std::min(m + 1, coef_cap);
@@ -759,7 +732,9 @@ krs_status SeqImpl<V, W>::recycle(int32_t* n_added) {
                !(desc.max_basis > 0 && desc.cap_policy == KRS_CAP_FREEZE && nc >= desc.max_basis)) {
         // (with a full frozen basis nothing could be appended: no extraction)
         const int hist = h_st->hist_cap;
-        const int mu = std::min(m, hist);  // leading part of the Lanczos run
+        // leading part of the Lanczos run: within the kept history and
+        // before the first direction restart (after it H_m is block diagonal)
+        const int mu = std::min(std::min(m, hist), h_st->first_restart);
         if (mu > 1) {
             std::vector<double> dd(mu), l2(mu - 1);
             for (int j = 0; j < mu; ++j) dd[j] = 1.0 / coef_alpha[j];

@@ -44,7 +44,7 @@ struct SeqBase {
     virtual krs_status recycle(int32_t* n_added) = 0;
     virtual krs_status basis(double* C, int64_t ld, int32_t cap, int32_t* n_c) = 0;
     virtual void destroy() = 0;
-    // sampled kernel timing (first iteration of every block)
+    // live kernel timing (sampled iterations, device wall clock)
     bool timing = false;
     int64_t kt_count[3] = {0, 0, 0};
     double kt_ms[3] = {0.0, 0.0, 0.0};
@@ -70,9 +70,8 @@ struct SeqImpl : SeqBase {
     int trks_slots = 0;
     bool submitted = false, solved = false;
     Buf d_col, d_slice_ptr, d_map, d_diag, d_val64, d_valV, d_minv, d_bad, d_in, d_b, d_x, d_r, d_s, d_w, d_q;
-    Buf d_C, d_C0, d_AC64, d_ACv, d_G, d_Ginv, d_mu, d_Z, d_coef, d_partials, d_st, d_F, d_tmp, d_Ctmp;
+    Buf d_C, d_C0, d_AC64, d_ACv, d_G, d_Ginv, d_mu, d_Z, d_coef, d_partials, d_st, d_F, d_tmp, d_Ctmp, d_kslots;
     DevState* h_st = nullptr;
-    hipEvent_t tev[4] = {nullptr, nullptr, nullptr, nullptr};
     // captured iteration blocks (16 and 64 iterations + refinement step)
     struct GraphSlot {
         hipGraph_t graph = nullptr;
@@ -82,8 +81,6 @@ struct SeqImpl : SeqBase {
     } gslot[2];
     krs_status graph_launch(const SysView<V, W>& v, int slot, int block);
     void graph_release();
-    bool tev_pending = false;
-    void collect_timing();
 
     krs_status create(const krs_seq_desc& d, const double* C0, int32_t m0, int64_t ldc0) override;
     krs_status submit(const double* values, const double* b, bool device) override;
