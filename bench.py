@@ -35,6 +35,8 @@ WORKLOADS = {
     "elasticity40": dict(kind="elasticity", size=40, n_systems=20, config_id=2, max_basis=60, eps=1e-8),
     "elasticity100": dict(kind="elasticity", size=100, n_systems=30, config_id=3, max_basis=200, eps=1e-8),
     "diffusion20": dict(kind="diffusion", size=(20, 20, 20), n_systems=8, config_id=1, max_basis=0, eps=1e-14),
+    # many independent diffusion sequences (n ~ U[5e3, 2e5]) solved in fused launches
+    "batched": dict(kind="batched", size=None, n_systems=10, config_id=4, max_basis=60, eps=1e-8),
 }
 
 
@@ -56,7 +58,8 @@ def run_phase(K, ctx, seq, dev_sys, reuse, args, wl, order, timing=False):
 
     s = K.sequence_for(ctx, seq, precision=args.precision, reuse=reuse, tol=1e-8, max_iter=args.max_iter,
                        ritz_eps=args.eps if args.eps else wl["eps"], max_basis=wl["max_basis"], cap_policy="freeze",
-                       refine_drop=args.refine_drop)
+                       refine_drop=args.refine_drop, autotune=args.autotune, update_rows=args.update_rows,
+                       eager=args.eager)
     x = torch.empty(seq.n, dtype=torch.float64, device="cuda")
     infos = []
     lat = []
@@ -129,6 +132,118 @@ def cpu_baseline(seq, k, C, m_avg, sample_iters, coeffs):
                 seconds_per_solve=solve_s)
 
 
+def _gen_system(task):
+    shape, seq_id, k, n_systems = task
+    import gen
+
+    sq = gen.make_sequence("diffusion", shape, n_systems, 4, seq_id)
+    vals, b = sq.system(k)
+    return seq_id, k, vals, b
+
+
+def gen_batched(args):
+    """Host data of the batched workload, generated by worker processes
+    before this process touches the GPU."""
+    import concurrent.futures as cf
+
+    import gen
+
+    wl = WORKLOADS["batched"]
+    shapes = gen.batched_diffusion_sizes(args.sequences)
+    nsys = wl["n_systems"]
+    ks = [k % nsys for k in range(args.warmup + args.steps)]
+    seqs = [gen.make_sequence("diffusion", sh, nsys, 4, i) for i, sh in enumerate(shapes)]
+    _log(f"batched: {len(seqs)} sequences, sum n = {sum(sq.n for sq in seqs)}, "
+         f"generating {len(set(ks))} systems each")
+    tasks = [(sh, i, k, nsys) for i, sh in enumerate(shapes) for k in sorted(set(ks))]
+    host = {}
+    with cf.ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 4)) as ex:
+        for i, k, vals, b in ex.map(_gen_system, tasks, chunksize=4):
+            host[(i, k)] = (vals, b)
+    return seqs, ks, host
+
+
+def run_batched(args, K, torch, data):
+    """Fused multi-sequence solves (one batch_solve per step over every
+    sequence) against the same sequences solved one after the other, and
+    plain PCG in fused launches."""
+    wl = WORKLOADS["batched"]
+    seqs, ks, host = data
+    n_tot = sum(sq.n for sq in seqs)
+    dev = {key: (torch.from_numpy(v).to("cuda"), torch.from_numpy(b).to("cuda")) for key, (v, b) in host.items()}
+    torch.cuda.synchronize()
+    ctx = K.Context(0)
+    kw = dict(precision=args.precision, tol=1e-8, max_iter=args.max_iter, ritz_eps=args.eps or wl["eps"],
+              max_basis=wl["max_basis"], cap_policy="freeze", history_cap=args.history_cap,
+              refine_drop=args.refine_drop)
+
+    def phase(reuse, fused):
+        hs = [K.sequence_for(ctx, sq, reuse=reuse, **kw) for sq in seqs]
+        xs = [torch.empty(sq.n, dtype=torch.float64, device="cuda") for sq in seqs]
+        iters, t_steps = [], []
+        try:
+            for step, k in enumerate(ks):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for i, h in enumerate(hs):
+                    h.submit(*dev[(i, k)])
+                if fused:
+                    _, infos = ctx.batch_solve(hs, xs=xs)
+                else:
+                    infos = [h.solve_device(x) for h, x in zip(hs, xs)]
+                if reuse != "none":
+                    for h in hs:
+                        h.recycle()
+                torch.cuda.synchronize()
+                if step >= args.warmup:
+                    t_steps.append(time.perf_counter() - t0)
+                    iters.append([inf["iters"] for inf in infos])
+                    bad = [inf for inf in infos if inf["rel_res_true"] > 1e-8 or inf["status"] != 0]
+                    if bad:
+                        raise RuntimeError(f"{len(bad)} systems missed the tolerance: {bad[0]}")
+        finally:
+            for h in hs:
+                h.close()
+        t = sum(t_steps)
+        return dict(value=len(hs) * len(t_steps) / t, time=t, iters_mean=float(np.mean(iters)),
+                    step_ms=[round(1e3 * x, 2) for x in t_steps])
+
+    _log("fused SRKS")
+    fused = phase("selective", True)
+    _log("sequential SRKS")
+    alone = phase("selective", False) if args.plain else None
+    _log("fused plain PCG")
+    plain = phase("none", True) if args.plain else None
+    ctx.close()
+    out = {
+        "metric": "solves/s at 1e-8 resid vs plain PCG same GPU; %HBM peak; p50/p99 latency",
+        "value": round(fused["value"], 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * fused["time"] / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"mixed": "f32+f64", "fp64": "f64", "fp32": "f32"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"batched: {len(seqs)} diffusion sequences, n ~ U[5e3, 2e5] (sum {n_tot}), "
+                               f"SRKS eps={kw['ritz_eps']:.0e} cap {wl['max_basis']}, fused launches",
+                   "sequences": len(seqs), "sum_n": n_tot, "precision": args.precision,
+                   "history_cap": args.history_cap},
+        "iters_mean": fused["iters_mean"],
+        "step_ms": fused["step_ms"],
+    }
+    if alone:
+        out["sequential"] = {"value": round(alone["value"], 4), "iters_mean": alone["iters_mean"]}
+        out["speedup_vs_sequential"] = fused["value"] / alone["value"]
+    if plain:
+        out["plain_pcg"] = {"value": round(plain["value"], 4), "iters_mean": plain["iters_mean"]}
+        out["speedup_vs_plain_pcg"] = fused["value"] / plain["value"]
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,6 +257,12 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=100)
     ap.add_argument("--eps", type=float, default=0.0, help="SRKS stagnation tolerance (default: per workload)")
     ap.add_argument("--refine-drop", type=float, default=0.0, help="mixed: refinement trigger (0 = library default)")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="keep the default update-kernel tile instead of timing candidates")
+    ap.add_argument("--update-rows", type=int, default=0, help="fixed update-kernel block rows per workgroup")
+    ap.add_argument("--sequences", type=int, default=64, help="batched workload: number of sequences")
+    ap.add_argument("--history-cap", type=int, default=256, help="batched workload: Krylov vectors kept per solve")
+    ap.add_argument("--eager", action="store_true", help="launch kernels one by one instead of graph replay")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -151,6 +272,8 @@ def main():
         print("bench.py: one process / one GPU only", file=sys.stderr)
         sys.exit(2)
 
+    batched_data = gen_batched(args) if args.workload == "batched" else None
+
     import torch
 
     import gen
@@ -159,6 +282,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.workload == "batched":
+        run_batched(args, K, torch, batched_data)
+        return
     wl = WORKLOADS[args.workload]
     seq = gen.make_sequence(wl["kind"], wl["size"], wl["n_systems"], wl["config_id"])
     total = args.warmup + args.steps
@@ -216,6 +342,7 @@ def main():
             "precision_detail": {"mixed": "fp32 matrix/preconditioner/basis, fp64 vectors and reductions", "fp64": "fp64 throughout", "fp32": "fp32 matrix, basis and vectors, fp64 reductions"}[args.precision],
         },
         "iters_mean": float(np.mean(iters)),
+        "update_rows": sorted({i["update_rows"] for i in infos}),
         "n_c_mean": float(np.mean([i["n_c"] for i in infos])),
         "rel_res_true_max": float(max(i["rel_res_true"] for i in infos)),
         "refinements_mean": float(np.mean([i["refinements"] for i in infos])),

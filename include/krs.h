@@ -108,6 +108,11 @@ typedef struct {
                               (0 = 0.1; negative: only when the recursion has converged).  A
                               replacement that more than doubles ||r|| restarts the direction. */
     int32_t exec_mode;     /* 0: iteration blocks replayed as captured HIP graphs; 1: eager kernel launches */
+    int32_t update_rows;   /* block rows per workgroup of the update / projector kernel (0 = about one
+                              range per compute unit); fixes the grouping of its partial sums */
+    int32_t autotune;      /* 1: when the basis width changed by half, time several update_rows values on
+                              the submitted system and keep the fastest (results then depend on the
+                              choice in the last bits only) */
 } krs_seq_desc;
 
 typedef struct {
@@ -118,7 +123,7 @@ typedef struct {
     int32_t dropped;        /* last solve: basis columns dropped by the rank guard */
     int32_t added;          /* last recycle: columns appended */
     int32_t status;         /* krs_status of the last solve */
-    int32_t reserved;
+    int32_t update_rows;    /* block rows per update workgroup used by the last solve */
     double rel_res_true;    /* ||b - A x|| / ||b|| with double-precision A and x */
     double rel_res_recursive;
     double t_setup_ms;      /* value intake and preconditioner setup */
@@ -182,11 +187,20 @@ krs_status krs_seq_kernel_time(krs_seq* s, int32_t kernel, int64_t* launches, do
 krs_status krs_seq_destroy(krs_seq* s);
 
 /* --------------------------------------------------------------- batch */
-/* Solve the submitted systems of `count` sequences (all on ctx) together:
- * the iterations of all systems run in shared launches.  x[i] (host, n_i
- * doubles) and info[i] receive each result.  Each result equals the one
- * krs_seq_solve gives for that sequence alone. */
+/* Solve the submitted systems of `count` distinct sequences of ctx
+ * together.  Sequences with the same precision and block size are fused:
+ * each iteration is one launch per kernel covering the workgroups of every
+ * member still iterating (members that finish drop out of the launches),
+ * replayed as captured HIP graphs.  Every member keeps the launch geometry
+ * of its own solve, so each result equals, bit for bit, the one
+ * krs_seq_solve gives for that sequence alone.  x[i] (host, n_i doubles;
+ * NULL or a NULL entry: not copied) and info[i] (may be NULL) receive the
+ * results.  Returns the first non-OK member status (KRS_E_MAXIT only when
+ * no member failed otherwise); every member's info is filled. */
 krs_status krs_batch_solve(krs_ctx* ctx, krs_seq* const* seqs, int32_t count, double* const* x, krs_solve_info* info);
+/* As krs_batch_solve with device output pointers d_x[i] (n_i doubles). */
+krs_status krs_batch_solve_device(krs_ctx* ctx, krs_seq* const* seqs, int32_t count, double* const* d_x,
+                                  krs_solve_info* info);
 
 /* ------------------------------------------------ host-side Ritz logic */
 /* Pure host computations exposed for testing the library's selection

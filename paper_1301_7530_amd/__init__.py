@@ -60,6 +60,8 @@ class SeqDesc(ctypes.Structure):
         ("rank_tol", ctypes.c_double),
         ("refine_drop", ctypes.c_double),
         ("exec_mode", ctypes.c_int32),
+        ("update_rows", ctypes.c_int32),
+        ("autotune", ctypes.c_int32),
     ]
 
 
@@ -72,7 +74,7 @@ class SolveInfo(ctypes.Structure):
         ("dropped", ctypes.c_int32),
         ("added", ctypes.c_int32),
         ("status", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("update_rows", ctypes.c_int32),
         ("rel_res_true", ctypes.c_double),
         ("rel_res_recursive", ctypes.c_double),
         ("t_setup_ms", ctypes.c_double),
@@ -83,7 +85,7 @@ class SolveInfo(ctypes.Structure):
     ]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -119,6 +121,7 @@ SIGNATURES = [
     ("krs_seq_kernel_time", _S, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), _D]),
     ("krs_seq_destroy", _S, [_P]),
     ("krs_batch_solve", _S, [_P, _PP, ctypes.c_int32, ctypes.POINTER(_D), ctypes.POINTER(SolveInfo)]),
+    ("krs_batch_solve_device", _S, [_P, _PP, ctypes.c_int32, _PP, ctypes.POINTER(SolveInfo)]),
     ("krs_ritz_select", _S, [_D, _D, ctypes.c_int32, ctypes.c_double, _D, _D, _U8]),
     ("krs_coarse_factor", _S, [ctypes.c_int32, _D, ctypes.c_double, _D, _U8, _I32]),
 ]
@@ -236,15 +239,25 @@ class Context:
     def __exit__(self, *a):
         self.close()
 
-    def batch_solve(self, seqs):
-        """Solve the submitted systems of several sequences together."""
+    def batch_solve(self, seqs, xs=None):
+        """Solve the submitted systems of several sequences in fused launches.
+
+        ``xs``: optional list of float64 device tensors (one per sequence)
+        that receive the solutions; otherwise host numpy arrays are returned.
+        Returns (xs, [info dict per sequence])."""
         cnt = len(seqs)
-        xs = [np.zeros(s.n) for s in seqs]
         arr_h = (ctypes.c_void_p * cnt)(*[s.handle.value for s in seqs])
-        arr_x = (_D * cnt)(*[_dptr(x) for x in xs])
         infos = (SolveInfo * cnt)()
-        st = _lib.krs_batch_solve(self.handle, ctypes.cast(arr_h, _PP), cnt, arr_x, infos)
-        _check(st, "krs_batch_solve", allow=(KRS_E_MAXIT,))
+        if xs is None:
+            xs = [np.zeros(s.n) for s in seqs]
+            arr_x = (_D * cnt)(*[_dptr(x) for x in xs])
+            st = _lib.krs_batch_solve(self.handle, ctypes.cast(arr_h, _PP), cnt, arr_x, infos)
+            _check(st, "krs_batch_solve", allow=(KRS_E_MAXIT,))
+        else:
+            arr_x = (ctypes.c_void_p * cnt)(*[x.data_ptr() for x in xs])
+            st = _lib.krs_batch_solve_device(self.handle, ctypes.cast(arr_h, _PP), cnt, ctypes.cast(arr_x, _PP),
+                                             infos)
+            _check(st, "krs_batch_solve_device", allow=(KRS_E_MAXIT,))
         return xs, [infos[i].as_dict() for i in range(cnt)]
 
 
@@ -256,7 +269,8 @@ class Sequence:
 
     def __init__(self, ctx: Context, row_ptr, col_idx, n, block=1, precision="fp64", reuse="selective",
                  precond=None, cap_policy="freeze", tol=1e-8, max_iter=10000, ritz_eps=1e-14, max_basis=0,
-                 refine_every=0, history_cap=0, rank_tol=0.0, refine_drop=0.0, C0=None, eager=False):
+                 refine_every=0, history_cap=0, rank_tol=0.0, refine_drop=0.0, C0=None, eager=False,
+                 update_rows=0, autotune=False):
         self.ctx = ctx
         self.n = int(n)
         self.block = int(block)
@@ -284,6 +298,8 @@ class Sequence:
         d.rank_tol = rank_tol
         d.refine_drop = refine_drop
         d.exec_mode = 1 if eager else 0
+        d.update_rows = update_rows
+        d.autotune = 1 if autotune else 0
         self.desc = d
         h = ctypes.c_void_p()
         if C0 is not None and C0.shape[1] > 0:

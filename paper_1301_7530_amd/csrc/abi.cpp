@@ -348,19 +348,38 @@ krs_status krs_coarse_factor(int32_t nc, const double* G, double rank_tol, doubl
     KRS_GUARD_END
 }
 
-krs_status krs_batch_solve(krs_ctx* ctx, krs_seq* const* seqs, int32_t count, double* const* x, krs_solve_info* info) {
-    KRS_GUARD_BEGIN
-    if (!ctx || (count > 0 && !seqs)) return KRS_E_INVALID;
-    krs_status worst = KRS_OK;
+static krs_status batch_common(krs_ctx* ctx, krs_seq* const* seqs, int32_t count, double* const* x, bool device_x,
+                               krs_solve_info* info) {
+    if (!ctx || count < 0 || (count > 0 && !seqs)) {
+        set_error("ctx and seqs are required");
+        return KRS_E_INVALID;
+    }
+    std::vector<krs::SeqBase*> v(count);
     for (int i = 0; i < count; ++i) {
         if (!seqs[i] || seqs[i]->impl->ctx != ctx) {
             set_error("every sequence must belong to ctx");
             return KRS_E_INVALID;
         }
-        krs_status st = seqs[i]->impl->solve(x ? x[i] : nullptr, false, info ? &info[i] : nullptr);
-        if (st != KRS_OK && worst == KRS_OK) worst = st;
+        for (int j = 0; j < i; ++j)
+            if (seqs[j] == seqs[i]) {
+                set_error("a sequence appears twice in the batch");
+                return KRS_E_INVALID;
+            }
+        v[i] = seqs[i]->impl.get();
     }
-    return worst;
+    return krs::batch_solve(ctx, v.data(), count, x, device_x, info);
+}
+
+krs_status krs_batch_solve(krs_ctx* ctx, krs_seq* const* seqs, int32_t count, double* const* x, krs_solve_info* info) {
+    KRS_GUARD_BEGIN
+    return batch_common(ctx, seqs, count, x, false, info);
+    KRS_GUARD_END
+}
+
+krs_status krs_batch_solve_device(krs_ctx* ctx, krs_seq* const* seqs, int32_t count, double* const* d_x,
+                                  krs_solve_info* info) {
+    KRS_GUARD_BEGIN
+    return batch_common(ctx, seqs, count, d_x, true, info);
     KRS_GUARD_END
 }
 

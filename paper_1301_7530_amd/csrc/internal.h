@@ -17,6 +17,25 @@ constexpr int kSlice = 64;
 // Doubles reserved at the head of the reduction scratch for SpMV partials
 // (>= the largest SpMV grid).
 constexpr int64_t kPart1 = 4096;
+// Threads of the update kernel (one block row each per step).
+constexpr int kT3 = 512;
+// Largest update grid (bounds the partial sums the finalize kernel reads).
+constexpr int64_t kMaxUpdateGrid = 2048;
+// Largest grid of a timed kernel (timing slots per kernel).
+constexpr int64_t kMaxTimedGrid = 8192;
+
+// Launch geometry of one system, fixed for a solve: the single-system and
+// the fused batch launches use the same per-system workgroup counts, so a
+// system's reductions (and results) are the same in both.
+struct Geometry {
+    int64_t cb3;  // block rows per update workgroup
+    int32_t g1;   // SpMV / true-residual workgroups
+    int32_t g3;   // update workgroups
+    int32_t g5;   // direction-update workgroups
+    int32_t gd;   // coarse-dot workgroups
+    int32_t gcc;  // coarse-correction workgroups
+    int32_t pad;
+};
 
 // Device-side solver status codes (DevState::status).
 enum DevStatus : int32_t {
@@ -61,6 +80,7 @@ struct DevState {
     unsigned long long ksum[3];
     unsigned long long kcnt[3];
 };
+static_assert(sizeof(DevState) % 8 == 0, "DevState is staged in 8-byte words");
 
 // Per-launch view of one system, passed by value to the kernels.  V is the
 // storage type of the matrix values, the preconditioner and the basis; W
@@ -84,8 +104,10 @@ struct SysView {
     W* w;
     W* q;
     // basis
-    const V* C;      // n x nc column-major, leading dim ldc
-    const V* AC;     // n x nc row-major, leading dim ldac
+    int32_t nc;      // columns of C in this solve
+    int32_t pad0;
+    const V* C;      // n x nc column-major, leading dim ldc (a multiple of 256 >= n)
+    const V* AC;     // n x nc row-major, leading dim ldac (a multiple of 32 >= nc)
     int64_t ldc;
     int64_t ldac;
     const double* Ginv;  // nc x nc column-major
@@ -105,26 +127,51 @@ struct SysView {
     double* partials;  // per-workgroup partials of the other reductions
     DevState* st;
     unsigned long long* kslots;  // per-workgroup start / end stamps of timed launches
+    Geometry geo;
+};
+
+// Launch maps of a fused batch: map[k][i] = (system, workgroup) of launch
+// k's workgroup i; count[k] = total workgroups.
+enum BatchKernel {
+    BK_SPMV = 0,  // SpMV and true residual (g1 per system)
+    BK_UPD,       // update (g3)
+    BK_ONE,       // one workgroup per system (F3, F11)
+    BK_DIR,       // direction update (g5)
+    BK_DOT,       // coarse dot (gd; systems with a basis)
+    BK_ONEC,      // one workgroup per system with a basis
+    BK_CC,        // coarse correction (gcc; systems with a basis)
+    BK_COUNT
+};
+struct BatchMaps {
+    const int2* map[BK_COUNT];
+    int64_t count[BK_COUNT];
 };
 
 // ------------------------------------------------------------ launchers
-// All launch on `stream`; the grid shapes are derived from the view.
+// All launch on `stream`; the grid shapes come from the view's geometry.
+Geometry make_geometry(int64_t n, int64_t nslices, int block, int64_t cb3_req);
+// doubles of reduction scratch (after kPart1) a solve with nc columns needs
+int64_t partial_doubles(const Geometry& g, int nc);
+
 template <typename V, typename W, int B> void launch_spmv_dot(const SysView<V, W>& v, hipStream_t stream);
 template <typename V, typename W, int B>
 void launch_update_reduce(const SysView<V, W>& v, int mode, hipStream_t stream);
+// the update kernel alone (mode 1 only rewrites s and the partials: used to time tile choices)
+template <typename V, typename W, int B>
+void launch_update_only(const SysView<V, W>& v, int mode, hipStream_t stream);
 template <typename V, typename W> void launch_correct_dir(const SysView<V, W>& v, int first, hipStream_t stream);
 template <typename V, typename W, int B>
 void launch_true_resid(const SysView<V, W>& v, int final_only, hipStream_t stream);
 template <typename V, typename W>
-void launch_coarse_dot(const SysView<V, W>& v, const double* src64, const W* srcV, int with_bb, uint32_t mask,
-                       hipStream_t stream);
+void launch_coarse_dot(const SysView<V, W>& v, int src_b, int with_bb, uint32_t mask, hipStream_t stream);
 template <typename V, typename W>
 void launch_coarse_correct(const SysView<V, W>& v, int from_b, uint32_t mask, hipStream_t stream);
 template <typename V, typename W, int B>
-void launch_spmm(const SysView<V, W>& v, const V* C, int64_t ldc, int nc, double* AC64, V* ACv, hipStream_t stream);
+void launch_spmm(const SysView<V, W>& v, const V* C, int64_t ldc, int nc, int64_t ldac, double* AC64, V* ACv,
+                 hipStream_t stream);
 template <typename V>
-void launch_gram(const V* C, int64_t ldc, const double* AC64, int64_t n, int nc, double* G, double* partials,
-                 int64_t partial_cap, hipStream_t stream);
+void launch_gram(const V* C, int64_t ldc, const double* AC64, int64_t ldac, int64_t n, int nc, double* G,
+                 double* partials, int64_t partial_cap, hipStream_t stream);
 template <typename V>
 void launch_basis_combine(const V* Z, int64_t ldz, int m, const double* F, int s, V* out, int64_t ldo, int64_t n,
                           hipStream_t stream);
@@ -142,11 +189,23 @@ void launch_precond_setup(const double* in, const int64_t* diag_idx, int64_t nb,
 template <typename V> void launch_d2v(const double* in, V* out, int64_t n, hipStream_t stream);
 template <typename V> void launch_v2d(const V* in, double* out, int64_t n, hipStream_t stream);
 
-// number of workgroups the reduction kernels use for a system (bounds partials)
-int64_t update_grid(int64_t n, int block);
-int64_t spmv_grid(int64_t nslices, int block);
-int64_t dot_grid(int64_t n);
-int64_t correct_grid(int64_t n);
+// fused launches over the systems of a batch (views: device array)
+template <typename V, typename W, int B>
+void batch_spmv_dot(const SysView<V, W>* views, const BatchMaps& m, hipStream_t stream);
+template <typename V, typename W, int B>
+void batch_update_reduce(const SysView<V, W>* views, const BatchMaps& m, int mode, hipStream_t stream);
+template <typename V, typename W>
+void batch_correct_dir(const SysView<V, W>* views, const BatchMaps& m, int first, hipStream_t stream);
+template <typename V, typename W, int B>
+void batch_true_resid(const SysView<V, W>* views, const BatchMaps& m, int final_only, hipStream_t stream);
+template <typename V, typename W>
+void batch_coarse_dot(const SysView<V, W>* views, const BatchMaps& m, int src_b, int with_bb, uint32_t mask,
+                      hipStream_t stream);
+template <typename V, typename W>
+void batch_coarse_correct(const SysView<V, W>* views, const BatchMaps& m, int from_b, uint32_t mask,
+                          hipStream_t stream);
+template <typename V, typename W>
+void batch_status(const SysView<V, W>* views, int count, int32_t* out, hipStream_t stream);
 
 // ----------------------------------------------------------- host logic
 // Tridiagonal eigenvalues of H = L D L^T (d_j = 1/alpha_j, l_j^2 = beta_{j+1}),

@@ -1,14 +1,16 @@
 // Device kernels of libkrs for gfx950 (CDNA4, wave64).
 //
-// One APCG iteration (Algorithm 1, standard Hestenes-Stiefel form) is three
-// launches, each ending in a fixed-order grid reduction finished by the last
-// workgroup to arrive (no floating-point atomics, so results are bitwise
+// One APCG iteration (Algorithm 1, standard Hestenes-Stiefel form) is four
+// launches; cross-workgroup sums go through per-workgroup partials reduced
+// in a fixed order (no floating-point atomics, so results are bitwise
 // reproducible):
-//   spmv_dot       q = A w, gamma = (w, q), alpha = rho / gamma
-//   update_reduce  x += alpha w, r -= alpha q, s = M^-1 r,
-//                  ||r||^2, (r, s), t = (AC)^T s;  last workgroup: beta, mu = G^-1 t
-//   correct_dir    z = s - C mu, w = z + beta w   (z / w recorded for reuse)
-// (r, s) equals (r, z) because C^T r = 0 (Section 2.2, constraint view).
+//   K1 spmv_dot         q = A w; partials of (w, q)
+//   K3 update_reduce    alpha = rho / (w, q), x += alpha w, r -= alpha q,
+//                       s = M^-1 r; partials of ||r||^2, (r, s), (AC)^T s,
+//                       (AC)^T w
+//   F3 finalize_update  one workgroup: gamma, alpha, mu = G^-1 (AC)^T s,
+//                       rho = (r, z), beta, convergence / refinement status
+//   K5 correct_dir      z = s - C mu, w = s - C mu2 + beta w
 //
 // Matrices are stored in sliced ELL: 64 (block) rows per slice, one lane
 // per block row, slot k of every row of a slice stored contiguously so a
@@ -16,8 +18,13 @@
 // 9 planes of 64 values per slot: value (d, e) of the block in slot k of
 // lane l sits at ((slot*9) + 3d + e)*64 + l.  Sub-row d of a slice is
 // handled by wave d of a 192-thread workgroup.
+//
+// Every iteration kernel is a device function of (system view, workgroup
+// index); the single-system kernels call it with blockIdx.x, the fused
+// multi-system kernels with the (system, workgroup) pair of a launch map.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "internal.h"
@@ -26,9 +33,8 @@ namespace krs {
 
 namespace {
 
-constexpr int kTpb = 256;          // threads per workgroup, scalar kernels
-constexpr int kMaxGrid = 512;      // cap on the update grid (bounds the partial sums)
-constexpr int kMaxChunks = 16;     // projector reduction: up to 16*64 = 1024 basis columns
+constexpr int kTpb = 256;  // threads per workgroup, scalar kernels
+constexpr int kTF3 = 512;  // threads of the single-workgroup finalize of the update
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -53,6 +59,7 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
 
 // Reduce `nv` values over `np` partial rows (row stride `stride`) in a fixed
 // order with all threads of the workgroup; out[k] for k < nv (LDS).
+template <int UNR = 32>
 __device__ void reduce_partials(const double* partials, int64_t np, int nv, int stride, double* out, double* lds) {
     const int T = blockDim.x;
     int tpv = T / (nv > 0 ? nv : 1);
@@ -64,21 +71,14 @@ __device__ void reduce_partials(const double* partials, int64_t np, int nv, int 
         const int p = threadIdx.x % tpv;
         double acc = 0.0;
         if (k < nv && threadIdx.x / tpv < T / tpv) {
-            // up to 32 independent loads in flight per thread
+            // UNR independent loads in flight per thread
             int64_t i = p;
-            for (; i + 32 * tpv <= np; i += 32 * tpv) {
-                double t[32];
+            for (; i + UNR * tpv <= np; i += UNR * tpv) {
+                double t[UNR];
 #pragma unroll
-                for (int u = 0; u < 32; ++u) t[u] = partials[(i + u * tpv) * stride + k];
+                for (int u = 0; u < UNR; ++u) t[u] = partials[(i + u * tpv) * stride + k];
 #pragma unroll
-                for (int u = 0; u < 32; ++u) acc += t[u];
-            }
-            for (; i + 8 * tpv <= np; i += 8 * tpv) {
-                double t[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) t[u] = partials[(i + u * tpv) * stride + k];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) acc += t[u];
+                for (int u = 0; u < UNR; ++u) acc += t[u];
             }
             for (; i < np; i += tpv) acc += partials[i * stride + k];
         }
@@ -143,21 +143,21 @@ __device__ void ginv_matvec(const double* __restrict__ Ginv, int nc, const doubl
 // workgroup of a sampled launch stores its start and end wall-clock stamps
 // in its own slot (plain stores, no contention); the finalize kernel adds
 // max(end) - min(start) to the running sums.
-constexpr int kSlotStride = 2 * 4096;
+constexpr int kSlotStride = 2 * kMaxTimedGrid;
 __device__ __forceinline__ bool ktime_sample(const DevState* st, int which) {
     return st->ktime_on && (st->iter & 31) == (which == 2 ? 2 : 1);
 }
-__device__ __forceinline__ void ktime_begin(unsigned long long* slots, int which, bool on) {
-    if (on && threadIdx.x == 0) slots[which * kSlotStride + 2 * blockIdx.x] = (unsigned long long)wall_clock64();
+__device__ __forceinline__ void ktime_begin(unsigned long long* slots, int which, int64_t bid, bool on) {
+    if (on && threadIdx.x == 0) slots[which * kSlotStride + 2 * bid] = (unsigned long long)wall_clock64();
 }
-__device__ __forceinline__ void ktime_end(unsigned long long* slots, int which, bool on) {
+__device__ __forceinline__ void ktime_end(unsigned long long* slots, int which, int64_t bid, bool on) {
     if (on) {
         __syncthreads();
-        if (threadIdx.x == 0) slots[which * kSlotStride + 2 * blockIdx.x + 1] = (unsigned long long)wall_clock64();
+        if (threadIdx.x == 0) slots[which * kSlotStride + 2 * bid + 1] = (unsigned long long)wall_clock64();
     }
 }
 // All threads: span of kernel `which` over np workgroup slots, added to
-// the sums by thread 0.  lds: 2 * blockDim.x entries.
+// the sums of st by thread 0.  lds: 2 * blockDim.x entries.
 __device__ void ktime_collect(DevState* st, const unsigned long long* slots, int which, int64_t np,
                               unsigned long long* lds) {
     unsigned long long lo = ~0ull, hi = 0ull;
@@ -273,19 +273,20 @@ __device__ __forceinline__ X ell_row3(const V* __restrict__ val, const int32_t* 
 
 // ------------------------------------------------------------------ K1
 // q = A w over sliced ELL; per-workgroup partial sums of (w, q) go to
-// part1[blockIdx.x].  alpha = rho / (w, q) is formed from them by every
-// workgroup of the next kernel (a fixed-order sum, so all agree).
+// part1[bid].  alpha = rho / (w, q) is formed from them by every workgroup
+// of the next kernel (a fixed-order sum, so all agree).
 template <typename V, typename W, int B>
-__global__ __launch_bounds__(256) void k_spmv_dot(SysView<V, W> v) {
+__device__ __forceinline__ void spmv_dot_body(const SysView<V, W>& v, int64_t bid) {
     if (!gate(v.st, M_RUN)) return;
     const bool tm = ktime_sample(v.st, 0);
-    ktime_begin(v.kslots, 0, tm);
+    ktime_begin(v.kslots, 0, bid, tm);
     __shared__ double lds[8];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t nblk = v.geo.g1;
     double part = 0.0;
     if (B == 1) {
         // 4 slices per workgroup, one per wave
-        for (int64_t sl = (int64_t)blockIdx.x * 4 + wave; sl < v.nslices; sl += (int64_t)gridDim.x * 4) {
+        for (int64_t sl = bid * 4 + wave; sl < v.nslices; sl += nblk * 4) {
             const int64_t k0 = v.slice_ptr[sl], k1 = v.slice_ptr[sl + 1];
             const W acc = ell_row1<V, W>(v.val, v.col, v.w, k0, k1, lane);
             const int64_t row = sl * 64 + lane;
@@ -297,7 +298,7 @@ __global__ __launch_bounds__(256) void k_spmv_dot(SysView<V, W> v) {
     } else {
         // one slice per workgroup step; wave d = sub-row d of the 3x3 blocks
         const int d = wave;
-        for (int64_t sl = blockIdx.x; sl < v.nslices; sl += gridDim.x) {
+        for (int64_t sl = bid; sl < v.nslices; sl += nblk) {
             const int64_t k0 = v.slice_ptr[sl], k1 = v.slice_ptr[sl + 1];
             const W acc = ell_row3<V, W>(v.val, v.col, v.w, k0, k1, lane, d);
             const int64_t p = sl * 64 + lane;
@@ -308,11 +309,100 @@ __global__ __launch_bounds__(256) void k_spmv_dot(SysView<V, W> v) {
         }
     }
     const double bs = block_sum(part, lds);
-    if (threadIdx.x == 0) v.part1[blockIdx.x] = bs;
-    ktime_end(v.kslots, 0, tm);
+    if (threadIdx.x == 0) v.part1[bid] = bs;
+    ktime_end(v.kslots, 0, bid, tm);
 }
 
 // ------------------------------------------------------------------ K3
+// Projector sums of one step: tacc[c] += sum_i AC[i, c] ss[i] and
+// vacc[c] += sum_i AC[i, c] ws[i] over `rows` rows of a row-major AC tile
+// (leading dimension ld, a multiple of 32 elements).  Columns are taken in
+// chunks of 128 bytes; a lane reads 16 bytes (QW columns) of one row, so
+// LPR = 8 lanes cover a chunk of a row and a wave reads 8 rows per load,
+// the 8 waves 64 rows per round.  Each lane keeps the sums of its QW
+// columns; lanes of equal column are combined by shuffles, the waves in a
+// fixed order through LDS.
+template <typename V>
+struct alignas(16) Vec16 {
+    V e[16 / sizeof(V)];
+};
+
+template <typename V>
+__device__ __forceinline__ void project_rows(const V* __restrict__ ACt, int64_t ld, int rows, int nc,
+                                             const double* ss, const double* ws, double* tacc, double* vacc,
+                                             double (*cred)[64]) {
+    constexpr int QW = 16 / sizeof(V);
+    constexpr int CW = 128 / sizeof(V);
+    constexpr int LPR = CW / QW;  // 8
+    constexpr int RPW = 64 / LPR;  // 8
+    constexpr int NW = kT3 / 64;
+    constexpr int RPR = RPW * NW;
+    constexpr int UR = 8;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int q = lane % LPR, rsub = lane / LPR;
+    const int nch = (nc + CW - 1) / CW;
+    for (int ch = 0; ch < nch; ++ch) {
+        double at[QW], av[QW];
+#pragma unroll
+        for (int e = 0; e < QW; ++e) {
+            at[e] = 0.0;
+            av[e] = 0.0;
+        }
+        const V* base = ACt + ch * CW + q * QW;
+        for (int r0 = wave * RPW + rsub; r0 < rows; r0 += RPR * UR) {
+            // rows past the step are clamped to its last row (weight 0) so
+            // every load of the group is issued unconditionally
+            Vec16<V> a[UR];
+#pragma unroll
+            for (int u = 0; u < UR; ++u) {
+                const int rr = min(r0 + u * RPR, rows - 1);
+                a[u] = *reinterpret_cast<const Vec16<V>*>(base + (int64_t)rr * ld);
+            }
+#pragma unroll
+            for (int u = 0; u < UR; ++u) {
+                const int rr = r0 + u * RPR;
+                const bool ok = rr < rows;
+                const double sv = ok ? ss[rr] : 0.0, wv = ok ? ws[rr] : 0.0;
+#pragma unroll
+                for (int e = 0; e < QW; ++e) {
+                    at[e] += (double)a[u].e[e] * sv;
+                    av[e] += (double)a[u].e[e] * wv;
+                }
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < QW; ++e) {
+#pragma unroll
+            for (int off = LPR; off < 64; off <<= 1) {
+                at[e] += __shfl_xor(at[e], off, 64);
+                av[e] += __shfl_xor(av[e], off, 64);
+            }
+        }
+        if (rsub == 0) {
+#pragma unroll
+            for (int e = 0; e < QW; ++e) {
+                cred[wave][q * QW + e] = at[e];
+                cred[wave][32 + q * QW + e] = av[e];
+            }
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < CW) {
+            const int c = ch * CW + threadIdx.x;
+            if (c < nc) {
+                double t = 0.0, u2 = 0.0;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    t += cred[w][threadIdx.x];
+                    u2 += cred[w][32 + threadIdx.x];
+                }
+                tacc[c] += t;
+                vacc[c] += u2;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // mode 0: x += alpha w, r -= alpha q (the regular step)
 // mode 1: initial step (r0 given), no update
 // mode 2: after a true-residual replacement, no update
@@ -320,126 +410,105 @@ __global__ __launch_bounds__(256) void k_spmv_dot(SysView<V, W> v) {
 //   [ ||r||^2, (r, s), t = (AC)^T s (nc), v = (AC)^T w (nc, modes 0 and 2) ]
 // v measures the A-component of w along C, which is zero in exact
 // arithmetic; it drives the recurrence for u = C^T r used to form
-// rho = (r, z) = (r, s) - (C^T r)^T mu exactly.  Tiles of TR rows (block
-// aligned); the projector part reads the tile's rows of AC (row-major) once
-// with one lane per column (CW lanes, RW rows per wave step) and
-// accumulates both sums per column in LDS.
+// rho = (r, z) = (r, s) - (C^T r)^T mu exactly.  Workgroup bid owns the
+// block rows [bid cb3, (bid + 1) cb3), one thread per block row, in steps
+// of kT3 block rows; the step's s and w go through LDS to the projector.
 template <typename V, typename W, int B>
-__global__ __launch_bounds__(1024) void k_update_reduce(SysView<V, W> v, int mode, int np1) {
+__device__ __forceinline__ void update_reduce_body(const SysView<V, W>& v, int64_t bid, int mode) {
     DevState* st = v.st;
     const uint32_t mask = (mode == 2) ? M_REFINE : M_RUN;
     if (!gate(st, mask)) return;
     const bool tm = mode == 0 && ktime_sample(st, 1);
-    ktime_begin(v.kslots, 1, tm);
-    constexpr int TR = (B == 1) ? 1024 : 768;  // rows per tile == threads
-    __shared__ double ss[TR];
-    __shared__ double ws[TR];
-    __shared__ double red[1024];
-    __shared__ double red2[1024];
+    ktime_begin(v.kslots, 1, bid, tm);
+    constexpr int T = kT3;
+    __shared__ double ss[T * B];
+    __shared__ double ws[T * B];
+    __shared__ double red[T];
     __shared__ double tacc[1024];
     __shared__ double vacc[1024];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    constexpr int nwaves = TR / 64;
-    const int nc = st->nc;
-    double a = 0.0;
-    if (mode == 0) a = st->rho / sum_all(v.part1, np1, red);
-    for (int c = tid; c < nc; c += TR) {
+    __shared__ double cred[T / 64][64];
+    const int tid = threadIdx.x;
+    const int nc = v.nc;
+    for (int c = tid; c < nc; c += T) {
         tacc[c] = 0.0;
         vacc[c] = 0.0;
     }
-    // projector reduction geometry
-    int CW = 64;
-    if (nc <= 32) CW = nc <= 1 ? 1 : (nc <= 2 ? 2 : (nc <= 4 ? 4 : (nc <= 8 ? 8 : (nc <= 16 ? 16 : 32))));
-    const int RW = 64 / CW;
-    const int nch = (nc + 63) / 64;
-    const int c0 = lane % CW, rsub = lane / CW;
-    const int G = nwaves * RW;
-    const int g0 = wave * RW + rsub;
+    const int64_t pb = bid * v.geo.cb3;
+    const int64_t pe = (pb + v.geo.cb3) < v.nb ? (pb + v.geo.cb3) : v.nb;
     double rr = 0.0, rs = 0.0;
-    const int64_t ntiles = (v.n + TR - 1) / TR;
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int64_t i = tile * TR + tid;
-        double ri = 0.0, wi = 0.0;
-        if (i < v.n) {
-            W rv = v.r[i];
-            if (mode != 1) wi = (double)v.w[i];
-            if (mode == 0) {
-                v.x[i] += a * wi;
-                rv = (W)((double)rv - a * (double)v.q[i]);
-                v.r[i] = rv;
-            }
-            ri = (double)rv;
+    double a = 0.0;
+    bool have_a = mode != 0;
+    for (int64_t ps = pb; ps < pe; ps += T) {
+        const int64_t p = ps + tid;
+        double ri[B], wi[B], si[B];
+#pragma unroll
+        for (int d = 0; d < B; ++d) {
+            ri[d] = 0.0;
+            wi[d] = 0.0;
+            si[d] = 0.0;
         }
-        double si = 0.0;
-        if (B == 1) {
-            if (i < v.n) si = (double)(W)((double)v.minv[i] * ri);
-        } else {
-            __syncthreads();
-            ss[tid] = ri;
-            __syncthreads();
-            if (i < v.n) {
-                const int d = tid % 3;
-                const int64_t p = i / 3;
-                const V* mb = v.minv + p * 9 + d * 3;
-                const int t0 = tid - d;
-                si = (double)(W)((double)mb[0] * ss[t0] + (double)mb[1] * ss[t0 + 1] + (double)mb[2] * ss[t0 + 2]);
+        // the step's vector loads are issued before alpha is formed from
+        // the SpMV partials, so the two latencies overlap
+        W rv[B], qv[B];
+        double xv[B];
+        if (p < pe) {
+#pragma unroll
+            for (int d = 0; d < B; ++d) {
+                const int64_t i = p * B + d;
+                rv[d] = v.r[i];
+                if (mode != 1) wi[d] = (double)v.w[i];
+                if (mode == 0) {
+                    qv[d] = v.q[i];
+                    xv[d] = v.x[i];
+                }
             }
         }
-        if (i < v.n) {
-            v.s[i] = (W)si;
-            rr += ri * ri;
-            rs += ri * si;
+        if (!have_a) {
+            a = st->rho / sum_all(v.part1, v.geo.g1, red);
+            have_a = true;
+        }
+        if (p < pe) {
+#pragma unroll
+            for (int d = 0; d < B; ++d) {
+                const int64_t i = p * B + d;
+                W r2 = rv[d];
+                if (mode == 0) {
+                    v.x[i] = xv[d] + a * wi[d];
+                    r2 = (W)((double)r2 - a * (double)qv[d]);
+                    v.r[i] = r2;
+                }
+                ri[d] = (double)r2;
+            }
+            if (B == 1) {
+                si[0] = (double)(W)((double)v.minv[p] * ri[0]);
+            } else {
+                const V* m = v.minv + p * 9;
+#pragma unroll
+                for (int d = 0; d < B; ++d)
+                    si[d] = (double)(W)((double)m[3 * d] * ri[0] + (double)m[3 * d + 1] * ri[1] +
+                                        (double)m[3 * d + 2] * ri[2]);
+            }
+#pragma unroll
+            for (int d = 0; d < B; ++d) {
+                v.s[p * B + d] = (W)si[d];
+                rr += ri[d] * ri[d];
+                rs += ri[d] * si[d];
+            }
         }
         if (nc > 0) {
             __syncthreads();
-            ss[tid] = (i < v.n) ? si : 0.0;
-            ws[tid] = (i < v.n) ? wi : 0.0;
-            __syncthreads();
-            const int rows = (int)((v.n - tile * TR) < TR ? (v.n - tile * TR) : TR);
-            const V* ACt = v.AC + tile * TR * v.ldac;
-            constexpr int UR = 8;
-            for (int ch = 0; ch < nch; ++ch) {
-                const int c = ch * 64 + c0;
-                double a2 = 0.0, b2 = 0.0;
-                if (c < nc) {
-                    for (int r = g0; r < rows; r += G * UR) {
-                        // rows past the tile end are clamped (weight 0) so
-                        // every load of the group is issued unconditionally
-                        V av[UR];
 #pragma unroll
-                        for (int u = 0; u < UR; ++u) {
-                            const int r2 = min(r + u * G, rows - 1);
-                            av[u] = ACt[(int64_t)r2 * v.ldac + c];
-                        }
-#pragma unroll
-                        for (int u = 0; u < UR; ++u) {
-                            const int r2 = r + u * G;
-                            const bool ok = r2 < rows;
-                            a2 += (double)av[u] * (ok ? ss[r2] : 0.0);
-                            b2 += (double)av[u] * (ok ? ws[r2] : 0.0);
-                        }
-                    }
-                }
-                // combine the G row groups of this chunk (fixed order)
-                __syncthreads();
-                red[g0 * CW + c0] = a2;
-                red2[g0 * CW + c0] = b2;
-                __syncthreads();
-                if (tid < CW && ch * 64 + tid < nc) {
-                    double t = 0.0, u2 = 0.0;
-                    for (int gg = 0; gg < G; ++gg) {
-                        t += red[gg * CW + tid];
-                        u2 += red2[gg * CW + tid];
-                    }
-                    tacc[ch * 64 + tid] += t;
-                    vacc[ch * 64 + tid] += u2;
-                }
+            for (int d = 0; d < B; ++d) {
+                ss[tid * B + d] = si[d];
+                ws[tid * B + d] = wi[d];
             }
+            __syncthreads();
+            const int64_t pn = (ps + T) < pe ? (ps + T) : pe;
+            project_rows<V>(v.AC + ps * B * v.ldac, v.ldac, (int)((pn - ps) * B), nc, ss, ws, tacc, vacc, cred);
         }
     }
-    // workgroup partials
     const int stride = 2 * nc + 2;
-    double* myp = v.partials + (int64_t)blockIdx.x * stride;
+    double* myp = v.partials + bid * stride;
     {
         const double brr = block_sum(rr, red);
         if (tid == 0) myp[0] = brr;
@@ -447,58 +516,77 @@ __global__ __launch_bounds__(1024) void k_update_reduce(SysView<V, W> v, int mod
         if (tid == 0) myp[1] = brs;
     }
     __syncthreads();
-    for (int c = tid; c < nc; c += TR) {
+    for (int c = tid; c < nc; c += T) {
         myp[2 + c] = tacc[c];
         myp[2 + nc + c] = vacc[c];
     }
-    ktime_end(v.kslots, 1, tm);
+    ktime_end(v.kslots, 1, bid, tm);
 }
 
 // F3: one workgroup.  Reduces the partials of K1 (mode 0) and K3, records
 // alpha_j, gamma_j, rho_{j+1}, decides convergence / refinement / breakdown
 // and forms beta, mu = G^-1 t, mu2 and u = C^T r for the direction update.
-// Being a single workgroup it is latency bound: every independent load
-// (K3 partials, K1 partials, G^-1, state) is issued before the first wait.
+// A single workgroup is latency bound, so every independent load (device
+// state, K3 and K1 partials, G^-1, u) is issued before the first wait, and
+// the state is worked on in LDS and written back once at the end.
 template <typename V, typename W>
-__global__ __launch_bounds__(1024) void k_finalize_update(SysView<V, W> v, int mode, int np1, int np3, int np5) {
-    DevState* st = v.st;
-    const uint32_t mask = (mode == 2) ? M_REFINE : M_RUN;
-    if (!gate(st, mask)) return;
-    __shared__ double red[1024];
+__device__ __forceinline__ void finalize_update_body(const SysView<V, W>& v, int mode) {
+    constexpr int T = kTF3;
+    constexpr int NWORD = (int)(sizeof(DevState) / 8);
+    constexpr int PRE = 64;  // partial sums preloaded per thread (one round trip for ~32k of them)
+    __shared__ DevState S;
+    __shared__ double red[T];
     __shared__ double fin[2048 + 4];
     __shared__ double muL[1024];
     __shared__ double gvL[1024];
+    __shared__ double uL[1024];
     __shared__ double Gl[4096];
     __shared__ double beta_s;
     const int tid = threadIdx.x;
-    const int T = blockDim.x;
-    const int nc = st->nc;
+    const int nc = v.nc;
     const int nv = 2 * nc + 2;
-    const int stride = nv;
-    // ---- issue loads: K3 partials (fast path: <= 32 per thread)
+    const int64_t np3 = v.geo.g3, np1 = v.geo.g1;
+    // ---- loads
+    unsigned long long sw = 0ull;
+    if (tid < NWORD) sw = reinterpret_cast<const unsigned long long*>(v.st)[tid];
+    const bool fast = nv <= T;
     int tpv = T / nv;
     if (tpv < 1) tpv = 1;
     if (tpv > 64) tpv = 64;
-    const int per = (np3 + tpv - 1) / tpv;
-    const bool fast = nv <= T && per <= 32;
     const int kv = tid / tpv, pv = tid % tpv;
     const bool act = fast && kv < nv && kv < T / tpv;
-    double vals[32];
+    double vals[PRE];
 #pragma unroll
-    for (int u = 0; u < 32; ++u) {
-        const int idx = pv + u * tpv;
-        vals[u] = (act && idx < np3) ? v.partials[(int64_t)idx * stride + kv] : 0.0;
+    for (int u = 0; u < PRE; ++u) {
+        const int64_t idx = pv + (int64_t)u * tpv;
+        vals[u] = (act && idx < np3) ? v.partials[idx * nv + kv] : 0.0;
     }
     double p1 = 0.0;
     if (mode == 0)
         for (int64_t i = tid; i < np1; i += T) p1 += v.part1[i];
+    for (int c = tid; c < nc; c += T) uL[c] = (mode == 0) ? v.u[c] : 0.0;
     const bool gsmall = nc <= 64;
     if (gsmall)
         for (int e = tid; e < nc * nc; e += T) Gl[e] = v.Ginv[e];
-    // ---- combine
+    if (tid < NWORD) reinterpret_cast<unsigned long long*>(&S)[tid] = sw;
+    __syncthreads();
+    const uint32_t mask = (mode == 2) ? M_REFINE : M_RUN;
+    if (((1u << S.status) & mask) == 0) return;
+    // ---- sums
     double acc = 0.0;
 #pragma unroll
-    for (int u = 0; u < 32; ++u) acc += vals[u];
+    for (int u = 0; u < PRE; ++u) acc += vals[u];
+    if (act) {
+        int64_t idx = pv + PRE * (int64_t)tpv;
+        for (; idx + 8 * tpv <= np3; idx += 8 * tpv) {
+            double t[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) t[u] = v.partials[(idx + u * tpv) * nv + kv];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += t[u];
+        }
+        for (; idx < np3; idx += tpv) acc += v.partials[idx * nv + kv];
+    }
     const double g = (mode == 0) ? sum_all_reg(p1, red) : 0.0;
     if (fast) {
         red[tid] = acc;
@@ -510,40 +598,39 @@ __global__ __launch_bounds__(1024) void k_finalize_update(SysView<V, W> v, int m
         }
         __syncthreads();
     } else {
-        reduce_partials(v.partials, np3, nv, stride, fin, red);
+        reduce_partials<8>(v.partials, np3, nv, nv, fin, red);
         __syncthreads();
     }
-    const double a = (mode == 0) ? st->rho / g : 0.0;
+    const double a = (mode == 0) ? S.rho / g : 0.0;
     double du = 0.0;
     if (nc > 0) {
         const double* Gi = gsmall ? Gl : v.Ginv;
         ginv_matvec(Gi, nc, fin + 2, muL, red);
         ginv_matvec(Gi, nc, fin + 2 + nc, gvL, red);
-        __syncthreads();
         // u = C^T r: recurrence u -= alpha (AC)^T w; zero after (re)projection
         double p = 0.0;
         for (int c = tid; c < nc; c += T) {
-            const double uc = (mode == 0) ? v.u[c] - a * fin[2 + nc + c] : 0.0;
+            const double uc = (mode == 0) ? uL[c] - a * fin[2 + nc + c] : 0.0;
             v.u[c] = uc;
             v.mu[c] = muL[c];
             p += uc * muL[c];
         }
         du = sum_all_reg(p, red);
     }
-    const int j0 = st->iter;
-    if (mode == 0 && st->ktime_on) {
+    const int j0 = S.iter;
+    if (mode == 0 && S.ktime_on) {
         unsigned long long* tl = reinterpret_cast<unsigned long long*>(Gl);
         if ((j0 & 31) == 1) {
-            ktime_collect(st, v.kslots, 0, np1, tl);
-            ktime_collect(st, v.kslots, 1, np3, tl);
+            ktime_collect(&S, v.kslots, 0, np1, tl);
+            ktime_collect(&S, v.kslots, 1, np3, tl);
         } else if ((j0 & 31) == 2) {
-            ktime_collect(st, v.kslots, 2, np5, tl);
+            ktime_collect(&S, v.kslots, 2, v.geo.g5, tl);
         }
     }
     if (tid == 0) {
         const double rrn = fin[0];
         const double rho_new = fin[1] - du;  // (r, z) = (r, s) - (C^T r)^T mu
-        const double rr_before = st->rr;
+        const double rr_before = S.rr;
         const int j = j0;
         int stn = ST_RUN;
         if (mode == 0) {
@@ -551,56 +638,57 @@ __global__ __launch_bounds__(1024) void k_finalize_update(SysView<V, W> v, int m
                 v.gamma_h[j] = g;
                 v.alpha_h[j] = a;
             }
-            st->alpha = a;
-            st->pending_dir = 0;
+            S.alpha = a;
+            S.pending_dir = 0;
             const int it = j + 1;
-            st->iter = it;
-            st->since_refine += 1;
-            st->rr = rrn;
+            S.iter = it;
+            S.since_refine += 1;
+            S.rr = rrn;
             if (!finite_pos(g) || !(rrn == rrn)) {
                 stn = ST_BREAKDOWN;
-            } else if (rrn <= st->tol2 * st->bb) {
+            } else if (rrn <= S.tol2 * S.bb) {
                 stn = ST_CHECK;
-            } else if (it >= st->max_iter) {
+            } else if (it >= S.max_iter) {
                 stn = ST_MAXIT;
-            } else if ((st->refine_every > 0 && st->since_refine >= st->refine_every) ||
-                       (st->drop2 > 0.0 && rrn < st->drop2 * st->rr_ref)) {
+            } else if ((S.refine_every > 0 && S.since_refine >= S.refine_every) ||
+                       (S.drop2 > 0.0 && rrn < S.drop2 * S.rr_ref)) {
                 stn = ST_REFINE;
             }
         } else {
-            st->rr = rrn;
-            st->rr_ref = rrn;
+            S.rr = rrn;
+            S.rr_ref = rrn;
             if (mode == 2) {
-                st->since_refine = 0;
-                st->pending_dir = 1;
+                S.since_refine = 0;
+                S.pending_dir = 1;
             } else {
-                if (rrn <= st->tol2 * st->bb) stn = ST_CHECK;
-                if (st->max_iter <= 0 && stn == ST_RUN) stn = ST_MAXIT;
+                if (rrn <= S.tol2 * S.bb) stn = ST_CHECK;
+                if (S.max_iter <= 0 && stn == ST_RUN) stn = ST_MAXIT;
             }
         }
         if (stn == ST_RUN) {
             if (!finite_pos(rho_new)) {
                 stn = ST_BREAKDOWN;
             } else {
-                const int it = st->iter;
-                double beta = (mode == 1) ? 0.0 : rho_new / st->rho;
+                const int it = S.iter;
+                double beta = (mode == 1) ? 0.0 : rho_new / S.rho;
                 // A replacement that more than doubles the residual (the
                 // single-precision operator's floor reached) voids the
                 // conjugacy with the old direction: restart from z.
                 if (mode == 2 && rrn > 4.0 * rr_before) {
                     beta = 0.0;
-                    st->restarts += 1;
-                    if (it < st->first_restart) st->first_restart = it;
+                    S.restarts += 1;
+                    if (it < S.first_restart) S.first_restart = it;
                 }
-                st->beta = beta;
-                st->rho = rho_new;
+                S.beta = beta;
+                S.rho = rho_new;
                 if (it < v.coef_cap) v.rho_h[it] = rho_new;
             }
         }
-        st->status = stn;
-        beta_s = (stn == ST_RUN) ? st->beta : 0.0;
+        S.status = stn;
+        beta_s = (stn == ST_RUN) ? S.beta : 0.0;
     }
     __syncthreads();
+    if (tid < NWORD) reinterpret_cast<unsigned long long*>(v.st)[tid] = reinterpret_cast<const unsigned long long*>(&S)[tid];
     // the new direction is projected as a whole: w = P (z + beta w_old)
     // = s + beta w_old - C (mu + beta G^-1 (AC)^T w_old)
     const double bt = beta_s;
@@ -608,73 +696,101 @@ __global__ __launch_bounds__(1024) void k_finalize_update(SysView<V, W> v, int m
 }
 
 // ------------------------------------------------------------------ K5
-// z = s - C mu (recorded for SRKS) and the new direction
-// w = s - C mu2 + beta w_old with mu2 = mu + beta G^-1 (AC)^T w_old, i.e.
-// w = P (z + beta w_old): the whole direction is kept A-orthogonal to C
-// (in exact arithmetic (AC)^T w_old = 0 and mu2 = mu).  first = 1: initial
-// direction w = z; first = 2: the update that follows a residual
-// replacement (runs only when one is pending).
-template <typename V, typename W>
-__device__ __forceinline__ void correct_row(const SysView<V, W>& v, int64_t i, int nc, const double* mu,
-                                            const double* mu2, double beta, int first, int j, int hist_cap) {
-    const double s = (double)v.s[i];
-    double cz = 0.0, cw = 0.0;
-    const V* Ci = v.C + i;
-    int c = 0;
-    for (; c + 4 <= nc; c += 4) {
-        const double c0 = (double)Ci[(int64_t)c * v.ldc], c1 = (double)Ci[(int64_t)(c + 1) * v.ldc];
-        const double c2 = (double)Ci[(int64_t)(c + 2) * v.ldc], c3 = (double)Ci[(int64_t)(c + 3) * v.ldc];
-        cz += c0 * mu[c] + c1 * mu[c + 1] + c2 * mu[c + 2] + c3 * mu[c + 3];
-        cw += c0 * mu2[c] + c1 * mu2[c + 1] + c2 * mu2[c + 2] + c3 * mu2[c + 3];
-    }
-    for (; c < nc; ++c) {
-        const double cc = (double)Ci[(int64_t)c * v.ldc];
-        cz += cc * mu[c];
-        cw += cc * mu2[c];
-    }
-    const W zv = (W)(s - cz);
-    const W wv = (first == 1) ? zv : (W)(s - cw + beta * (double)v.w[i]);
-    v.w[i] = wv;
-    if (j < hist_cap) {
-        if (v.zhist) v.zhist[(int64_t)j * v.ldh + i] = (V)zv;
-        if (v.whist) v.whist[(int64_t)j * v.ldh + i] = (V)wv;
-    }
-}
+// z = s - C mu and w = s - C mu2 + beta w_old with mu2 = mu + beta G^-1
+// (AC)^T w_old, i.e. w = P (z + beta w_old): the whole direction is kept
+// A-orthogonal to C (in exact arithmetic (AC)^T w_old = 0 and mu2 = mu).
+// first = 1: initial direction w = z; first = 2: the update that follows a
+// residual replacement (runs only when one is pending).  A workgroup owns
+// 256 rows: lane l of every wave reads 4 consecutive rows of a column of C
+// (16 or 32 bytes), wave k takes the columns k, k + 4, ...; the four
+// partial sums per row are added in LDS in a fixed order.
+template <typename V>
+struct alignas(4 * sizeof(V)) Quad {
+    V e[4];
+};
 
 template <typename V, typename W>
-__global__ __launch_bounds__(256) void k_correct_dir(SysView<V, W> v, int first) {
+__device__ __forceinline__ void correct_dir_body(const SysView<V, W>& v, int64_t bid, int first) {
     DevState* st = v.st;
     if (!gate(st, M_RUN)) return;
     if (first == 2 && st->pending_dir == 0) return;
     __shared__ double mu[1024];
     __shared__ double mu2[1024];
-    const int nc = st->nc;
-    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+    __shared__ double part[4][2][256];
+    const int nc = v.nc;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int c = tid; c < nc; c += 256) {
         mu[c] = v.mu[c];
         mu2[c] = (first == 1) ? v.mu[c] : v.mu2[c];
     }
-    __syncthreads();
     const double beta = (first == 1) ? 0.0 : st->beta;
     const int j = st->iter;
+    const int hist_cap = st->hist_cap;
     const bool tm = first == 0 && ktime_sample(st, 2);
-    ktime_begin(v.kslots, 2, tm);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < v.n; i += (int64_t)gridDim.x * blockDim.x)
-        correct_row(v, i, nc, mu, mu2, beta, first, j, st->hist_cap);
-    ktime_end(v.kslots, 2, tm);
+    ktime_begin(v.kslots, 2, bid, tm);
+    __syncthreads();
+    constexpr int U = 8;
+    const int64_t nblk = (v.n + 255) / 256;
+    for (int64_t blk = bid; blk < nblk; blk += v.geo.g5) {
+        double az[4] = {0.0, 0.0, 0.0, 0.0}, aw[4] = {0.0, 0.0, 0.0, 0.0};
+        const V* Cb = v.C + blk * 256 + 4 * lane;
+        for (int c0 = wave; c0 < nc; c0 += 4 * U) {
+            Quad<V> cq[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int c = c0 + 4 * u;
+                cq[u] = (c < nc) ? *reinterpret_cast<const Quad<V>*>(Cb + (int64_t)c * v.ldc) : Quad<V>{{0, 0, 0, 0}};
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int c = c0 + 4 * u;
+                if (c < nc) {
+                    const double m1 = mu[c], m2 = mu2[c];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        az[e] += (double)cq[u].e[e] * m1;
+                        aw[e] += (double)cq[u].e[e] * m2;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            part[wave][0][4 * lane + e] = az[e];
+            part[wave][1][4 * lane + e] = aw[e];
+        }
+        __syncthreads();
+        const int64_t i = blk * 256 + tid;
+        if (i < v.n) {
+            const double cz = ((part[0][0][tid] + part[1][0][tid]) + part[2][0][tid]) + part[3][0][tid];
+            const double cw = ((part[0][1][tid] + part[1][1][tid]) + part[2][1][tid]) + part[3][1][tid];
+            const double s = (double)v.s[i];
+            const W zv = (W)(s - cz);
+            const W wv = (first == 1) ? zv : (W)(s - cw + beta * (double)v.w[i]);
+            v.w[i] = wv;
+            if (j < hist_cap) {
+                if (v.zhist) v.zhist[(int64_t)j * v.ldh + i] = (V)zv;
+                if (v.whist) v.whist[(int64_t)j * v.ldh + i] = (V)wv;
+            }
+        }
+    }
+    ktime_end(v.kslots, 2, bid, tm);
 }
 
 // ----------------------------------------------------------------- K11
 // r = b - A x with double-precision values and x.  final_only: only record
 // ||r||^2 (for the report), leave r and the status alone.
 template <typename V, typename W, int B>
-__global__ __launch_bounds__(256) void k_true_resid(SysView<V, W> v, int final_only) {
+__device__ __forceinline__ void true_resid_body(const SysView<V, W>& v, int64_t bid, int final_only) {
     DevState* st = v.st;
     if (!final_only && !gate(st, M_CHECK | M_REFINE)) return;
     __shared__ double lds[8];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t nblk = v.geo.g1;
     double part = 0.0;
     if (B == 1) {
-        for (int64_t sl = (int64_t)blockIdx.x * 4 + wave; sl < v.nslices; sl += (int64_t)gridDim.x * 4) {
+        for (int64_t sl = bid * 4 + wave; sl < v.nslices; sl += nblk * 4) {
             const int64_t k0 = v.slice_ptr[sl], k1 = v.slice_ptr[sl + 1];
             const double acc = ell_row1<double, double>(v.val64, v.col, v.x, k0, k1, lane);
             const int64_t row = sl * 64 + lane;
@@ -686,7 +802,7 @@ __global__ __launch_bounds__(256) void k_true_resid(SysView<V, W> v, int final_o
         }
     } else {
         const int d = wave;
-        for (int64_t sl = blockIdx.x; sl < v.nslices; sl += gridDim.x) {
+        for (int64_t sl = bid; sl < v.nslices; sl += nblk) {
             const int64_t k0 = v.slice_ptr[sl], k1 = v.slice_ptr[sl + 1];
             const double acc = ell_row3<double, double>(v.val64, v.col, v.x, k0, k1, lane, d);
             const int64_t p = sl * 64 + lane;
@@ -698,16 +814,16 @@ __global__ __launch_bounds__(256) void k_true_resid(SysView<V, W> v, int final_o
         }
     }
     const double bs = block_sum(part, lds);
-    if (threadIdx.x == 0) v.partials[blockIdx.x] = bs;
+    if (threadIdx.x == 0) v.partials[bid] = bs;
 }
 
 // F11: one workgroup; ||b - A x||^2 and the decision after a true residual.
 template <typename V, typename W>
-__global__ __launch_bounds__(1024) void k_finalize_resid(SysView<V, W> v, int final_only, int np) {
+__device__ __forceinline__ void finalize_resid_body(const SysView<V, W>& v, int final_only) {
     DevState* st = v.st;
     if (!final_only && !gate(st, M_CHECK | M_REFINE)) return;
     __shared__ double red[32];
-    const double rt = sum_all(v.partials, np, red);
+    const double rt = sum_all(v.partials, v.geo.g1, red);
     if (threadIdx.x == 0) {
         st->rr_true = rt;
         if (!final_only) {
@@ -724,20 +840,20 @@ __global__ __launch_bounds__(1024) void k_finalize_resid(SysView<V, W> v, int fi
 }
 
 // ------------------------------------------------------- coarse (rare)
-// t = C^T u (u = src64 or srcV), optionally bb = (u, u); last workgroup:
-// mu = Ginv t.  Used for x0 (u = b) and for the re-projection after a
-// true-residual replacement (u = r).
+// t = C^T u (u = b when src_b, else r), optionally bb = (u, u), as
+// per-workgroup partials.  Used for x0 (u = b) and for the re-projection
+// after a true-residual replacement (u = r).
 template <typename V, typename W>
-__global__ __launch_bounds__(256) void k_coarse_dot(SysView<V, W> v, const double* src64, const W* srcV, int with_bb,
-                                                    uint32_t mask) {
+__device__ __forceinline__ void coarse_dot_body(const SysView<V, W>& v, int64_t bid, int src_b, uint32_t mask) {
     DevState* st = v.st;
     if (!gate(st, mask)) return;
     __shared__ double red[kTpb];
     __shared__ double wpart[4 * 1024];
-    const int nc = st->nc;
+    const int nc = v.nc;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int stride = nc + 1;
-    double* myp = v.partials + (int64_t)blockIdx.x * stride;
+    const int64_t nblk = v.geo.gd;
+    double* myp = v.partials + bid * stride;
     // each thread accumulates over its rows, then waves reduce per column,
     // 16 columns per pass over the rows
     double bbp = 0.0;
@@ -746,8 +862,8 @@ __global__ __launch_bounds__(256) void k_coarse_dot(SysView<V, W> v, const doubl
         const int cn = (nc - c0) < 16 ? (nc - c0) : 16;
 #pragma unroll
         for (int k = 0; k < 16; ++k) acc[k] = 0.0;
-        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < v.n; i += (int64_t)gridDim.x * blockDim.x) {
-            const double u = src64 ? src64[i] : (double)srcV[i];
+        for (int64_t i = bid * blockDim.x + threadIdx.x; i < v.n; i += nblk * blockDim.x) {
+            const double u = src_b ? v.b[i] : (double)v.r[i];
             if (c0 == 0) bbp += u * u;
 #pragma unroll
             for (int k = 0; k < 16; ++k)
@@ -772,16 +888,16 @@ __global__ __launch_bounds__(256) void k_coarse_dot(SysView<V, W> v, const doubl
     if (threadIdx.x == 0) myp[0] = bsum;
 }
 
-// One workgroup: t and (u, u) from the partials of k_coarse_dot; mu = Ginv t.
+// One workgroup: t and (u, u) from the partials of coarse_dot; mu = Ginv t.
 template <typename V, typename W>
-__global__ __launch_bounds__(1024) void k_finalize_dot(SysView<V, W> v, int with_bb, uint32_t mask, int np) {
+__device__ __forceinline__ void finalize_dot_body(const SysView<V, W>& v, int with_bb, uint32_t mask) {
     DevState* st = v.st;
     if (!gate(st, mask)) return;
     __shared__ double red[1024];
     __shared__ double fin[1024 + 4];
-    const int nc = st->nc;
+    const int nc = v.nc;
     const int stride = nc + 1;
-    reduce_partials(v.partials, np, stride, stride, fin, red);
+    reduce_partials<8>(v.partials, v.geo.gd, stride, stride, fin, red);
     __syncthreads();
     if (threadIdx.x == 0 && with_bb) st->bb = fin[0];
     if (nc > 0) ginv_matvec(v.Ginv, nc, fin + 1, v.mu, red);
@@ -789,14 +905,14 @@ __global__ __launch_bounds__(1024) void k_finalize_dot(SysView<V, W> v, int with
 
 // x = (from_b ? 0 : x) + C mu;  r = (from_b ? b : r) - AC mu
 template <typename V, typename W>
-__global__ __launch_bounds__(256) void k_coarse_correct(SysView<V, W> v, int from_b, uint32_t mask) {
+__device__ __forceinline__ void coarse_correct_body(const SysView<V, W>& v, int64_t bid, int from_b, uint32_t mask) {
     DevState* st = v.st;
     if (!gate(st, mask)) return;
     __shared__ double mu[1024];
-    const int nc = st->nc;
+    const int nc = v.nc;
     for (int c = threadIdx.x; c < nc; c += blockDim.x) mu[c] = v.mu[c];
     __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = bid * blockDim.x + threadIdx.x;
     if (i >= v.n) return;
     double xi = from_b ? 0.0 : v.x[i];
     double ri = from_b ? v.b[i] : (double)v.r[i];
@@ -809,15 +925,120 @@ __global__ __launch_bounds__(256) void k_coarse_correct(SysView<V, W> v, int fro
     v.r[i] = (W)ri;
 }
 
-// ------------------------------------------------------------ rebuild
-// AC64 = A C (double values), row-major n x nc; ACv = AC64 in V.
-// blockIdx.y selects 8 columns.
+// ------------------------------------------- single-system entry points
 template <typename V, typename W, int B>
-__global__ __launch_bounds__(256) void k_spmm(SysView<V, W> v, const V* C, int64_t ldc, int nc, double* AC64, V* ACv) {
+__global__ __launch_bounds__(256) void k_spmv_dot(SysView<V, W> v) {
+    spmv_dot_body<V, W, B>(v, blockIdx.x);
+}
+template <typename V, typename W, int B>
+__global__ __launch_bounds__(kT3) void k_update_reduce(SysView<V, W> v, int mode) {
+    update_reduce_body<V, W, B>(v, blockIdx.x, mode);
+}
+template <typename V, typename W>
+__global__ __launch_bounds__(kTF3) void k_finalize_update(SysView<V, W> v, int mode) {
+    finalize_update_body<V, W>(v, mode);
+}
+template <typename V, typename W>
+__global__ __launch_bounds__(256) void k_correct_dir(SysView<V, W> v, int first) {
+    correct_dir_body<V, W>(v, blockIdx.x, first);
+}
+template <typename V, typename W, int B>
+__global__ __launch_bounds__(256) void k_true_resid(SysView<V, W> v, int final_only) {
+    true_resid_body<V, W, B>(v, blockIdx.x, final_only);
+}
+template <typename V, typename W>
+__global__ __launch_bounds__(1024) void k_finalize_resid(SysView<V, W> v, int final_only) {
+    finalize_resid_body<V, W>(v, final_only);
+}
+template <typename V, typename W>
+__global__ __launch_bounds__(256) void k_coarse_dot(SysView<V, W> v, int src_b, uint32_t mask) {
+    coarse_dot_body<V, W>(v, blockIdx.x, src_b, mask);
+}
+template <typename V, typename W>
+__global__ __launch_bounds__(1024) void k_finalize_dot(SysView<V, W> v, int with_bb, uint32_t mask) {
+    finalize_dot_body<V, W>(v, with_bb, mask);
+}
+template <typename V, typename W>
+__global__ __launch_bounds__(256) void k_coarse_correct(SysView<V, W> v, int from_b, uint32_t mask) {
+    coarse_correct_body<V, W>(v, blockIdx.x, from_b, mask);
+}
+
+// ----------------------------------------------- fused multi-system launches
+// One launch covers the workgroups of every system of a batch: map[blockIdx.x]
+// = (system, workgroup index within that system's own grid), so each
+// system runs exactly the workgroups (and reductions) of its single launch.
+template <typename V, typename W, int B>
+__global__ __launch_bounds__(256) void kb_spmv_dot(const SysView<V, W>* __restrict__ views,
+                                                   const int2* __restrict__ map) {
+    const int2 e = map[blockIdx.x];
+    spmv_dot_body<V, W, B>(views[e.x], e.y);
+}
+template <typename V, typename W, int B>
+__global__ __launch_bounds__(kT3) void kb_update_reduce(const SysView<V, W>* __restrict__ views,
+                                                        const int2* __restrict__ map, int mode) {
+    const int2 e = map[blockIdx.x];
+    update_reduce_body<V, W, B>(views[e.x], e.y, mode);
+}
+template <typename V, typename W>
+__global__ __launch_bounds__(kTF3) void kb_finalize_update(const SysView<V, W>* __restrict__ views,
+                                                           const int2* __restrict__ map, int mode) {
+    finalize_update_body<V, W>(views[map[blockIdx.x].x], mode);
+}
+template <typename V, typename W>
+__global__ __launch_bounds__(256) void kb_correct_dir(const SysView<V, W>* __restrict__ views,
+                                                      const int2* __restrict__ map, int first) {
+    const int2 e = map[blockIdx.x];
+    correct_dir_body<V, W>(views[e.x], e.y, first);
+}
+template <typename V, typename W, int B>
+__global__ __launch_bounds__(256) void kb_true_resid(const SysView<V, W>* __restrict__ views,
+                                                     const int2* __restrict__ map, int final_only) {
+    const int2 e = map[blockIdx.x];
+    true_resid_body<V, W, B>(views[e.x], e.y, final_only);
+}
+template <typename V, typename W>
+__global__ __launch_bounds__(1024) void kb_finalize_resid(const SysView<V, W>* __restrict__ views,
+                                                          const int2* __restrict__ map, int final_only) {
+    finalize_resid_body<V, W>(views[map[blockIdx.x].x], final_only);
+}
+template <typename V, typename W>
+__global__ __launch_bounds__(256) void kb_coarse_dot(const SysView<V, W>* __restrict__ views,
+                                                     const int2* __restrict__ map, int src_b, uint32_t mask) {
+    const int2 e = map[blockIdx.x];
+    coarse_dot_body<V, W>(views[e.x], e.y, src_b, mask);
+}
+template <typename V, typename W>
+__global__ __launch_bounds__(1024) void kb_finalize_dot(const SysView<V, W>* __restrict__ views,
+                                                        const int2* __restrict__ map, int with_bb, uint32_t mask) {
+    finalize_dot_body<V, W>(views[map[blockIdx.x].x], with_bb, mask);
+}
+template <typename V, typename W>
+__global__ __launch_bounds__(256) void kb_coarse_correct(const SysView<V, W>* __restrict__ views,
+                                                         const int2* __restrict__ map, int from_b, uint32_t mask) {
+    const int2 e = map[blockIdx.x];
+    coarse_correct_body<V, W>(views[e.x], e.y, from_b, mask);
+}
+// status word and iteration count of every system of the batch
+template <typename V, typename W>
+__global__ void kb_status(const SysView<V, W>* __restrict__ views, int count, int32_t* out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    out[2 * i] = views[i].st->status;
+    out[2 * i + 1] = views[i].st->iter;
+}
+
+// ------------------------------------------------------------ rebuild
+// AC64 = A C (double values), row-major n x nc with leading dimension
+// ldac >= nc; ACv = AC64 in V.  blockIdx.y selects 8 columns; the pad
+// columns nc..ldac-1 are written as zeros by the blockIdx.y == 0 workgroups.
+template <typename V, typename W, int B>
+__global__ __launch_bounds__(256) void k_spmm(SysView<V, W> v, const V* C, int64_t ldc, int nc, int64_t ldac,
+                                              double* AC64, V* ACv) {
     constexpr int CW = 8;
     const int c0 = blockIdx.y * CW;
     const int cn = (nc - c0) < CW ? (nc - c0) : CW;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int npad = (blockIdx.y == 0) ? (int)(ldac - nc) : 0;
     if (B == 1) {
         for (int64_t sl = (int64_t)blockIdx.x * 4 + wave; sl < v.nslices; sl += (int64_t)gridDim.x * 4) {
             const int64_t k0 = v.slice_ptr[sl], k1 = v.slice_ptr[sl + 1];
@@ -837,9 +1058,13 @@ __global__ __launch_bounds__(256) void k_spmm(SysView<V, W> v, const V* C, int64
 #pragma unroll
                 for (int j = 0; j < CW; ++j)
                     if (j < cn) {
-                        AC64[row * nc + c0 + j] = acc[j];
-                        ACv[row * nc + c0 + j] = (V)acc[j];
+                        AC64[row * ldac + c0 + j] = acc[j];
+                        ACv[row * ldac + c0 + j] = (V)acc[j];
                     }
+                for (int j = 0; j < npad; ++j) {
+                    AC64[row * ldac + nc + j] = 0.0;
+                    ACv[row * ldac + nc + j] = (V)0;
+                }
             }
         }
     } else {
@@ -867,9 +1092,13 @@ __global__ __launch_bounds__(256) void k_spmm(SysView<V, W> v, const V* C, int64
 #pragma unroll
                 for (int j = 0; j < CW; ++j)
                     if (j < cn) {
-                        AC64[row * nc + c0 + j] = acc[j];
-                        ACv[row * nc + c0 + j] = (V)acc[j];
+                        AC64[row * ldac + c0 + j] = acc[j];
+                        ACv[row * ldac + c0 + j] = (V)acc[j];
                     }
+                for (int j = 0; j < npad; ++j) {
+                    AC64[row * ldac + nc + j] = 0.0;
+                    ACv[row * ldac + nc + j] = (V)0;
+                }
             }
         }
     }
@@ -878,8 +1107,8 @@ __global__ __launch_bounds__(256) void k_spmm(SysView<V, W> v, const V* C, int64
 // G = C^T AC64: 16x16 output tiles (blockIdx.y), row ranges (blockIdx.x)
 // into partials[blockIdx.x][nc*nc]; k_gram_reduce sums them in order.
 template <typename V>
-__global__ __launch_bounds__(256) void k_gram_partial(const V* C, int64_t ldc, const double* AC64, int64_t n, int nc,
-                                                      double* partials) {
+__global__ __launch_bounds__(256) void k_gram_partial(const V* C, int64_t ldc, const double* AC64, int64_t ldac,
+                                                      int64_t n, int nc, double* partials) {
     const int ntc = (nc + 15) / 16;
     const int ta = blockIdx.y / ntc, tb = blockIdx.y % ntc;
     const int a = threadIdx.x / 16, bcol = threadIdx.x % 16;
@@ -896,7 +1125,7 @@ __global__ __launch_bounds__(256) void k_gram_partial(const V* C, int64_t ldc, c
             const int64_t i = base + rr;
             const int ca = ta * 16 + cc, cb = tb * 16 + cc;
             sC[rr][cc] = (i < r1 && ca < nc) ? (double)C[(int64_t)ca * ldc + i] : 0.0;
-            sA[rr][cc] = (i < r1 && cb < nc) ? AC64[i * nc + cb] : 0.0;
+            sA[rr][cc] = (i < r1 && cb < nc) ? AC64[i * ldac + cb] : 0.0;
         }
         __syncthreads();
 #pragma unroll
@@ -1038,88 +1267,148 @@ inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b);
 
 // ------------------------------------------------------------ launchers
 
-int64_t spmv_grid(int64_t nslices, int block) {
+// ------------------------------------------------------------ geometry
+
+Geometry make_geometry(int64_t n, int64_t nslices, int block, int64_t cb3_req) {
+    Geometry g{};
+    const int64_t nb = n / block;
     const int64_t per = (block == 1) ? 4 : 1;
-    int64_t g = (nslices + per - 1) / per;
-    if (g > 2048) g = 2048;
-    return g < 1 ? 1 : g;
+    int64_t g1 = (nslices + per - 1) / per;
+    g.g1 = (int32_t)std::min<int64_t>(std::max<int64_t>(g1, 1), 2048);
+    // K3: contiguous ranges of cb3 block rows; by default one range per CU
+    int64_t cb = cb3_req > 0 ? cb3_req : (nb + 255) / 256;
+    if (cb < 64) cb = 64;
+    if ((nb + cb - 1) / cb > kMaxUpdateGrid) cb = (nb + kMaxUpdateGrid - 1) / kMaxUpdateGrid;
+    g.cb3 = cb;
+    g.g3 = (int32_t)std::max<int64_t>((nb + cb - 1) / cb, 1);
+    g.g5 = (int32_t)std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), kMaxTimedGrid);
+    g.gd = (int32_t)std::min<int64_t>(std::max<int64_t>((n + kTpb - 1) / kTpb, 1), 256);
+    g.gcc = (int32_t)std::max<int64_t>((n + 255) / 256, 1);
+    return g;
 }
 
-// Tiles are dealt round-robin; with at most kMaxGrid workgroups every
-// workgroup gets ceil(ntiles / grid) or one fewer.
-int64_t update_grid(int64_t n, int block) {
-    const int64_t TR = (block == 1) ? 1024 : 768;
-    const int64_t ntiles = (n + TR - 1) / TR;
-    const int64_t per = (ntiles + kMaxGrid - 1) / kMaxGrid;
-    const int64_t g = (ntiles + per - 1) / per;
-    return g < 1 ? 1 : g;
+int64_t partial_doubles(const Geometry& g, int nc) {
+    const int64_t c = std::max(nc, 1);
+    return std::max<int64_t>({(int64_t)g.g3 * (2 * c + 2), (int64_t)g.g1 + 8, (int64_t)g.gd * (c + 1), 1024});
 }
 
-int64_t correct_grid(int64_t n) {
-    int64_t g = (n + 255) / 256;
-    if (g > 4096) g = 4096;
-    return g < 1 ? 1 : g;
-}
-
-int64_t dot_grid(int64_t n) {
-    int64_t g = (n + kTpb - 1) / kTpb;
-    if (g > 256) g = 256;
-    return g < 1 ? 1 : g;
-}
+// ----------------------------------------------------- single-system launches
 
 template <typename V, typename W, int B>
 void launch_spmv_dot(const SysView<V, W>& v, hipStream_t stream) {
     const int threads = (B == 1) ? 256 : 192;
-    hipLaunchKernelGGL((k_spmv_dot<V, W, B>), dim3((unsigned)spmv_grid(v.nslices, B)), dim3(threads), 0, stream, v);
+    hipLaunchKernelGGL((k_spmv_dot<V, W, B>), dim3((unsigned)v.geo.g1), dim3(threads), 0, stream, v);
+}
+
+template <typename V, typename W, int B>
+void launch_update_only(const SysView<V, W>& v, int mode, hipStream_t stream) {
+    hipLaunchKernelGGL((k_update_reduce<V, W, B>), dim3((unsigned)v.geo.g3), dim3(kT3), 0, stream, v, mode);
 }
 
 template <typename V, typename W, int B>
 void launch_update_reduce(const SysView<V, W>& v, int mode, hipStream_t stream) {
-    const int threads = (B == 1) ? 1024 : 768;
-    const int np1 = (int)spmv_grid(v.nslices, B);
-    const int np3 = (int)update_grid(v.n, B);
-    hipLaunchKernelGGL((k_update_reduce<V, W, B>), dim3((unsigned)np3), dim3(threads), 0, stream, v, mode, np1);
-    hipLaunchKernelGGL((k_finalize_update<V, W>), dim3(1), dim3(1024), 0, stream, v, mode, np1, np3,
-                       (int)correct_grid(v.n));
+    hipLaunchKernelGGL((k_update_reduce<V, W, B>), dim3((unsigned)v.geo.g3), dim3(kT3), 0, stream, v, mode);
+    hipLaunchKernelGGL((k_finalize_update<V, W>), dim3(1), dim3(kTF3), 0, stream, v, mode);
 }
 
 template <typename V, typename W>
 void launch_correct_dir(const SysView<V, W>& v, int first, hipStream_t stream) {
-    hipLaunchKernelGGL((k_correct_dir<V, W>), dim3((unsigned)correct_grid(v.n)), dim3(256), 0, stream, v, first);
+    hipLaunchKernelGGL((k_correct_dir<V, W>), dim3((unsigned)v.geo.g5), dim3(256), 0, stream, v, first);
 }
 
 template <typename V, typename W, int B>
 void launch_true_resid(const SysView<V, W>& v, int final_only, hipStream_t stream) {
     const int threads = (B == 1) ? 256 : 192;
-    const int np = (int)spmv_grid(v.nslices, B);
-    hipLaunchKernelGGL((k_true_resid<V, W, B>), dim3((unsigned)np), dim3(threads), 0, stream, v, final_only);
-    hipLaunchKernelGGL((k_finalize_resid<V, W>), dim3(1), dim3(1024), 0, stream, v, final_only, np);
+    hipLaunchKernelGGL((k_true_resid<V, W, B>), dim3((unsigned)v.geo.g1), dim3(threads), 0, stream, v, final_only);
+    hipLaunchKernelGGL((k_finalize_resid<V, W>), dim3(1), dim3(1024), 0, stream, v, final_only);
 }
 
 template <typename V, typename W>
-void launch_coarse_dot(const SysView<V, W>& v, const double* src64, const W* srcV, int with_bb, uint32_t mask,
-                       hipStream_t stream) {
-    const int np = (int)dot_grid(v.n);
-    hipLaunchKernelGGL((k_coarse_dot<V, W>), dim3((unsigned)np), dim3(256), 0, stream, v, src64, srcV, with_bb, mask);
-    hipLaunchKernelGGL((k_finalize_dot<V, W>), dim3(1), dim3(1024), 0, stream, v, with_bb, mask, np);
+void launch_coarse_dot(const SysView<V, W>& v, int src_b, int with_bb, uint32_t mask, hipStream_t stream) {
+    hipLaunchKernelGGL((k_coarse_dot<V, W>), dim3((unsigned)v.geo.gd), dim3(256), 0, stream, v, src_b, mask);
+    hipLaunchKernelGGL((k_finalize_dot<V, W>), dim3(1), dim3(1024), 0, stream, v, with_bb, mask);
 }
 
 template <typename V, typename W>
 void launch_coarse_correct(const SysView<V, W>& v, int from_b, uint32_t mask, hipStream_t stream) {
-    hipLaunchKernelGGL((k_coarse_correct<V, W>), dim3(cdiv(v.n, 256)), dim3(256), 0, stream, v, from_b, mask);
+    hipLaunchKernelGGL((k_coarse_correct<V, W>), dim3((unsigned)v.geo.gcc), dim3(256), 0, stream, v, from_b, mask);
+}
+
+// ------------------------------------------------------ fused batch launches
+
+template <typename V, typename W, int B>
+void batch_spmv_dot(const SysView<V, W>* views, const BatchMaps& m, hipStream_t stream) {
+    if (m.count[BK_SPMV] <= 0) return;
+    const int threads = (B == 1) ? 256 : 192;
+    hipLaunchKernelGGL((kb_spmv_dot<V, W, B>), dim3((unsigned)m.count[BK_SPMV]), dim3(threads), 0, stream, views,
+                       m.map[BK_SPMV]);
 }
 
 template <typename V, typename W, int B>
-void launch_spmm(const SysView<V, W>& v, const V* C, int64_t ldc, int nc, double* AC64, V* ACv, hipStream_t stream) {
+void batch_update_reduce(const SysView<V, W>* views, const BatchMaps& m, int mode, hipStream_t stream) {
+    if (m.count[BK_UPD] > 0)
+        hipLaunchKernelGGL((kb_update_reduce<V, W, B>), dim3((unsigned)m.count[BK_UPD]), dim3(kT3), 0, stream, views,
+                           m.map[BK_UPD], mode);
+    if (m.count[BK_ONE] > 0)
+        hipLaunchKernelGGL((kb_finalize_update<V, W>), dim3((unsigned)m.count[BK_ONE]), dim3(kTF3), 0, stream, views,
+                           m.map[BK_ONE], mode);
+}
+
+template <typename V, typename W>
+void batch_correct_dir(const SysView<V, W>* views, const BatchMaps& m, int first, hipStream_t stream) {
+    if (m.count[BK_DIR] <= 0) return;
+    hipLaunchKernelGGL((kb_correct_dir<V, W>), dim3((unsigned)m.count[BK_DIR]), dim3(256), 0, stream, views,
+                       m.map[BK_DIR], first);
+}
+
+template <typename V, typename W, int B>
+void batch_true_resid(const SysView<V, W>* views, const BatchMaps& m, int final_only, hipStream_t stream) {
+    const int threads = (B == 1) ? 256 : 192;
+    if (m.count[BK_SPMV] > 0)
+        hipLaunchKernelGGL((kb_true_resid<V, W, B>), dim3((unsigned)m.count[BK_SPMV]), dim3(threads), 0, stream,
+                           views, m.map[BK_SPMV], final_only);
+    if (m.count[BK_ONE] > 0)
+        hipLaunchKernelGGL((kb_finalize_resid<V, W>), dim3((unsigned)m.count[BK_ONE]), dim3(1024), 0, stream, views,
+                           m.map[BK_ONE], final_only);
+}
+
+template <typename V, typename W>
+void batch_coarse_dot(const SysView<V, W>* views, const BatchMaps& m, int src_b, int with_bb, uint32_t mask,
+                      hipStream_t stream) {
+    if (m.count[BK_DOT] > 0)
+        hipLaunchKernelGGL((kb_coarse_dot<V, W>), dim3((unsigned)m.count[BK_DOT]), dim3(256), 0, stream, views,
+                           m.map[BK_DOT], src_b, mask);
+    if (m.count[BK_ONEC] > 0)
+        hipLaunchKernelGGL((kb_finalize_dot<V, W>), dim3((unsigned)m.count[BK_ONEC]), dim3(1024), 0, stream, views,
+                           m.map[BK_ONEC], with_bb, mask);
+}
+
+template <typename V, typename W>
+void batch_coarse_correct(const SysView<V, W>* views, const BatchMaps& m, int from_b, uint32_t mask,
+                          hipStream_t stream) {
+    if (m.count[BK_CC] <= 0) return;
+    hipLaunchKernelGGL((kb_coarse_correct<V, W>), dim3((unsigned)m.count[BK_CC]), dim3(256), 0, stream, views,
+                       m.map[BK_CC], from_b, mask);
+}
+
+template <typename V, typename W>
+void batch_status(const SysView<V, W>* views, int count, int32_t* out, hipStream_t stream) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL((kb_status<V, W>), dim3(cdiv(count, 256)), dim3(256), 0, stream, views, count, out);
+}
+
+template <typename V, typename W, int B>
+void launch_spmm(const SysView<V, W>& v, const V* C, int64_t ldc, int nc, int64_t ldac, double* AC64, V* ACv,
+                 hipStream_t stream) {
     if (nc <= 0) return;
     const int threads = (B == 1) ? 256 : 192;
-    dim3 grid((unsigned)spmv_grid(v.nslices, B), (unsigned)((nc + 7) / 8));
-    hipLaunchKernelGGL((k_spmm<V, W, B>), grid, dim3(threads), 0, stream, v, C, ldc, nc, AC64, ACv);
+    dim3 grid((unsigned)v.geo.g1, (unsigned)((nc + 7) / 8));
+    hipLaunchKernelGGL((k_spmm<V, W, B>), grid, dim3(threads), 0, stream, v, C, ldc, nc, ldac, AC64, ACv);
 }
 
 template <typename V>
-void launch_gram(const V* C, int64_t ldc, const double* AC64, int64_t n, int nc, double* G, double* partials,
-                 int64_t partial_cap, hipStream_t stream) {
+void launch_gram(const V* C, int64_t ldc, const double* AC64, int64_t ldac, int64_t n, int nc, double* G,
+                 double* partials, int64_t partial_cap, hipStream_t stream) {
     if (nc <= 0) return;
     const int64_t nn = (int64_t)nc * nc;
     int np = (int)(partial_cap / nn);
@@ -1127,7 +1416,7 @@ void launch_gram(const V* C, int64_t ldc, const double* AC64, int64_t n, int nc,
     if (np < 1) np = 1;
     const int ntc = (nc + 15) / 16;
     hipLaunchKernelGGL((k_gram_partial<V>), dim3((unsigned)np, (unsigned)(ntc * ntc)), dim3(256), 0, stream, C, ldc,
-                       AC64, n, nc, partials);
+                       AC64, ldac, n, nc, partials);
     hipLaunchKernelGGL(k_gram_reduce, dim3(cdiv(nn, 256)), dim3(256), 0, stream, partials, np, nc, G);
 }
 
@@ -1179,23 +1468,31 @@ void launch_v2d(const V* in, double* out, int64_t n, hipStream_t stream) {
 
 #define KRS_INST_VWB(V, W, B)                                                                                    \
     template void launch_spmv_dot<V, W, B>(const SysView<V, W>&, hipStream_t);                                    \
+    template void launch_update_only<V, W, B>(const SysView<V, W>&, int, hipStream_t);                           \
     template void launch_update_reduce<V, W, B>(const SysView<V, W>&, int, hipStream_t);                         \
     template void launch_true_resid<V, W, B>(const SysView<V, W>&, int, hipStream_t);                            \
-    template void launch_spmm<V, W, B>(const SysView<V, W>&, const V*, int64_t, int, double*, V*, hipStream_t);
+    template void launch_spmm<V, W, B>(const SysView<V, W>&, const V*, int64_t, int, int64_t, double*, V*,       \
+                                       hipStream_t);                                                              \
+    template void batch_spmv_dot<V, W, B>(const SysView<V, W>*, const BatchMaps&, hipStream_t);                  \
+    template void batch_update_reduce<V, W, B>(const SysView<V, W>*, const BatchMaps&, int, hipStream_t);        \
+    template void batch_true_resid<V, W, B>(const SysView<V, W>*, const BatchMaps&, int, hipStream_t);
 
 #define KRS_INST_VW(V, W)                                                                                         \
     template void launch_correct_dir<V, W>(const SysView<V, W>&, int, hipStream_t);                              \
-    template void launch_coarse_dot<V, W>(const SysView<V, W>&, const double*, const W*, int, uint32_t,          \
-                                          hipStream_t);                                                           \
-    template void launch_coarse_correct<V, W>(const SysView<V, W>&, int, uint32_t, hipStream_t);
+    template void launch_coarse_dot<V, W>(const SysView<V, W>&, int, int, uint32_t, hipStream_t);                \
+    template void launch_coarse_correct<V, W>(const SysView<V, W>&, int, uint32_t, hipStream_t);                 \
+    template void batch_correct_dir<V, W>(const SysView<V, W>*, const BatchMaps&, int, hipStream_t);             \
+    template void batch_coarse_dot<V, W>(const SysView<V, W>*, const BatchMaps&, int, int, uint32_t, hipStream_t); \
+    template void batch_coarse_correct<V, W>(const SysView<V, W>*, const BatchMaps&, int, uint32_t, hipStream_t); \
+    template void batch_status<V, W>(const SysView<V, W>*, int, int32_t*, hipStream_t);
 
 #define KRS_INST_VB(V, B)                                                                                        \
     template void launch_scatter_values<V, B>(const double*, const int64_t*, int64_t, double*, V*, hipStream_t); \
     template void launch_precond_setup<V, B>(const double*, const int64_t*, int64_t, V*, int32_t*, hipStream_t);
 
 #define KRS_INST_V(V)                                                                                             \
-    template void launch_gram<V>(const V*, int64_t, const double*, int64_t, int, double*, double*, int64_t,       \
-                                 hipStream_t);                                                                    \
+    template void launch_gram<V>(const V*, int64_t, const double*, int64_t, int64_t, int, double*, double*,      \
+                                 int64_t, hipStream_t);                                                           \
     template void launch_basis_combine<V>(const V*, int64_t, int, const double*, int, V*, int64_t, int64_t,       \
                                           hipStream_t);                                                           \
     template void launch_scale_columns<V>(V*, int64_t, int64_t, const double*, int, hipStream_t);                \

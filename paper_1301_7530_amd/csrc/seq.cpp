@@ -202,7 +202,8 @@ krs_status SeqImpl<V, W>::create(const krs_seq_desc& d, const double* C0, int32_
     KRS_HIP(hipHostMalloc((void**)&h_st, sizeof(DevState), hipHostMallocDefault));
     std::memset(h_st, 0, sizeof(DevState));
     // ---- initial basis C0
-    ldc = (n + 63) & ~(int64_t)63;
+    ldc = (n + 255) & ~(int64_t)255;
+    geo = make_geometry(n, nslices, B, desc.update_rows);
     nc = 0;
     if (m0 > 0) {
         if (!C0 || ldc0 < n) {
@@ -248,6 +249,8 @@ void SeqImpl<V, W>::destroy() {
         b->release(ctx);
     if (h_st) (void)hipHostFree(h_st);
     h_st = nullptr;
+    for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
     graph_release();
 }
 
@@ -321,8 +324,10 @@ SysView<V, W> SeqImpl<V, W>::view() {
     v.q = (W*)d_q.p;
     v.C = (const V*)d_C.p;
     v.AC = std::is_same<V, double>::value ? (const V*)d_AC64.p : (const V*)d_ACv.p;
+    v.nc = nc;
+    v.geo = geo;
     v.ldc = ldc;
-    v.ldac = nc > 0 ? nc : 1;
+    v.ldac = ldac;
     v.Ginv = (const double*)d_Ginv.p;
     v.mu = (double*)d_mu.p;
     v.u = (double*)d_mu.p + 1024;
@@ -374,7 +379,7 @@ template <typename V, typename W>
 void SeqImpl<V, W>::enqueue_refine(const SysView<V, W>& v) {
     k_resid(v, 0);
     if (nc > 0) {
-        launch_coarse_dot<V, W>(v, nullptr, v.r, 0, M_REFINE, stream);
+        launch_coarse_dot<V, W>(v, 0, 0, M_REFINE, stream);
         launch_coarse_correct<V, W>(v, 0, M_REFINE, stream);
     }
     k_update(v, 2);
@@ -426,8 +431,9 @@ template <typename V, typename W>
 krs_status SeqImpl<V, W>::coarse_pass(std::vector<double>& G) {
     const size_t nn = (size_t)nc * nc;
     const bool need_v = !std::is_same<V, double>::value;
-    if (!d_AC64.reserve(ctx, (size_t)n * nc * sizeof(double)) ||
-        (need_v && !d_ACv.reserve(ctx, (size_t)n * nc * sizeof(V))) || !d_G.reserve(ctx, nn * sizeof(double)) ||
+    ldac = std::max<int64_t>(32, ((int64_t)nc + 31) & ~(int64_t)31);
+    if (!d_AC64.reserve(ctx, (size_t)n * ldac * sizeof(double)) ||
+        (need_v && !d_ACv.reserve(ctx, (size_t)n * ldac * sizeof(V))) || !d_G.reserve(ctx, nn * sizeof(double)) ||
         !d_Ginv.reserve(ctx, nn * sizeof(double)) || !d_mu.reserve(ctx, 3072 * sizeof(double))) {
         set_error("device allocation failed for A C / C^T A C");
         return KRS_E_OOM;
@@ -436,9 +442,9 @@ krs_status SeqImpl<V, W>::coarse_pass(std::vector<double>& G) {
     if (!ensure_partials(gram_cap)) return KRS_E_OOM;
     SysView<V, W> v = view();
     V* ACv = std::is_same<V, double>::value ? (V*)d_AC64.p : (V*)d_ACv.p;
-    if (B == 1) launch_spmm<V, W, 1>(v, (const V*)d_C.p, ldc, nc, (double*)d_AC64.p, ACv, stream);
-    else launch_spmm<V, W, 3>(v, (const V*)d_C.p, ldc, nc, (double*)d_AC64.p, ACv, stream);
-    launch_gram<V>((const V*)d_C.p, ldc, (const double*)d_AC64.p, n, nc, (double*)d_G.p,
+    if (B == 1) launch_spmm<V, W, 1>(v, (const V*)d_C.p, ldc, nc, ldac, (double*)d_AC64.p, ACv, stream);
+    else launch_spmm<V, W, 3>(v, (const V*)d_C.p, ldc, nc, ldac, (double*)d_AC64.p, ACv, stream);
+    launch_gram<V>((const V*)d_C.p, ldc, (const double*)d_AC64.p, ldac, n, nc, (double*)d_G.p,
                    (double*)d_partials.p + kPart1, (int64_t)(d_partials.bytes / sizeof(double)) - kPart1, stream);
     KRS_CHECK_LAUNCH();
     G.resize(nn);
@@ -522,9 +528,7 @@ krs_status SeqImpl<V, W>::rebuild(int* dropped) {
 
 template <typename V, typename W>
 bool SeqImpl<V, W>::ensure_partials(int64_t extra) {
-    const int64_t need = kPart1 + std::max<int64_t>(
-        {update_grid(n, B) * (int64_t)(2 * std::max(nc, 1) + 2), spmv_grid(nslices, B) + 8,
-         dot_grid(n) * (int64_t)(std::max(nc, 1) + 1), extra, (int64_t)1024});
+    const int64_t need = kPart1 + std::max<int64_t>(partial_doubles(geo, nc), extra);
     if ((int64_t)(d_partials.bytes / sizeof(double)) >= need) return true;
     if (!d_partials.reserve(ctx, (size_t)need * sizeof(double))) {
         set_error("device allocation failed for reduction scratch");
@@ -536,7 +540,69 @@ bool SeqImpl<V, W>::ensure_partials(int64_t extra) {
 // --------------------------------------------------------------- solve
 
 template <typename V, typename W>
+int SeqImpl<V, W>::type_key() const {
+    return (std::is_same<V, double>::value ? 0 : 1) + (std::is_same<W, double>::value ? 0 : 2) + (B == 3 ? 4 : 0);
+}
+
+template <typename V, typename W>
 krs_status SeqImpl<V, W>::solve(double* x, bool device_x, krs_solve_info* info) {
+    krs_status st = begin_solve();
+    if (st != KRS_OK) return st;
+    st = iterate();
+    if (st != KRS_OK) return st;
+    return end_solve(x, device_x, info);
+}
+
+// Update-kernel tile choice: time the update kernel alone (mode 1 rewrites
+// only s = M^-1 r and the partial sums, which the initialisation that
+// follows recomputes) for several block-row ranges per workgroup and keep
+// the fastest.  Runs when the basis width changed by half since the last
+// choice, with the device state already set to RUN.
+template <typename V, typename W>
+krs_status SeqImpl<V, W>::tune_update() {
+    std::vector<int64_t> cand = {64, 128, 256, 512, 1024, 2048, (nb + 255) / 256, (nb + 511) / 512,
+                                 (nb + 127) / 128};
+    std::vector<Geometry> geos;
+    for (int64_t c : cand) {
+        const Geometry g = make_geometry(n, nslices, B, c);
+        bool seen = false;
+        for (const auto& h : geos) seen = seen || h.cb3 == g.cb3;
+        if (!seen) geos.push_back(g);
+    }
+    int64_t need = 0;
+    for (const auto& g : geos) need = std::max(need, partial_doubles(g, nc));
+    if (!ensure_partials(need)) return KRS_E_OOM;
+    for (auto& e : ev)
+        if (!e) KRS_HIP(hipEventCreate(&e));
+    SysView<V, W> v = view();
+    double best = 1e300;
+    Geometry bg = geo;
+    for (const auto& g : geos) {
+        v.geo = g;
+        if (B == 1) launch_update_only<V, W, 1>(v, 1, stream);
+        else launch_update_only<V, W, 3>(v, 1, stream);
+        KRS_HIP(hipEventRecord(ev[2], stream));
+        for (int r = 0; r < 5; ++r) {
+            if (B == 1) launch_update_only<V, W, 1>(v, 1, stream);
+            else launch_update_only<V, W, 3>(v, 1, stream);
+        }
+        KRS_HIP(hipEventRecord(ev[3], stream));
+        KRS_CHECK_LAUNCH();
+        KRS_HIP(hipEventSynchronize(ev[3]));
+        float ms = 0.f;
+        KRS_HIP(hipEventElapsedTime(&ms, ev[2], ev[3]));
+        if (ms < best) {
+            best = ms;
+            bg = g;
+        }
+    }
+    geo = bg;
+    tuned_nc = nc;
+    return KRS_OK;
+}
+
+template <typename V, typename W>
+krs_status SeqImpl<V, W>::begin_solve() {
     if (!submitted) {
         set_error("krs_seq_solve needs a submitted system");
         return KRS_E_STATE;
@@ -546,11 +612,13 @@ krs_status SeqImpl<V, W>::solve(double* x, bool device_x, krs_solve_info* info) 
         return KRS_E_INVALID;
     }
     solved = false;
-    Timer t_rb, t_it;
-    t_rb.start(stream);
+    for (auto& e : ev)
+        if (!e) KRS_HIP(hipEventCreate(&e));
+    KRS_HIP(hipEventRecord(ev[0], stream));
     int dropped = 0;
     krs_status st = rebuild(&dropped);
     if (st != KRS_OK) return st;
+    dropped_last = dropped;
     // histories
     const int max_iter = std::max(0, desc.max_iter);
     if (coef_cap < max_iter + 2) {
@@ -587,20 +655,32 @@ krs_status SeqImpl<V, W>::solve(double* x, bool device_x, krs_solve_info* info) 
     h_st->max_iter = max_iter;
     h_st->hist_cap = hist;
     h_st->nc = nc;
-    KRS_HIP(hipMemcpyAsync(d_st.p, h_st, sizeof(DevState), hipMemcpyHostToDevice, stream));
     h_st->ktime_on = timing ? 1 : 0;
-    if (timing && !d_kslots.reserve(ctx, (size_t)3 * 2 * 4096 * sizeof(unsigned long long))) return KRS_E_OOM;
+    if (timing && !d_kslots.reserve(ctx, (size_t)3 * 2 * kMaxTimedGrid * sizeof(unsigned long long))) return KRS_E_OOM;
+    KRS_HIP(hipMemcpyAsync(d_st.p, h_st, sizeof(DevState), hipMemcpyHostToDevice, stream));
     h_st->iter = 0;
+    if (desc.autotune && nc > 0 && (tuned_nc == 0 || 2 * nc > 3 * tuned_nc || 3 * nc < 2 * tuned_nc)) {
+        st = tune_update();
+        if (st != KRS_OK) return st;
+        if (!ensure_partials(0)) return KRS_E_OOM;
+    }
     SysView<V, W> v = view();
+    cur = v;
     // initialisation: mu0 = Ginv C^T b, x0 = C mu0, r0 = b - AC mu0, s0, z0, w0
-    launch_coarse_dot<V, W>(v, (const double*)d_b.p, nullptr, 1, M_RUN, stream);
+    launch_coarse_dot<V, W>(v, 1, 1, M_RUN, stream);
     launch_coarse_correct<V, W>(v, 1, M_RUN, stream);
     k_update(v, 1);
     launch_correct_dir<V, W>(v, 1, stream);
     KRS_CHECK_LAUNCH();
-    t_rb.stop(stream);
-    t_it.start(stream);
-    // iteration blocks; each block ends with the (gated) refinement step
+    KRS_HIP(hipEventRecord(ev[1], stream));
+    return KRS_OK;
+}
+
+// Iteration blocks on the sequence's own stream; each block ends with the
+// (gated) refinement step.
+template <typename V, typename W>
+krs_status SeqImpl<V, W>::iterate() {
+    const SysView<V, W> v = cur;
     const bool graphs = desc.exec_mode == 0;
     int block = graphs ? 16 : 8;
     int last_iter = -1, stuck = 0;
@@ -628,9 +708,15 @@ krs_status SeqImpl<V, W>::solve(double* x, bool device_x, krs_solve_info* info) 
         last_iter = h_st->iter;
         block = graphs ? 64 : std::min(block * 2, 64);
     }
+    return KRS_OK;
+}
+
+template <typename V, typename W>
+krs_status SeqImpl<V, W>::end_solve(double* x, bool device_x, krs_solve_info* info) {
+    const SysView<V, W> v = cur;
     k_resid(v, 1);
     KRS_CHECK_LAUNCH();
-    t_it.stop(stream);
+    KRS_HIP(hipEventRecord(ev[2], stream));
     KRS_HIP(hipMemcpyAsync(h_st, d_st.p, sizeof(DevState), hipMemcpyDeviceToHost, stream));
     if (x) {
         if (device_x) KRS_HIP(hipMemcpyAsync(x, d_x.p, n * sizeof(double), hipMemcpyDeviceToDevice, stream));
@@ -662,14 +748,18 @@ krs_status SeqImpl<V, W>::solve(double* x, bool device_x, krs_solve_info* info) 
     inf.iters = m;
     inf.n_c = nc;
     inf.refinements = h_st->refinements;
-    inf.dropped = dropped;
+    inf.dropped = dropped_last;
     inf.selected = 0;
     inf.added = 0;
+    inf.update_rows = (int32_t)geo.cb3;
     const double bb = h_st->bb > 0 ? h_st->bb : 1.0;
     inf.rel_res_true = std::sqrt(h_st->rr_true / bb);
     inf.rel_res_recursive = std::sqrt(h_st->rr / bb);
-    inf.t_rebuild_ms = t_rb.ms();
-    inf.t_iter_ms = t_it.ms();
+    float t0 = 0.f, t1 = 0.f;
+    (void)hipEventElapsedTime(&t0, ev[0], ev[1]);
+    (void)hipEventElapsedTime(&t1, ev[1], ev[2]);
+    inf.t_rebuild_ms = t0;
+    inf.t_iter_ms = t1;
     inf.t_recycle_ms = 0.0;
     inf.model_bytes = model_bytes_per_iter() * m;
     krs_status rs = KRS_OK;
@@ -875,5 +965,240 @@ krs_status SeqImpl<V, W>::basis(double* C, int64_t ld, int32_t cap, int32_t* n_c
 template struct SeqImpl<double, double>;
 template struct SeqImpl<float, double>;
 template struct SeqImpl<float, float>;
+
+// ---------------------------------------------------------------- batch
+
+namespace {
+
+template <typename V, typename W>
+struct BatchRunner {
+    krs_ctx* ctx;
+    hipStream_t stream;
+    int B;
+    std::vector<SeqImpl<V, W>*> mem;  // members iterating in the current launches
+    Buf d_views, d_maps, d_stat;
+    int32_t* h_stat = nullptr;
+    BatchMaps maps{};
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+
+    ~BatchRunner() {
+        drop_graphs();
+        d_views.release(ctx);
+        d_maps.release(ctx);
+        d_stat.release(ctx);
+        if (h_stat) (void)hipHostFree(h_stat);
+    }
+    void drop_graphs() {
+        for (int i = 0; i < 2; ++i) {
+            if (exec[i]) (void)hipGraphExecDestroy(exec[i]);
+            if (graph[i]) (void)hipGraphDestroy(graph[i]);
+            exec[i] = nullptr;
+            graph[i] = nullptr;
+        }
+    }
+    const SysView<V, W>* views() const { return (const SysView<V, W>*)d_views.p; }
+
+    // device copies of the members' views and the launch maps
+    krs_status stage() {
+        const int cnt = (int)mem.size();
+        std::vector<SysView<V, W>> hv(cnt);
+        std::vector<int2> lists[BK_COUNT];
+        for (int i = 0; i < cnt; ++i) {
+            const SysView<V, W>& v = mem[i]->cur;
+            hv[i] = v;
+            const bool basis = v.nc > 0;
+            for (int b = 0; b < v.geo.g1; ++b) lists[BK_SPMV].push_back(make_int2(i, b));
+            for (int b = 0; b < v.geo.g3; ++b) lists[BK_UPD].push_back(make_int2(i, b));
+            lists[BK_ONE].push_back(make_int2(i, 0));
+            for (int b = 0; b < v.geo.g5; ++b) lists[BK_DIR].push_back(make_int2(i, b));
+            if (basis) {
+                for (int b = 0; b < v.geo.gd; ++b) lists[BK_DOT].push_back(make_int2(i, b));
+                lists[BK_ONEC].push_back(make_int2(i, 0));
+                for (int b = 0; b < v.geo.gcc; ++b) lists[BK_CC].push_back(make_int2(i, b));
+            }
+        }
+        size_t total = 0;
+        for (auto& l : lists) total += l.size();
+        if (!d_views.reserve(ctx, std::max<size_t>(1, cnt) * sizeof(SysView<V, W>)) ||
+            !d_maps.reserve(ctx, std::max<size_t>(1, total) * sizeof(int2)) ||
+            !d_stat.reserve(ctx, std::max<size_t>(1, 2 * (size_t)cnt) * sizeof(int32_t))) {
+            set_error("device allocation failed for the batch tables");
+            return KRS_E_OOM;
+        }
+        if (!h_stat) KRS_HIP(hipHostMalloc((void**)&h_stat, 2 * mem.size() * sizeof(int32_t) + 64,
+                                           hipHostMallocDefault));
+        KRS_HIP(hipMemcpyAsync(d_views.p, hv.data(), cnt * sizeof(SysView<V, W>), hipMemcpyHostToDevice, stream));
+        size_t off = 0;
+        for (int k = 0; k < BK_COUNT; ++k) {
+            maps.map[k] = (const int2*)d_maps.p + off;
+            maps.count[k] = (int64_t)lists[k].size();
+            if (!lists[k].empty())
+                KRS_HIP(hipMemcpyAsync((int2*)d_maps.p + off, lists[k].data(), lists[k].size() * sizeof(int2),
+                                       hipMemcpyHostToDevice, stream));
+            off += lists[k].size();
+        }
+        KRS_HIP(hipStreamSynchronize(stream));
+        drop_graphs();
+        return KRS_OK;
+    }
+
+    void spmv() {
+        if (B == 1) batch_spmv_dot<V, W, 1>(views(), maps, stream);
+        else batch_spmv_dot<V, W, 3>(views(), maps, stream);
+    }
+    void update(int mode) {
+        if (B == 1) batch_update_reduce<V, W, 1>(views(), maps, mode, stream);
+        else batch_update_reduce<V, W, 3>(views(), maps, mode, stream);
+    }
+    void resid() {
+        if (B == 1) batch_true_resid<V, W, 1>(views(), maps, 0, stream);
+        else batch_true_resid<V, W, 3>(views(), maps, 0, stream);
+    }
+    // the same kernel sequence as a single system's iteration block
+    void enqueue(int block) {
+        for (int i = 0; i < block; ++i) {
+            spmv();
+            update(0);
+            batch_correct_dir<V, W>(views(), maps, 0, stream);
+        }
+        resid();
+        batch_coarse_dot<V, W>(views(), maps, 0, 0, M_REFINE, stream);
+        batch_coarse_correct<V, W>(views(), maps, 0, M_REFINE, stream);
+        update(2);
+        batch_correct_dir<V, W>(views(), maps, 2, stream);
+        batch_status<V, W>(views(), (int)mem.size(), (int32_t*)d_stat.p, stream);
+    }
+
+    krs_status launch(int slot, int block, bool graphs) {
+        if (!graphs) {
+            enqueue(block);
+            KRS_CHECK_LAUNCH();
+            return KRS_OK;
+        }
+        if (!exec[slot]) {
+            KRS_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+            enqueue(block);
+            hipError_t e = hipStreamEndCapture(stream, &graph[slot]);
+            if (e != hipSuccess) {
+                set_error(std::string("batch graph capture failed: ") + hipGetErrorString(e));
+                return KRS_E_DEVICE;
+            }
+            KRS_HIP(hipGraphInstantiate(&exec[slot], graph[slot], nullptr, nullptr, 0));
+        }
+        KRS_HIP(hipGraphLaunch(exec[slot], stream));
+        return KRS_OK;
+    }
+
+    // Iterate until every member has finished.  Members that finished
+    // leave the launches once the active set shrank by a quarter.
+    krs_status run(bool graphs) {
+        krs_status st = stage();
+        if (st != KRS_OK) return st;
+        // same block schedule as a single solve (so refinements fall on the same iterations)
+        int block = graphs ? 16 : 8;
+        std::vector<int> last(mem.size(), -1);
+        int stuck = 0;
+        while (!mem.empty()) {
+            st = launch(block == 16 ? 0 : 1, block, graphs);
+            if (st != KRS_OK) return st;
+            const int cnt = (int)mem.size();
+            KRS_HIP(hipMemcpyAsync(h_stat, d_stat.p, 2 * cnt * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+            KRS_HIP(hipStreamSynchronize(stream));
+            std::vector<SeqImpl<V, W>*> keep;
+            std::vector<int> keep_last;
+            bool progress = false;
+            for (int i = 0; i < cnt; ++i) {
+                const int s = h_stat[2 * i], it = h_stat[2 * i + 1];
+                if (it != last[i]) progress = true;
+                if (s == ST_DONE || s == ST_BREAKDOWN || s == ST_MAXIT) continue;
+                keep.push_back(mem[i]);
+                keep_last.push_back(it);
+            }
+            if (!progress && ++stuck > 4) {
+                set_error("batch made no progress");
+                return KRS_E_DEVICE;
+            }
+            if (progress) stuck = 0;
+            if (keep.empty()) break;
+            if (4 * keep.size() <= 3 * mem.size()) {
+                mem = keep;
+                last = keep_last;
+                st = stage();
+                if (st != KRS_OK) return st;
+            } else {
+                for (int i = 0; i < cnt; ++i) last[i] = h_stat[2 * i + 1];
+            }
+            block = graphs ? 64 : std::min(block * 2, 64);
+        }
+        return KRS_OK;
+    }
+};
+
+template <typename V, typename W>
+krs_status batch_group(krs_ctx* ctx, std::vector<SeqImpl<V, W>*>& seqs, std::vector<int>& idx,
+                       double* const* x, bool device_x, krs_solve_info* info, std::vector<krs_status>& out) {
+    BatchRunner<V, W> r{};
+    r.ctx = ctx;
+    r.stream = ctx->stream;
+    r.B = seqs.empty() ? 1 : seqs[0]->B;
+    std::vector<SeqImpl<V, W>*> begun;
+    std::vector<int> begun_idx;
+    for (size_t i = 0; i < seqs.size(); ++i) {
+        const krs_status st = seqs[i]->begin_solve();
+        out[idx[i]] = st;
+        if (st == KRS_OK) {
+            begun.push_back(seqs[i]);
+            begun_idx.push_back(idx[i]);
+        }
+    }
+    r.mem = begun;
+    const bool graphs = std::all_of(begun.begin(), begun.end(), [](SeqImpl<V, W>* s) { return s->desc.exec_mode == 0; });
+    krs_status st = begun.empty() ? KRS_OK : r.run(graphs);
+    if (st != KRS_OK) {
+        for (int i : begun_idx) out[i] = st;
+        return st;
+    }
+    for (size_t i = 0; i < begun.size(); ++i) {
+        const int k = begun_idx[i];
+        out[k] = begun[i]->end_solve(x ? x[k] : nullptr, device_x, info ? &info[k] : nullptr);
+    }
+    return KRS_OK;
+}
+
+}  // namespace
+
+krs_status batch_solve(krs_ctx* ctx, SeqBase* const* seqs, int count, double* const* x, bool device_x,
+                       krs_solve_info* info) {
+    std::vector<krs_status> out(count, KRS_OK);
+    // group by storage / vector precision and block size
+    std::vector<SeqImpl<double, double>*> g0[2];
+    std::vector<SeqImpl<float, double>*> g1[2];
+    std::vector<SeqImpl<float, float>*> g2[2];
+    std::vector<int> i0[2], i1[2], i2[2];
+    for (int i = 0; i < count; ++i) {
+        SeqBase* s = seqs[i];
+        if (auto* a = dynamic_cast<SeqImpl<double, double>*>(s)) {
+            g0[a->B == 3].push_back(a);
+            i0[a->B == 3].push_back(i);
+        } else if (auto* b = dynamic_cast<SeqImpl<float, double>*>(s)) {
+            g1[b->B == 3].push_back(b);
+            i1[b->B == 3].push_back(i);
+        } else if (auto* c = dynamic_cast<SeqImpl<float, float>*>(s)) {
+            g2[c->B == 3].push_back(c);
+            i2[c->B == 3].push_back(i);
+        }
+    }
+    for (int b = 0; b < 2; ++b) {
+        krs_status st;
+        if (!g0[b].empty() && (st = batch_group(ctx, g0[b], i0[b], x, device_x, info, out)) == KRS_E_DEVICE) return st;
+        if (!g1[b].empty() && (st = batch_group(ctx, g1[b], i1[b], x, device_x, info, out)) == KRS_E_DEVICE) return st;
+        if (!g2[b].empty() && (st = batch_group(ctx, g2[b], i2[b], x, device_x, info, out)) == KRS_E_DEVICE) return st;
+    }
+    krs_status worst = KRS_OK;
+    for (krs_status st : out)
+        if (st != KRS_OK && (worst == KRS_OK || worst == KRS_E_MAXIT)) worst = st;
+    return worst;
+}
 
 }  // namespace krs

@@ -41,6 +41,11 @@ struct SeqBase {
     virtual krs_status create(const krs_seq_desc& d, const double* C0, int32_t m0, int64_t ldc0) = 0;
     virtual krs_status submit(const double* values, const double* b, bool device) = 0;
     virtual krs_status solve(double* x, bool device_x, krs_solve_info* info) = 0;
+    // solve() = begin_solve() + iterate() + end_solve(); a batch runs the
+    // iterations of several begun systems in fused launches instead
+    virtual krs_status begin_solve() = 0;
+    virtual krs_status end_solve(double* x, bool device_x, krs_solve_info* info) = 0;
+    virtual int type_key() const = 0;
     virtual krs_status recycle(int32_t* n_added) = 0;
     virtual krs_status basis(double* C, int64_t ld, int32_t cap, int32_t* n_c) = 0;
     virtual void destroy() = 0;
@@ -65,6 +70,7 @@ struct SeqImpl : SeqBase {
     int B = 1;
     int64_t n = 0, nb = 0, nnzb = 0, nslices = 0, nslots = 0;
     int64_t ldc = 0;
+    int64_t ldac = 32;
     int nc_cap = 0, nc0 = 0;
     int coef_cap = 0;
     int trks_slots = 0;
@@ -72,6 +78,11 @@ struct SeqImpl : SeqBase {
     Buf d_col, d_slice_ptr, d_map, d_diag, d_val64, d_valV, d_minv, d_bad, d_in, d_b, d_x, d_r, d_s, d_w, d_q;
     Buf d_C, d_C0, d_AC64, d_ACv, d_G, d_Ginv, d_mu, d_Z, d_coef, d_partials, d_st, d_F, d_tmp, d_Ctmp, d_kslots;
     DevState* h_st = nullptr;
+    Geometry geo{};
+    int tuned_nc = 0;
+    int dropped_last = 0;
+    SysView<V, W> cur{};          // view of the solve in progress
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // rebuild / iteration timers
     // captured iteration blocks (16 and 64 iterations + refinement step)
     struct GraphSlot {
         hipGraph_t graph = nullptr;
@@ -85,6 +96,11 @@ struct SeqImpl : SeqBase {
     krs_status create(const krs_seq_desc& d, const double* C0, int32_t m0, int64_t ldc0) override;
     krs_status submit(const double* values, const double* b, bool device) override;
     krs_status solve(double* x, bool device_x, krs_solve_info* info) override;
+    krs_status begin_solve() override;
+    krs_status iterate();
+    krs_status end_solve(double* x, bool device_x, krs_solve_info* info) override;
+    int type_key() const override;
+    krs_status tune_update();
     krs_status recycle(int32_t* n_added) override;
     krs_status basis(double* C, int64_t ld, int32_t cap, int32_t* n_c) override;
     void destroy() override;
@@ -101,6 +117,10 @@ struct SeqImpl : SeqBase {
     void enqueue_refine(const SysView<V, W>& v);
     int64_t model_bytes_per_iter() const;
 };
+
+// Solve the submitted systems of several sequences in fused launches.
+krs_status batch_solve(krs_ctx* ctx, SeqBase* const* seqs, int count, double* const* x, bool device_x,
+                       krs_solve_info* info);
 
 }  // namespace krs
 

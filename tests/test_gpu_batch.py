@@ -1,0 +1,176 @@
+"""GPU: fused multi-system solves (krs_batch_solve) through the C ABI.
+
+A batch runs the iterations of several sequences in shared launches; each
+member keeps the launch geometry of its own solve, so its results must be
+bitwise identical to solving it alone.  Iteration counts are also checked
+against the FP64 oracle (+-2) and the true residual against 1e-8.
+"""
+import numpy as np
+import pytest
+
+import gen
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+# ragged sizes: several slices and workgroups, tails that are not multiples
+# of 64 rows, one system smaller than a slice
+SHAPES = [(13, 11, 7), (20, 20, 20), (9, 9, 9), (3, 4, 5), (17, 15, 12)]
+
+
+def _K():
+    import paper_1301_7530_amd as K
+
+    return K
+
+
+def _relres(csr, x):
+    rp, ci, v, b = csr
+    return np.linalg.norm(b - O.spmv(rp, ci, v, x)) / np.linalg.norm(b)
+
+
+def _sequences(n_systems):
+    return [gen.DiffusionSequence(sh, n_systems, (gen.SEED_ROOT, 93, i)) for i, sh in enumerate(SHAPES)]
+
+
+def _alone(ctx, seqs, n_systems, **kw):
+    K = _K()
+    out = []
+    for sq in seqs:
+        s = K.sequence_for(ctx, sq, **kw)
+        try:
+            recs = []
+            for k in range(n_systems):
+                s.submit(*sq.system(k))
+                x, info = s.solve()
+                info["x"] = x
+                info["coef"] = s.coeffs()
+                s.recycle()
+                info["C"] = s.basis()
+                recs.append(info)
+        finally:
+            s.close()
+        out.append(recs)
+    return out
+
+
+def _batched(ctx, seqs, n_systems, **kw):
+    K = _K()
+    hs = [K.sequence_for(ctx, sq, **kw) for sq in seqs]
+    out = [[] for _ in seqs]
+    try:
+        for k in range(n_systems):
+            for h, sq in zip(hs, seqs):
+                h.submit(*sq.system(k))
+            xs, infos = ctx.batch_solve(hs)
+            for i, h in enumerate(hs):
+                infos[i]["x"] = xs[i]
+                infos[i]["coef"] = h.coeffs()
+                h.recycle()
+                infos[i]["C"] = h.basis()
+                out[i].append(infos[i])
+    finally:
+        for h in hs:
+            h.close()
+    return out
+
+
+@pytest.mark.parametrize("precision,reuse", [("fp64", "total"), ("mixed", "selective"), ("fp64", "none")])
+def test_batch_equals_alone_bitwise(gpu, precision, reuse):
+    n_sys = 3
+    seqs = _sequences(n_sys)
+    kw = dict(precision=precision, reuse=reuse, tol=1e-8, max_iter=3000, max_basis=40, ritz_eps=1e-8,
+              history_cap=400)
+    print(f"batch vs alone: {precision} {reuse} shapes {SHAPES}", flush=True)
+    a = _alone(gpu, seqs, n_sys, **kw)
+    b = _batched(gpu, seqs, n_sys, **kw)
+    for i in range(len(seqs)):
+        for k in range(n_sys):
+            ra, rb = a[i][k], b[i][k]
+            assert ra["status"] == rb["status"] == 0, (i, k, ra["status"], rb["status"])
+            assert ra["iters"] == rb["iters"], (i, k)
+            assert ra["n_c"] == rb["n_c"]
+            assert np.array_equal(ra["x"], rb["x"]), (i, k)
+            for ca, cb in zip(ra["coef"], rb["coef"]):
+                assert np.array_equal(ca, cb)
+            assert np.array_equal(ra["C"], rb["C"])
+            assert rb["rel_res_true"] <= 1e-8
+            assert _relres(seqs[i].csr(k), rb["x"]) <= 1e-8
+
+
+def test_batch_matches_oracle_fp64(gpu):
+    n_sys = 3
+    seqs = _sequences(n_sys)
+    b = _batched(gpu, seqs, n_sys, precision="fp64", reuse="total", tol=1e-8, max_iter=3000)
+    for i, sq in enumerate(seqs):
+        recs, _ = O.solve_sequence(sq, n_sys, reuse="trks", tol=1e-8, max_iter=3000)
+        for k in range(n_sys):
+            assert abs(b[i][k]["iters"] - recs[k]["m"]) <= 2, (i, k, b[i][k]["iters"], recs[k]["m"])
+            assert b[i][k]["n_c"] == recs[k]["nc"]
+
+
+def test_batch_mixed_groups_and_empty(gpu):
+    """Members of different precisions run as separate fused groups."""
+    K = _K()
+    seqs = _sequences(1)
+    hs = []
+    try:
+        for i, sq in enumerate(seqs):
+            hs.append(K.sequence_for(gpu, sq, precision=("fp64", "mixed")[i % 2], reuse="none", tol=1e-8,
+                                     max_iter=3000))
+            hs[-1].submit(*sq.system(0))
+        xs, infos = gpu.batch_solve(hs)
+        for i, sq in enumerate(seqs):
+            assert infos[i]["status"] == 0
+            assert infos[i]["rel_res_true"] <= 1e-8
+            assert _relres(sq.csr(0), xs[i]) <= 1e-8
+        xs, infos = gpu.batch_solve([])
+        assert xs == [] and infos == []
+    finally:
+        for h in hs:
+            h.close()
+
+
+def test_batch_device_outputs(gpu):
+    import torch
+
+    K = _K()
+    seqs = _sequences(1)[:3]
+    hs = [K.sequence_for(gpu, sq, precision="fp64", reuse="none", tol=1e-8, max_iter=3000) for sq in seqs]
+    try:
+        for h, sq in zip(hs, seqs):
+            h.submit(*sq.system(0))
+        xs = [torch.zeros(sq.n, dtype=torch.float64, device="cuda") for sq in seqs]
+        _, infos = gpu.batch_solve(hs, xs=xs)
+        for i, sq in enumerate(seqs):
+            assert infos[i]["status"] == 0
+            assert _relres(sq.csr(0), xs[i].cpu().numpy()) <= 1e-8
+    finally:
+        for h in hs:
+            h.close()
+
+
+def test_update_tile_choices_agree(gpu):
+    """Explicit update tiles and the autotuner converge to the same solution
+    within the solve tolerance; each choice is reported."""
+    K = _K()
+    E = 6
+    seq = gen.ElasticitySequence(E, 3, (gen.SEED_ROOT, 94, 0))
+    sols = []
+    for rows, tune in [(0, False), (64, False), (200, False), (0, True)]:
+        s = K.sequence_for(gpu, seq, precision="fp64", reuse="selective", tol=1e-8, max_iter=4000, ritz_eps=1e-8,
+                           max_basis=30, update_rows=rows, autotune=tune)
+        try:
+            for k in range(3):
+                s.submit(*seq.system(k))
+                x, info = s.solve()
+                s.recycle()
+            assert info["status"] == 0 and info["rel_res_true"] <= 1e-8
+            if rows:
+                assert info["update_rows"] == max(rows, 64)
+            assert info["update_rows"] >= 64
+            sols.append(x)
+        finally:
+            s.close()
+    for x in sols[1:]:
+        assert np.linalg.norm(x - sols[0]) / np.linalg.norm(sols[0]) <= 1e-5
