@@ -202,6 +202,57 @@ krs_status krs_batch_solve(krs_ctx* ctx, krs_seq* const* seqs, int32_t count, do
 krs_status krs_batch_solve_device(krs_ctx* ctx, krs_seq* const* seqs, int32_t count, double* const* d_x,
                                   krs_solve_info* info);
 
+/* ------------------------------------------------------------- serving */
+/* A server owns a worker thread that serves systems of many sequences of
+ * one context with continuous batching: requests (one system each) are
+ * admitted between blocks of iterations while fewer than max_slots are in
+ * flight and their solve-time working sets (Krylov history, A C, staging)
+ * fit in hbm_budget bytes (0 = no limit); admitted systems join the fused
+ * launches of their type immediately, finished ones leave them, have their
+ * solution copied to x_out and their basis recycled (TRKS / SRKS), and
+ * release their working set; the basis itself stays resident with the
+ * sequence.  Requests of one sequence are served in order, one at a time
+ * (system k+1 needs the basis from system k); requests of different
+ * sequences overlap on the device.  Each result equals the one of
+ * krs_seq_submit + krs_seq_solve + krs_seq_recycle on the same sequence.
+ * While a server exists its worker owns the context's stream: the caller
+ * must not use that context's sequences directly, and a sequence with
+ * requests in flight cannot be destroyed (KRS_E_STATE). */
+typedef struct krs_server krs_server;
+
+typedef struct {
+    uint64_t tag;          /* as given to krs_server_enqueue */
+    krs_seq* seq;
+    int32_t status;        /* krs_status of the solve (or of the admission) */
+    int32_t batch_size;    /* members of the fused launches when it finished */
+    double latency_ms;     /* completion - enqueue */
+    double queue_ms;       /* admission - enqueue */
+    krs_solve_info info;   /* info.added: columns appended by the recycle */
+    char message[128];     /* error text when status != KRS_OK */
+} krs_completion;
+
+typedef struct {
+    int64_t enqueued, completed, failed, queued;
+    int64_t blocks;        /* blocks of iterations launched */
+    double mean_batch;     /* members per block, averaged over blocks */
+    double solves_per_s;   /* completed / (last completion - first enqueue) */
+    double p50_ms, p99_ms, mean_ms;  /* request latency (completion - enqueue) */
+    int64_t peak_bytes;    /* largest sum of admitted working sets */
+} krs_server_report;
+
+krs_status krs_server_create(krs_ctx* ctx, size_t hbm_budget, int32_t max_slots, krs_server** out);
+/* Queue one system of `seq`: values (host, nnzb*block^2 doubles) and b
+ * (host, n doubles) are copied; x_out (host, n doubles, or NULL) is written
+ * before the completion is posted.  KRS_E_BUSY when the queue is full. */
+krs_status krs_server_enqueue(krs_server* s, krs_seq* seq, const double* values, const double* b, double* x_out,
+                              uint64_t tag);
+/* Up to cap completions in completion order; waits up to timeout_ms
+ * (0: no wait, negative: until one is available or the server stopped). */
+krs_status krs_server_poll(krs_server* s, krs_completion* out, int32_t cap, int32_t* count, int32_t timeout_ms);
+krs_status krs_server_stats(krs_server* s, krs_server_report* out);
+/* Serves every queued request, then stops the worker and frees the server. */
+krs_status krs_server_destroy(krs_server* s);
+
 /* ------------------------------------------------ host-side Ritz logic */
 /* Pure host computations exposed for testing the library's selection
  * logic; no device is touched.

@@ -88,6 +88,35 @@ class SolveInfo(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class Completion(ctypes.Structure):
+    _fields_ = [
+        ("tag", ctypes.c_uint64),
+        ("seq", ctypes.c_void_p),
+        ("status", ctypes.c_int32),
+        ("batch_size", ctypes.c_int32),
+        ("latency_ms", ctypes.c_double),
+        ("queue_ms", ctypes.c_double),
+        ("info", SolveInfo),
+        ("message", ctypes.c_char * 128),
+    ]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [
+        ("enqueued", ctypes.c_int64),
+        ("completed", ctypes.c_int64),
+        ("failed", ctypes.c_int64),
+        ("queued", ctypes.c_int64),
+        ("blocks", ctypes.c_int64),
+        ("mean_batch", ctypes.c_double),
+        ("solves_per_s", ctypes.c_double),
+        ("p50_ms", ctypes.c_double),
+        ("p99_ms", ctypes.c_double),
+        ("mean_ms", ctypes.c_double),
+        ("peak_bytes", ctypes.c_int64),
+    ]
+
+
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 _FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
 
@@ -122,6 +151,11 @@ SIGNATURES = [
     ("krs_seq_destroy", _S, [_P]),
     ("krs_batch_solve", _S, [_P, _PP, ctypes.c_int32, ctypes.POINTER(_D), ctypes.POINTER(SolveInfo)]),
     ("krs_batch_solve_device", _S, [_P, _PP, ctypes.c_int32, _PP, ctypes.POINTER(SolveInfo)]),
+    ("krs_server_create", _S, [_P, ctypes.c_size_t, ctypes.c_int32, _PP]),
+    ("krs_server_enqueue", _S, [_P, _P, _D, _D, _D, ctypes.c_uint64]),
+    ("krs_server_poll", _S, [_P, ctypes.POINTER(Completion), ctypes.c_int32, _I32, ctypes.c_int32]),
+    ("krs_server_stats", _S, [_P, ctypes.POINTER(ServerStats)]),
+    ("krs_server_destroy", _S, [_P]),
     ("krs_ritz_select", _S, [_D, _D, ctypes.c_int32, ctypes.c_double, _D, _D, _U8]),
     ("krs_coarse_factor", _S, [ctypes.c_int32, _D, ctypes.c_double, _D, _U8, _I32]),
 ]
@@ -404,10 +438,73 @@ class Sequence:
                 self.ctx._seqs.remove(self)
 
 
+class Server:
+    """Continuous-batching server over the sequences of one context.
+
+    ``hbm_budget``: bytes of solve-time working sets admitted at once (0: no
+    limit); ``max_slots``: systems in flight at once.  While it exists the
+    server's worker owns the context's stream."""
+
+    def __init__(self, ctx: Context, hbm_budget=0, max_slots=64):
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        _check(_lib.krs_server_create(ctx.handle, int(hbm_budget), int(max_slots), ctypes.byref(h)),
+               "krs_server_create")
+        self.handle = h
+        self._pending = {}  # tag -> (sequence, x, values, b) kept alive until completion
+
+    def enqueue(self, seq, values, b, tag):
+        """Queue one system of ``seq`` (host arrays, copied); the solution
+        arrives with the completion of ``tag``."""
+        v = np.ascontiguousarray(values, dtype=np.float64)
+        bb = np.ascontiguousarray(b, dtype=np.float64)
+        if v.size != seq.nnzb * seq.block * seq.block or bb.size != seq.n:
+            raise ValueError("values / b have the wrong size")
+        x = np.zeros(seq.n)
+        if int(tag) in self._pending:
+            raise ValueError(f"tag {tag} is already in flight")
+        self._pending[int(tag)] = (seq, x)  # before the call: the completion may arrive at once
+        st = _lib.krs_server_enqueue(self.handle, seq.handle, _dptr(v), _dptr(bb), _dptr(x), int(tag))
+        if st != KRS_OK:
+            self._pending.pop(int(tag), None)
+        _check(st, "krs_server_enqueue")
+
+    def poll(self, timeout_ms=-1, cap=256):
+        """Completed requests: list of dicts with tag, status, latency_ms,
+        queue_ms, batch_size, info and x."""
+        buf = (Completion * cap)()
+        cnt = ctypes.c_int32(0)
+        _check(_lib.krs_server_poll(self.handle, buf, cap, ctypes.byref(cnt), int(timeout_ms)), "krs_server_poll")
+        out = []
+        for i in range(cnt.value):
+            c = buf[i]
+            seq, x = self._pending.pop(int(c.tag))
+            out.append(dict(tag=int(c.tag), status=int(c.status), latency_ms=c.latency_ms, queue_ms=c.queue_ms,
+                            batch_size=int(c.batch_size), info=c.info.as_dict(), x=x, seq=seq,
+                            message=c.message.decode(errors="replace")))
+        return out
+
+    def stats(self):
+        st = ServerStats()
+        _check(_lib.krs_server_stats(self.handle, ctypes.byref(st)), "krs_server_stats")
+        return {name: getattr(st, name) for name, _ in st._fields_}
+
+    def close(self):
+        if self.handle:
+            _check(_lib.krs_server_destroy(self.handle), "krs_server_destroy")
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
 def sequence_for(ctx, seq, **kw):
     """Sequence handle for a ``gen`` workload object (pattern taken from it)."""
     return Sequence(ctx, seq.row_ptr, seq.col_idx, seq.n, block=getattr(seq, "block", 1), **kw)
 
 
-__all__ = ["Context", "Sequence", "KrsError", "ritz_select", "coarse_factor", "sequence_for", "version", "lib",
+__all__ = ["Context", "Sequence", "Server", "KrsError", "ritz_select", "coarse_factor", "sequence_for", "version", "lib",
            "SIGNATURES", "LIB_PATH"]

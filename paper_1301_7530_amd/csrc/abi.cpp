@@ -96,8 +96,8 @@ krs_status krs_ctx_create(int device, void* hip_stream, const krs_allocator* a, 
 krs_status krs_ctx_destroy(krs_ctx* ctx) {
     KRS_GUARD_BEGIN
     if (!ctx) return KRS_OK;
-    if (ctx->live_seqs > 0) {
-        set_error("context still has live sequences");
+    if (ctx->live_seqs > 0 || ctx->live_servers > 0) {
+        set_error("context still has live sequences or a server");
         return KRS_E_STATE;
     }
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
@@ -291,6 +291,10 @@ krs_status krs_seq_kernel_time(krs_seq* s, int32_t kernel, int64_t* launches, do
 krs_status krs_seq_destroy(krs_seq* s) {
     KRS_GUARD_BEGIN
     if (!s) return KRS_OK;
+    if (s->impl->in_server.load() > 0) {
+        set_error("the sequence has server requests in flight");
+        return KRS_E_STATE;
+    }
     krs_ctx* ctx = s->impl->ctx;
     (void)hipStreamSynchronize(ctx->stream);
     s->impl->destroy();

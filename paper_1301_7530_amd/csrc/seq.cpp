@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <thread>
 
 namespace krs {
@@ -178,7 +179,6 @@ krs_status SeqImpl<V, W>::create(const krs_seq_desc& d, const double* C0, int32_
     if (!std::is_same<V, double>::value) ok = ok && d_valV.reserve(ctx, (size_t)nslots * kSlice * vb * sizeof(V));
     ok = ok && d_minv.reserve(ctx, (size_t)nb * vb * sizeof(V));
     ok = ok && d_bad.reserve(ctx, 64);
-    ok = ok && d_in.reserve(ctx, (size_t)nnzb * vb * sizeof(double));
     ok = ok && d_b.reserve(ctx, n * sizeof(double));
     ok = ok && d_x.reserve(ctx, n * sizeof(double));
     ok = ok && d_r.reserve(ctx, n * sizeof(W));
@@ -267,6 +267,10 @@ krs_status SeqImpl<V, W>::submit(const double* values, const double* b, bool dev
     const size_t vb = (size_t)B * B;
     const double* vin = values;
     if (!device) {
+        if (!d_in.reserve(ctx, (size_t)nnzb * vb * sizeof(double))) {
+            set_error("device allocation failed for the value staging buffer");
+            return KRS_E_OOM;
+        }
         KRS_HIP(hipMemcpyAsync(d_in.p, values, (size_t)nnzb * vb * sizeof(double), hipMemcpyHostToDevice, stream));
         KRS_HIP(hipMemcpyAsync(d_b.p, b, n * sizeof(double), hipMemcpyHostToDevice, stream));
         vin = (const double*)d_in.p;
@@ -538,6 +542,29 @@ bool SeqImpl<V, W>::ensure_partials(int64_t extra) {
 }
 
 // --------------------------------------------------------------- solve
+
+template <typename V, typename W>
+int64_t SeqImpl<V, W>::working_bytes() const {
+    const int max_iter = std::max(0, desc.max_iter);
+    int64_t hist = 0;
+    if (desc.reuse == KRS_REUSE_SELECTIVE)
+        hist = desc.history_cap > 0 ? std::min(desc.history_cap, max_iter + 1) : max_iter + 1;
+    const int ncmax = std::max(nc, desc.max_basis > 0 ? desc.max_basis : nc);
+    const int64_t ldm = std::max<int64_t>(32, ((int64_t)ncmax + 31) & ~(int64_t)31);
+    const int64_t vsz = std::is_same<V, double>::value ? 0 : (int64_t)sizeof(V);
+    int64_t b = ldc * hist * (int64_t)sizeof(V);                       // Z history
+    b += n * ldm * (8 + vsz);                                          // A C (double and V)
+    b += ldc * (int64_t)ncmax * (int64_t)sizeof(V);                    // basis change staging
+    b += nnzb * B * B * 8;                                             // value staging
+    b += (kPart1 + partial_doubles(make_geometry(n, nslices, B, desc.update_rows), ncmax)) * 8;
+    return b;
+}
+
+template <typename V, typename W>
+void SeqImpl<V, W>::trim() {
+    for (Buf* b : {&d_Z, &d_AC64, &d_ACv, &d_partials, &d_F, &d_Ctmp, &d_tmp, &d_in, &d_kslots}) b->release(ctx);
+    graph_release();
+}
 
 template <typename V, typename W>
 int SeqImpl<V, W>::type_key() const {
@@ -970,19 +997,23 @@ template struct SeqImpl<float, float>;
 
 namespace {
 
+// Fused launches over a changing set of begun solves of one (V, W, B) type.
 template <typename V, typename W>
-struct BatchRunner {
+struct BatchRunner : RunnerBase {
     krs_ctx* ctx;
     hipStream_t stream;
     int B;
-    std::vector<SeqImpl<V, W>*> mem;  // members iterating in the current launches
+    std::vector<SeqImpl<V, W>*> mem;
     Buf d_views, d_maps, d_stat;
     int32_t* h_stat = nullptr;
+    size_t h_stat_cap = 0;
     BatchMaps maps{};
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t exec[2] = {nullptr, nullptr};
+    int gblock[2] = {0, 0};
 
-    ~BatchRunner() {
+    BatchRunner(krs_ctx* c, int b) : ctx(c), stream(c->stream), B(b) {}
+    ~BatchRunner() override {
         drop_graphs();
         d_views.release(ctx);
         d_maps.release(ctx);
@@ -995,13 +1026,19 @@ struct BatchRunner {
             if (graph[i]) (void)hipGraphDestroy(graph[i]);
             exec[i] = nullptr;
             graph[i] = nullptr;
+            gblock[i] = 0;
         }
     }
+    size_t size() const override { return mem.size(); }
     const SysView<V, W>* views() const { return (const SysView<V, W>*)d_views.p; }
 
     // device copies of the members' views and the launch maps
-    krs_status stage() {
+    krs_status set_members(const std::vector<SeqBase*>& members) override {
+        mem.clear();
+        for (SeqBase* b : members) mem.push_back(static_cast<SeqImpl<V, W>*>(b));
+        drop_graphs();
         const int cnt = (int)mem.size();
+        if (cnt == 0) return KRS_OK;
         std::vector<SysView<V, W>> hv(cnt);
         std::vector<int2> lists[BK_COUNT];
         for (int i = 0; i < cnt; ++i) {
@@ -1020,14 +1057,17 @@ struct BatchRunner {
         }
         size_t total = 0;
         for (auto& l : lists) total += l.size();
-        if (!d_views.reserve(ctx, std::max<size_t>(1, cnt) * sizeof(SysView<V, W>)) ||
-            !d_maps.reserve(ctx, std::max<size_t>(1, total) * sizeof(int2)) ||
-            !d_stat.reserve(ctx, std::max<size_t>(1, 2 * (size_t)cnt) * sizeof(int32_t))) {
+        if (!d_views.reserve(ctx, cnt * sizeof(SysView<V, W>)) || !d_maps.reserve(ctx, total * sizeof(int2)) ||
+            !d_stat.reserve(ctx, 2 * (size_t)cnt * sizeof(int32_t))) {
             set_error("device allocation failed for the batch tables");
             return KRS_E_OOM;
         }
-        if (!h_stat) KRS_HIP(hipHostMalloc((void**)&h_stat, 2 * mem.size() * sizeof(int32_t) + 64,
-                                           hipHostMallocDefault));
+        if (h_stat_cap < 2 * (size_t)cnt) {
+            if (h_stat) (void)hipHostFree(h_stat);
+            h_stat = nullptr;
+            h_stat_cap = 2 * (size_t)cnt;
+            KRS_HIP(hipHostMalloc((void**)&h_stat, h_stat_cap * sizeof(int32_t), hipHostMallocDefault));
+        }
         KRS_HIP(hipMemcpyAsync(d_views.p, hv.data(), cnt * sizeof(SysView<V, W>), hipMemcpyHostToDevice, stream));
         size_t off = 0;
         for (int k = 0; k < BK_COUNT; ++k) {
@@ -1039,7 +1079,6 @@ struct BatchRunner {
             off += lists[k].size();
         }
         KRS_HIP(hipStreamSynchronize(stream));
-        drop_graphs();
         return KRS_OK;
     }
 
@@ -1070,130 +1109,118 @@ struct BatchRunner {
         batch_status<V, W>(views(), (int)mem.size(), (int32_t*)d_stat.p, stream);
     }
 
-    krs_status launch(int slot, int block, bool graphs) {
+    krs_status launch(int block, bool graphs) override {
+        if (mem.empty()) return KRS_OK;
         if (!graphs) {
             enqueue(block);
             KRS_CHECK_LAUNCH();
-            return KRS_OK;
-        }
-        if (!exec[slot]) {
-            KRS_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-            enqueue(block);
-            hipError_t e = hipStreamEndCapture(stream, &graph[slot]);
-            if (e != hipSuccess) {
-                set_error(std::string("batch graph capture failed: ") + hipGetErrorString(e));
-                return KRS_E_DEVICE;
+        } else {
+            int slot = (gblock[0] == block || gblock[0] == 0) ? 0 : 1;
+            if (gblock[slot] != block) {
+                if (exec[slot]) (void)hipGraphExecDestroy(exec[slot]);
+                if (graph[slot]) (void)hipGraphDestroy(graph[slot]);
+                exec[slot] = nullptr;
+                graph[slot] = nullptr;
             }
-            KRS_HIP(hipGraphInstantiate(&exec[slot], graph[slot], nullptr, nullptr, 0));
+            if (!exec[slot]) {
+                KRS_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+                enqueue(block);
+                hipError_t e = hipStreamEndCapture(stream, &graph[slot]);
+                if (e != hipSuccess) {
+                    set_error(std::string("batch graph capture failed: ") + hipGetErrorString(e));
+                    return KRS_E_DEVICE;
+                }
+                KRS_HIP(hipGraphInstantiate(&exec[slot], graph[slot], nullptr, nullptr, 0));
+                gblock[slot] = block;
+            }
+            KRS_HIP(hipGraphLaunch(exec[slot], stream));
         }
-        KRS_HIP(hipGraphLaunch(exec[slot], stream));
+        KRS_HIP(hipMemcpyAsync(h_stat, d_stat.p, 2 * mem.size() * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
         return KRS_OK;
     }
 
-    // Iterate until every member has finished.  Members that finished
-    // leave the launches once the active set shrank by a quarter.
-    krs_status run(bool graphs) {
-        krs_status st = stage();
-        if (st != KRS_OK) return st;
-        // same block schedule as a single solve (so refinements fall on the same iterations)
-        int block = graphs ? 16 : 8;
-        std::vector<int> last(mem.size(), -1);
-        int stuck = 0;
-        while (!mem.empty()) {
-            st = launch(block == 16 ? 0 : 1, block, graphs);
-            if (st != KRS_OK) return st;
-            const int cnt = (int)mem.size();
-            KRS_HIP(hipMemcpyAsync(h_stat, d_stat.p, 2 * cnt * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
-            KRS_HIP(hipStreamSynchronize(stream));
-            std::vector<SeqImpl<V, W>*> keep;
-            std::vector<int> keep_last;
-            bool progress = false;
-            for (int i = 0; i < cnt; ++i) {
-                const int s = h_stat[2 * i], it = h_stat[2 * i + 1];
-                if (it != last[i]) progress = true;
-                if (s == ST_DONE || s == ST_BREAKDOWN || s == ST_MAXIT) continue;
-                keep.push_back(mem[i]);
-                keep_last.push_back(it);
-            }
-            if (!progress && ++stuck > 4) {
-                set_error("batch made no progress");
-                return KRS_E_DEVICE;
-            }
-            if (progress) stuck = 0;
-            if (keep.empty()) break;
-            if (4 * keep.size() <= 3 * mem.size()) {
-                mem = keep;
-                last = keep_last;
-                st = stage();
-                if (st != KRS_OK) return st;
-            } else {
-                for (int i = 0; i < cnt; ++i) last[i] = h_stat[2 * i + 1];
-            }
-            block = graphs ? 64 : std::min(block * 2, 64);
-        }
+    krs_status read_status(std::vector<int32_t>& out) override {
+        KRS_HIP(hipStreamSynchronize(stream));
+        out.assign(h_stat, h_stat + 2 * mem.size());
         return KRS_OK;
     }
 };
 
-template <typename V, typename W>
-krs_status batch_group(krs_ctx* ctx, std::vector<SeqImpl<V, W>*>& seqs, std::vector<int>& idx,
-                       double* const* x, bool device_x, krs_solve_info* info, std::vector<krs_status>& out) {
-    BatchRunner<V, W> r{};
-    r.ctx = ctx;
-    r.stream = ctx->stream;
-    r.B = seqs.empty() ? 1 : seqs[0]->B;
-    std::vector<SeqImpl<V, W>*> begun;
-    std::vector<int> begun_idx;
-    for (size_t i = 0; i < seqs.size(); ++i) {
-        const krs_status st = seqs[i]->begin_solve();
-        out[idx[i]] = st;
-        if (st == KRS_OK) {
-            begun.push_back(seqs[i]);
-            begun_idx.push_back(idx[i]);
-        }
+}  // namespace
+
+std::unique_ptr<RunnerBase> make_runner(krs_ctx* ctx, int key) {
+    const int B = (key & 4) ? 3 : 1;
+    switch (key & 3) {
+        case 0: return std::unique_ptr<RunnerBase>(new BatchRunner<double, double>(ctx, B));
+        case 1: return std::unique_ptr<RunnerBase>(new BatchRunner<float, double>(ctx, B));
+        case 3: return std::unique_ptr<RunnerBase>(new BatchRunner<float, float>(ctx, B));
+        default: return nullptr;
     }
-    r.mem = begun;
-    const bool graphs = std::all_of(begun.begin(), begun.end(), [](SeqImpl<V, W>* s) { return s->desc.exec_mode == 0; });
-    krs_status st = begun.empty() ? KRS_OK : r.run(graphs);
-    if (st != KRS_OK) {
-        for (int i : begun_idx) out[i] = st;
-        return st;
-    }
-    for (size_t i = 0; i < begun.size(); ++i) {
-        const int k = begun_idx[i];
-        out[k] = begun[i]->end_solve(x ? x[k] : nullptr, device_x, info ? &info[k] : nullptr);
-    }
-    return KRS_OK;
 }
 
-}  // namespace
+bool finished_status(int s) { return s == ST_DONE || s == ST_BREAKDOWN || s == ST_MAXIT; }
 
 krs_status batch_solve(krs_ctx* ctx, SeqBase* const* seqs, int count, double* const* x, bool device_x,
                        krs_solve_info* info) {
     std::vector<krs_status> out(count, KRS_OK);
-    // group by storage / vector precision and block size
-    std::vector<SeqImpl<double, double>*> g0[2];
-    std::vector<SeqImpl<float, double>*> g1[2];
-    std::vector<SeqImpl<float, float>*> g2[2];
-    std::vector<int> i0[2], i1[2], i2[2];
+    // begin every member; group the begun ones by type
+    std::map<int, std::vector<int>> groups;
     for (int i = 0; i < count; ++i) {
-        SeqBase* s = seqs[i];
-        if (auto* a = dynamic_cast<SeqImpl<double, double>*>(s)) {
-            g0[a->B == 3].push_back(a);
-            i0[a->B == 3].push_back(i);
-        } else if (auto* b = dynamic_cast<SeqImpl<float, double>*>(s)) {
-            g1[b->B == 3].push_back(b);
-            i1[b->B == 3].push_back(i);
-        } else if (auto* c = dynamic_cast<SeqImpl<float, float>*>(s)) {
-            g2[c->B == 3].push_back(c);
-            i2[c->B == 3].push_back(i);
-        }
+        out[i] = seqs[i]->begin_solve();
+        if (out[i] == KRS_OK) groups[seqs[i]->type_key()].push_back(i);
     }
-    for (int b = 0; b < 2; ++b) {
-        krs_status st;
-        if (!g0[b].empty() && (st = batch_group(ctx, g0[b], i0[b], x, device_x, info, out)) == KRS_E_DEVICE) return st;
-        if (!g1[b].empty() && (st = batch_group(ctx, g1[b], i1[b], x, device_x, info, out)) == KRS_E_DEVICE) return st;
-        if (!g2[b].empty() && (st = batch_group(ctx, g2[b], i2[b], x, device_x, info, out)) == KRS_E_DEVICE) return st;
+    for (auto& kv : groups) {
+        std::unique_ptr<RunnerBase> r = make_runner(ctx, kv.first);
+        std::vector<int> act = kv.second;
+        bool graphs = true;
+        for (int i : act) graphs = graphs && seqs[i]->desc.exec_mode == 0;
+        auto members = [&](const std::vector<int>& idx) {
+            std::vector<SeqBase*> m;
+            for (int i : idx) m.push_back(seqs[i]);
+            return m;
+        };
+        krs_status st = r->set_members(members(act));
+        // same block schedule as a single solve
+        int block = graphs ? 16 : 8;
+        std::vector<int32_t> last(act.size(), -1), stat;
+        int stuck = 0;
+        while (st == KRS_OK && !act.empty()) {
+            st = r->launch(block, graphs);
+            if (st != KRS_OK) break;
+            st = r->read_status(stat);
+            if (st != KRS_OK) break;
+            std::vector<int> keep;
+            std::vector<int32_t> keep_last;
+            bool progress = false;
+            for (size_t i = 0; i < act.size(); ++i) {
+                if (stat[2 * i + 1] != last[i]) progress = true;
+                if (finished_status(stat[2 * i])) continue;
+                keep.push_back(act[i]);
+                keep_last.push_back(stat[2 * i + 1]);
+            }
+            if (!progress && ++stuck > 4) {
+                set_error("batch made no progress");
+                st = KRS_E_DEVICE;
+                break;
+            }
+            if (progress) stuck = 0;
+            if (keep.empty()) break;
+            if (4 * keep.size() <= 3 * act.size()) {
+                // finished members leave the launches once a quarter is done
+                act = keep;
+                last = keep_last;
+                st = r->set_members(members(act));
+            } else {
+                for (size_t i = 0; i < act.size(); ++i) last[i] = stat[2 * i + 1];
+            }
+            block = graphs ? 64 : std::min(block * 2, 64);
+        }
+        if (st != KRS_OK) {
+            for (int i : kv.second) out[i] = st;
+            if (st == KRS_E_DEVICE) return st;
+            continue;
+        }
+        for (int i : kv.second) out[i] = seqs[i]->end_solve(x ? x[i] : nullptr, device_x, info ? &info[i] : nullptr);
     }
     krs_status worst = KRS_OK;
     for (krs_status st : out)

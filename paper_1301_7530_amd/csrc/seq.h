@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <memory>
 #include <string>
@@ -18,6 +19,7 @@ struct krs_ctx {
     bool has_alloc = false;
     krs_allocator alloc{};
     int live_seqs = 0;
+    int live_servers = 0;
     int64_t bytes_live = 0;
 };
 
@@ -46,6 +48,12 @@ struct SeqBase {
     virtual krs_status begin_solve() = 0;
     virtual krs_status end_solve(double* x, bool device_x, krs_solve_info* info) = 0;
     virtual int type_key() const = 0;
+    // device bytes a solve adds on top of the resident sequence (matrix,
+    // vectors, basis): Krylov history, A C, staging and reduction scratch
+    virtual int64_t working_bytes() const = 0;
+    // release those solve-time buffers (they are re-created by the next solve)
+    virtual void trim() = 0;
+    std::atomic<int> in_server{0};  // requests of a server not yet completed
     virtual krs_status recycle(int32_t* n_added) = 0;
     virtual krs_status basis(double* C, int64_t ld, int32_t cap, int32_t* n_c) = 0;
     virtual void destroy() = 0;
@@ -101,6 +109,8 @@ struct SeqImpl : SeqBase {
     krs_status end_solve(double* x, bool device_x, krs_solve_info* info) override;
     int type_key() const override;
     krs_status tune_update();
+    int64_t working_bytes() const override;
+    void trim() override;
     krs_status recycle(int32_t* n_added) override;
     krs_status basis(double* C, int64_t ld, int32_t cap, int32_t* n_c) override;
     void destroy() override;
@@ -117,6 +127,21 @@ struct SeqImpl : SeqBase {
     void enqueue_refine(const SysView<V, W>& v);
     int64_t model_bytes_per_iter() const;
 };
+
+// Fused launches over a set of begun solves of one (V, W, B) type
+// (type_key); members may change between blocks.
+struct RunnerBase {
+    virtual ~RunnerBase() {}
+    virtual krs_status set_members(const std::vector<SeqBase*>& members) = 0;
+    // enqueue one block of iterations (+ refinement step) for every member
+    // and the read-back of their status words
+    virtual krs_status launch(int block, bool graphs) = 0;
+    // wait for the last launch; out[2 i] = status, out[2 i + 1] = iteration of member i
+    virtual krs_status read_status(std::vector<int32_t>& out) = 0;
+    virtual size_t size() const = 0;
+};
+std::unique_ptr<RunnerBase> make_runner(krs_ctx* ctx, int type_key);
+bool finished_status(int device_status);
 
 // Solve the submitted systems of several sequences in fused launches.
 krs_status batch_solve(krs_ctx* ctx, SeqBase* const* seqs, int count, double* const* x, bool device_x,

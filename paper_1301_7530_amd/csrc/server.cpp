@@ -1,0 +1,383 @@
+// Serving loop: continuous batching of requests from many sequences.
+//
+// Each request is one system of one sequence.  A worker thread owns the
+// context's stream; between blocks of iterations it admits queued requests
+// (at most one in flight per sequence, in arrival order, while slots and
+// the HBM budget for working sets allow), begins their solves and adds them
+// to the fused launches of their type, and completes the members that
+// finished (solution copied out, basis recycled, solve-time buffers
+// released).  A member's iterations are gated by its own device status, so
+// joining or leaving the launches does not change its arithmetic: every
+// result equals the one of a solve alone.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <set>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "seq.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+double ms_since(Clock::time_point t0, Clock::time_point t) {
+    return std::chrono::duration<double, std::milli>(t - t0).count();
+}
+
+struct Request {
+    krs_seq* seq = nullptr;
+    krs::SeqBase* impl = nullptr;
+    std::vector<double> values, b;
+    double* x_out = nullptr;
+    uint64_t tag = 0;
+    Clock::time_point t_arrive, t_admit;
+    int64_t bytes = 0;
+};
+
+}  // namespace
+
+struct krs_server {
+    krs_ctx* ctx = nullptr;
+    size_t budget = 0;
+    int max_slots = 0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request> queue;
+    std::deque<krs_completion> done;
+    std::set<krs::SeqBase*> busy;
+    bool stop = false;
+    std::thread worker;
+    // statistics
+    Clock::time_point t0;
+    bool started = false;
+    Clock::time_point t_last;
+    int64_t enqueued = 0, completed = 0, failed = 0, blocks = 0, member_blocks = 0, peak_bytes = 0;
+    std::vector<double> lat_ms;
+    krs_status fatal = KRS_OK;
+    std::string fatal_msg;
+
+    void post(Request& r, krs_status st, const krs_solve_info& info, int batch) {
+        krs_completion c;
+        std::memset(&c, 0, sizeof c);
+        const auto now = Clock::now();
+        c.tag = r.tag;
+        c.seq = r.seq;
+        c.status = st;
+        c.batch_size = batch;
+        c.latency_ms = ms_since(r.t_arrive, now);
+        c.queue_ms = ms_since(r.t_arrive, r.t_admit);
+        c.info = info;
+        if (st != KRS_OK) {
+            const char* m = krs_last_error();
+            std::strncpy(c.message, m ? m : "", sizeof c.message - 1);
+        }
+        r.impl->in_server.fetch_sub(1);
+        std::lock_guard<std::mutex> g(mu);
+        busy.erase(r.impl);
+        done.push_back(c);
+        ++completed;
+        if (st != KRS_OK && st != KRS_E_MAXIT) ++failed;
+        lat_ms.push_back(c.latency_ms);
+        t_last = now;
+        cv_done.notify_all();
+    }
+
+    void run();
+};
+
+void krs_server::run() {
+    (void)hipSetDevice(ctx->device);
+    struct Active {
+        Request req;
+        int64_t bytes;
+    };
+    std::map<int, std::vector<Active>> members;  // by type key
+    std::map<int, std::unique_ptr<krs::RunnerBase>> runners;
+    int64_t used = 0;
+    int nact = 0;
+    std::vector<int32_t> stat;
+    while (true) {
+        // ---- admission
+        std::vector<Request> admit;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            if (nact == 0 && queue.empty()) {
+                if (stop) break;
+                cv_work.wait_for(lk, std::chrono::milliseconds(20));
+                continue;
+            }
+            std::set<krs::SeqBase*> seen;  // a sequence's later requests wait for its earlier ones
+            for (auto it = queue.begin(); it != queue.end();) {
+                if (nact + (int)admit.size() >= max_slots) break;
+                if (busy.count(it->impl) || seen.count(it->impl)) {
+                    seen.insert(it->impl);
+                    ++it;
+                    continue;
+                }
+                const int64_t bytes = it->impl->working_bytes();
+                const bool fits = budget == 0 || used + bytes <= (int64_t)budget;
+                if (!fits && (nact + admit.size()) > 0) break;  // in order: wait for memory
+                it->bytes = bytes;
+                it->t_admit = Clock::now();
+                used += bytes;
+                busy.insert(it->impl);
+                admit.push_back(std::move(*it));
+                it = queue.erase(it);
+            }
+            peak_bytes = std::max(peak_bytes, used);
+        }
+        std::set<int> dirty;
+        for (Request& r : admit) {
+            krs_status st = r.impl->submit(r.values.data(), r.b.data(), false);
+            if (st == KRS_OK) st = r.impl->begin_solve();
+            if (st != KRS_OK) {
+                krs_solve_info none;
+                std::memset(&none, 0, sizeof none);
+                none.status = st;
+                used -= r.bytes;
+                r.impl->trim();
+                post(r, st, none, 0);
+                continue;
+            }
+            std::vector<double>().swap(r.values);
+            std::vector<double>().swap(r.b);
+            const int key = r.impl->type_key();
+            const int64_t bytes = r.bytes;
+            members[key].push_back(Active{std::move(r), bytes});
+            dirty.insert(key);
+            ++nact;
+        }
+        krs_status st = KRS_OK;
+        for (int key : dirty) {
+            auto& rp = runners[key];
+            if (!rp) rp = krs::make_runner(ctx, key);
+            std::vector<krs::SeqBase*> m;
+            for (auto& a : members[key]) m.push_back(a.req.impl);
+            st = rp->set_members(m);
+            if (st != KRS_OK) break;
+        }
+        if (nact == 0 && st == KRS_OK) continue;
+        // ---- one block of iterations for every member, all types
+        for (auto& kv : runners) {
+            if (st != KRS_OK) break;
+            if (kv.second->size() > 0) st = kv.second->launch(32, true);
+        }
+        if (st == KRS_OK) {
+            ++blocks;
+            member_blocks += nact;
+        }
+        // ---- completions
+        for (auto& kv : runners) {
+            if (st != KRS_OK) break;
+            if (kv.second->size() == 0) continue;
+            st = kv.second->read_status(stat);
+            if (st != KRS_OK) break;
+            auto& mem = members[kv.first];
+            std::vector<Active> keep;
+            bool changed = false;
+            const int batch = (int)mem.size();
+            for (size_t i = 0; i < mem.size(); ++i) {
+                if (!krs::finished_status(stat[2 * i])) {
+                    keep.push_back(std::move(mem[i]));
+                    continue;
+                }
+                changed = true;
+                Active& a = mem[i];
+                krs_solve_info info;
+                std::memset(&info, 0, sizeof info);
+                krs_status rs = a.req.impl->end_solve(a.req.x_out, false, &info);
+                if (rs == KRS_OK || rs == KRS_E_MAXIT) {
+                    int32_t added = 0;
+                    const krs_status rc = a.req.impl->recycle(&added);
+                    if (rc != KRS_OK && rs == KRS_OK) rs = rc;
+                    info.added = added;
+                }
+                a.req.impl->trim();
+                used -= a.bytes;
+                --nact;
+                post(a.req, rs, info, batch);
+            }
+            if (changed) {
+                mem = std::move(keep);
+                std::vector<krs::SeqBase*> m;
+                for (auto& a : mem) m.push_back(a.req.impl);
+                st = kv.second->set_members(m);
+            }
+        }
+        if (st != KRS_OK) {
+            // device failure: fail every request in flight and stop serving
+            std::string msg = krs_last_error() ? krs_last_error() : "";
+            for (auto& kv : members)
+                for (auto& a : kv.second) {
+                    krs_solve_info none;
+                    std::memset(&none, 0, sizeof none);
+                    post(a.req, st, none, 0);
+                }
+            members.clear();
+            runners.clear();
+            std::lock_guard<std::mutex> g(mu);
+            fatal = st;
+            fatal_msg = msg;
+            for (auto& r : queue) r.impl->in_server.fetch_sub(1);
+            queue.clear();
+            busy.clear();
+            stop = true;
+            cv_done.notify_all();
+            break;
+        }
+    }
+}
+
+extern "C" {
+
+krs_status krs_server_create(krs_ctx* ctx, size_t hbm_budget, int32_t max_slots, krs_server** out) {
+    try {
+        if (!ctx || !out || max_slots <= 0) {
+            krs::set_error("ctx, out and max_slots > 0 are required");
+            return KRS_E_INVALID;
+        }
+        *out = nullptr;
+        if (ctx->live_servers > 0) {
+            krs::set_error("the context already has a server");
+            return KRS_E_STATE;
+        }
+        krs_server* s = new krs_server();
+        s->ctx = ctx;
+        s->budget = hbm_budget;
+        s->max_slots = max_slots;
+        ctx->live_servers += 1;
+        s->worker = std::thread([s] { s->run(); });
+        *out = s;
+        return KRS_OK;
+    } catch (const std::exception& e) {
+        krs::set_error(e.what());
+        return KRS_E_OOM;
+    }
+}
+
+krs_status krs_server_enqueue(krs_server* s, krs_seq* seq, const double* values, const double* b, double* x_out,
+                              uint64_t tag) {
+    try {
+        if (!s || !seq || !values || !b) {
+            krs::set_error("server, seq, values and b are required");
+            return KRS_E_INVALID;
+        }
+        if (seq->impl->ctx != s->ctx) {
+            krs::set_error("the sequence belongs to another context");
+            return KRS_E_INVALID;
+        }
+        Request r;
+        r.seq = seq;
+        r.impl = seq->impl.get();
+        const krs_seq_desc& d = r.impl->desc;
+        const size_t nv = (size_t)d.nnzb * d.block * d.block;
+        r.values.assign(values, values + nv);
+        r.b.assign(b, b + d.n);
+        r.x_out = x_out;
+        r.tag = tag;
+        std::lock_guard<std::mutex> g(s->mu);
+        if (s->stop) {
+            krs::set_error(s->fatal != KRS_OK ? "server stopped after a device error: " + s->fatal_msg
+                                              : std::string("server is shutting down"));
+            return KRS_E_STATE;
+        }
+        if (s->queue.size() >= 65536) {
+            krs::set_error("server queue is full");
+            return KRS_E_BUSY;
+        }
+        r.t_arrive = Clock::now();
+        if (!s->started) {
+            s->started = true;
+            s->t0 = r.t_arrive;
+        }
+        r.impl->in_server.fetch_add(1);
+        s->queue.push_back(std::move(r));
+        ++s->enqueued;
+        s->cv_work.notify_one();
+        return KRS_OK;
+    } catch (const std::bad_alloc&) {
+        krs::set_error("host allocation failed");
+        return KRS_E_OOM;
+    }
+}
+
+krs_status krs_server_poll(krs_server* s, krs_completion* out, int32_t cap, int32_t* count, int32_t timeout_ms) {
+    if (!s || !count || (cap > 0 && !out)) {
+        krs::set_error("server, count (and out when cap > 0) are required");
+        return KRS_E_INVALID;
+    }
+    *count = 0;
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (s->done.empty() && timeout_ms != 0) {
+        auto pred = [s] { return !s->done.empty() || s->stop; };
+        if (timeout_ms < 0) s->cv_done.wait(lk, pred);
+        else s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), pred);
+    }
+    int k = 0;
+    while (k < cap && !s->done.empty()) {
+        out[k++] = s->done.front();
+        s->done.pop_front();
+    }
+    *count = k;
+    if (s->fatal != KRS_OK && k == 0) {
+        krs::set_error("server stopped after a device error: " + s->fatal_msg);
+        return s->fatal;
+    }
+    return KRS_OK;
+}
+
+krs_status krs_server_stats(krs_server* s, krs_server_report* out) {
+    if (!s || !out) {
+        krs::set_error("server and out are required");
+        return KRS_E_INVALID;
+    }
+    std::lock_guard<std::mutex> g(s->mu);
+    std::memset(out, 0, sizeof *out);
+    out->enqueued = s->enqueued;
+    out->completed = s->completed;
+    out->failed = s->failed;
+    out->queued = (int64_t)s->queue.size();
+    out->blocks = s->blocks;
+    out->mean_batch = s->blocks ? (double)s->member_blocks / (double)s->blocks : 0.0;
+    out->peak_bytes = s->peak_bytes;
+    if (s->completed > 0 && s->started) {
+        const double span = ms_since(s->t0, s->t_last);
+        out->solves_per_s = span > 0 ? 1e3 * (double)s->completed / span : 0.0;
+        std::vector<double> l = s->lat_ms;
+        auto pct = [&l](double q) {
+            const size_t i = std::min(l.size() - 1, (size_t)(q * (double)(l.size() - 1) + 0.5));
+            std::nth_element(l.begin(), l.begin() + i, l.end());
+            return l[i];
+        };
+        out->p50_ms = pct(0.50);
+        out->p99_ms = pct(0.99);
+        double sum = 0.0;
+        for (double v : s->lat_ms) sum += v;
+        out->mean_ms = sum / (double)s->lat_ms.size();
+    }
+    return KRS_OK;
+}
+
+krs_status krs_server_destroy(krs_server* s) {
+    if (!s) return KRS_OK;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->stop = true;
+        s->cv_work.notify_all();
+    }
+    if (s->worker.joinable()) s->worker.join();
+    s->ctx->live_servers -= 1;
+    delete s;
+    return KRS_OK;
+}
+
+}  // extern "C"
