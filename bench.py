@@ -37,6 +37,8 @@ WORKLOADS = {
     "diffusion20": dict(kind="diffusion", size=(20, 20, 20), n_systems=8, config_id=1, max_basis=0, eps=1e-14),
     # many independent diffusion sequences (n ~ U[5e3, 2e5]) solved in fused launches
     "batched": dict(kind="batched", size=None, n_systems=10, config_id=4, max_basis=60, eps=1e-8),
+    # clients with elasticity sequences (1e4..5e5 dofs) served with continuous batching
+    "serving": dict(kind="serving", size=None, n_systems=50, config_id=5, max_basis=200, eps=1e-8),
 }
 
 
@@ -163,6 +165,124 @@ def gen_batched(args):
     return seqs, ks, host
 
 
+def _gen_client(task):
+    E, cid, systems, n_systems = task
+    import gen
+
+    sq = gen.make_sequence("elasticity", E, n_systems, 5, cid)
+    return cid, [sq.system(k) for k in range(systems)]
+
+
+def gen_serving(args):
+    """Host data of the serving workload (worker processes, before the GPU is touched)."""
+    import concurrent.futures as cf
+
+    import gen
+
+    wl = WORKLOADS["serving"]
+    Es = gen.serving_elasticity_sizes(64)[: args.clients]
+    seqs = [gen.make_sequence("elasticity", E, wl["n_systems"], 5, c) for c, E in enumerate(Es)]
+    _log(f"serving: {len(seqs)} clients, dofs {min(s.n for s in seqs)}..{max(s.n for s in seqs)}, "
+         f"{args.systems} systems each")
+    host = {}
+    with cf.ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 4)) as ex:
+        for cid, systems in ex.map(_gen_client, [(E, c, args.systems, wl["n_systems"]) for c, E in enumerate(Es)]):
+            host[cid] = systems
+    return seqs, host
+
+
+def run_serving(args, K, torch, data):
+    """Open-loop Poisson arrivals per client into the continuous-batching
+    server; the same requests served one at a time for comparison."""
+    import threading
+
+    wl = WORKLOADS["serving"]
+    seqs, host = data
+    ctx = K.Context(0)
+    kw = dict(precision=args.precision, reuse="selective", tol=1e-8, max_iter=args.max_iter,
+              ritz_eps=args.eps or wl["eps"], max_basis=wl["max_basis"], cap_policy="freeze",
+              history_cap=args.history_cap, refine_drop=args.refine_drop)
+    rng = np.random.default_rng(np.random.SeedSequence((13017530, 5, 1 << 21)))
+    arrivals = []
+    for c in range(len(seqs)):
+        t = np.cumsum(rng.exponential(1.0 / args.rate, size=args.systems))
+        arrivals += [(float(t[k]), c, k) for k in range(args.systems)]
+    arrivals.sort()
+
+    def serve(max_slots):
+        hs = [K.sequence_for(ctx, sq, **kw) for sq in seqs]
+        srv = K.Server(ctx, hbm_budget=int(args.hbm_budget * (1 << 30)), max_slots=max_slots)
+        done = []
+        try:
+            def producer():
+                t0 = time.perf_counter()
+                for t, c, k in arrivals:
+                    dt = t - (time.perf_counter() - t0)
+                    if dt > 0:
+                        time.sleep(dt)
+                    srv.enqueue(hs[c], *host[c][k], tag=c * 1000 + k)
+
+            th = threading.Thread(target=producer)
+            t_start = time.perf_counter()
+            th.start()
+            while len(done) < len(arrivals):
+                got = srv.poll(timeout_ms=60000)
+                if not got:
+                    raise RuntimeError("server made no progress for 60 s")
+                done += got
+                _log(f"served {len(done)}/{len(arrivals)}")
+            th.join()
+            wall = time.perf_counter() - t_start
+            st = srv.stats()
+        finally:
+            srv.close()
+            for h in hs:
+                h.close()
+        bad = [c for c in done if c["status"] != 0 or c["info"]["rel_res_true"] > 1e-8]
+        if bad:
+            raise RuntimeError(f"{len(bad)} requests missed the tolerance: {bad[0]['message']}")
+        st["wall_s"] = wall
+        st["iters_mean"] = float(np.mean([c["info"]["iters"] for c in done]))
+        return st
+
+    _log("continuous batching")
+    cb = serve(args.clients)
+    seq_st = None
+    if args.plain:
+        _log("one request at a time")
+        seq_st = serve(1)
+    ctx.close()
+    n_tot = sum(sq.n for sq in seqs)
+    out = {
+        "metric": "solves/s at 1e-8 resid vs plain PCG same GPU; %HBM peak; p50/p99 latency",
+        "value": round(cb["solves_per_s"], 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": len(arrivals),
+        "warmup": 0,
+        "ms_per_step": round(1e3 / cb["solves_per_s"], 3) if cb["solves_per_s"] else None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"mixed": "f32+f64", "fp64": "f64", "fp32": "f32"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"serving: {len(seqs)} clients, Q1 elasticity "
+                               f"{min(s.n for s in seqs)}..{max(s.n for s in seqs)} dofs, {args.systems} systems "
+                               f"each, Poisson arrivals {args.rate}/s per client, SRKS cap {wl['max_basis']}",
+                   "clients": len(seqs), "sum_n": n_tot, "rate_per_client": args.rate,
+                   "hbm_budget_gib": args.hbm_budget, "precision": args.precision},
+        "latency_ms": {"p50": cb["p50_ms"], "p99": cb["p99_ms"], "mean": cb["mean_ms"]},
+        "mean_batch": cb["mean_batch"],
+        "peak_working_set_gib": cb["peak_bytes"] / (1 << 30),
+        "iters_mean": cb["iters_mean"],
+    }
+    if seq_st:
+        out["one_at_a_time"] = {"value": round(seq_st["solves_per_s"], 4),
+                                "latency_ms": {"p50": seq_st["p50_ms"], "p99": seq_st["p99_ms"]}}
+        out["speedup_vs_one_at_a_time"] = cb["solves_per_s"] / seq_st["solves_per_s"]
+    print(json.dumps(out), flush=True)
+
+
 def run_batched(args, K, torch, data):
     """Fused multi-sequence solves (one batch_solve per step over every
     sequence) against the same sequences solved one after the other, and
@@ -180,7 +300,7 @@ def run_batched(args, K, torch, data):
     def phase(reuse, fused):
         hs = [K.sequence_for(ctx, sq, reuse=reuse, **kw) for sq in seqs]
         xs = [torch.empty(sq.n, dtype=torch.float64, device="cuda") for sq in seqs]
-        iters, t_steps = [], []
+        iters, t_steps, t_rec = [], [], []
         try:
             for step, k in enumerate(ks):
                 torch.cuda.synchronize()
@@ -191,12 +311,14 @@ def run_batched(args, K, torch, data):
                     _, infos = ctx.batch_solve(hs, xs=xs)
                 else:
                     infos = [h.solve_device(x) for h, x in zip(hs, xs)]
+                t1 = time.perf_counter()
                 if reuse != "none":
                     for h in hs:
                         h.recycle()
                 torch.cuda.synchronize()
                 if step >= args.warmup:
                     t_steps.append(time.perf_counter() - t0)
+                    t_rec.append(time.perf_counter() - t1)
                     iters.append([inf["iters"] for inf in infos])
                     bad = [inf for inf in infos if inf["rel_res_true"] > 1e-8 or inf["status"] != 0]
                     if bad:
@@ -206,7 +328,7 @@ def run_batched(args, K, torch, data):
                 h.close()
         t = sum(t_steps)
         return dict(value=len(hs) * len(t_steps) / t, time=t, iters_mean=float(np.mean(iters)),
-                    step_ms=[round(1e3 * x, 2) for x in t_steps])
+                    step_ms=[round(1e3 * x, 2) for x in t_steps], recycle_ms=[round(1e3 * x, 2) for x in t_rec])
 
     _log("fused SRKS")
     fused = phase("selective", True)
@@ -234,6 +356,7 @@ def run_batched(args, K, torch, data):
                    "history_cap": args.history_cap},
         "iters_mean": fused["iters_mean"],
         "step_ms": fused["step_ms"],
+        "recycle_ms": fused["recycle_ms"],
     }
     if alone:
         out["sequential"] = {"value": round(alone["value"], 4), "iters_mean": alone["iters_mean"]}
@@ -263,6 +386,10 @@ def main():
     ap.add_argument("--sequences", type=int, default=64, help="batched workload: number of sequences")
     ap.add_argument("--history-cap", type=int, default=256, help="batched workload: Krylov vectors kept per solve")
     ap.add_argument("--eager", action="store_true", help="launch kernels one by one instead of graph replay")
+    ap.add_argument("--clients", type=int, default=16, help="serving workload: clients (sequences)")
+    ap.add_argument("--systems", type=int, default=3, help="serving workload: systems per client")
+    ap.add_argument("--rate", type=float, default=1.0, help="serving workload: arrivals per second per client")
+    ap.add_argument("--hbm-budget", type=float, default=64.0, help="serving workload: working-set budget (GiB)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -273,6 +400,7 @@ def main():
         sys.exit(2)
 
     batched_data = gen_batched(args) if args.workload == "batched" else None
+    serving_data = gen_serving(args) if args.workload == "serving" else None
 
     import torch
 
@@ -284,6 +412,11 @@ def main():
         sys.exit(1)
     if args.workload == "batched":
         run_batched(args, K, torch, batched_data)
+        return
+    if args.workload == "serving":
+        if args.history_cap == 256:
+            args.history_cap = 1000
+        run_serving(args, K, torch, serving_data)
         return
     wl = WORKLOADS[args.workload]
     seq = gen.make_sequence(wl["kind"], wl["size"], wl["n_systems"], wl["config_id"])
