@@ -61,7 +61,7 @@ def run_phase(K, ctx, seq, dev_sys, reuse, args, wl, order, timing=False):
     s = K.sequence_for(ctx, seq, precision=args.precision, reuse=reuse, tol=1e-8, max_iter=args.max_iter,
                        ritz_eps=args.eps if args.eps else wl["eps"], max_basis=wl["max_basis"], cap_policy="freeze",
                        refine_drop=args.refine_drop, autotune=args.autotune, update_rows=args.update_rows,
-                       eager=args.eager)
+                       eager=args.eager, separate_finalize=args.separate_finalize)
     x = torch.empty(seq.n, dtype=torch.float64, device="cuda")
     infos = []
     lat = []
@@ -386,6 +386,8 @@ def main():
     ap.add_argument("--sequences", type=int, default=64, help="batched workload: number of sequences")
     ap.add_argument("--history-cap", type=int, default=256, help="batched workload: Krylov vectors kept per solve")
     ap.add_argument("--eager", action="store_true", help="launch kernels one by one instead of graph replay")
+    ap.add_argument("--separate-finalize", action="store_true",
+                    help="run the end-of-step reduction as its own kernel")
     ap.add_argument("--clients", type=int, default=16, help="serving workload: clients (sequences)")
     ap.add_argument("--systems", type=int, default=3, help="serving workload: systems per client")
     ap.add_argument("--rate", type=float, default=1.0, help="serving workload: arrivals per second per client")

@@ -113,6 +113,9 @@ typedef struct {
     int32_t autotune;      /* 1: when the basis width changed by half, time several update_rows values on
                               the submitted system and keep the fastest (results then depend on the
                               choice in the last bits only) */
+    int32_t kernel_flags;  /* bit 0: run the end-of-step reduction (coarse solve, beta, status) as a
+                              kernel of its own instead of in the last workgroup of the update kernel;
+                              same arithmetic, one more launch per iteration */
 } krs_seq_desc;
 
 typedef struct {

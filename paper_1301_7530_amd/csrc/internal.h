@@ -17,6 +17,11 @@ constexpr int kSlice = 64;
 // Doubles reserved at the head of the reduction scratch for SpMV partials
 // (>= the largest SpMV grid).
 constexpr int64_t kPart1 = 4096;
+// Byte offset of the fused update's ticket counters in the state allocation
+// (one global counter, then one per group of kGroup update workgroups).
+constexpr int kSyncOffset = 256;
+constexpr int kGroup = 16;
+constexpr int kSyncBytes = 4 * (1 + 2048 / kGroup) + 60;
 // Threads of the update kernel (one block row each per step).
 constexpr int kT3 = 512;
 // Largest update grid (bounds the partial sums the finalize kernel reads).
@@ -126,8 +131,11 @@ struct SysView {
     double* part1;     // per-workgroup (w, A w) partials of the SpMV
     double* partials;  // per-workgroup partials of the other reductions
     DevState* st;
+    unsigned* sync;              // ticket counter of the fused update (zero between launches)
     unsigned long long* kslots;  // per-workgroup start / end stamps of timed launches
     Geometry geo;
+    int32_t fused;               // 1: the update kernel's last workgroup runs the finalize
+    int32_t pad1;
 };
 
 // Launch maps of a fused batch: map[k][i] = (system, workgroup) of launch
@@ -145,6 +153,7 @@ enum BatchKernel {
 struct BatchMaps {
     const int2* map[BK_COUNT];
     int64_t count[BK_COUNT];
+    int32_t fused;  // every member uses the fused update
 };
 
 // ------------------------------------------------------------ launchers

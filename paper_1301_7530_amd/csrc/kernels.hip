@@ -35,6 +35,9 @@ namespace {
 
 constexpr int kTpb = 256;  // threads per workgroup, scalar kernels
 constexpr int kTF3 = 512;  // threads of the single-workgroup finalize of the update
+static_assert(kTF3 == kT3, "the fused update runs the finalize in one of its workgroups");
+// s_waitcnt operand: vector memory counter 0, the other counters unconstrained
+constexpr int kWaitVm0 = 0x0F70;
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -59,7 +62,33 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
 
 // Reduce `nv` values over `np` partial rows (row stride `stride`) in a fixed
 // order with all threads of the workgroup; out[k] for k < nv (LDS).
-template <int UNR = 32>
+// Load of a value written by another workgroup of the same launch (agent-
+// coherent: bypasses a possibly stale L2 of another XCD) or a plain load.
+template <bool COH>
+__device__ __forceinline__ double ld_part(const double* p) {
+    if (COH) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return *p;
+}
+
+// sum_r P[r * stride + k] over r = 0 .. rows-1 in ascending order (16
+// loads in flight).  The update's partial sums are reduced in two levels
+// with it: each group of kGroup consecutive workgroups, then the groups.
+template <bool COH>
+__device__ __forceinline__ double col_sum(const double* P, int64_t rows, int64_t stride, int k) {
+    double s = 0.0;
+    int64_t r = 0;
+    for (; r + 16 <= rows; r += 16) {
+        double t[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) t[u] = ld_part<COH>(P + (r + u) * stride + k);
+#pragma unroll
+        for (int u = 0; u < 16; ++u) s += t[u];
+    }
+    for (; r < rows; ++r) s += ld_part<COH>(P + r * stride + k);
+    return s;
+}
+
+template <int UNR = 32, bool COH = false>
 __device__ void reduce_partials(const double* partials, int64_t np, int nv, int stride, double* out, double* lds) {
     const int T = blockDim.x;
     int tpv = T / (nv > 0 ? nv : 1);
@@ -76,11 +105,11 @@ __device__ void reduce_partials(const double* partials, int64_t np, int nv, int 
             for (; i + UNR * tpv <= np; i += UNR * tpv) {
                 double t[UNR];
 #pragma unroll
-                for (int u = 0; u < UNR; ++u) t[u] = partials[(i + u * tpv) * stride + k];
+                for (int u = 0; u < UNR; ++u) t[u] = ld_part<COH>(partials + (i + u * tpv) * stride + k);
 #pragma unroll
                 for (int u = 0; u < UNR; ++u) acc += t[u];
             }
-            for (; i < np; i += tpv) acc += partials[i * stride + k];
+            for (; i < np; i += tpv) acc += ld_part<COH>(partials + i * stride + k);
         }
         __syncthreads();
         lds[threadIdx.x] = acc;
@@ -94,10 +123,27 @@ __device__ void reduce_partials(const double* partials, int64_t np, int nv, int 
     }
 }
 
+// Fixed-order per-thread sum of p[tid], p[tid + T], ... (T = blockDim.x)
+// with the first UNR loads issued together (a loop would wait for each).
+template <int UNR>
+__device__ __forceinline__ double thread_sum(const double* p, int64_t np) {
+    const int64_t T = blockDim.x;
+    double t[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+        const int64_t i = threadIdx.x + u * T;
+        t[u] = i < np ? p[i] : 0.0;
+    }
+    double a = 0.0;
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) a += t[u];
+    for (int64_t i = threadIdx.x + UNR * T; i < np; i += T) a += p[i];
+    return a;
+}
+
 // Fixed-order sum of p[0..np), returned to every thread of the workgroup.
 __device__ double sum_all(const double* p, int64_t np, double* lds) {
-    double a = 0.0;
-    for (int64_t i = threadIdx.x; i < np; i += blockDim.x) a += p[i];
+    double a = thread_sum<4>(p, np);
     a = wave_sum(a);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     __syncthreads();
@@ -124,8 +170,18 @@ __device__ void ginv_matvec(const double* __restrict__ Ginv, int nc, const doubl
         const int p = threadIdx.x % P;
         const bool act = (int)(threadIdx.x / P) < rows_per_round && r < nc;
         double m = 0.0;
-        if (act)
-            for (int c = p; c < nc; c += P) m += Ginv[(int64_t)c * nc + r] * t[c];
+        if (act) {
+            // same order as a plain loop over c = p, p + P, ...; 8 loads in flight
+            int c = p;
+            for (; c + 7 * P < nc; c += 8 * P) {
+                double g[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) g[u] = Ginv[(int64_t)(c + u * P) * nc + r];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) m += g[u] * t[c + u * P];
+            }
+            for (; c < nc; c += P) m += Ginv[(int64_t)c * nc + r] * t[c];
+        }
         __syncthreads();
         lds[threadIdx.x] = m;
         __syncthreads();
@@ -337,7 +393,7 @@ __device__ __forceinline__ void project_rows(const V* __restrict__ ACt, int64_t 
     constexpr int RPW = 64 / LPR;  // 8
     constexpr int NW = kT3 / 64;
     constexpr int RPR = RPW * NW;
-    constexpr int UR = 8;
+    constexpr int UR = sizeof(V) == 4 ? 6 : 8;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int q = lane % LPR, rsub = lane / LPR;
     const int nch = (nc + CW - 1) / CW;
@@ -413,194 +469,84 @@ __device__ __forceinline__ void project_rows(const V* __restrict__ ACt, int64_t 
 // rho = (r, z) = (r, s) - (C^T r)^T mu exactly.  Workgroup bid owns the
 // block rows [bid cb3, (bid + 1) cb3), one thread per block row, in steps
 // of kT3 block rows; the step's s and w go through LDS to the projector.
-template <typename V, typename W, int B>
-__device__ __forceinline__ void update_reduce_body(const SysView<V, W>& v, int64_t bid, int mode) {
-    DevState* st = v.st;
-    const uint32_t mask = (mode == 2) ? M_REFINE : M_RUN;
-    if (!gate(st, mask)) return;
-    const bool tm = mode == 0 && ktime_sample(st, 1);
-    ktime_begin(v.kslots, 1, bid, tm);
-    constexpr int T = kT3;
-    __shared__ double ss[T * B];
-    __shared__ double ws[T * B];
-    __shared__ double red[T];
-    __shared__ double tacc[1024];
-    __shared__ double vacc[1024];
-    __shared__ double cred[T / 64][64];
-    const int tid = threadIdx.x;
-    const int nc = v.nc;
-    for (int c = tid; c < nc; c += T) {
-        tacc[c] = 0.0;
-        vacc[c] = 0.0;
-    }
-    const int64_t pb = bid * v.geo.cb3;
-    const int64_t pe = (pb + v.geo.cb3) < v.nb ? (pb + v.geo.cb3) : v.nb;
-    double rr = 0.0, rs = 0.0;
-    double a = 0.0;
-    bool have_a = mode != 0;
-    for (int64_t ps = pb; ps < pe; ps += T) {
-        const int64_t p = ps + tid;
-        double ri[B], wi[B], si[B];
-#pragma unroll
-        for (int d = 0; d < B; ++d) {
-            ri[d] = 0.0;
-            wi[d] = 0.0;
-            si[d] = 0.0;
-        }
-        // the step's vector loads are issued before alpha is formed from
-        // the SpMV partials, so the two latencies overlap
-        W rv[B], qv[B];
-        double xv[B];
-        if (p < pe) {
-#pragma unroll
-            for (int d = 0; d < B; ++d) {
-                const int64_t i = p * B + d;
-                rv[d] = v.r[i];
-                if (mode != 1) wi[d] = (double)v.w[i];
-                if (mode == 0) {
-                    qv[d] = v.q[i];
-                    xv[d] = v.x[i];
-                }
-            }
-        }
-        if (!have_a) {
-            a = st->rho / sum_all(v.part1, v.geo.g1, red);
-            have_a = true;
-        }
-        if (p < pe) {
-#pragma unroll
-            for (int d = 0; d < B; ++d) {
-                const int64_t i = p * B + d;
-                W r2 = rv[d];
-                if (mode == 0) {
-                    v.x[i] = xv[d] + a * wi[d];
-                    r2 = (W)((double)r2 - a * (double)qv[d]);
-                    v.r[i] = r2;
-                }
-                ri[d] = (double)r2;
-            }
-            if (B == 1) {
-                si[0] = (double)(W)((double)v.minv[p] * ri[0]);
-            } else {
-                const V* m = v.minv + p * 9;
-#pragma unroll
-                for (int d = 0; d < B; ++d)
-                    si[d] = (double)(W)((double)m[3 * d] * ri[0] + (double)m[3 * d + 1] * ri[1] +
-                                        (double)m[3 * d + 2] * ri[2]);
-            }
-#pragma unroll
-            for (int d = 0; d < B; ++d) {
-                v.s[p * B + d] = (W)si[d];
-                rr += ri[d] * ri[d];
-                rs += ri[d] * si[d];
-            }
-        }
-        if (nc > 0) {
-            __syncthreads();
-#pragma unroll
-            for (int d = 0; d < B; ++d) {
-                ss[tid * B + d] = si[d];
-                ws[tid * B + d] = wi[d];
-            }
-            __syncthreads();
-            const int64_t pn = (ps + T) < pe ? (ps + T) : pe;
-            project_rows<V>(v.AC + ps * B * v.ldac, v.ldac, (int)((pn - ps) * B), nc, ss, ws, tacc, vacc, cred);
-        }
-    }
-    const int stride = 2 * nc + 2;
-    double* myp = v.partials + bid * stride;
-    {
-        const double brr = block_sum(rr, red);
-        if (tid == 0) myp[0] = brr;
-        const double brs = block_sum(rs, red);
-        if (tid == 0) myp[1] = brs;
-    }
-    __syncthreads();
-    for (int c = tid; c < nc; c += T) {
-        myp[2 + c] = tacc[c];
-        myp[2 + nc + c] = vacc[c];
-    }
-    ktime_end(v.kslots, 1, bid, tm);
-}
-
 // F3: one workgroup.  Reduces the partials of K1 (mode 0) and K3, records
 // alpha_j, gamma_j, rho_{j+1}, decides convergence / refinement / breakdown
 // and forms beta, mu = G^-1 t, mu2 and u = C^T r for the direction update.
 // A single workgroup is latency bound, so every independent load (device
 // state, K3 and K1 partials, G^-1, u) is issued before the first wait, and
 // the state is worked on in LDS and written back once at the end.
-template <typename V, typename W>
-__device__ __forceinline__ void finalize_update_body(const SysView<V, W>& v, int mode) {
+// LDS (doubles) of the finalize body
+constexpr int kStateWords = 32;
+constexpr int fin_pool() { return kStateWords + kTF3 + 2056 + 3 * 1024 + 4096 + 8; }
+
+template <typename V, typename W, bool COH>
+__device__ __forceinline__ void finalize_update_body(const SysView<V, W>& v, int mode, double* pool) {
     constexpr int T = kTF3;
     constexpr int NWORD = (int)(sizeof(DevState) / 8);
-    constexpr int PRE = 64;  // partial sums preloaded per thread (one round trip for ~32k of them)
-    __shared__ DevState S;
-    __shared__ double red[T];
-    __shared__ double fin[2048 + 4];
-    __shared__ double muL[1024];
-    __shared__ double gvL[1024];
-    __shared__ double uL[1024];
-    __shared__ double Gl[4096];
-    __shared__ double beta_s;
+    static_assert(NWORD <= kStateWords, "state staging area too small");
+    DevState& S = *reinterpret_cast<DevState*>(pool);
+    double* red = pool + kStateWords;
+    double* fin = red + T;
+    double* muL = fin + 2056;
+    double* gvL = muL + 1024;
+    double* uL = gvL + 1024;
+    double* Gl = uL + 1024;
+    double& beta_s = Gl[4096];
     const int tid = threadIdx.x;
     const int nc = v.nc;
     const int nv = 2 * nc + 2;
     const int64_t np3 = v.geo.g3, np1 = v.geo.g1;
-    // ---- loads
+    const int64_t ng = (np3 + kGroup - 1) / kGroup;
+    // ---- loads (state, SpMV partials, u, G^-1 and the update's sums together)
     unsigned long long sw = 0ull;
     if (tid < NWORD) sw = reinterpret_cast<const unsigned long long*>(v.st)[tid];
-    const bool fast = nv <= T;
-    int tpv = T / nv;
-    if (tpv < 1) tpv = 1;
-    if (tpv > 64) tpv = 64;
-    const int kv = tid / tpv, pv = tid % tpv;
-    const bool act = fast && kv < nv && kv < T / tpv;
-    double vals[PRE];
+    const double p1 = (mode == 0) ? thread_sum<4>(v.part1, np1) : 0.0;
+    {
+        constexpr int UU = 1024 / T;
+        double uv[UU];
 #pragma unroll
-    for (int u = 0; u < PRE; ++u) {
-        const int64_t idx = pv + (int64_t)u * tpv;
-        vals[u] = (act && idx < np3) ? v.partials[idx * nv + kv] : 0.0;
+        for (int u = 0; u < UU; ++u) {
+            const int c = tid + u * T;
+            uv[u] = (mode == 0 && c < nc) ? v.u[c] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < UU; ++u)
+            if (tid + u * T < nc) uL[tid + u * T] = uv[u];
     }
-    double p1 = 0.0;
-    if (mode == 0)
-        for (int64_t i = tid; i < np1; i += T) p1 += v.part1[i];
-    for (int c = tid; c < nc; c += T) uL[c] = (mode == 0) ? v.u[c] : 0.0;
     const bool gsmall = nc <= 64;
-    if (gsmall)
-        for (int e = tid; e < nc * nc; e += T) Gl[e] = v.Ginv[e];
+    if (gsmall) {
+        constexpr int GU = 4096 / T;
+        double gv[GU];
+#pragma unroll
+        for (int u = 0; u < GU; ++u) {
+            const int e = tid + u * T;
+            gv[u] = e < nc * nc ? v.Ginv[e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < GU; ++u)
+            if (tid + u * T < nc * nc) Gl[tid + u * T] = gv[u];
+    }
+    // fin[k]: the groups' sums (written by the group reducers, COH) in
+    // ascending order, or both levels here
+    const double* gsum = v.partials + np3 * nv;
+    for (int kk = tid; kk < nv; kk += T) {
+        double s = 0.0;
+        if (COH) {
+            s = col_sum<true>(gsum, ng, nv, kk);
+        } else {
+            for (int64_t g = 0; g < ng; ++g) {
+                const int64_t r0 = g * kGroup;
+                const int64_t rn = (np3 - r0) < kGroup ? (np3 - r0) : kGroup;
+                s += col_sum<false>(v.partials + r0 * nv, rn, nv, kk);
+            }
+        }
+        fin[kk] = s;
+    }
     if (tid < NWORD) reinterpret_cast<unsigned long long*>(&S)[tid] = sw;
     __syncthreads();
     const uint32_t mask = (mode == 2) ? M_REFINE : M_RUN;
     if (((1u << S.status) & mask) == 0) return;
-    // ---- sums
-    double acc = 0.0;
-#pragma unroll
-    for (int u = 0; u < PRE; ++u) acc += vals[u];
-    if (act) {
-        int64_t idx = pv + PRE * (int64_t)tpv;
-        for (; idx + 8 * tpv <= np3; idx += 8 * tpv) {
-            double t[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) t[u] = v.partials[(idx + u * tpv) * nv + kv];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) acc += t[u];
-        }
-        for (; idx < np3; idx += tpv) acc += v.partials[idx * nv + kv];
-    }
     const double g = (mode == 0) ? sum_all_reg(p1, red) : 0.0;
-    if (fast) {
-        red[tid] = acc;
-        __syncthreads();
-        if (act && pv == 0) {
-            double t = 0.0;
-            for (int j = 0; j < tpv; ++j) t += red[tid + j];
-            fin[kv] = t;
-        }
-        __syncthreads();
-    } else {
-        reduce_partials<8>(v.partials, np3, nv, nv, fin, red);
-        __syncthreads();
-    }
     const double a = (mode == 0) ? S.rho / g : 0.0;
     double du = 0.0;
     if (nc > 0) {
@@ -693,6 +639,168 @@ __device__ __forceinline__ void finalize_update_body(const SysView<V, W>& v, int
     // = s + beta w_old - C (mu + beta G^-1 (AC)^T w_old)
     const double bt = beta_s;
     for (int c = tid; c < nc; c += T) v.mu2[c] = muL[c] + bt * gvL[c];
+}
+
+// LDS (doubles) of the update body for block size B
+template <int B>
+constexpr int upd_pool() {
+    return 2 * kT3 * B + kT3 + 2048 + kT3;
+}
+
+template <typename V, typename W, int B, bool FUSE>
+__device__ __forceinline__ void update_reduce_body(const SysView<V, W>& v, int64_t bid, int mode, double* pool) {
+    DevState* st = v.st;
+    const uint32_t mask = (mode == 2) ? M_REFINE : M_RUN;
+    if (!gate(st, mask)) return;
+    const bool tm = mode == 0 && ktime_sample(st, 1);
+    ktime_begin(v.kslots, 1, bid, tm);
+    constexpr int T = kT3;
+    double* ss = pool;
+    double* ws = ss + T * B;
+    double* red = ws + T * B;
+    double* tacc = red + T;
+    double* vacc = tacc + 1024;
+    double(*cred)[64] = reinterpret_cast<double(*)[64]>(vacc + 1024);
+    const int tid = threadIdx.x;
+    const int nc = v.nc;
+    for (int c = tid; c < nc; c += T) {
+        tacc[c] = 0.0;
+        vacc[c] = 0.0;
+    }
+    const int64_t pb = bid * v.geo.cb3;
+    const int64_t pe = (pb + v.geo.cb3) < v.nb ? (pb + v.geo.cb3) : v.nb;
+    double rr = 0.0, rs = 0.0;
+    double a = 0.0;
+    bool have_a = mode != 0;
+    for (int64_t ps = pb; ps < pe; ps += T) {
+        const int64_t p = ps + tid;
+        double ri[B], wi[B], si[B];
+#pragma unroll
+        for (int d = 0; d < B; ++d) {
+            ri[d] = 0.0;
+            wi[d] = 0.0;
+            si[d] = 0.0;
+        }
+        // the step's vector loads are issued before alpha is formed from
+        // the SpMV partials, so the two latencies overlap
+        W rv[B], qv[B];
+        double xv[B];
+        if (p < pe) {
+#pragma unroll
+            for (int d = 0; d < B; ++d) {
+                const int64_t i = p * B + d;
+                rv[d] = v.r[i];
+                if (mode != 1) wi[d] = (double)v.w[i];
+                if (mode == 0) {
+                    qv[d] = v.q[i];
+                    xv[d] = v.x[i];
+                }
+            }
+        }
+        if (!have_a) {
+            a = st->rho / sum_all(v.part1, v.geo.g1, red);
+            have_a = true;
+        }
+        if (p < pe) {
+#pragma unroll
+            for (int d = 0; d < B; ++d) {
+                const int64_t i = p * B + d;
+                W r2 = rv[d];
+                if (mode == 0) {
+                    v.x[i] = xv[d] + a * wi[d];
+                    r2 = (W)((double)r2 - a * (double)qv[d]);
+                    v.r[i] = r2;
+                }
+                ri[d] = (double)r2;
+            }
+            if (B == 1) {
+                si[0] = (double)(W)((double)v.minv[p] * ri[0]);
+            } else {
+                const V* m = v.minv + p * 9;
+#pragma unroll
+                for (int d = 0; d < B; ++d)
+                    si[d] = (double)(W)((double)m[3 * d] * ri[0] + (double)m[3 * d + 1] * ri[1] +
+                                        (double)m[3 * d + 2] * ri[2]);
+            }
+#pragma unroll
+            for (int d = 0; d < B; ++d) {
+                v.s[p * B + d] = (W)si[d];
+                rr += ri[d] * ri[d];
+                rs += ri[d] * si[d];
+            }
+        }
+        if (nc > 0) {
+            __syncthreads();
+#pragma unroll
+            for (int d = 0; d < B; ++d) {
+                ss[tid * B + d] = si[d];
+                ws[tid * B + d] = wi[d];
+            }
+            __syncthreads();
+            const int64_t pn = (ps + T) < pe ? (ps + T) : pe;
+            project_rows<V>(v.AC + ps * B * v.ldac, v.ldac, (int)((pn - ps) * B), nc, ss, ws, tacc, vacc, cred);
+        }
+    }
+    const int stride = 2 * nc + 2;
+    double* myp = v.partials + bid * stride;
+    const double brr = block_sum(rr, red);
+    const double brs = block_sum(rs, red);
+    __syncthreads();
+    if (!FUSE) {
+        if (tid == 0) {
+            myp[0] = brr;
+            myp[1] = brs;
+        }
+        for (int c = tid; c < nc; c += T) {
+            myp[2 + c] = tacc[c];
+            myp[2 + nc + c] = vacc[c];
+        }
+        ktime_end(v.kslots, 1, bid, tm);
+        return;
+    }
+    // Fused finalize: the partials are stored agent-coherent (written
+    // through to where every XCD reads them), each thread waits for its
+    // stores to complete, and the workgroup that takes the last ticket of
+    // the counter reduces them with coherent loads.  Only that workgroup
+    // continues; the ticket counter is reset for the next launch.
+    if (tid == 0) {
+        __hip_atomic_store(myp, brr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(myp + 1, brs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    for (int c = tid; c < nc; c += T) {
+        __hip_atomic_store(myp + 2 + c, tacc[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(myp + 2 + nc + c, vacc[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
+    ktime_end(v.kslots, 1, bid, tm);
+    __syncthreads();
+    unsigned* ticket = reinterpret_cast<unsigned*>(red);
+    const int64_t g3 = v.geo.g3;
+    const int64_t grp = bid / kGroup;
+    const int64_t ng = (g3 + kGroup - 1) / kGroup;
+    const int64_t gsz = (g3 - grp * kGroup) < kGroup ? (g3 - grp * kGroup) : kGroup;
+    // level 1: the last workgroup of each group sums the group's rows
+    if (tid == 0) *ticket = __hip_atomic_fetch_add(v.sync + 1 + grp, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    unsigned mine = *ticket;
+    __syncthreads();
+    if (mine != (unsigned)(gsz - 1)) return;
+    if (tid == 0) __hip_atomic_store(v.sync + 1 + grp, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    double* gsum = v.partials + g3 * stride;
+    for (int kk = tid; kk < stride; kk += T) {
+        const double s = col_sum<true>(v.partials + grp * kGroup * stride, gsz, stride, kk);
+        __hip_atomic_store(gsum + grp * stride + kk, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
+    __syncthreads();
+    // level 2: the last group reducer finishes the step
+    if (tid == 0) *ticket = __hip_atomic_fetch_add(v.sync, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    mine = *ticket;
+    __syncthreads();
+    if (mine != (unsigned)(ng - 1)) return;
+    if (tid == 0) __hip_atomic_store(v.sync, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    finalize_update_body<V, W, true>(v, mode, pool);
 }
 
 // ------------------------------------------------------------------ K5
@@ -931,12 +1039,19 @@ __global__ __launch_bounds__(256) void k_spmv_dot(SysView<V, W> v) {
     spmv_dot_body<V, W, B>(v, blockIdx.x);
 }
 template <typename V, typename W, int B>
-__global__ __launch_bounds__(kT3) void k_update_reduce(SysView<V, W> v, int mode) {
-    update_reduce_body<V, W, B>(v, blockIdx.x, mode);
+__global__ __launch_bounds__(kT3, 4) void k_update_reduce(SysView<V, W> v, int mode) {
+    __shared__ double pool[upd_pool<B>()];
+    update_reduce_body<V, W, B, false>(v, blockIdx.x, mode, pool);
+}
+template <typename V, typename W, int B>
+__global__ __launch_bounds__(kT3, 4) void k_update_fused(SysView<V, W> v, int mode) {
+    __shared__ double pool[upd_pool<B>() > fin_pool() ? upd_pool<B>() : fin_pool()];
+    update_reduce_body<V, W, B, true>(v, blockIdx.x, mode, pool);
 }
 template <typename V, typename W>
 __global__ __launch_bounds__(kTF3) void k_finalize_update(SysView<V, W> v, int mode) {
-    finalize_update_body<V, W>(v, mode);
+    __shared__ double pool[fin_pool()];
+    finalize_update_body<V, W, false>(v, mode, pool);
 }
 template <typename V, typename W>
 __global__ __launch_bounds__(256) void k_correct_dir(SysView<V, W> v, int first) {
@@ -974,15 +1089,24 @@ __global__ __launch_bounds__(256) void kb_spmv_dot(const SysView<V, W>* __restri
     spmv_dot_body<V, W, B>(views[e.x], e.y);
 }
 template <typename V, typename W, int B>
-__global__ __launch_bounds__(kT3) void kb_update_reduce(const SysView<V, W>* __restrict__ views,
+__global__ __launch_bounds__(kT3, 4) void kb_update_reduce(const SysView<V, W>* __restrict__ views,
                                                         const int2* __restrict__ map, int mode) {
+    __shared__ double pool[upd_pool<B>()];
     const int2 e = map[blockIdx.x];
-    update_reduce_body<V, W, B>(views[e.x], e.y, mode);
+    update_reduce_body<V, W, B, false>(views[e.x], e.y, mode, pool);
+}
+template <typename V, typename W, int B>
+__global__ __launch_bounds__(kT3, 4) void kb_update_fused(const SysView<V, W>* __restrict__ views,
+                                                       const int2* __restrict__ map, int mode) {
+    __shared__ double pool[upd_pool<B>() > fin_pool() ? upd_pool<B>() : fin_pool()];
+    const int2 e = map[blockIdx.x];
+    update_reduce_body<V, W, B, true>(views[e.x], e.y, mode, pool);
 }
 template <typename V, typename W>
 __global__ __launch_bounds__(kTF3) void kb_finalize_update(const SysView<V, W>* __restrict__ views,
                                                            const int2* __restrict__ map, int mode) {
-    finalize_update_body<V, W>(views[map[blockIdx.x].x], mode);
+    __shared__ double pool[fin_pool()];
+    finalize_update_body<V, W, false>(views[map[blockIdx.x].x], mode, pool);
 }
 template <typename V, typename W>
 __global__ __launch_bounds__(256) void kb_correct_dir(const SysView<V, W>* __restrict__ views,
@@ -1289,7 +1413,8 @@ Geometry make_geometry(int64_t n, int64_t nslices, int block, int64_t cb3_req) {
 
 int64_t partial_doubles(const Geometry& g, int nc) {
     const int64_t c = std::max(nc, 1);
-    return std::max<int64_t>({(int64_t)g.g3 * (2 * c + 2), (int64_t)g.g1 + 8, (int64_t)g.gd * (c + 1), 1024});
+    const int64_t ng = (g.g3 + kGroup - 1) / kGroup;
+    return std::max<int64_t>({(int64_t)(g.g3 + ng) * (2 * c + 2), (int64_t)g.g1 + 8, (int64_t)g.gd * (c + 1), 1024});
 }
 
 // ----------------------------------------------------- single-system launches
@@ -1307,6 +1432,10 @@ void launch_update_only(const SysView<V, W>& v, int mode, hipStream_t stream) {
 
 template <typename V, typename W, int B>
 void launch_update_reduce(const SysView<V, W>& v, int mode, hipStream_t stream) {
+    if (v.fused) {
+        hipLaunchKernelGGL((k_update_fused<V, W, B>), dim3((unsigned)v.geo.g3), dim3(kT3), 0, stream, v, mode);
+        return;
+    }
     hipLaunchKernelGGL((k_update_reduce<V, W, B>), dim3((unsigned)v.geo.g3), dim3(kT3), 0, stream, v, mode);
     hipLaunchKernelGGL((k_finalize_update<V, W>), dim3(1), dim3(kTF3), 0, stream, v, mode);
 }
@@ -1346,6 +1475,12 @@ void batch_spmv_dot(const SysView<V, W>* views, const BatchMaps& m, hipStream_t 
 
 template <typename V, typename W, int B>
 void batch_update_reduce(const SysView<V, W>* views, const BatchMaps& m, int mode, hipStream_t stream) {
+    if (m.fused) {
+        if (m.count[BK_UPD] > 0)
+            hipLaunchKernelGGL((kb_update_fused<V, W, B>), dim3((unsigned)m.count[BK_UPD]), dim3(kT3), 0, stream,
+                               views, m.map[BK_UPD], mode);
+        return;
+    }
     if (m.count[BK_UPD] > 0)
         hipLaunchKernelGGL((kb_update_reduce<V, W, B>), dim3((unsigned)m.count[BK_UPD]), dim3(kT3), 0, stream, views,
                            m.map[BK_UPD], mode);

@@ -185,7 +185,7 @@ krs_status SeqImpl<V, W>::create(const krs_seq_desc& d, const double* C0, int32_
     ok = ok && d_s.reserve(ctx, n * sizeof(W));
     ok = ok && d_w.reserve(ctx, n * sizeof(W));
     ok = ok && d_q.reserve(ctx, n * sizeof(W));
-    ok = ok && d_st.reserve(ctx, sizeof(DevState));
+    ok = ok && d_st.reserve(ctx, kSyncOffset + kSyncBytes);
     ok = ok && d_mu.reserve(ctx, 3072 * sizeof(double));
     if (!ok) {
         set_error("device allocation failed while creating the sequence");
@@ -198,7 +198,7 @@ krs_status SeqImpl<V, W>::create(const krs_seq_desc& d, const double* C0, int32_
     KRS_HIP(hipMemcpyAsync(d_diag.p, diag.data(), diag.size() * sizeof(int64_t), hipMemcpyHostToDevice, stream));
     KRS_HIP(hipMemsetAsync(d_val64.p, 0, d_val64.bytes, stream));
     if (d_valV.p) KRS_HIP(hipMemsetAsync(d_valV.p, 0, d_valV.bytes, stream));
-    KRS_HIP(hipMemsetAsync(d_st.p, 0, sizeof(DevState), stream));
+    KRS_HIP(hipMemsetAsync(d_st.p, 0, kSyncOffset + kSyncBytes, stream));
     KRS_HIP(hipHostMalloc((void**)&h_st, sizeof(DevState), hipHostMallocDefault));
     std::memset(h_st, 0, sizeof(DevState));
     // ---- initial basis C0
@@ -348,7 +348,9 @@ SysView<V, W> SeqImpl<V, W>::view() {
     v.part1 = (double*)d_partials.p;
     v.partials = (double*)d_partials.p + kPart1;
     v.st = (DevState*)d_st.p;
+    v.sync = (unsigned*)((char*)d_st.p + kSyncOffset);
     v.kslots = (unsigned long long*)d_kslots.p;
+    v.fused = (desc.kernel_flags & 1) ? 0 : 1;
     return v;
 }
 
@@ -568,7 +570,8 @@ void SeqImpl<V, W>::trim() {
 
 template <typename V, typename W>
 int SeqImpl<V, W>::type_key() const {
-    return (std::is_same<V, double>::value ? 0 : 1) + (std::is_same<W, double>::value ? 0 : 2) + (B == 3 ? 4 : 0);
+    return (std::is_same<V, double>::value ? 0 : 1) + (std::is_same<W, double>::value ? 0 : 2) + (B == 3 ? 4 : 0) +
+           ((desc.kernel_flags & 1) ? 8 : 0);
 }
 
 template <typename V, typename W>
@@ -1078,6 +1081,7 @@ struct BatchRunner : RunnerBase {
                                        hipMemcpyHostToDevice, stream));
             off += lists[k].size();
         }
+        maps.fused = mem[0]->cur.fused;
         KRS_HIP(hipStreamSynchronize(stream));
         return KRS_OK;
     }
@@ -1149,7 +1153,7 @@ struct BatchRunner : RunnerBase {
 }  // namespace
 
 std::unique_ptr<RunnerBase> make_runner(krs_ctx* ctx, int key) {
-    const int B = (key & 4) ? 3 : 1;
+    const int B = (key & 4) ? 3 : 1;  // bit 3 (separate finalize) only splits the groups
     switch (key & 3) {
         case 0: return std::unique_ptr<RunnerBase>(new BatchRunner<double, double>(ctx, B));
         case 1: return std::unique_ptr<RunnerBase>(new BatchRunner<float, double>(ctx, B));

@@ -180,6 +180,23 @@ def test_graph_replay_matches_eager(gpu, precision):
         assert np.array_equal(a[k]["alpha"], b[k]["alpha"])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fused_finalize_matches_separate(gpu, precision):
+    """The end-of-step reduction run by the update kernel's last workgroup
+    (agent-coherent partials + ticket counter) gives the same iterates as a
+    separate single-workgroup kernel, bit for bit."""
+    seq = gen.config_elasticity(6, 3)
+    kw = dict(precision=precision, reuse="selective", ritz_eps=1e-8, max_basis=20, cap_policy="freeze",
+              tol=1e-8, max_iter=6000, update_rows=64)
+    a = _run_gpu(gpu, seq, 3, separate_finalize=True, **kw)
+    b = _run_gpu(gpu, seq, 3, separate_finalize=False, **kw)
+    for k in range(3):
+        assert a[k]["status"] == b[k]["status"] == 0
+        assert a[k]["iters"] == b[k]["iters"] and a[k]["n_c"] == b[k]["n_c"]
+        assert np.array_equal(a[k]["x"], b[k]["x"])
+        assert np.array_equal(a[k]["alpha"], b[k]["alpha"]) and np.array_equal(a[k]["rho"], b[k]["rho"])
+
+
 def test_fp32_vectors_mode_converges(gpu):
     seq = gen.config_elasticity(6, 2)
     res = _run_gpu(gpu, seq, 2, precision="fp32", reuse="selective", ritz_eps=1e-10, max_basis=24,
