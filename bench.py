@@ -11,9 +11,16 @@ basis update (SRKS).  The same systems are then solved with plain PCG
 Default workload: Q1 elasticity on a 40^3 mesh (n = 201,720 dofs,
 15,548,742 nonzeros in 3x3 blocks), 64 stiff cubic inclusions, cumulative
 damage between systems, 3x3 block-Jacobi, SRKS with eps = 1e-8 and a basis
-of at most 60 vectors (frozen once full), mixed precision.
+of at most 60 vectors (frozen once full); double-precision operator and
+vectors with the basis and preconditioner streamed in single precision
+(--precision fp32basis; "mixed" also rounds the matrix values, which on this
+stiff-inclusion problem costs about half again as many iterations).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision mixed|fp64]
+Other workloads: --workload batched (many diffusion sequences in fused
+launches), --workload serving (Poisson arrivals into the continuous-batching
+server), elasticity100, diffusion20.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32basis|mixed|fp64|fp32]
 
 Prints one JSON line.
 """
@@ -264,7 +271,7 @@ def run_serving(args, K, torch, data):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"mixed": "f32+f64", "fp64": "f64", "fp32": "f32"}[args.precision],
+        "dtype": {"mixed": "f32+f64", "fp64": "f64", "fp32": "f32", "fp32basis": "f64+f32"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"serving: {len(seqs)} clients, Q1 elasticity "
                                f"{min(s.n for s in seqs)}..{max(s.n for s in seqs)} dofs, {args.systems} systems "
@@ -348,7 +355,7 @@ def run_batched(args, K, torch, data):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"mixed": "f32+f64", "fp64": "f64", "fp32": "f32"}[args.precision],
+        "dtype": {"mixed": "f32+f64", "fp64": "f64", "fp32": "f32", "fp32basis": "f64+f32"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"batched: {len(seqs)} diffusion sequences, n ~ U[5e3, 2e5] (sum {n_tot}), "
                                f"SRKS eps={kw['ritz_eps']:.0e} cap {wl['max_basis']}, fused launches",
@@ -373,7 +380,7 @@ def main():
     ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="elasticity40", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64", "fp32"])
+    ap.add_argument("--precision", default="fp32basis", choices=["mixed", "fp64", "fp32", "fp32basis"])
     ap.add_argument("--max-iter", type=int, default=30000)
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--no-plain", dest="plain", action="store_false")
@@ -439,7 +446,7 @@ def main():
         plain = run_phase(K, ctx, seq, dev_sys, "none", args, wl, order)
     ctx.close()
 
-    p = 8 if args.precision == "fp64" else 4       # matrix value bytes
+    p = 8 if args.precision in ("fp64", "fp32basis") else 4       # matrix value bytes
     pw = 4 if args.precision == "fp32" else 8      # Krylov vector bytes
     value = args.steps / srks["time"]
     infos = srks["infos"]
@@ -460,7 +467,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"mixed": "f32+f64", "fp64": "f64", "fp32": "f32"}[args.precision],
+        "dtype": {"mixed": "f32+f64", "fp64": "f64", "fp32": "f32", "fp32basis": "f64+f32"}[args.precision],
         "data": "synthetic",
         "config": {
             "workload": f"{args.workload}: Q1 elasticity {wl['size']}^3" if wl["kind"] == "elasticity"
@@ -474,7 +481,7 @@ def main():
             "precond": "3x3 block-Jacobi" if seq.block == 3 else "Jacobi",
             "tol": 1e-8,
             "precision": args.precision,
-            "precision_detail": {"mixed": "fp32 matrix/preconditioner/basis, fp64 vectors and reductions", "fp64": "fp64 throughout", "fp32": "fp32 matrix, basis and vectors, fp64 reductions"}[args.precision],
+            "precision_detail": {"mixed": "fp32 matrix/preconditioner/basis, fp64 vectors and reductions", "fp64": "fp64 throughout", "fp32": "fp32 matrix, basis and vectors, fp64 reductions", "fp32basis": "fp64 matrix and vectors, fp32 basis (C, AC) and preconditioner, fp64 reductions"}[args.precision],
         },
         "iters_mean": float(np.mean(iters)),
         "update_rows": sorted({i["update_rows"] for i in infos}),

@@ -46,7 +46,7 @@ typedef enum {
     KRS_E_STATE = 8            /* call not valid in the object's current state */
 } krs_status;
 
-typedef enum { KRS_FP64 = 0, KRS_MIXED = 1, KRS_FP32 = 2 } krs_precision;
+typedef enum { KRS_FP64 = 0, KRS_MIXED = 1, KRS_FP32 = 2, KRS_FP32_BASIS = 3 } krs_precision;
 /* KRS_FP64: every vector, value and reduction in double precision.
  * KRS_MIXED: matrix values, preconditioner and basis (C, A C) stored and
  *   streamed in single precision; Krylov vectors, the iterate, every
@@ -54,7 +54,14 @@ typedef enum { KRS_FP64 = 0, KRS_MIXED = 1, KRS_FP32 = 2 } krs_precision;
  *   eigenproblem and periodic true-residual refinement (r = b - A x with the
  *   double-precision matrix, then a coarse re-projection) in double.
  * KRS_FP32: as KRS_MIXED but the Krylov vectors are single precision too
- *   (fewer bytes per iteration, more iterations on ill-conditioned systems). */
+ *   (fewer bytes per iteration, more iterations on ill-conditioned systems).
+ * KRS_FP32_BASIS: double-precision operator (matrix values) and vectors;
+ *   the basis (C, A C) and the preconditioner stored and streamed in single
+ *   precision, with the periodic refinement of KRS_MIXED (it re-projects the
+ *   residual, whose C^T r recurrence runs on the rounded A C).  On
+ *   ill-conditioned systems, where single-precision matrix values perturb
+ *   the low end of the spectrum and cost iterations, this keeps the
+ *   iteration count of KRS_FP64 with fewer bytes. */
 
 typedef enum { KRS_REUSE_NONE = 0, KRS_REUSE_TOTAL = 1, KRS_REUSE_SELECTIVE = 2 } krs_reuse;
 typedef enum { KRS_PC_JACOBI = 0, KRS_PC_BJACOBI3 = 1 } krs_precond;

@@ -29,7 +29,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 # ------------------------------------------------------------ ABI mirror
 KRS_OK, KRS_E_INVALID, KRS_E_OOM, KRS_E_NOT_SPD, KRS_E_COARSE_SINGULAR, KRS_E_MAXIT, KRS_E_DEVICE, KRS_E_BUSY, \
     KRS_E_STATE = range(9)
-PRECISION = {"fp64": 0, "mixed": 1, "fp32": 2}
+PRECISION = {"fp64": 0, "mixed": 1, "fp32": 2, "fp32basis": 3}
 REUSE = {"none": 0, "total": 1, "trks": 1, "selective": 2, "srks": 2}
 PRECOND = {"jacobi": 0, "bjacobi3": 1, "block3": 1}
 CAP_POLICY = {"restart": 0, "freeze": 1}

@@ -120,7 +120,8 @@ krs_status krs_seq_create(krs_ctx* ctx, const krs_seq_desc* d, const double* C0,
         set_error("invalid sequence description");
         return KRS_E_INVALID;
     }
-    if (d->precision != KRS_FP64 && d->precision != KRS_MIXED && d->precision != KRS_FP32) {
+    if (d->precision != KRS_FP64 && d->precision != KRS_MIXED && d->precision != KRS_FP32 &&
+        d->precision != KRS_FP32_BASIS) {
         set_error("unknown precision");
         return KRS_E_INVALID;
     }
@@ -164,7 +165,7 @@ krs_status krs_seq_create(krs_ctx* ctx, const krs_seq_desc* d, const double* C0,
         return KRS_E_DEVICE;
     }
     krs_seq* s = new krs_seq();
-    if (d->precision == KRS_MIXED) s->impl.reset(new krs::SeqImpl<float, double>());
+    if (d->precision == KRS_MIXED || d->precision == KRS_FP32_BASIS) s->impl.reset(new krs::SeqImpl<float, double>());
     else if (d->precision == KRS_FP32) s->impl.reset(new krs::SeqImpl<float, float>());
     else s->impl.reset(new krs::SeqImpl<double, double>());
     s->impl->ctx = ctx;

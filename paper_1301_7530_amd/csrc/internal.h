@@ -96,6 +96,8 @@ struct SysView {
     const int32_t* col;        // [slots*64] block column per entry
     const int64_t* slice_ptr;  // [nslices+1] slot offsets
     const V* val;              // values in V precision (planar per slot)
+    int32_t op64;              // 1: the SpMV streams val64 (double-precision operator)
+    int32_t pad_op;
     const double* val64;       // values in double (for true residuals / A C)
     const V* minv;             // preconditioner inverse: n (Jacobi) or 9*nb (3x3 blocks)
     int64_t n;                 // scalar rows

@@ -344,7 +344,8 @@ __device__ __forceinline__ void spmv_dot_body(const SysView<V, W>& v, int64_t bi
         // 4 slices per workgroup, one per wave
         for (int64_t sl = bid * 4 + wave; sl < v.nslices; sl += nblk * 4) {
             const int64_t k0 = v.slice_ptr[sl], k1 = v.slice_ptr[sl + 1];
-            const W acc = ell_row1<V, W>(v.val, v.col, v.w, k0, k1, lane);
+            const W acc = v.op64 ? ell_row1<double, W>(v.val64, v.col, v.w, k0, k1, lane)
+                                 : ell_row1<V, W>(v.val, v.col, v.w, k0, k1, lane);
             const int64_t row = sl * 64 + lane;
             if (row < v.n) {
                 v.q[row] = acc;
@@ -356,7 +357,8 @@ __device__ __forceinline__ void spmv_dot_body(const SysView<V, W>& v, int64_t bi
         const int d = wave;
         for (int64_t sl = bid; sl < v.nslices; sl += nblk) {
             const int64_t k0 = v.slice_ptr[sl], k1 = v.slice_ptr[sl + 1];
-            const W acc = ell_row3<V, W>(v.val, v.col, v.w, k0, k1, lane, d);
+            const W acc = v.op64 ? ell_row3<double, W>(v.val64, v.col, v.w, k0, k1, lane, d)
+                                 : ell_row3<V, W>(v.val, v.col, v.w, k0, k1, lane, d);
             const int64_t p = sl * 64 + lane;
             if (p < v.nb) {
                 v.q[3 * p + d] = acc;

@@ -176,7 +176,8 @@ krs_status SeqImpl<V, W>::create(const krs_seq_desc& d, const double* C0, int32_
     ok = ok && d_map.reserve(ctx, map.size() * sizeof(int64_t));
     ok = ok && d_diag.reserve(ctx, diag.size() * sizeof(int64_t));
     ok = ok && d_val64.reserve(ctx, (size_t)nslots * kSlice * vb * sizeof(double));
-    if (!std::is_same<V, double>::value) ok = ok && d_valV.reserve(ctx, (size_t)nslots * kSlice * vb * sizeof(V));
+    if (!std::is_same<V, double>::value && !op64())
+        ok = ok && d_valV.reserve(ctx, (size_t)nslots * kSlice * vb * sizeof(V));
     ok = ok && d_minv.reserve(ctx, (size_t)nb * vb * sizeof(V));
     ok = ok && d_bad.reserve(ctx, 64);
     ok = ok && d_b.reserve(ctx, n * sizeof(double));
@@ -277,7 +278,7 @@ krs_status SeqImpl<V, W>::submit(const double* values, const double* b, bool dev
     } else {
         KRS_HIP(hipMemcpyAsync(d_b.p, b, n * sizeof(double), hipMemcpyDeviceToDevice, stream));
     }
-    V* valV = std::is_same<V, double>::value ? nullptr : (V*)d_valV.p;
+    V* valV = (std::is_same<V, double>::value || op64()) ? nullptr : (V*)d_valV.p;
     KRS_HIP(hipMemsetAsync(d_bad.p, 0, 64, stream));
     if (B == 1) {
         launch_scatter_values<V, 1>(vin, (const int64_t*)d_map.p, nnzb, (double*)d_val64.p, valV, stream);
@@ -315,6 +316,7 @@ SysView<V, W> SeqImpl<V, W>::view() {
     v.col = (const int32_t*)d_col.p;
     v.slice_ptr = (const int64_t*)d_slice_ptr.p;
     v.val = std::is_same<V, double>::value ? (const V*)d_val64.p : (const V*)d_valV.p;
+    v.op64 = (std::is_same<V, double>::value || op64()) ? 1 : 0;
     v.val64 = (const double*)d_val64.p;
     v.minv = (const V*)d_minv.p;
     v.n = n;
@@ -677,6 +679,8 @@ krs_status SeqImpl<V, W>::begin_solve() {
     std::memset(h_st, 0, sizeof(DevState));
     h_st->tol2 = desc.tol * desc.tol;
     // reliable updates whenever single precision is involved
+    // periodic re-projection and residual replacement whenever the basis
+    // (and so the C^T r recurrence) is single precision
     const bool lowp = !std::is_same<V, double>::value;
     h_st->drop2 = (lowp && desc.refine_drop > 0.0) ? desc.refine_drop * desc.refine_drop : 0.0;
     h_st->refine_every = lowp ? desc.refine_every : 0;
@@ -812,8 +816,9 @@ int64_t SeqImpl<V, W>::model_bytes_per_iter() const {
     // B_A + B_M + 11 n p_w + 2 n p_x + 2 n nc p (see the design notes);
     // p: matrix / basis storage, p_w: Krylov vectors, p_x = 8
     const int64_t p = sizeof(V), pw = sizeof(W);
+    const int64_t pa = op64() ? 8 : p;  // matrix value bytes
     const int64_t nnz = nnzb * B * B;
-    const int64_t BA = (B == 1) ? nnz * (p + 4) : nnz * p + 4 * nnzb;
+    const int64_t BA = (B == 1) ? nnz * (pa + 4) : nnz * pa + 4 * nnzb;
     const int64_t BM = (B == 1) ? n * p : 3 * n * p;
     const int64_t vec = 11 * n * pw + 2 * n * 8 - (desc.reuse == KRS_REUSE_SELECTIVE ? 0 : n * pw);
     return BA + BM + vec + 2 * n * (int64_t)nc * p;

@@ -126,6 +126,8 @@ struct SeqImpl : SeqBase {
     void enqueue_iterations(const SysView<V, W>& v, int k);
     void enqueue_refine(const SysView<V, W>& v);
     int64_t model_bytes_per_iter() const;
+    // double-precision operator with a single-precision basis / preconditioner
+    bool op64() const { return desc.precision == KRS_FP32_BASIS; }
 };
 
 // Fused launches over a set of begun solves of one (V, W, B) type

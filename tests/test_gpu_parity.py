@@ -197,6 +197,23 @@ def test_fused_finalize_matches_separate(gpu, precision):
         assert np.array_equal(a[k]["alpha"], b[k]["alpha"]) and np.array_equal(a[k]["rho"], b[k]["rho"])
 
 
+def test_fp32_basis_mode_keeps_fp64_iterations(gpu):
+    """Double-precision operator with a single-precision basis and
+    preconditioner: same true-residual bar, iteration counts close to FP64
+    (the residual recursion uses the exact operator; only the projector and
+    preconditioner are rounded, and periodic re-projection bounds the drift
+    of C^T r)."""
+    seq = gen.config_elasticity(6, 3)
+    kw = dict(reuse="selective", ritz_eps=1e-8, max_basis=24, cap_policy="freeze", tol=1e-8, max_iter=8000)
+    a = _run_gpu(gpu, seq, 3, precision="fp64", **kw)
+    b = _run_gpu(gpu, seq, 3, precision="fp32basis", **kw)
+    for k in range(3):
+        assert b[k]["status"] == 0
+        assert _relres(seq.csr(k), b[k]["x"]) <= 1e-8 * 1.05
+        assert abs(b[k]["iters"] - a[k]["iters"]) <= max(5, 0.05 * a[k]["iters"]), (k, a[k]["iters"], b[k]["iters"])
+        assert abs(b[k]["n_c"] - a[k]["n_c"]) <= 2
+
+
 def test_fp32_vectors_mode_converges(gpu):
     seq = gen.config_elasticity(6, 2)
     res = _run_gpu(gpu, seq, 2, precision="fp32", reuse="selective", ritz_eps=1e-10, max_basis=24,
