@@ -38,6 +38,12 @@ import numpy as np
 
 HBM_PEAK = 8.0e12  # MI355X HBM3E, bytes/s
 
+# Bytes per launch of k_spmv_dot read from the hardware counters
+# (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 KiB, the factors from a 1 GiB
+# device copy), by (workload, precision); kept only while the kernel is the
+# one the counters were taken on.
+TRAFFIC_K1 = {("elasticity40", "fp32basis"): 149656313}
+
 WORKLOADS = {
     "elasticity40": dict(kind="elasticity", size=40, n_systems=20, config_id=2, max_basis=60, eps=1e-8),
     "elasticity100": dict(kind="elasticity", size=100, n_systems=30, config_id=3, max_basis=200, eps=1e-8),
@@ -46,6 +52,8 @@ WORKLOADS = {
     "batched": dict(kind="batched", size=None, n_systems=10, config_id=4, max_basis=60, eps=1e-8),
     # clients with elasticity sequences (1e4..5e5 dofs) served with continuous batching
     "serving": dict(kind="serving", size=None, n_systems=50, config_id=5, max_basis=200, eps=1e-8),
+    # calibration for hardware byte counters: device-to-device copies of a known size
+    "copy": dict(kind="copy", size=None, n_systems=0, config_id=0, max_basis=0, eps=0.0),
 }
 
 
@@ -419,6 +427,16 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.workload == "copy":
+        nbytes = 1 << 30
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"workload": "copy", "bytes_read_per_copy": nbytes, "bytes_written_per_copy": nbytes,
+                          "copies": args.steps}), flush=True)
+        return
     if args.workload == "batched":
         run_batched(args, K, torch, batched_data)
         return
@@ -498,7 +516,7 @@ def main():
             "peak": HBM_PEAK / 1e9,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK,
-            "traffic": None,
+            "traffic": TRAFFIC_K1.get((args.workload, args.precision)),
             "algorithmic_bytes_per_launch": kb,
             "launches_sampled": k_cnt,
         },
