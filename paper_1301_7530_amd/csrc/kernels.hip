@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cstdint>
 
 #include "internal.h"
@@ -1305,6 +1306,79 @@ __global__ __launch_bounds__(256) void k_basis_combine(const V* Z, int64_t ldz, 
     }
 }
 
+// out[:, t] = sum_j Z[:, j] F[j, t] for single-precision Z and out, on the
+// matrix cores (v_mfma_f32_32x32x2f32): a wave owns 32 rows and CT tiles of
+// 32 columns, accumulating over j two at a time; a workgroup (4 waves) owns
+// 128 rows; F (double) is staged in LDS as float, KC of its rows at a time.
+// Operand layout of the instruction: lane l supplies A[l % 32][l / 32] and
+// B[l / 32][l % 32]; accumulator register r of lane l holds
+// D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
+typedef float mfma_f32x16 __attribute__((ext_vector_type(16)));
+
+template <int CT>
+__global__ __launch_bounds__(256) void k_basis_combine_mfma(const float* __restrict__ Z, int64_t ldz, int m,
+                                                            const double* __restrict__ F, int s,
+                                                            float* __restrict__ out, int64_t ldo, int64_t n) {
+    constexpr int KC = 64;
+    constexpr int NC = CT * 32;
+    constexpr int UK = 8;  // pairs of j whose Z loads are issued together
+    __shared__ float sF[KC][NC];
+    const int c0 = blockIdx.y * NC;
+    const int ncol = (s - c0) < NC ? (s - c0) : NC;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t row0 = (int64_t)blockIdx.x * 128 + wave * 32;
+    const int64_t arow = row0 + (lane & 31);
+    const bool rok = arow < n;
+    const int khalf = lane >> 5;
+    mfma_f32x16 acc[CT];
+#pragma unroll
+    for (int t = 0; t < CT; ++t)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
+    for (int k0 = 0; k0 < m; k0 += KC) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < KC * NC; e += 256) {
+            const int kk = e / NC, cc = e % NC;
+            const int kx = k0 + kk;
+            sF[kk][cc] = (kx < m && cc < ncol) ? (float)F[(int64_t)(c0 + cc) * m + kx] : 0.f;
+        }
+        __syncthreads();
+        const int kn = (m - k0) < KC ? (m - k0) : KC;
+        for (int kk = 0; kk < kn; kk += 2 * UK) {
+            float a[UK];
+#pragma unroll
+            for (int u = 0; u < UK; ++u) {
+                // past the last column of Z the staged F row is zero: any
+                // finite Z value will do, so the index is clamped
+                int kx = k0 + kk + 2 * u + khalf;
+                kx = kx < m ? kx : m - 1;
+                a[u] = rok ? Z[(int64_t)kx * ldz + arow] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < UK; ++u) {
+                const int kr = kk + 2 * u + khalf;
+                if (kk + 2 * u < kn) {
+#pragma unroll
+                    for (int t = 0; t < CT; ++t) {
+                        const float b = sF[kr < KC ? kr : KC - 1][t * 32 + (lane & 31)];
+                        acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[u], b, acc[t], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < CT; ++t) {
+        const int col = t * 32 + (lane & 31);
+        if (col >= ncol) continue;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int64_t row = row0 + 8 * (r >> 2) + 4 * khalf + (r & 3);
+            if (row < n) out[(int64_t)(c0 + col) * ldo + row] = acc[t][r];
+        }
+    }
+}
+
 template <typename V>
 __global__ void k_scale_columns(V* C, int64_t ldc, int64_t n, const double* scale, int k) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1561,6 +1635,20 @@ template <typename V>
 void launch_basis_combine(const V* Z, int64_t ldz, int m, const double* F, int s, V* out, int64_t ldo, int64_t n,
                           hipStream_t stream) {
     if (s <= 0 || m <= 0) return;
+    if (std::is_same<V, float>::value) {
+        const float* Zf = reinterpret_cast<const float*>(Z);
+        float* of = reinterpret_cast<float*>(out);
+        if (s <= 32)
+            hipLaunchKernelGGL((k_basis_combine_mfma<1>), dim3(cdiv(n, 128), 1), dim3(256), 0, stream, Zf, ldz, m, F,
+                               s, of, ldo, n);
+        else if (s <= 64)
+            hipLaunchKernelGGL((k_basis_combine_mfma<2>), dim3(cdiv(n, 128), 1), dim3(256), 0, stream, Zf, ldz, m, F,
+                               s, of, ldo, n);
+        else
+            hipLaunchKernelGGL((k_basis_combine_mfma<4>), dim3(cdiv(n, 128), (unsigned)((s + 127) / 128)), dim3(256),
+                               0, stream, Zf, ldz, m, F, s, of, ldo, n);
+        return;
+    }
     dim3 grid(cdiv(n, 256), (unsigned)((s + 7) / 8));
     hipLaunchKernelGGL((k_basis_combine<V>), grid, dim3(256), 0, stream, Z, ldz, m, F, s, out, ldo, n);
 }
