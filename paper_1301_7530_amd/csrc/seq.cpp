@@ -661,10 +661,16 @@ krs_status SeqImpl<V, W>::begin_solve() {
     trks_slots = 0;
     if (desc.reuse == KRS_REUSE_SELECTIVE) {
         hist = desc.history_cap > 0 ? std::min(desc.history_cap, max_iter + 1) : max_iter + 1;
-        if (!d_Z.reserve(ctx, (size_t)ldc * hist * sizeof(V))) {
-            set_error("device allocation failed for the Krylov history");
-            return KRS_E_OOM;
+        // keep as much of the run as memory allows: a shorter history only
+        // shortens the Lanczos pair used for the Ritz analysis
+        while (!d_Z.reserve(ctx, (size_t)ldc * hist * sizeof(V))) {
+            if (hist <= 64) {
+                set_error("device allocation failed for the Krylov history");
+                return KRS_E_OOM;
+            }
+            hist /= 2;
         }
+        history_kept = hist;
     } else if (desc.reuse == KRS_REUSE_TOTAL) {
         hist = max_iter + 1;
         if (desc.max_basis > 0) hist = std::min(hist, std::max(0, desc.max_basis - nc));

@@ -89,6 +89,7 @@ struct SeqImpl : SeqBase {
     Geometry geo{};
     int tuned_nc = 0;
     int dropped_last = 0;
+    int history_kept = 0;
     SysView<V, W> cur{};          // view of the solve in progress
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // rebuild / iteration timers
     // captured iteration blocks (16 and 64 iterations + refinement step)
