@@ -52,7 +52,7 @@ WORKLOADS = {
                           history_cap=16000),
     "diffusion20": dict(kind="diffusion", size=(20, 20, 20), n_systems=8, config_id=1, max_basis=0, eps=1e-14),
     # many independent diffusion sequences (n ~ U[5e3, 2e5]) solved in fused launches
-    "batched": dict(kind="batched", size=None, n_systems=10, config_id=4, max_basis=60, eps=1e-8),
+    "batched": dict(kind="batched", size=None, n_systems=10, config_id=4, max_basis=60, eps=1e-8, cap_policy="cost"),
     # clients with elasticity sequences (1e4..5e5 dofs) served with continuous batching
     "serving": dict(kind="serving", size=None, n_systems=50, config_id=5, max_basis=200, eps=1e-8),
     # calibration for hardware byte counters: device-to-device copies of a known size
@@ -78,7 +78,8 @@ def run_phase(K, ctx, seq, dev_sys, reuse, args, wl, order, timing=False):
 
     s = K.sequence_for(ctx, seq, precision=args.precision, reuse=reuse, tol=1e-8, max_iter=args.max_iter,
                        history_cap=wl.get("history_cap", 0),
-                       ritz_eps=args.eps if args.eps else wl["eps"], max_basis=wl["max_basis"], cap_policy="freeze",
+                       ritz_eps=args.eps if args.eps else wl["eps"], max_basis=args.max_basis or wl["max_basis"],
+                       cap_policy="freeze",
                        refine_drop=args.refine_drop, autotune=args.autotune, update_rows=args.update_rows,
                        eager=args.eager, separate_finalize=args.separate_finalize)
     x = torch.empty(seq.n, dtype=torch.float64, device="cuda")
@@ -314,7 +315,7 @@ def run_batched(args, K, torch, data):
     torch.cuda.synchronize()
     ctx = K.Context(0)
     kw = dict(precision=args.precision, tol=1e-8, max_iter=args.max_iter, ritz_eps=args.eps or wl["eps"],
-              max_basis=wl["max_basis"], cap_policy="freeze", history_cap=args.history_cap,
+              max_basis=wl["max_basis"], cap_policy=wl.get("cap_policy", "freeze"), history_cap=args.history_cap,
               refine_drop=args.refine_drop)
 
     def phase(reuse, fused):
@@ -371,7 +372,8 @@ def run_batched(args, K, torch, data):
         "dtype": {"mixed": "f32+f64", "fp64": "f64", "fp32": "f32", "fp32basis": "f64+f32"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"batched: {len(seqs)} diffusion sequences, n ~ U[5e3, 2e5] (sum {n_tot}), "
-                               f"SRKS eps={kw['ritz_eps']:.0e} cap {wl['max_basis']}, fused launches",
+                               f"SRKS eps={kw['ritz_eps']:.0e} cap {wl['max_basis']} ({kw['cap_policy']}), "
+                               f"fused launches",
                    "sequences": len(seqs), "sum_n": n_tot, "precision": args.precision,
                    "history_cap": args.history_cap},
         "iters_mean": fused["iters_mean"],
@@ -403,6 +405,7 @@ def main():
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="keep the default update-kernel tile instead of timing candidates")
     ap.add_argument("--update-rows", type=int, default=0, help="fixed update-kernel block rows per workgroup")
+    ap.add_argument("--max-basis", type=int, default=0, help="basis cap (0: the workload's)")
     ap.add_argument("--sequences", type=int, default=64, help="batched workload: number of sequences")
     ap.add_argument("--history-cap", type=int, default=256, help="batched workload: Krylov vectors kept per solve")
     ap.add_argument("--eager", action="store_true", help="launch kernels one by one instead of graph replay")
@@ -499,7 +502,7 @@ def main():
             "nnz": seq.nnzb * seq.block * seq.block,
             "systems_timed": args.steps,
             "reuse": f"SRKS eps={args.eps if args.eps else wl['eps']:.0e}" if wl["max_basis"] else "TRKS",
-            "max_basis": wl["max_basis"],
+            "max_basis": args.max_basis or wl["max_basis"],
             "cap_policy": "freeze",
             "precond": "3x3 block-Jacobi" if seq.block == 3 else "Jacobi",
             "tol": 1e-8,
@@ -512,6 +515,8 @@ def main():
         "rel_res_true_max": float(max(i["rel_res_true"] for i in infos)),
         "refinements_mean": float(np.mean([i["refinements"] for i in infos])),
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
+        "phase_ms_mean": {k: float(np.mean([i[k] for i in infos])) for k in
+                          ("t_setup_ms", "t_rebuild_ms", "t_iter_ms", "t_recycle_ms")},
         "hbm_frac_model": model_bytes / srks["time"] / HBM_PEAK,
         "kernel_ms_mean": {name: srks["ktimes"][j][1] for j, name in enumerate(("spmv_dot", "update_reduce", "correct_dir"))},
         "roofline": {

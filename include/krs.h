@@ -68,13 +68,20 @@ typedef enum { KRS_PC_JACOBI = 0, KRS_PC_BJACOBI3 = 1 } krs_precond;
 /* KRS_PC_JACOBI: M = diag(A).  KRS_PC_BJACOBI3: M = the 3x3 diagonal blocks
  * (requires block == 3). */
 
-typedef enum { KRS_CAP_RESTART = 0, KRS_CAP_FREEZE = 1 } krs_cap_policy;
+typedef enum { KRS_CAP_RESTART = 0, KRS_CAP_FREEZE = 1, KRS_CAP_COST = 2 } krs_cap_policy;
 /* With max_basis = n_c_lim > 0:
  * KRS_CAP_RESTART: once the basis reaches n_c_lim columns it is reset to the
  *   initial basis C0 (Algorithm 3, last step).
  * KRS_CAP_FREEZE: columns are appended only while the basis is below
  *   n_c_lim; SRKS appends the smallest selected Ritz values first, TRKS the
- *   first search directions. */
+ *   first search directions.
+ * KRS_CAP_COST: as KRS_CAP_FREEZE, and after each solve its modelled bytes
+ *   (iterations x bytes per iteration, krs_solve_info.model_bytes) are
+ *   compared with those of the latest solve made with the initial basis
+ *   alone; when the recycled columns did not lower them, the basis is reset
+ *   to C0 and nothing is appended for the next three systems, six after a
+ *   second failed trial in a row, and so on up to 48 (the limit "set after a
+ *   complexity analysis" of Section 4.4). */
 
 typedef struct krs_ctx krs_ctx;
 typedef struct krs_seq krs_seq;

@@ -32,7 +32,7 @@ KRS_OK, KRS_E_INVALID, KRS_E_OOM, KRS_E_NOT_SPD, KRS_E_COARSE_SINGULAR, KRS_E_MA
 PRECISION = {"fp64": 0, "mixed": 1, "fp32": 2, "fp32basis": 3}
 REUSE = {"none": 0, "total": 1, "trks": 1, "selective": 2, "srks": 2}
 PRECOND = {"jacobi": 0, "bjacobi3": 1, "block3": 1}
-CAP_POLICY = {"restart": 0, "freeze": 1}
+CAP_POLICY = {"restart": 0, "freeze": 1, "cost": 2}
 
 _D = ctypes.POINTER(ctypes.c_double)
 _I64 = ctypes.POINTER(ctypes.c_int64)

@@ -134,7 +134,7 @@ krs_status krs_seq_create(krs_ctx* ctx, const krs_seq_desc* d, const double* C0,
         set_error("KRS_PC_BJACOBI3 goes with block 3, KRS_PC_JACOBI with block 1");
         return KRS_E_INVALID;
     }
-    if (d->cap_policy != KRS_CAP_RESTART && d->cap_policy != KRS_CAP_FREEZE) {
+    if (d->cap_policy != KRS_CAP_RESTART && d->cap_policy != KRS_CAP_FREEZE && d->cap_policy != KRS_CAP_COST) {
         set_error("unknown cap policy");
         return KRS_E_INVALID;
     }

@@ -846,7 +846,38 @@ krs_status SeqImpl<V, W>::recycle(int32_t* n_added) {
     int added = 0;
     last_theta.clear();
     last_sel.clear();
-    if (desc.reuse == KRS_REUSE_TOTAL && m > 0) {
+    // Cost cap: the modelled bytes of the last solve (iterations times bytes
+    // per iteration, which grow with the basis) against those of the latest
+    // solve made with the initial basis alone.  Recycled columns that did
+    // not pay for themselves are dropped (back to C0) and nothing is
+    // appended for the next kCostHold systems (doubling with each failed
+    // trial in a row).
+    bool append_ok = true;
+    if (desc.cap_policy == KRS_CAP_COST) {
+        const int64_t cost = info_last.model_bytes;
+        if (info_last.n_c <= nc0) {
+            ref_cost = cost;
+            if (cost_hold > 0) {
+                --cost_hold;
+                append_ok = false;
+            }
+        } else if (ref_cost > 0 && cost >= ref_cost) {
+            if (nc0 > 0)
+                KRS_HIP(hipMemcpyAsync(d_C.p, d_C0.p, (size_t)ldc * nc0 * sizeof(V), hipMemcpyDeviceToDevice, stream));
+            nc = nc0;
+            restarts += 1;
+            // every failed trial doubles the wait before the next one
+            cost_hold = kCostHold << std::min(cost_fails, 4);
+            cost_fails += 1;
+            append_ok = false;
+        } else {
+            cost_fails = 0;
+        }
+    }
+    const bool capped = desc.max_basis > 0 && (desc.cap_policy == KRS_CAP_FREEZE || desc.cap_policy == KRS_CAP_COST);
+    if (!append_ok) {
+        // nothing appended
+    } else if (desc.reuse == KRS_REUSE_TOTAL && m > 0) {
         // w_j / sqrt((w_j, A w_j)) for the captured directions (Algorithm 2)
         const int cnt = std::min(m, trks_slots);
         if (cnt > 0) {
@@ -859,8 +890,7 @@ krs_status SeqImpl<V, W>::recycle(int32_t* n_added) {
             nc += cnt;
             added = cnt;
         }
-    } else if (desc.reuse == KRS_REUSE_SELECTIVE && m > 1 &&
-               !(desc.max_basis > 0 && desc.cap_policy == KRS_CAP_FREEZE && nc >= desc.max_basis)) {
+    } else if (desc.reuse == KRS_REUSE_SELECTIVE && m > 1 && !(capped && nc >= desc.max_basis)) {
         // (with a full frozen basis nothing could be appended: no extraction)
         const int hist = h_st->hist_cap;
         // leading part of the Lanczos run: within the kept history and
@@ -873,7 +903,7 @@ krs_status SeqImpl<V, W>::recycle(int32_t* n_added) {
             std::vector<double> d1(dd.begin(), dd.end() - 1);
             std::vector<double> l21(l2.begin(), l2.begin() + (mu - 2));
             const int nt = host_threads();
-            const bool frozen = desc.max_basis > 0 && desc.cap_policy == KRS_CAP_FREEZE;
+            const bool frozen = capped;
             std::vector<double> th_m(mu, 0.0);  // descending (Algorithm 3 order)
             std::vector<int> sel;               // descending indices, ascending order
             if (!frozen) {

@@ -90,6 +90,10 @@ struct SeqImpl : SeqBase {
     int tuned_nc = 0;
     int dropped_last = 0;
     int history_kept = 0;
+    int64_t ref_cost = 0;   // modelled bytes of the latest solve with the initial basis (cost cap)
+    int cost_hold = 0;      // systems left before the cost cap lets columns be appended again
+    int cost_fails = 0;     // failed trials of recycled columns in a row
+    static constexpr int kCostHold = 3;
     SysView<V, W> cur{};          // view of the solve in progress
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // rebuild / iteration timers
     // captured iteration blocks (16 and 64 iterations + refinement step)

@@ -134,3 +134,52 @@ def test_single_row_slice_and_tiny_system(gpu):
         assert info["status"] == 0 and _relres(seq.csr(1), x) <= 1e-8
     finally:
         s.close()
+
+
+def test_cost_cap_drops_columns_that_do_not_pay(gpu):
+    """Cost cap: after every solve the basis holds recycled columns only if
+    the last solve with them cost fewer modelled bytes than the latest solve
+    with the initial (empty) basis; every solve meets the tolerance."""
+    K = _K()
+    seq = gen.DiffusionSequence((14, 13, 12), 8, (gen.SEED_ROOT, 97, 6))
+    s = K.sequence_for(gpu, seq, precision="fp64", reuse="selective", tol=1e-8, max_iter=2000, ritz_eps=1e-8,
+                       max_basis=60, cap_policy="cost")
+    ref = None
+    try:
+        for k in range(8):
+            s.submit(*seq.system(k))
+            x, info = s.solve()
+            assert info["status"] == 0 and _relres(seq.csr(k), x) <= 1e-8
+            s.recycle()
+            if info["n_c"] == 0:
+                ref = info["model_bytes"]
+            elif info["model_bytes"] >= ref:
+                assert s.n_c == 0, (k, info["model_bytes"], ref)
+    finally:
+        s.close()
+
+
+def test_cost_cap_keeps_paying_columns(gpu):
+    """The other branch of the cost cap: columns whose solve cost fewer
+    modelled bytes than the reference are kept."""
+    K = _K()
+    seq = gen.config_elasticity(12, 3)
+    s = K.sequence_for(gpu, seq, precision="fp64", reuse="selective", tol=1e-8, max_iter=8000, ritz_eps=1e-8,
+                       max_basis=24, cap_policy="cost")
+    ref = None
+    try:
+        for k in range(3):
+            s.submit(*seq.system(k))
+            x, info = s.solve()
+            assert info["status"] == 0 and _relres(seq.csr(k), x) <= 1e-8
+            n_before = info["n_c"]
+            s.recycle()
+            if n_before == 0:
+                ref = info["model_bytes"]
+                assert s.n_c > 0  # columns appended after the reference solve
+            elif info["model_bytes"] < ref:
+                assert s.n_c >= n_before, (k, info["model_bytes"], ref)
+            else:
+                assert s.n_c == 0
+    finally:
+        s.close()
