@@ -16,8 +16,10 @@
 // per block row, slot k of every row of a slice stored contiguously so a
 // wavefront reads 64 consecutive values per load.  3x3 blocks are stored as
 // 9 planes of 64 values per slot: value (d, e) of the block in slot k of
-// lane l sits at ((slot*9) + 3d + e)*64 + l.  Sub-row d of a slice is
-// handled by wave d of a 192-thread workgroup.
+// lane l sits at ((slot*9) + 3d + e)*64 + l.  In the SpMV a lane owns a
+// whole block row (all nine planes stream in lane order; the block column
+// and the three entries of x are loaded once per block); the A C product
+// takes sub-row d in wave d of a 192-thread workgroup.
 //
 // Every iteration kernel is a device function of (system view, workgroup
 // index); the single-system kernels call it with blockIdx.x, the fused
@@ -290,24 +292,24 @@ __device__ __forceinline__ X ell_row1(const V* __restrict__ val, const int32_t* 
     return acc;
 }
 
-// Sub-row d of one 3x3-block ELL row: the three entries (d, 0..2) of every
-// block, times the three entries of x at its block column.
+// A whole 3x3-block ELL row (one lane): the three sub-rows at once, so the
+// block column index and the three entries of x are loaded once per block
+// and all nine value planes stream in lane order.  UNR blocks in flight.
 template <typename V, typename X>
-__device__ __forceinline__ X ell_row3(const V* __restrict__ val, const int32_t* __restrict__ col,
-                                      const X* __restrict__ x, int64_t k0, int64_t k1, int lane, int d) {
-    constexpr int UNR = 4;
-    X acc = 0;
+__device__ __forceinline__ void ell_row3all(const V* __restrict__ val, const int32_t* __restrict__ col,
+                                            const X* __restrict__ x, int64_t k0, int64_t k1, int lane, X out[3]) {
+    constexpr int UNR = 2;
+    X a0 = 0, a1 = 0, a2 = 0;
     int64_t k = k0;
     for (; k + UNR <= k1; k += UNR) {
         int32_t cc[UNR];
-        V a[UNR][3];
+        V a[UNR][9];
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
             cc[u] = col[(k + u) * 64 + lane];
-            const V* vb = val + ((k + u) * 9 + 3 * d) * 64 + lane;
-            a[u][0] = vb[0];
-            a[u][1] = vb[64];
-            a[u][2] = vb[128];
+            const V* vb = val + (k + u) * 9 * 64 + lane;
+#pragma unroll
+            for (int e = 0; e < 9; ++e) a[u][e] = vb[e * 64];
         }
         X xs[UNR][3];
 #pragma unroll
@@ -318,14 +320,23 @@ __device__ __forceinline__ X ell_row3(const V* __restrict__ val, const int32_t* 
             xs[u][2] = x[c + 2];
         }
 #pragma unroll
-        for (int u = 0; u < UNR; ++u) acc += (X)a[u][0] * xs[u][0] + (X)a[u][1] * xs[u][1] + (X)a[u][2] * xs[u][2];
+        for (int u = 0; u < UNR; ++u) {
+            a0 += (X)a[u][0] * xs[u][0] + (X)a[u][1] * xs[u][1] + (X)a[u][2] * xs[u][2];
+            a1 += (X)a[u][3] * xs[u][0] + (X)a[u][4] * xs[u][1] + (X)a[u][5] * xs[u][2];
+            a2 += (X)a[u][6] * xs[u][0] + (X)a[u][7] * xs[u][1] + (X)a[u][8] * xs[u][2];
+        }
     }
     for (; k < k1; ++k) {
         const int64_t c = 3 * (int64_t)col[k * 64 + lane];
-        const V* vb = val + (k * 9 + 3 * d) * 64 + lane;
-        acc += (X)vb[0] * x[c] + (X)vb[64] * x[c + 1] + (X)vb[128] * x[c + 2];
+        const V* vb = val + k * 9 * 64 + lane;
+        const X x0 = x[c], x1 = x[c + 1], x2 = x[c + 2];
+        a0 += (X)vb[0] * x0 + (X)vb[64] * x1 + (X)vb[128] * x2;
+        a1 += (X)vb[192] * x0 + (X)vb[256] * x1 + (X)vb[320] * x2;
+        a2 += (X)vb[384] * x0 + (X)vb[448] * x1 + (X)vb[512] * x2;
     }
-    return acc;
+    out[0] = a0;
+    out[1] = a1;
+    out[2] = a2;
 }
 
 // ------------------------------------------------------------------ K1
@@ -354,16 +365,19 @@ __device__ __forceinline__ void spmv_dot_body(const SysView<V, W>& v, int64_t bi
             }
         }
     } else {
-        // one slice per workgroup step; wave d = sub-row d of the 3x3 blocks
-        const int d = wave;
-        for (int64_t sl = bid; sl < v.nslices; sl += nblk) {
+        // two slices per workgroup step, one per wave; a lane owns a block row
+        for (int64_t sl = bid * 2 + wave; sl < v.nslices; sl += nblk * 2) {
             const int64_t k0 = v.slice_ptr[sl], k1 = v.slice_ptr[sl + 1];
-            const W acc = v.op64 ? ell_row3<double, W>(v.val64, v.col, v.w, k0, k1, lane, d)
-                                 : ell_row3<V, W>(v.val, v.col, v.w, k0, k1, lane, d);
+            W acc[3];
+            if (v.op64) ell_row3all<double, W>(v.val64, v.col, v.w, k0, k1, lane, acc);
+            else ell_row3all<V, W>(v.val, v.col, v.w, k0, k1, lane, acc);
             const int64_t p = sl * 64 + lane;
             if (p < v.nb) {
-                v.q[3 * p + d] = acc;
-                part += (double)v.w[3 * p + d] * (double)acc;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    v.q[3 * p + d] = acc[d];
+                    part += (double)v.w[3 * p + d] * (double)acc[d];
+                }
             }
         }
     }
@@ -912,15 +926,18 @@ __device__ __forceinline__ void true_resid_body(const SysView<V, W>& v, int64_t 
             }
         }
     } else {
-        const int d = wave;
-        for (int64_t sl = bid; sl < v.nslices; sl += nblk) {
+        for (int64_t sl = bid * 2 + wave; sl < v.nslices; sl += nblk * 2) {
             const int64_t k0 = v.slice_ptr[sl], k1 = v.slice_ptr[sl + 1];
-            const double acc = ell_row3<double, double>(v.val64, v.col, v.x, k0, k1, lane, d);
+            double acc[3];
+            ell_row3all<double, double>(v.val64, v.col, v.x, k0, k1, lane, acc);
             const int64_t p = sl * 64 + lane;
             if (p < v.nb) {
-                const double ri = v.b[3 * p + d] - acc;
-                if (!final_only) v.r[3 * p + d] = (W)ri;
-                part += ri * ri;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const double ri = v.b[3 * p + d] - acc[d];
+                    if (!final_only) v.r[3 * p + d] = (W)ri;
+                    part += ri * ri;
+                }
             }
         }
     }
@@ -1472,7 +1489,7 @@ inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b);
 Geometry make_geometry(int64_t n, int64_t nslices, int block, int64_t cb3_req) {
     Geometry g{};
     const int64_t nb = n / block;
-    const int64_t per = (block == 1) ? 4 : 1;
+    const int64_t per = (block == 1) ? 4 : 2;  // slices per workgroup step (one per wave)
     int64_t g1 = (nslices + per - 1) / per;
     g.g1 = (int32_t)std::min<int64_t>(std::max<int64_t>(g1, 1), 2048);
     // K3: contiguous ranges of cb3 block rows; by default one range per CU
@@ -1497,7 +1514,7 @@ int64_t partial_doubles(const Geometry& g, int nc) {
 
 template <typename V, typename W, int B>
 void launch_spmv_dot(const SysView<V, W>& v, hipStream_t stream) {
-    const int threads = (B == 1) ? 256 : 192;
+    const int threads = (B == 1) ? 256 : 128;
     hipLaunchKernelGGL((k_spmv_dot<V, W, B>), dim3((unsigned)v.geo.g1), dim3(threads), 0, stream, v);
 }
 
@@ -1523,7 +1540,7 @@ void launch_correct_dir(const SysView<V, W>& v, int first, hipStream_t stream) {
 
 template <typename V, typename W, int B>
 void launch_true_resid(const SysView<V, W>& v, int final_only, hipStream_t stream) {
-    const int threads = (B == 1) ? 256 : 192;
+    const int threads = (B == 1) ? 256 : 128;
     hipLaunchKernelGGL((k_true_resid<V, W, B>), dim3((unsigned)v.geo.g1), dim3(threads), 0, stream, v, final_only);
     hipLaunchKernelGGL((k_finalize_resid<V, W>), dim3(1), dim3(1024), 0, stream, v, final_only);
 }
@@ -1544,7 +1561,7 @@ void launch_coarse_correct(const SysView<V, W>& v, int from_b, uint32_t mask, hi
 template <typename V, typename W, int B>
 void batch_spmv_dot(const SysView<V, W>* views, const BatchMaps& m, hipStream_t stream) {
     if (m.count[BK_SPMV] <= 0) return;
-    const int threads = (B == 1) ? 256 : 192;
+    const int threads = (B == 1) ? 256 : 128;
     hipLaunchKernelGGL((kb_spmv_dot<V, W, B>), dim3((unsigned)m.count[BK_SPMV]), dim3(threads), 0, stream, views,
                        m.map[BK_SPMV]);
 }
@@ -1574,7 +1591,7 @@ void batch_correct_dir(const SysView<V, W>* views, const BatchMaps& m, int first
 
 template <typename V, typename W, int B>
 void batch_true_resid(const SysView<V, W>* views, const BatchMaps& m, int final_only, hipStream_t stream) {
-    const int threads = (B == 1) ? 256 : 192;
+    const int threads = (B == 1) ? 256 : 128;
     if (m.count[BK_SPMV] > 0)
         hipLaunchKernelGGL((kb_true_resid<V, W, B>), dim3((unsigned)m.count[BK_SPMV]), dim3(threads), 0, stream,
                            views, m.map[BK_SPMV], final_only);
