@@ -52,7 +52,10 @@ WORKLOADS = {
                           history_cap=16000),
     "diffusion20": dict(kind="diffusion", size=(20, 20, 20), n_systems=8, config_id=1, max_basis=0, eps=1e-14),
     # many independent diffusion sequences (n ~ U[5e3, 2e5]) solved in fused launches
-    "batched": dict(kind="batched", size=None, n_systems=10, config_id=4, max_basis=60, eps=1e-8, cap_policy="cost"),
+    # fused launches use wide update tiles (fewer, longer workgroups per
+    # system); the one-at-a-time comparison keeps the default tile
+    "batched": dict(kind="batched", size=None, n_systems=10, config_id=4, max_basis=60, eps=1e-8, cap_policy="cost",
+                    update_rows=4096),
     # clients with elasticity sequences (1e4..5e5 dofs) served with continuous batching
     "serving": dict(kind="serving", size=None, n_systems=50, config_id=5, max_basis=200, eps=1e-8),
     # calibration for hardware byte counters: device-to-device copies of a known size
@@ -317,9 +320,10 @@ def run_batched(args, K, torch, data):
     kw = dict(precision=args.precision, tol=1e-8, max_iter=args.max_iter, ritz_eps=args.eps or wl["eps"],
               max_basis=wl["max_basis"], cap_policy=wl.get("cap_policy", "freeze"), history_cap=args.history_cap,
               refine_drop=args.refine_drop)
+    fused_rows = args.update_rows or wl["update_rows"]
 
     def phase(reuse, fused):
-        hs = [K.sequence_for(ctx, sq, reuse=reuse, **kw) for sq in seqs]
+        hs = [K.sequence_for(ctx, sq, reuse=reuse, update_rows=fused_rows if fused else 0, **kw) for sq in seqs]
         xs = [torch.empty(sq.n, dtype=torch.float64, device="cuda") for sq in seqs]
         iters, t_steps, t_rec = [], [], []
         try:
@@ -375,7 +379,7 @@ def run_batched(args, K, torch, data):
                                f"SRKS eps={kw['ritz_eps']:.0e} cap {wl['max_basis']} ({kw['cap_policy']}), "
                                f"fused launches",
                    "sequences": len(seqs), "sum_n": n_tot, "precision": args.precision,
-                   "history_cap": args.history_cap},
+                   "history_cap": args.history_cap, "update_rows_fused": fused_rows},
         "iters_mean": fused["iters_mean"],
         "step_ms": fused["step_ms"],
         "recycle_ms": fused["recycle_ms"],
@@ -395,7 +399,8 @@ def main():
     ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="elasticity40", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="fp32basis", choices=["mixed", "fp64", "fp32", "fp32basis"])
+    ap.add_argument("--precision", default=None, choices=["mixed", "fp64", "fp32", "fp32basis"],
+                    help="default: fp32basis (elasticity, serving), mixed (batched diffusion), fp64 (diffusion20)")
     ap.add_argument("--max-iter", type=int, default=30000)
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--no-plain", dest="plain", action="store_false")
@@ -416,6 +421,8 @@ def main():
     ap.add_argument("--rate", type=float, default=1.0, help="serving workload: arrivals per second per client")
     ap.add_argument("--hbm-budget", type=float, default=64.0, help="serving workload: working-set budget (GiB)")
     args = ap.parse_args()
+    if args.precision is None:
+        args.precision = {"batched": "mixed", "diffusion20": "fp64"}.get(args.workload, "fp32basis")
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "multi-GPU sharding is not implemented", file=sys.stderr)

@@ -840,8 +840,9 @@ krs_status SeqImpl<V, W>::recycle(int32_t* n_added) {
         return KRS_E_STATE;
     }
     solved = false;
-    Timer tm;
-    tm.start(stream);
+    // host wall time: the call only enqueues device work (stream-ordered
+    // after it), so it does not wait for the device
+    const auto t_start = std::chrono::steady_clock::now();
     const int m = m_last;
     int added = 0;
     last_theta.clear();
@@ -881,7 +882,8 @@ krs_status SeqImpl<V, W>::recycle(int32_t* n_added) {
         // w_j / sqrt((w_j, A w_j)) for the captured directions (Algorithm 2)
         const int cnt = std::min(m, trks_slots);
         if (cnt > 0) {
-            std::vector<double> sc(cnt);
+            std::vector<double>& sc = h_F;  // kept alive: the copy below is asynchronous
+            sc.assign(cnt, 0.0);
             for (int j = 0; j < cnt; ++j) sc[j] = 1.0 / std::sqrt(coef_gamma[j]);
             if (!d_F.reserve(ctx, cnt * sizeof(double))) return KRS_E_OOM;
             KRS_HIP(hipMemcpyAsync(d_F.p, sc.data(), cnt * sizeof(double), hipMemcpyHostToDevice, stream));
@@ -979,7 +981,8 @@ krs_status SeqImpl<V, W>::recycle(int32_t* n_added) {
                 std::vector<double> diag(mu), off(mu - 1);
                 for (int j = 0; j < mu; ++j) diag[j] = dd[j] + (j > 0 ? l2[j - 1] * dd[j - 1] : 0.0);
                 for (int j = 0; j + 1 < mu; ++j) off[j] = std::sqrt(l2[j]) * dd[j];
-                std::vector<double> F((size_t)mu * s);
+                std::vector<double>& F = h_F;  // kept alive: the copy below is asynchronous
+                F.assign((size_t)mu * s, 0.0);
                 std::vector<double> q;
                 for (int t = 0; t < s; ++t) {
                     const double th = th_m[sel[t]];
@@ -1007,11 +1010,11 @@ krs_status SeqImpl<V, W>::recycle(int32_t* n_added) {
         nc = nc0;
         restarts += 1;
     }
-    tm.stop(stream);
-    KRS_HIP(hipStreamSynchronize(stream));
+    KRS_CHECK_LAUNCH();
     info_last.added = added;
     info_last.selected = last_selected;
-    info_last.t_recycle_ms = tm.ms();
+    info_last.t_recycle_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     if (n_added) *n_added = added;
     return KRS_OK;
 }

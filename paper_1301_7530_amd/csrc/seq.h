@@ -90,6 +90,7 @@ struct SeqImpl : SeqBase {
     int tuned_nc = 0;
     int dropped_last = 0;
     int history_kept = 0;
+    std::vector<double> h_F;  // host source of the last basis-update upload
     int64_t ref_cost = 0;   // modelled bytes of the latest solve with the initial basis (cost cap)
     int cost_hold = 0;      // systems left before the cost cap lets columns be appended again
     int cost_fails = 0;     // failed trials of recycled columns in a row
