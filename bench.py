@@ -338,8 +338,11 @@ def run_batched(args, K, torch, data):
                     infos = [h.solve_device(x) for h, x in zip(hs, xs)]
                 t1 = time.perf_counter()
                 if reuse != "none":
-                    for h in hs:
-                        h.recycle()
+                    if fused:
+                        ctx.batch_recycle(hs)
+                    else:
+                        for h in hs:
+                            h.recycle()
                 torch.cuda.synchronize()
                 if step >= args.warmup:
                     t_steps.append(time.perf_counter() - t0)

@@ -218,6 +218,10 @@ krs_status krs_batch_solve(krs_ctx* ctx, krs_seq* const* seqs, int32_t count, do
 /* As krs_batch_solve with device output pointers d_x[i] (n_i doubles). */
 krs_status krs_batch_solve_device(krs_ctx* ctx, krs_seq* const* seqs, int32_t count, double* const* d_x,
                                   krs_solve_info* info);
+/* krs_seq_recycle for `count` distinct sequences of ctx, their host-side
+ * Ritz analysis on parallel threads.  n_added[i] (may be NULL) receives
+ * each count; returns the first non-OK status (every member is attempted). */
+krs_status krs_batch_recycle(krs_ctx* ctx, krs_seq* const* seqs, int32_t count, int32_t* n_added);
 
 /* ------------------------------------------------------------- serving */
 /* A server owns a worker thread that serves systems of many sequences of

@@ -152,6 +152,7 @@ SIGNATURES = [
     ("krs_seq_destroy", _S, [_P]),
     ("krs_batch_solve", _S, [_P, _PP, ctypes.c_int32, ctypes.POINTER(_D), ctypes.POINTER(SolveInfo)]),
     ("krs_batch_solve_device", _S, [_P, _PP, ctypes.c_int32, _PP, ctypes.POINTER(SolveInfo)]),
+    ("krs_batch_recycle", _S, [_P, _PP, ctypes.c_int32, _I32]),
     ("krs_server_create", _S, [_P, ctypes.c_size_t, ctypes.c_int32, _PP]),
     ("krs_server_enqueue", _S, [_P, _P, _D, _D, _D, ctypes.c_uint64]),
     ("krs_server_poll", _S, [_P, ctypes.POINTER(Completion), ctypes.c_int32, _I32, ctypes.c_int32]),
@@ -294,6 +295,17 @@ class Context:
                                              infos)
             _check(st, "krs_batch_solve_device", allow=(KRS_E_MAXIT,))
         return xs, [infos[i].as_dict() for i in range(cnt)]
+
+
+    def batch_recycle(self, seqs):
+        """krs_seq_recycle for several sequences (host work in parallel);
+        returns the number of columns appended to each."""
+        cnt = len(seqs)
+        arr_h = (ctypes.c_void_p * cnt)(*[s.handle.value for s in seqs])
+        added = (ctypes.c_int32 * max(cnt, 1))()
+        _check(_lib.krs_batch_recycle(self.handle, ctypes.cast(arr_h, _PP), cnt,
+                                      ctypes.cast(added, _I32)), "krs_batch_recycle")
+        return [int(added[i]) for i in range(cnt)]
 
 
 class Sequence:

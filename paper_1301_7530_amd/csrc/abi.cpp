@@ -375,6 +375,29 @@ static krs_status batch_common(krs_ctx* ctx, krs_seq* const* seqs, int32_t count
     return krs::batch_solve(ctx, v.data(), count, x, device_x, info);
 }
 
+krs_status krs_batch_recycle(krs_ctx* ctx, krs_seq* const* seqs, int32_t count, int32_t* n_added) {
+    KRS_GUARD_BEGIN
+    if (!ctx || count < 0 || (count > 0 && !seqs)) {
+        set_error("ctx and seqs are required");
+        return KRS_E_INVALID;
+    }
+    std::vector<krs::SeqBase*> v(count);
+    for (int i = 0; i < count; ++i) {
+        if (!seqs[i] || seqs[i]->impl->ctx != ctx) {
+            set_error("every sequence must belong to ctx");
+            return KRS_E_INVALID;
+        }
+        for (int j = 0; j < i; ++j)
+            if (seqs[j] == seqs[i]) {
+                set_error("a sequence appears twice in the batch");
+                return KRS_E_INVALID;
+            }
+        v[i] = seqs[i]->impl.get();
+    }
+    return krs::recycle_all(ctx, v.data(), count, n_added);
+    KRS_GUARD_END
+}
+
 krs_status krs_batch_solve(krs_ctx* ctx, krs_seq* const* seqs, int32_t count, double* const* x, krs_solve_info* info) {
     KRS_GUARD_BEGIN
     return batch_common(ctx, seqs, count, x, false, info);

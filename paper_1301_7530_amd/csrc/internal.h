@@ -226,6 +226,10 @@ void ldl_eigenvalues(const std::vector<double>& d, const std::vector<double>& l2
 // Ascending eigenvalues k0..k1-1 (0 = smallest) of L D L^T into asc[k].
 void ldl_eigenvalues_range(const std::vector<double>& d, const std::vector<double>& l2, int k0, int k1,
                            double* asc, int threads);
+// Number of eigenvalues of L D L^T below sigma.
+int ldl_count_below(const std::vector<double>& d, const std::vector<double>& l2, double sigma);
+// Whether L D L^T has an eigenvalue in [lo, hi]; l2d[i] = l2[i] * d[i].
+bool ldl_has_eigenvalue_in(const std::vector<double>& d, const std::vector<double>& l2d, double lo, double hi);
 // Eigenvector (unit 2-norm) of the explicit tridiagonal (diag, off) for eigenvalue theta.
 void tridiag_eigvec(const std::vector<double>& diag, const std::vector<double>& off, double theta,
                     std::vector<double>& v);

@@ -89,6 +89,22 @@ void ldl_eigenvalues_range(const std::vector<double>& d, const std::vector<doubl
     for (auto& th : pool) th.join();
 }
 
+int ldl_count_below(const std::vector<double>& d, const std::vector<double>& l2, double sigma) {
+    const int m = (int)d.size();
+    if (m == 0) return 0;
+    std::vector<double> l2d(m, 0.0);
+    for (int i = 0; i + 1 < m; ++i) l2d[i] = l2[i] * d[i];
+    return inertia_below(m, d.data(), l2d.data(), sigma);
+}
+
+bool ldl_has_eigenvalue_in(const std::vector<double>& d, const std::vector<double>& l2d, double lo, double hi) {
+    const int m = (int)d.size();
+    if (m == 0) return false;
+    // eigenvalues in [lo, hi]: count below the next double above hi, minus count below lo
+    return inertia_below(m, d.data(), l2d.data(), std::nextafter(hi, INFINITY)) >
+           inertia_below(m, d.data(), l2d.data(), lo);
+}
+
 void ldl_eigenvalues(const std::vector<double>& d, const std::vector<double>& l2, std::vector<double>& theta,
                      int threads) {
     const int m = (int)d.size();

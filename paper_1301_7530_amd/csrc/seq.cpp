@@ -33,7 +33,7 @@ void* dev_alloc(krs_ctx* ctx, size_t bytes) {
     } else {
         if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
     }
-    if (p) ctx->bytes_live += bytes;
+    if (p) ctx->bytes_live.fetch_add((int64_t)bytes);
     return p;
 }
 
@@ -42,7 +42,7 @@ void dev_free(krs_ctx* ctx, void* p, size_t bytes) {
     bytes = (bytes + 255) & ~(size_t)255;
     if (ctx->has_alloc) ctx->alloc.free(ctx->alloc.user, p, (void*)ctx->stream);
     else (void)hipFree(p);
-    ctx->bytes_live -= bytes;
+    ctx->bytes_live.fetch_sub((int64_t)bytes);
 }
 
 bool Buf::reserve(krs_ctx* ctx, size_t nbytes) {
@@ -904,7 +904,7 @@ krs_status SeqImpl<V, W>::recycle(int32_t* n_added) {
             for (int j = 0; j + 1 < mu; ++j) l2[j] = coef_rho[j + 1] / coef_rho[j];
             std::vector<double> d1(dd.begin(), dd.end() - 1);
             std::vector<double> l21(l2.begin(), l2.begin() + (mu - 2));
-            const int nt = host_threads();
+            const int nt = recycle_threads > 0 ? recycle_threads : host_threads();
             const bool frozen = capped;
             std::vector<double> th_m(mu, 0.0);  // descending (Algorithm 3 order)
             std::vector<int> sel;               // descending indices, ascending order
@@ -924,8 +924,14 @@ krs_status SeqImpl<V, W>::recycle(int32_t* n_added) {
                 // iff it is within eps of one of its interlacing neighbours
                 // b_{k-1} <= a_k <= b_k.  Stop once the room is filled (and
                 // any exact ties of the last value are seen).
+                // The interlacing neighbours of a_k are the only eigenvalues
+                // of H_{m-1} that can lie within eps |a_k| of it, so the test
+                // is whether H_{m-1} has an eigenvalue in that window: two
+                // inertia counts instead of bisecting H_{m-1}'s spectrum.
                 const int room = std::max(0, desc.max_basis - nc);
-                std::vector<double> a(mu), bv(mu);
+                std::vector<double> a(mu);
+                std::vector<double> l21d(mu - 1, 0.0);
+                for (int i = 0; i + 1 < mu - 1; ++i) l21d[i] = l21[i] * d1[i];
                 std::vector<int> sel_asc;
                 bool have_cut = false, stop = false;
                 double cut = 0.0;
@@ -934,16 +940,13 @@ krs_status SeqImpl<V, W>::recycle(int32_t* n_added) {
                 while (k < mu && !stop) {
                     const int k1 = std::min(mu, k + CH);
                     ldl_eigenvalues_range(dd, l2, k, k1, a.data(), nt);
-                    ldl_eigenvalues_range(d1, l21, k, std::min(k1, mu - 1), bv.data(), nt);
                     for (int kk = k; kk < k1; ++kk) {
                         if (have_cut && a[kk] > cut) {
                             stop = true;
                             break;
                         }
                         const double e = desc.ritz_eps * std::fabs(a[kk]);
-                        const bool s1 = kk >= 1 && std::fabs(a[kk] - bv[kk - 1]) <= e;
-                        const bool s2 = kk <= mu - 2 && std::fabs(a[kk] - bv[kk]) <= e;
-                        if (s1 || s2) {
+                        if (ldl_has_eigenvalue_in(d1, l21d, a[kk] - e, a[kk] + e)) {
                             sel_asc.push_back(kk);
                             if (!have_cut && (int)sel_asc.size() >= room) {
                                 have_cut = true;
@@ -1274,6 +1277,35 @@ krs_status batch_solve(krs_ctx* ctx, SeqBase* const* seqs, int count, double* co
     for (krs_status st : out)
         if (st != KRS_OK && (worst == KRS_OK || worst == KRS_E_MAXIT)) worst = st;
     return worst;
+}
+
+krs_status recycle_all(krs_ctx* ctx, SeqBase* const* seqs, int count, int32_t* added) {
+    // Independent sequences: their host-side Ritz work runs on up to 16
+    // threads (one bisection thread each); the device work they enqueue on
+    // the shared stream is independent, so its interleaving is immaterial.
+    std::vector<krs_status> st(count, KRS_OK);
+    const int nt = std::max(1, std::min(count, host_threads()));
+    std::atomic<int> next{0};
+    auto work = [&]() {
+        (void)hipSetDevice(ctx->device);
+        for (int i = next.fetch_add(1); i < count; i = next.fetch_add(1)) {
+            seqs[i]->recycle_threads = 1;
+            int32_t a = 0;
+            st[i] = seqs[i]->recycle(&a);
+            seqs[i]->recycle_threads = 0;
+            if (added) added[i] = a;
+        }
+    };
+    if (nt == 1) {
+        work();
+    } else {
+        std::vector<std::thread> pool;
+        for (int t = 0; t < nt; ++t) pool.emplace_back(work);
+        for (auto& th : pool) th.join();
+    }
+    for (krs_status x : st)
+        if (x != KRS_OK) return x;
+    return KRS_OK;
 }
 
 }  // namespace krs

@@ -20,7 +20,7 @@ struct krs_ctx {
     krs_allocator alloc{};
     int live_seqs = 0;
     int live_servers = 0;
-    int64_t bytes_live = 0;
+    std::atomic<int64_t> bytes_live{0};
 };
 
 namespace krs {
@@ -54,6 +54,7 @@ struct SeqBase {
     // release those solve-time buffers (they are re-created by the next solve)
     virtual void trim() = 0;
     std::atomic<int> in_server{0};  // requests of a server not yet completed
+    int recycle_threads = 0;        // host threads of the Ritz bisection (0: automatic)
     virtual krs_status recycle(int32_t* n_added) = 0;
     virtual krs_status basis(double* C, int64_t ld, int32_t cap, int32_t* n_c) = 0;
     virtual void destroy() = 0;
@@ -150,6 +151,9 @@ struct RunnerBase {
 };
 std::unique_ptr<RunnerBase> make_runner(krs_ctx* ctx, int type_key);
 bool finished_status(int device_status);
+
+// Recycle several sequences, their host work on parallel threads.
+krs_status recycle_all(krs_ctx* ctx, SeqBase* const* seqs, int count, int32_t* added);
 
 // Solve the submitted systems of several sequences in fused launches.
 krs_status batch_solve(krs_ctx* ctx, SeqBase* const* seqs, int count, double* const* x, bool device_x,

@@ -182,29 +182,39 @@ void krs_server::run() {
             st = kv.second->read_status(stat);
             if (st != KRS_OK) break;
             auto& mem = members[kv.first];
-            std::vector<Active> keep;
-            bool changed = false;
+            std::vector<Active> keep, fin;
             const int batch = (int)mem.size();
             for (size_t i = 0; i < mem.size(); ++i) {
-                if (!krs::finished_status(stat[2 * i])) {
-                    keep.push_back(std::move(mem[i]));
-                    continue;
+                if (krs::finished_status(stat[2 * i])) fin.push_back(std::move(mem[i]));
+                else keep.push_back(std::move(mem[i]));
+            }
+            const bool changed = !fin.empty();
+            // copy the solutions out, then recycle the finished members together
+            std::vector<krs_solve_info> infos(fin.size());
+            std::vector<krs_status> sts(fin.size());
+            std::vector<krs::SeqBase*> rec;
+            std::vector<size_t> rec_idx;
+            for (size_t i = 0; i < fin.size(); ++i) {
+                std::memset(&infos[i], 0, sizeof infos[i]);
+                sts[i] = fin[i].req.impl->end_solve(fin[i].req.x_out, false, &infos[i]);
+                if (sts[i] == KRS_OK || sts[i] == KRS_E_MAXIT) {
+                    rec.push_back(fin[i].req.impl);
+                    rec_idx.push_back(i);
                 }
-                changed = true;
-                Active& a = mem[i];
-                krs_solve_info info;
-                std::memset(&info, 0, sizeof info);
-                krs_status rs = a.req.impl->end_solve(a.req.x_out, false, &info);
-                if (rs == KRS_OK || rs == KRS_E_MAXIT) {
-                    int32_t added = 0;
-                    const krs_status rc = a.req.impl->recycle(&added);
-                    if (rc != KRS_OK && rs == KRS_OK) rs = rc;
-                    info.added = added;
+            }
+            if (!rec.empty()) {
+                std::vector<int32_t> added(rec.size(), 0);
+                const krs_status rc = krs::recycle_all(ctx, rec.data(), (int)rec.size(), added.data());
+                for (size_t j = 0; j < rec.size(); ++j) {
+                    infos[rec_idx[j]].added = added[j];
+                    if (rc != KRS_OK && sts[rec_idx[j]] == KRS_OK) sts[rec_idx[j]] = rc;
                 }
-                a.req.impl->trim();
-                used -= a.bytes;
+            }
+            for (size_t i = 0; i < fin.size(); ++i) {
+                fin[i].req.impl->trim();
+                used -= fin[i].bytes;
                 --nact;
-                post(a.req, rs, info, batch);
+                post(fin[i].req, sts[i], infos[i], batch);
             }
             if (changed) {
                 mem = std::move(keep);

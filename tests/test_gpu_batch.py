@@ -2,7 +2,8 @@
 
 A batch runs the iterations of several sequences in shared launches; each
 member keeps the launch geometry of its own solve, so its results must be
-bitwise identical to solving it alone.  Iteration counts are also checked
+bitwise identical to solving it alone (and the batched recycle, whose host
+work runs on parallel threads, to recycling it alone).  Iteration counts are also checked
 against the FP64 oracle (+-2) and the true residual against 1e-8.
 """
 import numpy as np
@@ -66,7 +67,9 @@ def _batched(ctx, seqs, n_systems, **kw):
             for i, h in enumerate(hs):
                 infos[i]["x"] = xs[i]
                 infos[i]["coef"] = h.coeffs()
-                h.recycle()
+            # host-side Ritz work of all members in parallel threads
+            ctx.batch_recycle(hs)
+            for i, h in enumerate(hs):
                 infos[i]["C"] = h.basis()
                 out[i].append(infos[i])
     finally:
