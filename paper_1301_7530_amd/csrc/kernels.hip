@@ -74,20 +74,21 @@ __device__ __forceinline__ double ld_part(const double* p) {
 }
 
 // sum_r P[r * stride + k] over r = 0 .. rows-1 in ascending order (16
-// loads in flight).  The update's partial sums are reduced in two levels
-// with it: each group of kGroup consecutive workgroups, then the groups.
+// loads in flight, also for a ragged last group: rows past the end load the
+// last row and are not added).  The update's partial sums are reduced in two
+// levels with it: each group of kGroup consecutive workgroups, then the
+// groups.
 template <bool COH>
 __device__ __forceinline__ double col_sum(const double* P, int64_t rows, int64_t stride, int k) {
     double s = 0.0;
-    int64_t r = 0;
-    for (; r + 16 <= rows; r += 16) {
+    for (int64_t r = 0; r < rows; r += 16) {
         double t[16];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) t[u] = ld_part<COH>(P + (r + u) * stride + k);
+        for (int u = 0; u < 16; ++u) t[u] = ld_part<COH>(P + min(r + u, rows - 1) * stride + k);
 #pragma unroll
-        for (int u = 0; u < 16; ++u) s += t[u];
+        for (int u = 0; u < 16; ++u)
+            if (r + u < rows) s += t[u];
     }
-    for (; r < rows; ++r) s += ld_part<COH>(P + r * stride + k);
     return s;
 }
 
@@ -132,11 +133,16 @@ template <int UNR>
 __device__ __forceinline__ double thread_sum(const double* p, int64_t np) {
     const int64_t T = blockDim.x;
     double t[UNR];
+    // every load is issued (clamped into the array), then masked
+    const int64_t last = np > 0 ? np - 1 : 0;
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
         const int64_t i = threadIdx.x + u * T;
-        t[u] = i < np ? p[i] : 0.0;
+        t[u] = np > 0 ? p[i < np ? i : last] : 0.0;
     }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u)
+        if (threadIdx.x + u * T >= np) t[u] = 0.0;
     double a = 0.0;
 #pragma unroll
     for (int u = 0; u < UNR; ++u) a += t[u];
@@ -192,6 +198,60 @@ __device__ void ginv_matvec(const double* __restrict__ Ginv, int nc, const doubl
             double s = 0.0;
             for (int j = 0; j < P; ++j) s += lds[threadIdx.x + j];
             mu[r] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// mu = Ginv t and gv = Ginv tv with one pass over Ginv (each output in the
+// order of ginv_matvec, so the results are those of two calls); lds needs
+// blockDim.x doubles.
+__device__ void ginv_matvec2(const double* __restrict__ Ginv, int nc, const double* t, const double* tv, double* mu,
+                             double* gv, double* lds) {
+    const int T = blockDim.x;
+    int P = T / nc;
+    if (P < 1) P = 1;
+    if (P > 64) P = 64;
+    const int rows_per_round = T / P;
+    for (int base = 0; base < nc; base += rows_per_round) {
+        const int r = base + threadIdx.x / P;
+        const int p = threadIdx.x % P;
+        const bool act = (int)(threadIdx.x / P) < rows_per_round && r < nc;
+        double m = 0.0, mv = 0.0;
+        if (act) {
+            int c = p;
+            for (; c + 7 * P < nc; c += 8 * P) {
+                double g[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) g[u] = Ginv[(int64_t)(c + u * P) * nc + r];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    m += g[u] * t[c + u * P];
+                    mv += g[u] * tv[c + u * P];
+                }
+            }
+            for (; c < nc; c += P) {
+                const double g = Ginv[(int64_t)c * nc + r];
+                m += g * t[c];
+                mv += g * tv[c];
+            }
+        }
+        // the parts are combined through the one LDS buffer, mu then gv
+        __syncthreads();
+        lds[threadIdx.x] = m;
+        __syncthreads();
+        if (act && p == 0) {
+            double s = 0.0;
+            for (int j = 0; j < P; ++j) s += lds[threadIdx.x + j];
+            mu[r] = s;
+        }
+        __syncthreads();
+        lds[threadIdx.x] = mv;
+        __syncthreads();
+        if (act && p == 0) {
+            double s = 0.0;
+            for (int j = 0; j < P; ++j) s += lds[threadIdx.x + j];
+            gv[r] = s;
         }
         __syncthreads();
     }
@@ -391,55 +451,87 @@ __device__ __forceinline__ void spmv_dot_body(const SysView<V, W>& v, int64_t bi
 // vacc[c] += sum_i AC[i, c] ws[i] over `rows` rows of a row-major AC tile
 // (leading dimension ld, a multiple of 32 elements).  Columns are taken in
 // chunks of 128 bytes; a lane reads 16 bytes (QW columns) of one row, so
-// LPR = 8 lanes cover a chunk of a row and a wave reads 8 rows per load,
-// the 8 waves 64 rows per round.  Each lane keeps the sums of its QW
-// columns; lanes of equal column are combined by shuffles, the waves in a
-// fixed order through LDS.
+// LPR = 8 lanes cover a chunk of a row and a wave reads 8 rows per load.
+// Each wave works on one (chunk, row phase) item: with fewer chunks than
+// waves a chunk gets P waves that interleave its rows, so every chunk of the
+// tile streams at once and each lane keeps UR loads in flight (the rows of a
+// step take one or two rounds of loads instead of one per chunk).  Lanes of
+// equal column are combined by shuffles, the waves of a chunk in a fixed
+// order through LDS.
 template <typename V>
 struct alignas(16) Vec16 {
     V e[16 / sizeof(V)];
 };
 
+// Rows per load group of a lane: the single-system update kernel runs one
+// workgroup per compute unit (up to 256 registers per lane), the fused batch
+// kernel several (128).  The summation order does not depend on it.
+constexpr int kUrOne = 16;
 template <typename V>
+constexpr int ur_batch() {
+    return 4;
+}
+
+// Work split of the projection: wave `wave` takes item wave + k NW of the
+// items (chunk it % nch, row phase it / nch), P waves per chunk.
+template <typename V>
+struct ProjSplit {
+    static constexpr int QW = 16 / sizeof(V);
+    static constexpr int CW = 128 / sizeof(V);
+    static constexpr int LPR = CW / QW;  // 8
+    static constexpr int RPW = 64 / LPR;  // 8
+    static constexpr int NW = kT3 / 64;
+    int nch, P, items, step, q, rsub;
+    __device__ explicit ProjSplit(int nc) {
+        const int lane = threadIdx.x & 63;
+        q = lane % LPR;
+        rsub = lane / LPR;
+        nch = (nc + CW - 1) / CW;
+        P = nch < NW ? NW / nch : 1;
+        items = P * nch;
+        step = RPW * P;
+    }
+};
+
+template <typename V, int UR>
 __device__ __forceinline__ void project_rows(const V* __restrict__ ACt, int64_t ld, int rows, int nc,
                                              const double* ss, const double* ws, double* tacc, double* vacc,
-                                             double (*cred)[64]) {
-    constexpr int QW = 16 / sizeof(V);
-    constexpr int CW = 128 / sizeof(V);
-    constexpr int LPR = CW / QW;  // 8
-    constexpr int RPW = 64 / LPR;  // 8
-    constexpr int NW = kT3 / 64;
-    constexpr int RPR = RPW * NW;
-    constexpr int UR = sizeof(V) == 4 ? 6 : 8;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int q = lane % LPR, rsub = lane / LPR;
-    const int nch = (nc + CW - 1) / CW;
-    for (int ch = 0; ch < nch; ++ch) {
+                                             double (*cred)[64], const ProjSplit<V>& g) {
+    using G = ProjSplit<V>;
+    constexpr int QW = G::QW, CW = G::CW, LPR = G::LPR, RPW = G::RPW, NW = G::NW;
+    const int wave = threadIdx.x >> 6;
+    const int q = g.q, rsub = g.rsub, nch = g.nch, P = g.P, items = g.items, step = g.step;
+    for (int k0 = 0; k0 < items; k0 += NW) {
+        const int it = k0 + wave;
+        const bool act = it < items;
+        const int ch = it % nch, ph = it / nch;
         double at[QW], av[QW];
 #pragma unroll
         for (int e = 0; e < QW; ++e) {
             at[e] = 0.0;
             av[e] = 0.0;
         }
-        const V* base = ACt + ch * CW + q * QW;
-        for (int r0 = wave * RPW + rsub; r0 < rows; r0 += RPR * UR) {
-            // rows past the step are clamped to its last row (weight 0) so
-            // every load of the group is issued unconditionally
-            Vec16<V> a[UR];
+        if (act) {
+            const V* base = ACt + ch * CW + q * QW;
+            for (int r0 = ph * RPW + rsub; r0 < rows; r0 += step * UR) {
+                // rows past the step are clamped to its last row (weight 0)
+                // so every load of the group is issued unconditionally
+                Vec16<V> a[UR];
 #pragma unroll
-            for (int u = 0; u < UR; ++u) {
-                const int rr = min(r0 + u * RPR, rows - 1);
-                a[u] = *reinterpret_cast<const Vec16<V>*>(base + (int64_t)rr * ld);
-            }
+                for (int u = 0; u < UR; ++u) {
+                    const int rr = min(r0 + u * step, rows - 1);
+                    a[u] = *reinterpret_cast<const Vec16<V>*>(base + (int64_t)rr * ld);
+                }
 #pragma unroll
-            for (int u = 0; u < UR; ++u) {
-                const int rr = r0 + u * RPR;
-                const bool ok = rr < rows;
-                const double sv = ok ? ss[rr] : 0.0, wv = ok ? ws[rr] : 0.0;
+                for (int u = 0; u < UR; ++u) {
+                    const int rr = r0 + u * step;
+                    const bool ok = rr < rows;
+                    const double sv = ok ? ss[rr] : 0.0, wv = ok ? ws[rr] : 0.0;
 #pragma unroll
-                for (int e = 0; e < QW; ++e) {
-                    at[e] += (double)a[u].e[e] * sv;
-                    av[e] += (double)a[u].e[e] * wv;
+                    for (int e = 0; e < QW; ++e) {
+                        at[e] += (double)a[u].e[e] * sv;
+                        av[e] += (double)a[u].e[e] * wv;
+                    }
                 }
             }
         }
@@ -451,7 +543,7 @@ __device__ __forceinline__ void project_rows(const V* __restrict__ ACt, int64_t 
                 av[e] += __shfl_xor(av[e], off, 64);
             }
         }
-        if (rsub == 0) {
+        if (rsub == 0 && act) {
 #pragma unroll
             for (int e = 0; e < QW; ++e) {
                 cred[wave][q * QW + e] = at[e];
@@ -459,17 +551,22 @@ __device__ __forceinline__ void project_rows(const V* __restrict__ ACt, int64_t 
             }
         }
         __syncthreads();
-        if ((int)threadIdx.x < CW) {
-            const int c = ch * CW + threadIdx.x;
+        // chunks of this round: all of them when there are fewer than waves
+        // (wave cl + p nch holds phase p of chunk cl), else NW of them
+        const int nchr = nch <= NW ? nch : min(NW, nch - k0);
+        const int t = threadIdx.x;
+        if (t < nchr * CW) {
+            const int cl = t / CW, e = t % CW;
+            const int c = (nch <= NW ? cl : k0 + cl) * CW + e;
             if (c < nc) {
-                double t = 0.0, u2 = 0.0;
-#pragma unroll
-                for (int w = 0; w < NW; ++w) {
-                    t += cred[w][threadIdx.x];
-                    u2 += cred[w][32 + threadIdx.x];
+                double ts = 0.0, vs = 0.0;
+                for (int p = 0; p < P; ++p) {
+                    const int w = cl + p * nch;
+                    ts += cred[w][e];
+                    vs += cred[w][32 + e];
                 }
-                tacc[c] += t;
-                vacc[c] += u2;
+                tacc[c] += ts;
+                vacc[c] += vs;
             }
         }
         __syncthreads();
@@ -496,8 +593,11 @@ __device__ __forceinline__ void project_rows(const V* __restrict__ ACt, int64_t 
 constexpr int kStateWords = 32;
 constexpr int fin_pool() { return kStateWords + kTF3 + 2056 + 3 * 1024 + 4096 + 8; }
 
+// g_in: (w, q) of this step when the caller has already reduced the SpMV
+// partials (the fused update, in the same order), else negative.
 template <typename V, typename W, bool COH>
-__device__ __forceinline__ void finalize_update_body(const SysView<V, W>& v, int mode, double* pool) {
+__device__ __forceinline__ void finalize_update_body(const SysView<V, W>& v, int mode, double* pool,
+                                                     double g_in = -1.0) {
     constexpr int T = kTF3;
     constexpr int NWORD = (int)(sizeof(DevState) / 8);
     static_assert(NWORD <= kStateWords, "state staging area too small");
@@ -514,62 +614,91 @@ __device__ __forceinline__ void finalize_update_body(const SysView<V, W>& v, int
     const int nv = 2 * nc + 2;
     const int64_t np3 = v.geo.g3, np1 = v.geo.g1;
     const int64_t ng = (np3 + kGroup - 1) / kGroup;
-    // ---- loads (state, SpMV partials, u, G^-1 and the update's sums together)
+    // ---- loads (state, SpMV partials, u, G^-1 and the update's sums): each
+    // is issued at a clamped, valid address before any is used, so their
+    // latencies overlap
     unsigned long long sw = 0ull;
     if (tid < NWORD) sw = reinterpret_cast<const unsigned long long*>(v.st)[tid];
-    const double p1 = (mode == 0) ? thread_sum<4>(v.part1, np1) : 0.0;
-    {
-        constexpr int UU = 1024 / T;
-        double uv[UU];
+    const bool need_g = mode == 0 && !(g_in >= 0.0);
+    double pt[4];
+    if (need_g) {
 #pragma unroll
-        for (int u = 0; u < UU; ++u) {
-            const int c = tid + u * T;
-            uv[u] = (mode == 0 && c < nc) ? v.u[c] : 0.0;
-        }
+        for (int u = 0; u < 4; ++u) pt[u] = v.part1[min((int64_t)tid + u * T, np1 - 1)];
+    }
+    constexpr int UU = 1024 / T;
+    double uv[UU];
+    const bool have_u = mode == 0 && nc > 0;
+    if (have_u) {
 #pragma unroll
-        for (int u = 0; u < UU; ++u)
-            if (tid + u * T < nc) uL[tid + u * T] = uv[u];
+        for (int u = 0; u < UU; ++u) uv[u] = v.u[min(tid + u * T, nc - 1)];
     }
     const bool gsmall = nc <= 64;
-    if (gsmall) {
-        constexpr int GU = 4096 / T;
-        double gv[GU];
+    constexpr int GU = 4096 / T;
+    double gv[GU];
+    if (gsmall && nc > 0) {
 #pragma unroll
-        for (int u = 0; u < GU; ++u) {
-            const int e = tid + u * T;
-            gv[u] = e < nc * nc ? v.Ginv[e] : 0.0;
-        }
+        for (int u = 0; u < GU; ++u) gv[u] = v.Ginv[min(tid + u * T, nc * nc - 1)];
+    }
+    // the groups' sums of this thread's column in one pass (the usual case)
+    const double* gsum = v.partials + np3 * nv;
+    const bool one = COH && nv <= T && ng <= 16;
+    double gl[16];
+    if (one) {
+        const int kk = min(tid, nv - 1);
+#pragma unroll
+        for (int u = 0; u < 16; ++u) gl[u] = ld_part<true>(gsum + min((int64_t)u, ng - 1) * nv + kk);
+    }
+    // ---- use
+    double p1 = 0.0;
+    if (need_g) {
+        // the order of thread_sum<4>
+#pragma unroll
+        for (int u = 0; u < 4; ++u) p1 += (tid + (int64_t)u * T < np1) ? pt[u] : 0.0;
+        for (int64_t i = tid + 4 * (int64_t)T; i < np1; i += T) p1 += v.part1[i];
+    }
+#pragma unroll
+    for (int u = 0; u < UU; ++u)
+        if (tid + u * T < nc) uL[tid + u * T] = have_u ? uv[u] : 0.0;
+    if (gsmall) {
 #pragma unroll
         for (int u = 0; u < GU; ++u)
             if (tid + u * T < nc * nc) Gl[tid + u * T] = gv[u];
     }
     // fin[k]: the groups' sums (written by the group reducers, COH) in
     // ascending order, or both levels here
-    const double* gsum = v.partials + np3 * nv;
-    for (int kk = tid; kk < nv; kk += T) {
-        double s = 0.0;
-        if (COH) {
-            s = col_sum<true>(gsum, ng, nv, kk);
-        } else {
-            for (int64_t g = 0; g < ng; ++g) {
-                const int64_t r0 = g * kGroup;
-                const int64_t rn = (np3 - r0) < kGroup ? (np3 - r0) : kGroup;
-                s += col_sum<false>(v.partials + r0 * nv, rn, nv, kk);
-            }
+    if (one) {
+        if (tid < nv) {
+            double s2 = 0.0;
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                if (u < ng) s2 += gl[u];
+            fin[tid] = s2;
         }
-        fin[kk] = s;
+    } else {
+        for (int kk = tid; kk < nv; kk += T) {
+            double s2 = 0.0;
+            if (COH) {
+                s2 = col_sum<true>(gsum, ng, nv, kk);
+            } else {
+                for (int64_t g = 0; g < ng; ++g) {
+                    const int64_t r0 = g * kGroup;
+                    const int64_t rn = (np3 - r0) < kGroup ? (np3 - r0) : kGroup;
+                    s2 += col_sum<false>(v.partials + r0 * nv, rn, nv, kk);
+                }
+            }
+            fin[kk] = s2;
+        }
     }
     if (tid < NWORD) reinterpret_cast<unsigned long long*>(&S)[tid] = sw;
     __syncthreads();
     const uint32_t mask = (mode == 2) ? M_REFINE : M_RUN;
     if (((1u << S.status) & mask) == 0) return;
-    const double g = (mode == 0) ? sum_all_reg(p1, red) : 0.0;
+    const double g = need_g ? sum_all_reg(p1, red) : (mode == 0 ? g_in : 0.0);
     const double a = (mode == 0) ? S.rho / g : 0.0;
     double du = 0.0;
     if (nc > 0) {
         const double* Gi = gsmall ? Gl : v.Ginv;
-        ginv_matvec(Gi, nc, fin + 2, muL, red);
-        ginv_matvec(Gi, nc, fin + 2 + nc, gvL, red);
+        ginv_matvec2(Gi, nc, fin + 2, fin + 2 + nc, muL, gvL, red);
         // u = C^T r: recurrence u -= alpha (AC)^T w; zero after (re)projection
         double p = 0.0;
         for (int c = tid; c < nc; c += T) {
@@ -664,13 +793,14 @@ constexpr int upd_pool() {
     return 2 * kT3 * B + kT3 + 2048 + kT3;
 }
 
-template <typename V, typename W, int B, bool FUSE>
+template <typename V, typename W, int B, bool FUSE, int UR>
 __device__ __forceinline__ void update_reduce_body(const SysView<V, W>& v, int64_t bid, int mode, double* pool) {
     DevState* st = v.st;
     const uint32_t mask = (mode == 2) ? M_REFINE : M_RUN;
-    if (!gate(st, mask)) return;
-    const bool tm = mode == 0 && ktime_sample(st, 1);
-    ktime_begin(v.kslots, 1, bid, tm);
+    // the state words this body reads, loaded together up front (the
+    // finalize that rewrites them runs after every workgroup has read them)
+    const int32_t st_status = st->status, st_iter = st->iter, st_kt = st->ktime_on;
+    const double st_rho = st->rho;
     constexpr int T = kT3;
     double* ss = pool;
     double* ws = ss + T * B;
@@ -686,9 +816,13 @@ __device__ __forceinline__ void update_reduce_body(const SysView<V, W>& v, int64
     }
     const int64_t pb = bid * v.geo.cb3;
     const int64_t pe = (pb + v.geo.cb3) < v.nb ? (pb + v.geo.cb3) : v.nb;
+    const ProjSplit<V> pg(nc);
+    bool tm = false;
     double rr = 0.0, rs = 0.0;
-    double a = 0.0;
+    double a = 0.0, gam = -1.0;
     bool have_a = mode != 0;
+    const bool run = ((1u << st_status) & mask) != 0;
+    if (pb >= pe && !run) return;
     for (int64_t ps = pb; ps < pe; ps += T) {
         const int64_t p = ps + tid;
         double ri[B], wi[B], si[B];
@@ -702,6 +836,7 @@ __device__ __forceinline__ void update_reduce_body(const SysView<V, W>& v, int64
         // the SpMV partials, so the two latencies overlap
         W rv[B], qv[B];
         double xv[B];
+        V mv[B * B];
         if (p < pe) {
 #pragma unroll
             for (int d = 0; d < B; ++d) {
@@ -713,49 +848,74 @@ __device__ __forceinline__ void update_reduce_body(const SysView<V, W>& v, int64
                     xv[d] = v.x[i];
                 }
             }
+#pragma unroll
+            for (int e = 0; e < B * B; ++e) mv[e] = v.minv[p * B * B + e];
+        }
+        // the status is tested once the first step's loads are issued (they
+        // are in bounds whatever it is), so the latencies overlap
+        if (ps == pb) {
+            if (!run) return;
+            tm = mode == 0 && st_kt && (st_iter & 31) == 1;
+            ktime_begin(v.kslots, 1, bid, tm);
         }
         if (!have_a) {
-            a = st->rho / sum_all(v.part1, v.geo.g1, red);
+            gam = sum_all(v.part1, v.geo.g1, red);
+            a = st_rho / gam;
             have_a = true;
         }
+        double xn[B];
+        W rn[B];
         if (p < pe) {
 #pragma unroll
             for (int d = 0; d < B; ++d) {
-                const int64_t i = p * B + d;
                 W r2 = rv[d];
                 if (mode == 0) {
-                    v.x[i] = xv[d] + a * wi[d];
+                    xn[d] = xv[d] + a * wi[d];
                     r2 = (W)((double)r2 - a * (double)qv[d]);
-                    v.r[i] = r2;
                 }
+                rn[d] = r2;
                 ri[d] = (double)r2;
             }
             if (B == 1) {
-                si[0] = (double)(W)((double)v.minv[p] * ri[0]);
+                si[0] = (double)(W)((double)mv[0] * ri[0]);
             } else {
-                const V* m = v.minv + p * 9;
 #pragma unroll
                 for (int d = 0; d < B; ++d)
-                    si[d] = (double)(W)((double)m[3 * d] * ri[0] + (double)m[3 * d + 1] * ri[1] +
-                                        (double)m[3 * d + 2] * ri[2]);
+                    si[d] = (double)(W)((double)mv[3 * d] * ri[0] + (double)mv[3 * d + 1] * ri[1] +
+                                        (double)mv[3 * d + 2] * ri[2]);
             }
 #pragma unroll
             for (int d = 0; d < B; ++d) {
-                v.s[p * B + d] = (W)si[d];
                 rr += ri[d] * ri[d];
                 rs += ri[d] * si[d];
             }
         }
+        // s and w go to LDS before the stores are issued, so the barrier
+        // does not wait for them (the previous step's projection ended with
+        // a barrier, so the buffers are free)
         if (nc > 0) {
-            __syncthreads();
 #pragma unroll
             for (int d = 0; d < B; ++d) {
                 ss[tid * B + d] = si[d];
                 ws[tid * B + d] = wi[d];
             }
             __syncthreads();
+        }
+        if (p < pe) {
+#pragma unroll
+            for (int d = 0; d < B; ++d) {
+                const int64_t i = p * B + d;
+                if (mode == 0) {
+                    v.x[i] = xn[d];
+                    v.r[i] = rn[d];
+                }
+                v.s[i] = (W)si[d];
+            }
+        }
+        if (nc > 0) {
             const int64_t pn = (ps + T) < pe ? (ps + T) : pe;
-            project_rows<V>(v.AC + ps * B * v.ldac, v.ldac, (int)((pn - ps) * B), nc, ss, ws, tacc, vacc, cred);
+            project_rows<V, UR>(v.AC + ps * B * v.ldac, v.ldac, (int)((pn - ps) * B), nc, ss, ws, tacc, vacc, cred,
+                                pg);
         }
     }
     const int stride = 2 * nc + 2;
@@ -817,7 +977,7 @@ __device__ __forceinline__ void update_reduce_body(const SysView<V, W>& v, int64
     __syncthreads();
     if (mine != (unsigned)(ng - 1)) return;
     if (tid == 0) __hip_atomic_store(v.sync, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    finalize_update_body<V, W, true>(v, mode, pool);
+    finalize_update_body<V, W, true>(v, mode, pool, gam);
 }
 
 // ------------------------------------------------------------------ K5
@@ -827,23 +987,50 @@ __device__ __forceinline__ void update_reduce_body(const SysView<V, W>& v, int64
 // first = 1: initial direction w = z; first = 2: the update that follows a
 // residual replacement (runs only when one is pending).  A workgroup owns
 // 256 rows: lane l of every wave reads 4 consecutive rows of a column of C
-// (16 or 32 bytes), wave k takes the columns k, k + 4, ...; the four
+// (16 or 32 bytes), wave k takes the columns k, k + 4, ... (U of them per
+// load group; the order of the sums does not depend on U); the four
 // partial sums per row are added in LDS in a fixed order.
 template <typename V>
 struct alignas(4 * sizeof(V)) Quad {
     V e[4];
 };
 
-template <typename V, typename W>
+template <typename V, typename W, int U>
 __device__ __forceinline__ void correct_dir_body(const SysView<V, W>& v, int64_t bid, int first) {
     DevState* st = v.st;
-    if (!gate(st, M_RUN)) return;
-    if (first == 2 && st->pending_dir == 0) return;
     __shared__ double mu[1024];
     __shared__ double mu2[1024];
     __shared__ double part[4][2][256];
     const int nc = v.nc;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t nblk = (v.n + 255) / 256;
+    // the first block's loads of C, s and w are issued before the status
+    // test and the wait for the coefficients, so the latencies overlap
+    Quad<V> cq[U];
+    W sv = 0, wv0 = 0;
+    auto load_c = [&](int64_t blk, int c0) {
+        const V* Cb = v.C + blk * 256 + 4 * lane;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int c = c0 + 4 * u;
+            cq[u] = (c < nc) ? *reinterpret_cast<const Quad<V>*>(Cb + (int64_t)c * v.ldc) : Quad<V>{{0, 0, 0, 0}};
+        }
+    };
+    auto load_sw = [&](int64_t blk) {
+        const int64_t i = blk * 256 + tid;
+        if (i < v.n) {
+            sv = v.s[i];
+            if (first != 1) wv0 = v.w[i];
+        }
+    };
+    if (bid < nblk) {
+        if (wave < nc) load_c(bid, wave);
+        load_sw(bid);
+    }
+    // the status is tested after those loads are issued (they are in bounds
+    // whatever it is), so its latency overlaps theirs
+    if (!gate(st, M_RUN)) return;
+    if (first == 2 && st->pending_dir == 0) return;
     for (int c = tid; c < nc; c += 256) {
         mu[c] = v.mu[c];
         mu2[c] = (first == 1) ? v.mu[c] : v.mu2[c];
@@ -854,18 +1041,13 @@ __device__ __forceinline__ void correct_dir_body(const SysView<V, W>& v, int64_t
     const bool tm = first == 0 && ktime_sample(st, 2);
     ktime_begin(v.kslots, 2, bid, tm);
     __syncthreads();
-    constexpr int U = 8;
-    const int64_t nblk = (v.n + 255) / 256;
+    bool pre = true;
     for (int64_t blk = bid; blk < nblk; blk += v.geo.g5) {
         double az[4] = {0.0, 0.0, 0.0, 0.0}, aw[4] = {0.0, 0.0, 0.0, 0.0};
-        const V* Cb = v.C + blk * 256 + 4 * lane;
+        if (!pre) load_sw(blk);
         for (int c0 = wave; c0 < nc; c0 += 4 * U) {
-            Quad<V> cq[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int c = c0 + 4 * u;
-                cq[u] = (c < nc) ? *reinterpret_cast<const Quad<V>*>(Cb + (int64_t)c * v.ldc) : Quad<V>{{0, 0, 0, 0}};
-            }
+            if (!pre) load_c(blk, c0);
+            pre = false;
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int c = c0 + 4 * u;
@@ -879,6 +1061,7 @@ __device__ __forceinline__ void correct_dir_body(const SysView<V, W>& v, int64_t
                 }
             }
         }
+        pre = false;
         __syncthreads();
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -890,9 +1073,9 @@ __device__ __forceinline__ void correct_dir_body(const SysView<V, W>& v, int64_t
         if (i < v.n) {
             const double cz = ((part[0][0][tid] + part[1][0][tid]) + part[2][0][tid]) + part[3][0][tid];
             const double cw = ((part[0][1][tid] + part[1][1][tid]) + part[2][1][tid]) + part[3][1][tid];
-            const double s = (double)v.s[i];
+            const double s = (double)sv;
             const W zv = (W)(s - cz);
-            const W wv = (first == 1) ? zv : (W)(s - cw + beta * (double)v.w[i]);
+            const W wv = (first == 1) ? zv : (W)(s - cw + beta * (double)wv0);
             v.w[i] = wv;
             if (j < hist_cap) {
                 if (v.zhist) v.zhist[(int64_t)j * v.ldh + i] = (V)zv;
@@ -1059,14 +1242,14 @@ __global__ __launch_bounds__(256) void k_spmv_dot(SysView<V, W> v) {
     spmv_dot_body<V, W, B>(v, blockIdx.x);
 }
 template <typename V, typename W, int B>
-__global__ __launch_bounds__(kT3, 4) void k_update_reduce(SysView<V, W> v, int mode) {
+__global__ __launch_bounds__(kT3, 2) void k_update_reduce(SysView<V, W> v, int mode) {
     __shared__ double pool[upd_pool<B>()];
-    update_reduce_body<V, W, B, false>(v, blockIdx.x, mode, pool);
+    update_reduce_body<V, W, B, false, kUrOne>(v, blockIdx.x, mode, pool);
 }
 template <typename V, typename W, int B>
-__global__ __launch_bounds__(kT3, 4) void k_update_fused(SysView<V, W> v, int mode) {
+__global__ __launch_bounds__(kT3, 2) void k_update_fused(SysView<V, W> v, int mode) {
     __shared__ double pool[upd_pool<B>() > fin_pool() ? upd_pool<B>() : fin_pool()];
-    update_reduce_body<V, W, B, true>(v, blockIdx.x, mode, pool);
+    update_reduce_body<V, W, B, true, kUrOne>(v, blockIdx.x, mode, pool);
 }
 template <typename V, typename W>
 __global__ __launch_bounds__(kTF3) void k_finalize_update(SysView<V, W> v, int mode) {
@@ -1075,7 +1258,7 @@ __global__ __launch_bounds__(kTF3) void k_finalize_update(SysView<V, W> v, int m
 }
 template <typename V, typename W>
 __global__ __launch_bounds__(256) void k_correct_dir(SysView<V, W> v, int first) {
-    correct_dir_body<V, W>(v, blockIdx.x, first);
+    correct_dir_body<V, W, 8>(v, blockIdx.x, first);
 }
 template <typename V, typename W, int B>
 __global__ __launch_bounds__(256) void k_true_resid(SysView<V, W> v, int final_only) {
@@ -1113,14 +1296,14 @@ __global__ __launch_bounds__(kT3, 4) void kb_update_reduce(const SysView<V, W>* 
                                                         const int2* __restrict__ map, int mode) {
     __shared__ double pool[upd_pool<B>()];
     const int2 e = map[blockIdx.x];
-    update_reduce_body<V, W, B, false>(views[e.x], e.y, mode, pool);
+    update_reduce_body<V, W, B, false, ur_batch<V>()>(views[e.x], e.y, mode, pool);
 }
 template <typename V, typename W, int B>
 __global__ __launch_bounds__(kT3, 4) void kb_update_fused(const SysView<V, W>* __restrict__ views,
                                                        const int2* __restrict__ map, int mode) {
     __shared__ double pool[upd_pool<B>() > fin_pool() ? upd_pool<B>() : fin_pool()];
     const int2 e = map[blockIdx.x];
-    update_reduce_body<V, W, B, true>(views[e.x], e.y, mode, pool);
+    update_reduce_body<V, W, B, true, ur_batch<V>()>(views[e.x], e.y, mode, pool);
 }
 template <typename V, typename W>
 __global__ __launch_bounds__(kTF3) void kb_finalize_update(const SysView<V, W>* __restrict__ views,
@@ -1132,7 +1315,7 @@ template <typename V, typename W>
 __global__ __launch_bounds__(256) void kb_correct_dir(const SysView<V, W>* __restrict__ views,
                                                       const int2* __restrict__ map, int first) {
     const int2 e = map[blockIdx.x];
-    correct_dir_body<V, W>(views[e.x], e.y, first);
+    correct_dir_body<V, W, 8>(views[e.x], e.y, first);
 }
 template <typename V, typename W, int B>
 __global__ __launch_bounds__(256) void kb_true_resid(const SysView<V, W>* __restrict__ views,
