@@ -414,7 +414,7 @@ def main():
                     help="keep the default update-kernel tile instead of timing candidates")
     ap.add_argument("--update-rows", type=int, default=0, help="fixed update-kernel block rows per workgroup")
     ap.add_argument("--max-basis", type=int, default=0, help="basis cap (0: the workload's)")
-    ap.add_argument("--sequences", type=int, default=64, help="batched workload: number of sequences")
+    ap.add_argument("--sequences", type=int, default=256, help="batched workload: number of sequences")
     ap.add_argument("--history-cap", type=int, default=256, help="batched workload: Krylov vectors kept per solve")
     ap.add_argument("--eager", action="store_true", help="launch kernels one by one instead of graph replay")
     ap.add_argument("--separate-finalize", action="store_true",

@@ -662,13 +662,17 @@ krs_status SeqImpl<V, W>::begin_solve() {
     if (desc.reuse == KRS_REUSE_SELECTIVE) {
         hist = desc.history_cap > 0 ? std::min(desc.history_cap, max_iter + 1) : max_iter + 1;
         // keep as much of the run as memory allows: a shorter history only
-        // shortens the Lanczos pair used for the Ritz analysis
+        // shortens the Lanczos pair used for the Ritz analysis.  A length
+        // that did not fit is not tried again by later solves (the attempt
+        // would first release the reservation that does fit).
+        if (history_fit > 0) hist = std::min(hist, history_fit);
         while (!d_Z.reserve(ctx, (size_t)ldc * hist * sizeof(V))) {
             if (hist <= 64) {
                 set_error("device allocation failed for the Krylov history");
                 return KRS_E_OOM;
             }
             hist /= 2;
+            history_fit = hist;
         }
         history_kept = hist;
     } else if (desc.reuse == KRS_REUSE_TOTAL) {
