@@ -63,6 +63,28 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
     return t;
 }
 
+// Two sums over the workgroup at once (each in the order of block_sum);
+// results valid in thread 0.  lds: 2 * (blockDim.x / 64) doubles.
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* lds) {
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
+    __syncthreads();
+    if (lane == 0) {
+        lds[wave] = a;
+        lds[nw + wave] = b;
+    }
+    __syncthreads();
+    double ta = 0.0, tb = 0.0;
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < nw; ++i) ta += lds[i];
+        for (int i = 0; i < nw; ++i) tb += lds[nw + i];
+    }
+    a = ta;
+    b = tb;
+}
+
 // Reduce `nv` values over `np` partial rows (row stride `stride`) in a fixed
 // order with all threads of the workgroup; out[k] for k < nv (LDS).
 // Load of a value written by another workgroup of the same launch (agent-
@@ -466,7 +488,7 @@ struct alignas(16) Vec16 {
 // Rows per load group of a lane: the single-system update kernel runs one
 // workgroup per compute unit (up to 256 registers per lane), the fused batch
 // kernel several (128).  The summation order does not depend on it.
-constexpr int kUrOne = 16;
+constexpr int kUrOne = 12;
 template <typename V>
 constexpr int ur_batch() {
     return 4;
@@ -593,11 +615,40 @@ __device__ __forceinline__ void project_rows(const V* __restrict__ ACt, int64_t 
 constexpr int kStateWords = 32;
 constexpr int fin_pool() { return kStateWords + kTF3 + 2056 + 3 * 1024 + 4096 + 8; }
 
+// Inputs of the finalize that no workgroup of the launch writes before it
+// runs (state words, u, G^-1): loaded into registers by fin_prefetch, which
+// the fused update's group reducers issue before their last ticket.
+struct FinPre {
+    static constexpr int UU = 1024 / kTF3;
+    static constexpr int GU = 4096 / kTF3;
+    unsigned long long sw;
+    double uv[UU];
+    double gv[GU];
+};
+template <typename V, typename W>
+__device__ __forceinline__ void fin_prefetch(const SysView<V, W>& v, int mode, FinPre& f) {
+    constexpr int T = kTF3;
+    constexpr int NWORD = (int)(sizeof(DevState) / 8);
+    const int tid = threadIdx.x;
+    const int nc = v.nc;
+    f.sw = 0ull;
+    if (tid < NWORD) f.sw = reinterpret_cast<const unsigned long long*>(v.st)[tid];
+    if (mode == 0 && nc > 0) {
+#pragma unroll
+        for (int u = 0; u < FinPre::UU; ++u) f.uv[u] = v.u[min(tid + u * T, nc - 1)];
+    }
+    if (nc <= 64 && nc > 0) {
+#pragma unroll
+        for (int u = 0; u < FinPre::GU; ++u) f.gv[u] = v.Ginv[min(tid + u * T, nc * nc - 1)];
+    }
+}
+
 // g_in: (w, q) of this step when the caller has already reduced the SpMV
-// partials (the fused update, in the same order), else negative.
+// partials (the fused update, in the same order), else negative.  pre:
+// fin_prefetch of this launch, or null.
 template <typename V, typename W, bool COH>
 __device__ __forceinline__ void finalize_update_body(const SysView<V, W>& v, int mode, double* pool,
-                                                     double g_in = -1.0) {
+                                                     double g_in = -1.0, const FinPre* pre = nullptr) {
     constexpr int T = kTF3;
     constexpr int NWORD = (int)(sizeof(DevState) / 8);
     static_assert(NWORD <= kStateWords, "state staging area too small");
@@ -617,28 +668,18 @@ __device__ __forceinline__ void finalize_update_body(const SysView<V, W>& v, int
     // ---- loads (state, SpMV partials, u, G^-1 and the update's sums): each
     // is issued at a clamped, valid address before any is used, so their
     // latencies overlap
-    unsigned long long sw = 0ull;
-    if (tid < NWORD) sw = reinterpret_cast<const unsigned long long*>(v.st)[tid];
+    FinPre f;
+    if (pre) f = *pre;
+    else fin_prefetch(v, mode, f);
     const bool need_g = mode == 0 && !(g_in >= 0.0);
     double pt[4];
     if (need_g) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) pt[u] = v.part1[min((int64_t)tid + u * T, np1 - 1)];
     }
-    constexpr int UU = 1024 / T;
-    double uv[UU];
+    constexpr int UU = FinPre::UU, GU = FinPre::GU;
     const bool have_u = mode == 0 && nc > 0;
-    if (have_u) {
-#pragma unroll
-        for (int u = 0; u < UU; ++u) uv[u] = v.u[min(tid + u * T, nc - 1)];
-    }
     const bool gsmall = nc <= 64;
-    constexpr int GU = 4096 / T;
-    double gv[GU];
-    if (gsmall && nc > 0) {
-#pragma unroll
-        for (int u = 0; u < GU; ++u) gv[u] = v.Ginv[min(tid + u * T, nc * nc - 1)];
-    }
     // the groups' sums of this thread's column in one pass (the usual case)
     const double* gsum = v.partials + np3 * nv;
     const bool one = COH && nv <= T && ng <= 16;
@@ -658,11 +699,11 @@ __device__ __forceinline__ void finalize_update_body(const SysView<V, W>& v, int
     }
 #pragma unroll
     for (int u = 0; u < UU; ++u)
-        if (tid + u * T < nc) uL[tid + u * T] = have_u ? uv[u] : 0.0;
+        if (tid + u * T < nc) uL[tid + u * T] = have_u ? f.uv[u] : 0.0;
     if (gsmall) {
 #pragma unroll
         for (int u = 0; u < GU; ++u)
-            if (tid + u * T < nc * nc) Gl[tid + u * T] = gv[u];
+            if (tid + u * T < nc * nc) Gl[tid + u * T] = f.gv[u];
     }
     // fin[k]: the groups' sums (written by the group reducers, COH) in
     // ascending order, or both levels here
@@ -689,7 +730,7 @@ __device__ __forceinline__ void finalize_update_body(const SysView<V, W>& v, int
             fin[kk] = s2;
         }
     }
-    if (tid < NWORD) reinterpret_cast<unsigned long long*>(&S)[tid] = sw;
+    if (tid < NWORD) reinterpret_cast<unsigned long long*>(&S)[tid] = f.sw;
     __syncthreads();
     const uint32_t mask = (mode == 2) ? M_REFINE : M_RUN;
     if (((1u << S.status) & mask) == 0) return;
@@ -920,8 +961,8 @@ __device__ __forceinline__ void update_reduce_body(const SysView<V, W>& v, int64
     }
     const int stride = 2 * nc + 2;
     double* myp = v.partials + bid * stride;
-    const double brr = block_sum(rr, red);
-    const double brs = block_sum(rs, red);
+    double brr = rr, brs = rs;
+    block_sum2(brr, brs, red);
     __syncthreads();
     if (!FUSE) {
         if (tid == 0) {
@@ -970,14 +1011,20 @@ __device__ __forceinline__ void update_reduce_body(const SysView<V, W>& v, int64
     }
     __builtin_amdgcn_s_waitcnt(kWaitVm0);
     __syncthreads();
-    // level 2: the last group reducer finishes the step
-    if (tid == 0) *ticket = __hip_atomic_fetch_add(v.sync, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // level 2: the last group reducer finishes the step.  The finalize's
+    // read-only inputs are loaded while the ticket is in flight, in case
+    // this reducer is the last.
+    unsigned tk = 0;
+    if (tid == 0) tk = __hip_atomic_fetch_add(v.sync, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    FinPre fpre;
+    fin_prefetch(v, mode, fpre);
+    if (tid == 0) *ticket = tk;
     __syncthreads();
     mine = *ticket;
     __syncthreads();
     if (mine != (unsigned)(ng - 1)) return;
     if (tid == 0) __hip_atomic_store(v.sync, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    finalize_update_body<V, W, true>(v, mode, pool, gam);
+    finalize_update_body<V, W, true>(v, mode, pool, gam, &fpre);
 }
 
 // ------------------------------------------------------------------ K5
