@@ -1284,16 +1284,19 @@ krs_status batch_solve(krs_ctx* ctx, SeqBase* const* seqs, int count, double* co
 }
 
 krs_status recycle_all(krs_ctx* ctx, SeqBase* const* seqs, int count, int32_t* added) {
-    // Independent sequences: their host-side Ritz work runs on up to 16
-    // threads (one bisection thread each); the device work they enqueue on
-    // the shared stream is independent, so its interleaving is immaterial.
+    // Independent sequences: their host-side Ritz work runs on up to
+    // host_threads() threads, one sequence per thread, the threads left over
+    // shared out as bisection threads of each (all of them when there is a
+    // single sequence); the device work they enqueue on the shared stream is
+    // independent, so its interleaving is immaterial.
     std::vector<krs_status> st(count, KRS_OK);
     const int nt = std::max(1, std::min(count, host_threads()));
+    const int per = std::max(1, host_threads() / nt);
     std::atomic<int> next{0};
     auto work = [&]() {
         (void)hipSetDevice(ctx->device);
         for (int i = next.fetch_add(1); i < count; i = next.fetch_add(1)) {
-            seqs[i]->recycle_threads = 1;
+            seqs[i]->recycle_threads = per;
             int32_t a = 0;
             st[i] = seqs[i]->recycle(&a);
             seqs[i]->recycle_threads = 0;
