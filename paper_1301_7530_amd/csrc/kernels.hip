@@ -489,10 +489,7 @@ struct alignas(16) Vec16 {
 // workgroup per compute unit (up to 256 registers per lane), the fused batch
 // kernel several (128).  The summation order does not depend on it.
 constexpr int kUrOne = 12;
-template <typename V>
-constexpr int ur_batch() {
-    return 4;
-}
+constexpr int kUrBatch = 4;
 
 // Work split of the projection: wave `wave` takes item wave + k NW of the
 // items (chunk it % nch, row phase it / nch), P waves per chunk.
@@ -1343,14 +1340,14 @@ __global__ __launch_bounds__(kT3, 4) void kb_update_reduce(const SysView<V, W>* 
                                                         const int2* __restrict__ map, int mode) {
     __shared__ double pool[upd_pool<B>()];
     const int2 e = map[blockIdx.x];
-    update_reduce_body<V, W, B, false, ur_batch<V>()>(views[e.x], e.y, mode, pool);
+    update_reduce_body<V, W, B, false, kUrBatch>(views[e.x], e.y, mode, pool);
 }
 template <typename V, typename W, int B>
 __global__ __launch_bounds__(kT3, 4) void kb_update_fused(const SysView<V, W>* __restrict__ views,
                                                        const int2* __restrict__ map, int mode) {
     __shared__ double pool[upd_pool<B>() > fin_pool() ? upd_pool<B>() : fin_pool()];
     const int2 e = map[blockIdx.x];
-    update_reduce_body<V, W, B, true, ur_batch<V>()>(views[e.x], e.y, mode, pool);
+    update_reduce_body<V, W, B, true, kUrBatch>(views[e.x], e.y, mode, pool);
 }
 template <typename V, typename W>
 __global__ __launch_bounds__(kTF3) void kb_finalize_update(const SysView<V, W>* __restrict__ views,
