@@ -1552,65 +1552,87 @@ __global__ __launch_bounds__(256) void k_basis_combine(const V* Z, int64_t ldz, 
 
 // out[:, t] = sum_j Z[:, j] F[j, t] for single-precision Z and out, on the
 // matrix cores (v_mfma_f32_32x32x2f32): a wave owns 32 rows and CT tiles of
-// 32 columns, accumulating over j two at a time; a workgroup (4 waves) owns
-// 128 rows; F (double) is staged in LDS as float, KC of its rows at a time.
+// 32 columns, accumulating over j two at a time (ascending); a workgroup
+// (4 waves) owns 128 rows.  Both operands go through LDS in chunks of KC
+// values of j, double-buffered: while the waves multiply one chunk, the
+// next one is loaded into registers (Z in 16-byte row segments, F as double
+// and rounded to float) and stored to the other buffer.
 // Operand layout of the instruction: lane l supplies A[l % 32][l / 32] and
 // B[l / 32][l % 32]; accumulator register r of lane l holds
 // D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
+// Bounds: rows up to the next multiple of 128 lie within the leading
+// dimension (a multiple of 256, at least n); indices of j past m are clamped
+// to m - 1 and their F rows staged as zero.
 typedef float mfma_f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 template <int CT>
 __global__ __launch_bounds__(256) void k_basis_combine_mfma(const float* __restrict__ Z, int64_t ldz, int m,
                                                             const double* __restrict__ F, int s,
                                                             float* __restrict__ out, int64_t ldo, int64_t n) {
-    constexpr int KC = 64;
+    constexpr int KC = 32;
     constexpr int NC = CT * 32;
-    constexpr int UK = 8;  // pairs of j whose Z loads are issued together
-    __shared__ float sF[KC][NC];
+    constexpr int FPT = KC * NC / 256;  // F values staged per thread and chunk
+    __shared__ float sZ[2][KC][128];
+    __shared__ float sF[2][KC][NC];
     const int c0 = blockIdx.y * NC;
     const int ncol = (s - c0) < NC ? (s - c0) : NC;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t row0 = (int64_t)blockIdx.x * 128 + wave * 32;
-    const int64_t arow = row0 + (lane & 31);
-    const bool rok = arow < n;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int64_t rowb = (int64_t)blockIdx.x * 128;
     const int khalf = lane >> 5;
+    // staging roles: Z element (j = zj + 8 i, rows zr .. zr + 3); F element
+    // (j = fj, column fc + 8 i)
+    const int zj = tid >> 5, zr = (tid & 31) * 4;
+    const int fj = tid & 31, fc = tid >> 5;
+    f32x4 zreg[4];
+    float freg[FPT];
     mfma_f32x16 acc[CT];
 #pragma unroll
     for (int t = 0; t < CT; ++t)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
-    for (int k0 = 0; k0 < m; k0 += KC) {
-        __syncthreads();
-        for (int e = threadIdx.x; e < KC * NC; e += 256) {
-            const int kk = e / NC, cc = e % NC;
-            const int kx = k0 + kk;
-            sF[kk][cc] = (kx < m && cc < ncol) ? (float)F[(int64_t)(c0 + cc) * m + kx] : 0.f;
-        }
-        __syncthreads();
-        const int kn = (m - k0) < KC ? (m - k0) : KC;
-        for (int kk = 0; kk < kn; kk += 2 * UK) {
-            float a[UK];
+    const int nchunk = (m + KC - 1) / KC;
+    for (int q = 0; q <= nchunk; ++q) {
+        // load chunk q (into registers), multiply chunk q - 1 (from LDS),
+        // store chunk q to the other buffer
+        const int buf = q & 1;
+        if (q < nchunk) {
+            const int k0 = q * KC;
 #pragma unroll
-            for (int u = 0; u < UK; ++u) {
-                // past the last column of Z the staged F row is zero: any
-                // finite Z value will do, so the index is clamped
-                int kx = k0 + kk + 2 * u + khalf;
+            for (int i = 0; i < 4; ++i) {
+                int kx = k0 + zj + 8 * i;
                 kx = kx < m ? kx : m - 1;
-                a[u] = rok ? Z[(int64_t)kx * ldz + arow] : 0.f;
+                zreg[i] = *reinterpret_cast<const f32x4*>(Z + (int64_t)kx * ldz + rowb + zr);
             }
+            const int kx = k0 + fj;
 #pragma unroll
-            for (int u = 0; u < UK; ++u) {
-                const int kr = kk + 2 * u + khalf;
-                if (kk + 2 * u < kn) {
+            for (int i = 0; i < FPT; ++i) {
+                const int cc = fc + 8 * i;
+                freg[i] = (kx < m && cc < ncol) ? (float)F[(int64_t)(c0 + cc) * m + kx] : 0.f;
+            }
+        }
+        if (q > 0) {
+            const int pb = buf ^ 1;
 #pragma unroll
-                    for (int t = 0; t < CT; ++t) {
-                        const float b = sF[kr < KC ? kr : KC - 1][t * 32 + (lane & 31)];
-                        acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[u], b, acc[t], 0, 0, 0);
-                    }
+            for (int kk = 0; kk < KC; kk += 2) {
+                const float a = sZ[pb][kk + khalf][wave * 32 + (lane & 31)];
+#pragma unroll
+                for (int t = 0; t < CT; ++t) {
+                    const float b = sF[pb][kk + khalf][t * 32 + (lane & 31)];
+                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc[t], 0, 0, 0);
                 }
             }
         }
+        if (q < nchunk) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) *reinterpret_cast<f32x4*>(&sZ[buf][zj + 8 * i][zr]) = zreg[i];
+#pragma unroll
+            for (int i = 0; i < FPT; ++i) sF[buf][fj][fc + 8 * i] = freg[i];
+        }
+        __syncthreads();
     }
+    const int64_t row0 = rowb + wave * 32;
 #pragma unroll
     for (int t = 0; t < CT; ++t) {
         const int col = t * 32 + (lane & 31);
