@@ -551,7 +551,7 @@ template <typename V, typename W>
 int64_t SeqImpl<V, W>::working_bytes() const {
     const int max_iter = std::max(0, desc.max_iter);
     int64_t hist = 0;
-    if (desc.reuse == KRS_REUSE_SELECTIVE)
+    if (desc.reuse == KRS_REUSE_SELECTIVE && history_needed())
         hist = desc.history_cap > 0 ? std::min(desc.history_cap, max_iter + 1) : max_iter + 1;
     const int ncmax = std::max(nc, desc.max_basis > 0 ? desc.max_basis : nc);
     const int64_t ldm = std::max<int64_t>(32, ((int64_t)ncmax + 31) & ~(int64_t)31);
@@ -659,7 +659,11 @@ krs_status SeqImpl<V, W>::begin_solve() {
     }
     int hist = 0;
     trks_slots = 0;
-    if (desc.reuse == KRS_REUSE_SELECTIVE) {
+    if (desc.reuse == KRS_REUSE_SELECTIVE && !history_needed()) {
+        // a full frozen basis takes nothing from this run: no history
+        d_Z.release(ctx);
+        history_kept = 0;
+    } else if (desc.reuse == KRS_REUSE_SELECTIVE) {
         hist = desc.history_cap > 0 ? std::min(desc.history_cap, max_iter + 1) : max_iter + 1;
         // keep as much of the run as memory allows: a shorter history only
         // shortens the Lanczos pair used for the Ritz analysis.  A length

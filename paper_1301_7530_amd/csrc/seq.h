@@ -92,6 +92,10 @@ struct SeqImpl : SeqBase {
     int dropped_last = 0;
     int history_kept = 0;
     int history_fit = 0;  // history length that fit after a longer one did not (0: none failed)
+    // SRKS needs the run's directions unless the basis is full and frozen
+    bool history_needed() const {
+        return !(desc.cap_policy == KRS_CAP_FREEZE && desc.max_basis > 0 && nc >= desc.max_basis);
+    }
     std::vector<double> h_F;  // host source of the last basis-update upload
     int64_t ref_cost = 0;   // modelled bytes of the latest solve with the initial basis (cost cap)
     int cost_hold = 0;      // systems left before the cost cap lets columns be appended again
