@@ -840,19 +840,29 @@ int64_t SeqImpl<V, W>::model_bytes_per_iter() const {
 
 // ------------------------------------------------------------- recycle
 
+// recycle() = recycle_plan() + recycle_apply().  The plan is host work only
+// (the cost-cap decision, the Ritz analysis and selection, the combination
+// matrix F) and touches no device state, so several sequences' plans can
+// run on other threads while the device works; the apply step enqueues the
+// basis update on the stream.
 template <typename V, typename W>
 krs_status SeqImpl<V, W>::recycle(int32_t* n_added) {
-    if (n_added) *n_added = 0;
+    krs_status st = recycle_plan();
+    if (st != KRS_OK) return st;
+    return recycle_apply(n_added);
+}
+
+template <typename V, typename W>
+krs_status SeqImpl<V, W>::recycle_plan() {
+    plan = RecyclePlan{};
     if (!solved) {
         set_error("krs_seq_recycle needs a completed solve");
         return KRS_E_STATE;
     }
     solved = false;
-    // host wall time: the call only enqueues device work (stream-ordered
-    // after it), so it does not wait for the device
+    plan.ready = true;
     const auto t_start = std::chrono::steady_clock::now();
     const int m = m_last;
-    int added = 0;
     last_theta.clear();
     last_sel.clear();
     // Cost cap: the modelled bytes of the last solve (iterations times bytes
@@ -871,8 +881,7 @@ krs_status SeqImpl<V, W>::recycle(int32_t* n_added) {
                 append_ok = false;
             }
         } else if (ref_cost > 0 && cost >= ref_cost) {
-            if (nc0 > 0)
-                KRS_HIP(hipMemcpyAsync(d_C.p, d_C0.p, (size_t)ldc * nc0 * sizeof(V), hipMemcpyDeviceToDevice, stream));
+            plan.restore_c0 = nc0 > 0;
             nc = nc0;
             restarts += 1;
             // every failed trial doubles the wait before the next one
@@ -890,15 +899,11 @@ krs_status SeqImpl<V, W>::recycle(int32_t* n_added) {
         // w_j / sqrt((w_j, A w_j)) for the captured directions (Algorithm 2)
         const int cnt = std::min(m, trks_slots);
         if (cnt > 0) {
-            std::vector<double>& sc = h_F;  // kept alive: the copy below is asynchronous
+            std::vector<double>& sc = h_F;  // kept alive: the copy in the apply step is asynchronous
             sc.assign(cnt, 0.0);
             for (int j = 0; j < cnt; ++j) sc[j] = 1.0 / std::sqrt(coef_gamma[j]);
-            if (!d_F.reserve(ctx, cnt * sizeof(double))) return KRS_E_OOM;
-            KRS_HIP(hipMemcpyAsync(d_F.p, sc.data(), cnt * sizeof(double), hipMemcpyHostToDevice, stream));
-            launch_scale_columns<V>((V*)d_C.p + (size_t)nc * ldc, ldc, n, (const double*)d_F.p, cnt, stream);
-            KRS_CHECK_LAUNCH();
-            nc += cnt;
-            added = cnt;
+            plan.kind = 1;
+            plan.add = cnt;
         }
     } else if (desc.reuse == KRS_REUSE_SELECTIVE && m > 1 && !(capped && nc >= desc.max_basis)) {
         // (with a full frozen basis nothing could be appended: no extraction)
@@ -992,7 +997,7 @@ krs_status SeqImpl<V, W>::recycle(int32_t* n_added) {
                 std::vector<double> diag(mu), off(mu - 1);
                 for (int j = 0; j < mu; ++j) diag[j] = dd[j] + (j > 0 ? l2[j - 1] * dd[j - 1] : 0.0);
                 for (int j = 0; j + 1 < mu; ++j) off[j] = std::sqrt(l2[j]) * dd[j];
-                std::vector<double>& F = h_F;  // kept alive: the copy below is asynchronous
+                std::vector<double>& F = h_F;  // kept alive: the copy in the apply step is asynchronous
                 F.assign((size_t)mu * s, 0.0);
                 std::vector<double> q;
                 for (int t = 0; t < s; ++t) {
@@ -1002,16 +1007,48 @@ krs_status SeqImpl<V, W>::recycle(int32_t* n_added) {
                     for (int j = 0; j < mu; ++j)
                         F[(size_t)t * mu + j] = ((j & 1) ? -1.0 : 1.0) * q[j] * sc / std::sqrt(coef_rho[j]);
                 }
-                if (!ensure_c_capacity(nc + s)) return KRS_E_OOM;
-                if (!d_F.reserve(ctx, F.size() * sizeof(double))) return KRS_E_OOM;
-                KRS_HIP(hipMemcpyAsync(d_F.p, F.data(), F.size() * sizeof(double), hipMemcpyHostToDevice, stream));
-                launch_basis_combine<V>((const V*)d_Z.p, ldc, mu, (const double*)d_F.p, s, (V*)d_C.p + (size_t)nc * ldc,
-                                        ldc, n, stream);
-                KRS_CHECK_LAUNCH();
-                nc += s;
-                added = s;
+                plan.kind = 2;
+                plan.add = s;
+                plan.mu = mu;
             }
         }
+    }
+    info_last.added = plan.add;
+    info_last.selected = last_selected;
+    plan.host_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    return KRS_OK;
+}
+
+// Device side of a recycle: restore C0 (cost cap), scale the captured
+// directions (TRKS) or combine the history into the new columns (SRKS),
+// then the restart cap.  Only enqueues; stream-ordered before the next solve.
+template <typename V, typename W>
+krs_status SeqImpl<V, W>::recycle_apply(int32_t* n_added) {
+    if (n_added) *n_added = 0;
+    if (!plan.ready) {
+        set_error("krs_seq_recycle needs a completed solve");
+        return KRS_E_STATE;
+    }
+    plan.ready = false;
+    const auto t_start = std::chrono::steady_clock::now();
+    if (plan.restore_c0)
+        KRS_HIP(hipMemcpyAsync(d_C.p, d_C0.p, (size_t)ldc * nc0 * sizeof(V), hipMemcpyDeviceToDevice, stream));
+    if (plan.kind == 1) {
+        const int cnt = plan.add;
+        if (!d_F.reserve(ctx, cnt * sizeof(double))) return KRS_E_OOM;
+        KRS_HIP(hipMemcpyAsync(d_F.p, h_F.data(), cnt * sizeof(double), hipMemcpyHostToDevice, stream));
+        launch_scale_columns<V>((V*)d_C.p + (size_t)nc * ldc, ldc, n, (const double*)d_F.p, cnt, stream);
+        KRS_CHECK_LAUNCH();
+        nc += cnt;
+    } else if (plan.kind == 2) {
+        const int s = plan.add;
+        if (!ensure_c_capacity(nc + s)) return KRS_E_OOM;
+        if (!d_F.reserve(ctx, h_F.size() * sizeof(double))) return KRS_E_OOM;
+        KRS_HIP(hipMemcpyAsync(d_F.p, h_F.data(), h_F.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+        launch_basis_combine<V>((const V*)d_Z.p, ldc, plan.mu, (const double*)d_F.p, s, (V*)d_C.p + (size_t)nc * ldc,
+                                ldc, n, stream);
+        KRS_CHECK_LAUNCH();
+        nc += s;
     }
     // restart cap (Algorithm 3, last step)
     if (desc.max_basis > 0 && desc.cap_policy == KRS_CAP_RESTART && nc >= desc.max_basis) {
@@ -1022,11 +1059,10 @@ krs_status SeqImpl<V, W>::recycle(int32_t* n_added) {
         restarts += 1;
     }
     KRS_CHECK_LAUNCH();
-    info_last.added = added;
-    info_last.selected = last_selected;
+    // host wall time of plan and apply: neither waits for the device
     info_last.t_recycle_ms =
-        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
-    if (n_added) *n_added = added;
+        plan.host_ms + std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    if (n_added) *n_added = plan.add;
     return KRS_OK;
 }
 
@@ -1287,24 +1323,19 @@ krs_status batch_solve(krs_ctx* ctx, SeqBase* const* seqs, int count, double* co
     return worst;
 }
 
-krs_status recycle_all(krs_ctx* ctx, SeqBase* const* seqs, int count, int32_t* added) {
+void plan_all(SeqBase* const* seqs, int count, krs_status* st) {
     // Independent sequences: their host-side Ritz work runs on up to
     // host_threads() threads, one sequence per thread, the threads left over
     // shared out as bisection threads of each (all of them when there is a
-    // single sequence); the device work they enqueue on the shared stream is
-    // independent, so its interleaving is immaterial.
-    std::vector<krs_status> st(count, KRS_OK);
+    // single sequence).  Host work only: no device calls.
     const int nt = std::max(1, std::min(count, host_threads()));
     const int per = std::max(1, host_threads() / nt);
     std::atomic<int> next{0};
     auto work = [&]() {
-        (void)hipSetDevice(ctx->device);
         for (int i = next.fetch_add(1); i < count; i = next.fetch_add(1)) {
             seqs[i]->recycle_threads = per;
-            int32_t a = 0;
-            st[i] = seqs[i]->recycle(&a);
+            st[i] = seqs[i]->recycle_plan();
             seqs[i]->recycle_threads = 0;
-            if (added) added[i] = a;
         }
     };
     if (nt == 1) {
@@ -1314,9 +1345,21 @@ krs_status recycle_all(krs_ctx* ctx, SeqBase* const* seqs, int count, int32_t* a
         for (int t = 0; t < nt; ++t) pool.emplace_back(work);
         for (auto& th : pool) th.join();
     }
-    for (krs_status x : st)
-        if (x != KRS_OK) return x;
-    return KRS_OK;
+}
+
+krs_status recycle_all(krs_ctx* ctx, SeqBase* const* seqs, int count, int32_t* added) {
+    (void)ctx;
+    std::vector<krs_status> st(count, KRS_OK);
+    plan_all(seqs, count, st.data());
+    // the device work of the plans, in order, on the shared stream
+    krs_status first = KRS_OK;
+    for (int i = 0; i < count; ++i) {
+        int32_t a = 0;
+        if (st[i] == KRS_OK) st[i] = seqs[i]->recycle_apply(&a);
+        if (added) added[i] = a;
+        if (st[i] != KRS_OK && first == KRS_OK) first = st[i];
+    }
+    return first;
 }
 
 }  // namespace krs

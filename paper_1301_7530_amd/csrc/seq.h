@@ -56,6 +56,10 @@ struct SeqBase {
     std::atomic<int> in_server{0};  // requests of a server not yet completed
     int recycle_threads = 0;        // host threads of the Ritz bisection (0: automatic)
     virtual krs_status recycle(int32_t* n_added) = 0;
+    // recycle() in two steps: host work only (may run on another thread
+    // while the device is busy), then the device work on the stream
+    virtual krs_status recycle_plan() = 0;
+    virtual krs_status recycle_apply(int32_t* n_added) = 0;
     virtual krs_status basis(double* C, int64_t ld, int32_t cap, int32_t* n_c) = 0;
     virtual void destroy() = 0;
     // live kernel timing (sampled iterations, device wall clock)
@@ -97,6 +101,14 @@ struct SeqImpl : SeqBase {
         return !(desc.cap_policy == KRS_CAP_FREEZE && desc.max_basis > 0 && nc >= desc.max_basis);
     }
     std::vector<double> h_F;  // host source of the last basis-update upload
+    struct RecyclePlan {
+        bool ready = false;       // planned, not yet applied
+        bool restore_c0 = false;  // cost cap: back to the initial basis
+        int kind = 0;             // 0: nothing appended, 1: TRKS scaling, 2: SRKS combination
+        int add = 0;              // columns appended
+        int mu = 0;               // SRKS: length of the Lanczos pair combined
+        double host_ms = 0.0;
+    } plan;
     int64_t ref_cost = 0;   // modelled bytes of the latest solve with the initial basis (cost cap)
     int cost_hold = 0;      // systems left before the cost cap lets columns be appended again
     int cost_fails = 0;     // failed trials of recycled columns in a row
@@ -124,6 +136,8 @@ struct SeqImpl : SeqBase {
     int64_t working_bytes() const override;
     void trim() override;
     krs_status recycle(int32_t* n_added) override;
+    krs_status recycle_plan() override;
+    krs_status recycle_apply(int32_t* n_added) override;
     krs_status basis(double* C, int64_t ld, int32_t cap, int32_t* n_c) override;
     void destroy() override;
 
@@ -159,6 +173,9 @@ bool finished_status(int device_status);
 
 // Recycle several sequences, their host work on parallel threads.
 krs_status recycle_all(krs_ctx* ctx, SeqBase* const* seqs, int count, int32_t* added);
+// The host step (recycle_plan) of several sequences on parallel threads;
+// st[i] receives each status.  Makes no device calls.
+void plan_all(SeqBase* const* seqs, int count, krs_status* st);
 
 // Solve the submitted systems of several sequences in fused launches.
 krs_status batch_solve(krs_ctx* ctx, SeqBase* const* seqs, int count, double* const* x, bool device_x,

@@ -6,12 +6,16 @@
 // the HBM budget for working sets allow), begins their solves and adds them
 // to the fused launches of their type, and completes the members that
 // finished (solution copied out, basis recycled, solve-time buffers
-// released).  A member's iterations are gated by its own device status, so
+// released).  The host part of a recycle (Ritz analysis and selection) runs
+// on a helper thread while the worker keeps launching the other members; its
+// device part is enqueued by the worker once the helper is done, and only
+// then is the request completed and its sequence free for its next request.  A member's iterations are gated by its own device status, so
 // joining or leaving the launches does not change its arithmetic: every
 // result equals the one of a solve alone.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -102,15 +106,53 @@ void krs_server::run() {
     };
     std::map<int, std::vector<Active>> members;  // by type key
     std::map<int, std::unique_ptr<krs::RunnerBase>> runners;
+    // finished members whose recycle is planned on a helper thread
+    struct Pending {
+        std::vector<Active> fin;
+        std::vector<krs_solve_info> infos;
+        std::vector<krs_status> sts;
+        std::vector<krs::SeqBase*> rec;
+        std::vector<size_t> rec_idx;
+        std::vector<krs_status> pst;
+        int batch = 0;
+        std::atomic<bool> planned{false};
+        std::thread th;
+    };
+    std::deque<std::unique_ptr<Pending>> pending;
     int64_t used = 0;
     int nact = 0;
     std::vector<int32_t> stat;
+    // apply the planned recycles (in order), release and complete; with
+    // `block`, wait for the oldest plan first
+    auto finish_pending = [&](bool block, krs_status fail) {
+        while (!pending.empty()) {
+            Pending& p = *pending.front();
+            if (!block && !p.planned.load()) break;
+            block = false;
+            p.th.join();
+            for (size_t j = 0; j < p.rec.size(); ++j) {
+                krs_status a = p.pst[j];
+                int32_t added = 0;
+                if (a == KRS_OK && fail == KRS_OK) a = p.rec[j]->recycle_apply(&added);
+                if (fail != KRS_OK) a = fail;
+                p.infos[p.rec_idx[j]].added = added;
+                if (a != KRS_OK && p.sts[p.rec_idx[j]] == KRS_OK) p.sts[p.rec_idx[j]] = a;
+            }
+            for (size_t i = 0; i < p.fin.size(); ++i) {
+                p.fin[i].req.impl->trim();
+                used -= p.fin[i].bytes;
+                post(p.fin[i].req, p.sts[i], p.infos[i], p.batch);
+            }
+            pending.pop_front();
+        }
+    };
     while (true) {
+        finish_pending(false, KRS_OK);
         // ---- admission
         std::vector<Request> admit;
         {
             std::unique_lock<std::mutex> lk(mu);
-            if (nact == 0 && queue.empty()) {
+            if (nact == 0 && queue.empty() && pending.empty()) {
                 if (stop) break;
                 cv_work.wait_for(lk, std::chrono::milliseconds(20));
                 continue;
@@ -165,7 +207,11 @@ void krs_server::run() {
             st = rp->set_members(m);
             if (st != KRS_OK) break;
         }
-        if (nact == 0 && st == KRS_OK) continue;
+        if (nact == 0 && st == KRS_OK) {
+            // nothing to iterate: the queued requests wait for recycles
+            finish_pending(true, KRS_OK);
+            continue;
+        }
         // ---- one block of iterations for every member, all types
         for (auto& kv : runners) {
             if (st != KRS_OK) break;
@@ -189,32 +235,30 @@ void krs_server::run() {
                 else keep.push_back(std::move(mem[i]));
             }
             const bool changed = !fin.empty();
-            // copy the solutions out, then recycle the finished members together
-            std::vector<krs_solve_info> infos(fin.size());
-            std::vector<krs_status> sts(fin.size());
-            std::vector<krs::SeqBase*> rec;
-            std::vector<size_t> rec_idx;
-            for (size_t i = 0; i < fin.size(); ++i) {
-                std::memset(&infos[i], 0, sizeof infos[i]);
-                sts[i] = fin[i].req.impl->end_solve(fin[i].req.x_out, false, &infos[i]);
-                if (sts[i] == KRS_OK || sts[i] == KRS_E_MAXIT) {
-                    rec.push_back(fin[i].req.impl);
-                    rec_idx.push_back(i);
+            if (changed) {
+                // copy the solutions out; plan the recycles on a helper thread
+                auto p = std::make_unique<Pending>();
+                p->batch = batch;
+                p->fin = std::move(fin);
+                const size_t nf = p->fin.size();
+                p->infos.resize(nf);
+                p->sts.resize(nf);
+                for (size_t i = 0; i < nf; ++i) {
+                    std::memset(&p->infos[i], 0, sizeof p->infos[i]);
+                    p->sts[i] = p->fin[i].req.impl->end_solve(p->fin[i].req.x_out, false, &p->infos[i]);
+                    if (p->sts[i] == KRS_OK || p->sts[i] == KRS_E_MAXIT) {
+                        p->rec.push_back(p->fin[i].req.impl);
+                        p->rec_idx.push_back(i);
+                    }
                 }
-            }
-            if (!rec.empty()) {
-                std::vector<int32_t> added(rec.size(), 0);
-                const krs_status rc = krs::recycle_all(ctx, rec.data(), (int)rec.size(), added.data());
-                for (size_t j = 0; j < rec.size(); ++j) {
-                    infos[rec_idx[j]].added = added[j];
-                    if (rc != KRS_OK && sts[rec_idx[j]] == KRS_OK) sts[rec_idx[j]] = rc;
-                }
-            }
-            for (size_t i = 0; i < fin.size(); ++i) {
-                fin[i].req.impl->trim();
-                used -= fin[i].bytes;
-                --nact;
-                post(fin[i].req, sts[i], infos[i], batch);
+                nact -= (int)nf;
+                p->pst.assign(p->rec.size(), KRS_OK);
+                Pending* pp = p.get();
+                pp->th = std::thread([pp] {
+                    krs::plan_all(pp->rec.data(), (int)pp->rec.size(), pp->pst.data());
+                    pp->planned.store(true);
+                });
+                pending.push_back(std::move(p));
             }
             if (changed) {
                 mem = std::move(keep);
@@ -226,6 +270,7 @@ void krs_server::run() {
         if (st != KRS_OK) {
             // device failure: fail every request in flight and stop serving
             std::string msg = krs_last_error() ? krs_last_error() : "";
+            while (!pending.empty()) finish_pending(true, st);
             for (auto& kv : members)
                 for (auto& a : kv.second) {
                     krs_solve_info none;
