@@ -222,6 +222,14 @@ krs_status krs_batch_solve_device(krs_ctx* ctx, krs_seq* const* seqs, int32_t co
  * Ritz analysis on parallel threads.  n_added[i] (may be NULL) receives
  * each count; returns the first non-OK status (every member is attempted). */
 krs_status krs_batch_recycle(krs_ctx* ctx, krs_seq* const* seqs, int32_t count, int32_t* n_added);
+/* krs_batch_solve_device followed by krs_batch_recycle, with the host-side
+ * Ritz analysis of a member (Section 4.1; selection of Section 3 or 4.4)
+ * started as soon as that member has finished, while the others still
+ * iterate.  d_x[i] (device, n_i doubles; NULL or a NULL entry: not copied),
+ * info[i] and n_added[i] (each may be NULL) receive the results; the same
+ * results as the two calls in sequence.  Returns as krs_batch_solve. */
+krs_status krs_batch_solve_recycle(krs_ctx* ctx, krs_seq* const* seqs, int32_t count, double* const* d_x,
+                                   krs_solve_info* info, int32_t* n_added);
 
 /* ------------------------------------------------------------- serving */
 /* A server owns a worker thread that serves systems of many sequences of

@@ -153,6 +153,7 @@ SIGNATURES = [
     ("krs_batch_solve", _S, [_P, _PP, ctypes.c_int32, ctypes.POINTER(_D), ctypes.POINTER(SolveInfo)]),
     ("krs_batch_solve_device", _S, [_P, _PP, ctypes.c_int32, _PP, ctypes.POINTER(SolveInfo)]),
     ("krs_batch_recycle", _S, [_P, _PP, ctypes.c_int32, _I32]),
+    ("krs_batch_solve_recycle", _S, [_P, _PP, ctypes.c_int32, _PP, ctypes.POINTER(SolveInfo), _I32]),
     ("krs_server_create", _S, [_P, ctypes.c_size_t, ctypes.c_int32, _PP]),
     ("krs_server_enqueue", _S, [_P, _P, _D, _D, _D, ctypes.c_uint64]),
     ("krs_server_poll", _S, [_P, ctypes.POINTER(Completion), ctypes.c_int32, _I32, ctypes.c_int32]),
@@ -296,6 +297,19 @@ class Context:
             _check(st, "krs_batch_solve_device", allow=(KRS_E_MAXIT,))
         return xs, [infos[i].as_dict() for i in range(cnt)]
 
+    def batch_solve_recycle(self, seqs, xs):
+        """batch_solve into the device tensors ``xs`` followed by
+        batch_recycle, each member's recycle planned as soon as it finishes.
+        Returns ([info dict per sequence], [columns appended per sequence])."""
+        cnt = len(seqs)
+        arr_h = (ctypes.c_void_p * cnt)(*[s.handle.value for s in seqs])
+        infos = (SolveInfo * cnt)()
+        added = (ctypes.c_int32 * max(cnt, 1))()
+        arr_x = (ctypes.c_void_p * cnt)(*[x.data_ptr() for x in xs])
+        st = _lib.krs_batch_solve_recycle(self.handle, ctypes.cast(arr_h, _PP), cnt, ctypes.cast(arr_x, _PP), infos,
+                                          ctypes.cast(added, _I32))
+        _check(st, "krs_batch_solve_recycle", allow=(KRS_E_MAXIT,))
+        return [infos[i].as_dict() for i in range(cnt)], [int(added[i]) for i in range(cnt)]
 
     def batch_recycle(self, seqs):
         """krs_seq_recycle for several sequences (host work in parallel);

@@ -354,7 +354,7 @@ krs_status krs_coarse_factor(int32_t nc, const double* G, double rank_tol, doubl
 }
 
 static krs_status batch_common(krs_ctx* ctx, krs_seq* const* seqs, int32_t count, double* const* x, bool device_x,
-                               krs_solve_info* info) {
+                               krs_solve_info* info, int32_t* n_added = nullptr, bool recycle = false) {
     if (!ctx || count < 0 || (count > 0 && !seqs)) {
         set_error("ctx and seqs are required");
         return KRS_E_INVALID;
@@ -372,7 +372,12 @@ static krs_status batch_common(krs_ctx* ctx, krs_seq* const* seqs, int32_t count
             }
         v[i] = seqs[i]->impl.get();
     }
-    return krs::batch_solve(ctx, v.data(), count, x, device_x, info);
+    if (!recycle) return krs::batch_solve(ctx, v.data(), count, x, device_x, info);
+    std::vector<int32_t> added(count, 0);
+    const krs_status st = krs::batch_solve(ctx, v.data(), count, x, device_x, info, added.data());
+    if (n_added)
+        for (int i = 0; i < count; ++i) n_added[i] = added[i];
+    return st;
 }
 
 krs_status krs_batch_recycle(krs_ctx* ctx, krs_seq* const* seqs, int32_t count, int32_t* n_added) {
@@ -408,6 +413,13 @@ krs_status krs_batch_solve_device(krs_ctx* ctx, krs_seq* const* seqs, int32_t co
                                   krs_solve_info* info) {
     KRS_GUARD_BEGIN
     return batch_common(ctx, seqs, count, d_x, true, info);
+    KRS_GUARD_END
+}
+
+krs_status krs_batch_solve_recycle(krs_ctx* ctx, krs_seq* const* seqs, int32_t count, double* const* d_x,
+                                   krs_solve_info* info, int32_t* n_added) {
+    KRS_GUARD_BEGIN
+    return batch_common(ctx, seqs, count, d_x, true, info, n_added, true);
     KRS_GUARD_END
 }
 

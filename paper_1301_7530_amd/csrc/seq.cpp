@@ -1256,14 +1256,41 @@ std::unique_ptr<RunnerBase> make_runner(krs_ctx* ctx, int key) {
 bool finished_status(int s) { return s == ST_DONE || s == ST_BREAKDOWN || s == ST_MAXIT; }
 
 krs_status batch_solve(krs_ctx* ctx, SeqBase* const* seqs, int count, double* const* x, bool device_x,
-                       krs_solve_info* info) {
+                       krs_solve_info* info, int32_t* added) {
     std::vector<krs_status> out(count, KRS_OK);
+    // with `added`: every member is recycled too; a member that has finished
+    // is completed (solution out) at once and its recycle planned on a helper
+    // thread while the others iterate; the device steps follow in order
+    const bool rec = added != nullptr;
+    std::vector<char> ended(count, 0);
+    std::vector<krs_status> pst(count, KRS_OK);
+    std::vector<std::thread> helpers;
+    auto end_member = [&](int i) {
+        if (ended[i]) return;
+        ended[i] = 1;
+        out[i] = seqs[i]->end_solve(x ? x[i] : nullptr, device_x, info ? &info[i] : nullptr);
+    };
+    auto plan_members = [&](std::vector<int> idx) {
+        std::vector<int> ok;
+        for (int i : idx)
+            if (out[i] == KRS_OK || out[i] == KRS_E_MAXIT) ok.push_back(i);
+        if (ok.empty()) return;
+        helpers.emplace_back([&, ok] {
+            std::vector<SeqBase*> m;
+            for (int i : ok) m.push_back(seqs[i]);
+            std::vector<krs_status> st(ok.size(), KRS_OK);
+            plan_all(m.data(), (int)m.size(), st.data());
+            for (size_t j = 0; j < ok.size(); ++j) pst[ok[j]] = st[j];
+        });
+    };
     // begin every member; group the begun ones by type
     std::map<int, std::vector<int>> groups;
     for (int i = 0; i < count; ++i) {
         out[i] = seqs[i]->begin_solve();
         if (out[i] == KRS_OK) groups[seqs[i]->type_key()].push_back(i);
+        else ended[i] = 1;
     }
+    krs_status fatal = KRS_OK;
     for (auto& kv : groups) {
         std::unique_ptr<RunnerBase> r = make_runner(ctx, kv.first);
         std::vector<int> act = kv.second;
@@ -1284,12 +1311,15 @@ krs_status batch_solve(krs_ctx* ctx, SeqBase* const* seqs, int count, double* co
             if (st != KRS_OK) break;
             st = r->read_status(stat);
             if (st != KRS_OK) break;
-            std::vector<int> keep;
+            std::vector<int> keep, done_now;
             std::vector<int32_t> keep_last;
             bool progress = false;
             for (size_t i = 0; i < act.size(); ++i) {
                 if (stat[2 * i + 1] != last[i]) progress = true;
-                if (finished_status(stat[2 * i])) continue;
+                if (finished_status(stat[2 * i])) {
+                    if (rec && !ended[act[i]]) done_now.push_back(act[i]);
+                    continue;
+                }
                 keep.push_back(act[i]);
                 keep_last.push_back(stat[2 * i + 1]);
             }
@@ -1299,6 +1329,12 @@ krs_status batch_solve(krs_ctx* ctx, SeqBase* const* seqs, int count, double* co
                 break;
             }
             if (progress) stuck = 0;
+            if (!keep.empty() && !done_now.empty()) {
+                // finished while others still iterate: complete and plan now
+                // (its launches are gated from here on)
+                for (int i : done_now) end_member(i);
+                plan_members(done_now);
+            }
             if (keep.empty()) break;
             if (4 * keep.size() <= 3 * act.size()) {
                 // finished members leave the launches once a quarter is done
@@ -1311,11 +1347,37 @@ krs_status batch_solve(krs_ctx* ctx, SeqBase* const* seqs, int count, double* co
             block = graphs ? 64 : std::min(block * 2, 64);
         }
         if (st != KRS_OK) {
-            for (int i : kv.second) out[i] = st;
-            if (st == KRS_E_DEVICE) return st;
+            for (int i : kv.second) {
+                out[i] = st;
+                ended[i] = 1;
+            }
+            if (st == KRS_E_DEVICE) {
+                fatal = st;
+                break;
+            }
             continue;
         }
-        for (int i : kv.second) out[i] = seqs[i]->end_solve(x ? x[i] : nullptr, device_x, info ? &info[i] : nullptr);
+        std::vector<int> rest;
+        for (int i : kv.second)
+            if (!ended[i]) {
+                end_member(i);
+                rest.push_back(i);
+            }
+        if (rec) plan_members(rest);
+    }
+    for (auto& th : helpers) th.join();
+    if (fatal != KRS_OK) return fatal;
+    if (rec) {
+        for (int i = 0; i < count; ++i) {
+            int32_t a = 0;
+            if ((out[i] == KRS_OK || out[i] == KRS_E_MAXIT) && ended[i]) {
+                krs_status r2 = pst[i];
+                if (r2 == KRS_OK) r2 = seqs[i]->recycle_apply(&a);
+                if (r2 != KRS_OK) out[i] = r2;
+                else if (info) info[i].added = a;
+            }
+            added[i] = a;
+        }
     }
     krs_status worst = KRS_OK;
     for (krs_status st : out)

@@ -178,8 +178,10 @@ krs_status recycle_all(krs_ctx* ctx, SeqBase* const* seqs, int count, int32_t* a
 void plan_all(SeqBase* const* seqs, int count, krs_status* st);
 
 // Solve the submitted systems of several sequences in fused launches.
+// With `added` (count entries) every member is also recycled (as by
+// recycle_all), the host step of a member planned as soon as it finishes.
 krs_status batch_solve(krs_ctx* ctx, SeqBase* const* seqs, int count, double* const* x, bool device_x,
-                       krs_solve_info* info);
+                       krs_solve_info* info, int32_t* added = nullptr);
 
 }  // namespace krs
 

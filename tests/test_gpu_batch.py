@@ -101,6 +101,55 @@ def test_batch_equals_alone_bitwise(gpu, precision, reuse):
             assert _relres(seqs[i].csr(k), rb["x"]) <= 1e-8
 
 
+def _batched_solve_recycle(ctx, seqs, n_systems, **kw):
+    import torch
+
+    K = _K()
+    hs = [K.sequence_for(ctx, sq, **kw) for sq in seqs]
+    out = [[] for _ in seqs]
+    try:
+        for k in range(n_systems):
+            for h, sq in zip(hs, seqs):
+                h.submit(*sq.system(k))
+            xs = [torch.zeros(sq.n, dtype=torch.float64, device="cuda") for sq in seqs]
+            # recycles planned as members finish, applied after the last one
+            infos, added = ctx.batch_solve_recycle(hs, xs)
+            for i, h in enumerate(hs):
+                infos[i]["x"] = xs[i].cpu().numpy()
+                infos[i]["coef"] = h.coeffs()
+                infos[i]["C"] = h.basis()
+                infos[i]["n_added"] = added[i]
+                out[i].append(infos[i])
+    finally:
+        for h in hs:
+            h.close()
+    return out
+
+
+@pytest.mark.parametrize("precision,reuse", [("mixed", "selective"), ("fp64", "total")])
+def test_batch_solve_recycle_equals_alone_bitwise(gpu, precision, reuse):
+    """krs_batch_solve_recycle: members finishing early are completed and
+    their recycle planned while the others iterate; solutions, coefficients
+    and bases still equal those of each sequence alone, bit for bit."""
+    n_sys = 3
+    seqs = _sequences(n_sys)
+    kw = dict(precision=precision, reuse=reuse, tol=1e-8, max_iter=3000, max_basis=40, ritz_eps=1e-8,
+              history_cap=400)
+    a = _alone(gpu, seqs, n_sys, **kw)
+    b = _batched_solve_recycle(gpu, seqs, n_sys, **kw)
+    for i in range(len(seqs)):
+        for k in range(n_sys):
+            ra, rb = a[i][k], b[i][k]
+            assert ra["status"] == rb["status"] == 0, (i, k)
+            assert ra["iters"] == rb["iters"] and ra["n_c"] == rb["n_c"], (i, k)
+            assert np.array_equal(ra["x"], rb["x"]), (i, k)
+            for ca, cb in zip(ra["coef"], rb["coef"]):
+                assert np.array_equal(ca, cb)
+            assert np.array_equal(ra["C"], rb["C"]), (i, k)
+            assert 0 <= rb["n_added"] <= rb["C"].shape[1]
+            assert _relres(seqs[i].csr(k), rb["x"]) <= 1e-8
+
+
 def test_batch_matches_oracle_fp64(gpu):
     n_sys = 3
     seqs = _sequences(n_sys)
