@@ -325,7 +325,7 @@ def run_batched(args, K, torch, data):
     def phase(reuse, fused):
         hs = [K.sequence_for(ctx, sq, reuse=reuse, update_rows=fused_rows if fused else 0, **kw) for sq in seqs]
         xs = [torch.empty(sq.n, dtype=torch.float64, device="cuda") for sq in seqs]
-        iters, t_steps, t_rec = [], [], []
+        iters, t_steps, t_rec, ncs = [], [], [], []
         try:
             for step, k in enumerate(ks):
                 torch.cuda.synchronize()
@@ -348,6 +348,7 @@ def run_batched(args, K, torch, data):
                     t_steps.append(time.perf_counter() - t0)
                     t_rec.append(time.perf_counter() - t1)
                     iters.append([inf["iters"] for inf in infos])
+                    ncs.append(float(np.mean([inf["n_c"] for inf in infos])))
                     bad = [inf for inf in infos if inf["rel_res_true"] > 1e-8 or inf["status"] != 0]
                     if bad:
                         raise RuntimeError(f"{len(bad)} systems missed the tolerance: {bad[0]}")
@@ -356,7 +357,8 @@ def run_batched(args, K, torch, data):
                 h.close()
         t = sum(t_steps)
         return dict(value=len(hs) * len(t_steps) / t, time=t, iters_mean=float(np.mean(iters)),
-                    step_ms=[round(1e3 * x, 2) for x in t_steps], recycle_ms=[round(1e3 * x, 2) for x in t_rec])
+                    step_ms=[round(1e3 * x, 2) for x in t_steps], recycle_ms=[round(1e3 * x, 2) for x in t_rec],
+                    n_c_mean=[round(x, 2) for x in ncs])
 
     _log("fused SRKS")
     fused = phase("selective", True)
@@ -386,6 +388,7 @@ def run_batched(args, K, torch, data):
         "iters_mean": fused["iters_mean"],
         "step_ms": fused["step_ms"],
         "recycle_ms": fused["recycle_ms"],
+        "n_c_mean_per_step": fused["n_c_mean"],
         "recycle_mode": "host Ritz work of each member started when it finishes, during the fused launches "
                         "(krs_batch_solve_recycle); recycle_ms is the part left after that call returns",
     }
