@@ -1265,6 +1265,13 @@ krs_status batch_solve(krs_ctx* ctx, SeqBase* const* seqs, int count, double* co
     std::vector<char> ended(count, 0);
     std::vector<krs_status> pst(count, KRS_OK);
     std::vector<std::thread> helpers;
+    struct Joiner {  // helpers are joined on every way out
+        std::vector<std::thread>& t;
+        ~Joiner() {
+            for (auto& th : t)
+                if (th.joinable()) th.join();
+        }
+    } joiner{helpers};
     auto end_member = [&](int i) {
         if (ended[i]) return;
         ended[i] = 1;
@@ -1366,6 +1373,7 @@ krs_status batch_solve(krs_ctx* ctx, SeqBase* const* seqs, int count, double* co
         if (rec) plan_members(rest);
     }
     for (auto& th : helpers) th.join();
+    helpers.clear();
     if (fatal != KRS_OK) return fatal;
     if (rec) {
         for (int i = 0; i < count; ++i) {
