@@ -424,7 +424,7 @@ def main():
     ap.add_argument("--eager", action="store_true", help="launch kernels one by one instead of graph replay")
     ap.add_argument("--separate-finalize", action="store_true",
                     help="run the end-of-step reduction as its own kernel")
-    ap.add_argument("--clients", type=int, default=16, help="serving workload: clients (sequences)")
+    ap.add_argument("--clients", type=int, default=64, help="serving workload: clients (sequences)")
     ap.add_argument("--systems", type=int, default=3, help="serving workload: systems per client")
     ap.add_argument("--rate", type=float, default=1.0, help="serving workload: arrivals per second per client")
     ap.add_argument("--hbm-budget", type=float, default=64.0, help="serving workload: working-set budget (GiB)")
