@@ -734,7 +734,39 @@ __device__ __forceinline__ void finalize_update_body(const SysView<V, W>& v, int
     const double g = need_g ? sum_all_reg(p1, red) : (mode == 0 ? g_in : 0.0);
     const double a = (mode == 0) ? S.rho / g : 0.0;
     double du = 0.0;
-    if (nc > 0) {
+    if (nc > 0 && gsmall) {
+        // G^-1 t, G^-1 (AC)^T w and the u recurrence with one barrier: row r
+        // of G^-1 is taken by the 8 lanes 8 r .. 8 r + 7 of one wave (part p
+        // sums the columns p, p + 8, ...; the parts are added by shuffles);
+        // u^T mu is summed in row order by thread 0.
+        static_assert(T == 512, "eight lanes per row of an up to 64-column G^-1");
+        const int r = tid >> 3, p = tid & 7;
+        double m = 0.0, mv = 0.0;
+        if (r < nc) {
+            for (int c = p; c < nc; c += 8) {
+                const double g = Gl[c * nc + r];
+                m += g * fin[2 + c];
+                mv += g * fin[2 + nc + c];
+            }
+        }
+#pragma unroll
+        for (int off = 1; off < 8; off <<= 1) {
+            m += __shfl_xor(m, off, 64);
+            mv += __shfl_xor(mv, off, 64);
+        }
+        if (r < nc && p == 0) {
+            muL[r] = m;
+            gvL[r] = mv;
+            // u = C^T r: recurrence u -= alpha (AC)^T w; zero after (re)projection
+            const double uc = (mode == 0) ? uL[r] - a * fin[2 + nc + r] : 0.0;
+            v.u[r] = uc;
+            v.mu[r] = m;
+            red[r] = uc * m;
+        }
+        __syncthreads();
+        if (tid == 0)
+            for (int i = 0; i < nc; ++i) du += red[i];
+    } else if (nc > 0) {
         const double* Gi = gsmall ? Gl : v.Ginv;
         ginv_matvec2(Gi, nc, fin + 2, fin + 2 + nc, muL, gvL, red);
         // u = C^T r: recurrence u -= alpha (AC)^T w; zero after (re)projection
