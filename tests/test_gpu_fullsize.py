@@ -3,6 +3,8 @@
 * Diffusion 20^3 (n = 8,000), 8 systems, total reuse, FP64: every system
   against the oracle run on the whole sequence (iterations +-2, same basis
   width, true residual).
+* Elasticity 100^3 (n = 3,060,300): the same kind of sampled checks for the
+  FP32-basis setup of the benchmark's large configuration.
 * Elasticity 40^3 (n = 201,720, 15,548,742 nonzeros): the oracle cannot run
   thousands of iterations here in a test, so it checks what it can compute
   one by one or what holds at any size: the first CG coefficients of a solve
@@ -124,3 +126,38 @@ def test_elasticity40_bench_setup(gpu, elasticity40):
             assert s.n_c <= 60
     finally:
         s.close()
+
+
+@pytest.mark.skipif(bool(__import__("os").environ.get("KRS_SKIP_100")),
+                    reason="elasticity 100^3 (3.06 M unknowns, about 40 s) skipped by KRS_SKIP_100")
+def test_elasticity100_sampled(gpu):
+    """Elasticity 100^3 in the benchmark's FP32-basis setup, checked on what
+    the oracle computes one by one or what holds at any size: the first CG
+    coefficients of the solve from an empty basis against the FP64 oracle,
+    the true residual of both solutions with the oracle's SpMV, and fewer
+    iterations for the second system with the recycled basis."""
+    K = _K()
+    seq = gen.config_elasticity(100, 2, config_id=3)
+    print("elasticity 100^3: n", seq.n, flush=True)
+    s = K.sequence_for(gpu, seq, precision="fp32basis", reuse="selective", ritz_eps=1e-8, max_basis=200,
+                       cap_policy="freeze", tol=1e-8, max_iter=30000, history_cap=16000)
+    its = []
+    try:
+        for k in range(2):
+            vals, b = seq.system(k)
+            s.submit(vals, b)
+            x, info = s.solve()
+            print("system", k, info["iters"], info["n_c"], info["rel_res_true"], flush=True)
+            assert info["status"] == 0 and info["rel_res_true"] <= 1e-8
+            assert _relres(seq.csr(k), x) <= 1e-8
+            its.append(info["iters"])
+            if k == 0:
+                alpha, rho, _ = s.coeffs()
+                rp, ci, v, _ = seq.csr(0)
+                ref = O.apcg(rp, ci, v, b, "block3", tol=1e-8, max_iter=25)
+                assert np.allclose(alpha[:25], ref["alpha"][:25], rtol=1e-5, atol=0)
+                assert np.allclose(rho[:25], ref["rho"][:25], rtol=1e-5, atol=0)
+            s.recycle()
+    finally:
+        s.close()
+    assert its[1] < its[0]
