@@ -226,3 +226,49 @@ def test_update_tile_choices_agree(gpu):
             s.close()
     for x in sols[1:]:
         assert np.linalg.norm(x - sols[0]) / np.linalg.norm(sols[0]) <= 1e-5
+
+
+def test_batched_full_size_sampled(gpu):
+    """The batched workload at its full size (256 diffusion sequences,
+    n ~ U[5e3, 2e5], sum n = 26.5 M) in the benchmark's setup, two systems:
+    every member meets 1e-8 (true residual), a sample of members is checked
+    with the oracle's SpMV and against the same sequence solved alone (bit
+    for bit)."""
+    import torch
+
+    K = _K()
+    shapes = gen.batched_diffusion_sizes(256)
+    seqs = [gen.make_sequence("diffusion", sh, 10, 4, i) for i, sh in enumerate(shapes)]
+    kw = dict(precision="mixed", reuse="selective", tol=1e-8, max_iter=30000, ritz_eps=1e-8, max_basis=60,
+              cap_policy="cost", history_cap=256, update_rows=4096)
+    sample = [0, 37, 128, 255]
+    systems = {(i, k): seqs[i].system(k) for i in range(len(seqs)) for k in range(2)}
+    print("batched full size: sum n", sum(s.n for s in seqs), flush=True)
+    hs = [K.sequence_for(gpu, sq, **kw) for sq in seqs]
+    got = {}
+    try:
+        for k in range(2):
+            for i, h in enumerate(hs):
+                h.submit(*systems[(i, k)])
+            xs = [torch.zeros(sq.n, dtype=torch.float64, device="cuda") for sq in seqs]
+            infos, _ = gpu.batch_solve_recycle(hs, xs)
+            assert all(inf["status"] == 0 and inf["rel_res_true"] <= 1e-8 for inf in infos)
+            for i in sample:
+                got[(i, k)] = (xs[i].cpu().numpy(), infos[i]["iters"])
+    finally:
+        for h in hs:
+            h.close()
+    for i in sample:
+        s = K.sequence_for(gpu, seqs[i], **kw)
+        try:
+            for k in range(2):
+                s.submit(*systems[(i, k)])
+                x, info = s.solve()
+                s.recycle()
+                xb, itb = got[(i, k)]
+                assert info["iters"] == itb, (i, k)
+                assert np.array_equal(x, xb), (i, k)
+                rp, ci, v, b = seqs[i].csr(k)
+                assert np.linalg.norm(b - O.spmv(rp, ci, v, xb)) / np.linalg.norm(b) <= 1e-8
+        finally:
+            s.close()
