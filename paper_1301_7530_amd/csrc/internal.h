@@ -32,6 +32,16 @@ constexpr int64_t kMaxTimedGrid = 8192;
 // Launch geometry of one system, fixed for a solve: the single-system and
 // the fused batch launches use the same per-system workgroup counts, so a
 // system's reductions (and results) are the same in both.
+// Row length of the row-major A C: the next power of two of at least 4
+// elements up to 32 columns (16-byte segments, whole rows per 128-byte
+// chunk), else a multiple of 32 (128-byte chunks of FP32 values).
+inline int64_t ac_leading_dim(int64_t nc) {
+    if (nc > 32) return (nc + 31) & ~(int64_t)31;
+    int64_t l = 4;
+    while (l < nc) l *= 2;
+    return l;
+}
+
 struct Geometry {
     int64_t cb3;  // block rows per update workgroup
     int32_t g1;   // SpMV / true-residual workgroups
@@ -114,7 +124,7 @@ struct SysView {
     int32_t nc;      // columns of C in this solve
     int32_t pad0;
     const V* C;      // n x nc column-major, leading dim ldc (a multiple of 256 >= n)
-    const V* AC;     // n x nc row-major, leading dim ldac (a multiple of 32 >= nc)
+    const V* AC;     // n x nc row-major, leading dim ldac = ac_leading_dim(nc)
     int64_t ldc;
     int64_t ldac;
     const double* Ginv;  // nc x nc column-major

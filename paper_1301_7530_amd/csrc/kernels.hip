@@ -471,9 +471,11 @@ __device__ __forceinline__ void spmv_dot_body(const SysView<V, W>& v, int64_t bi
 // ------------------------------------------------------------------ K3
 // Projector sums of one step: tacc[c] += sum_i AC[i, c] ss[i] and
 // vacc[c] += sum_i AC[i, c] ws[i] over `rows` rows of a row-major AC tile
-// (leading dimension ld, a multiple of 32 elements).  Columns are taken in
-// chunks of 128 bytes; a lane reads 16 bytes (QW columns) of one row, so
-// LPR = 8 lanes cover a chunk of a row and a wave reads 8 rows per load.
+// (leading dimension ld: 4, 8, 16 or a multiple of 32 elements, so that a
+// basis of a few columns costs few bytes).  Columns are taken in chunks of
+// 128 bytes (or the whole row when it is shorter); a lane reads 16 bytes (QW
+// columns) of one row, so LPR lanes cover a chunk of a row and a wave reads
+// 64 / LPR rows per load.
 // Each wave works on one (chunk, row phase) item: with fewer chunks than
 // waves a chunk gets P waves that interleave its rows, so every chunk of the
 // tile streams at once and each lane keeps UR loads in flight (the rows of a
@@ -492,32 +494,39 @@ constexpr int kUrOne = 12;
 constexpr int kUrBatch = 4;
 
 // Work split of the projection: wave `wave` takes item wave + k NW of the
-// items (chunk it % nch, row phase it / nch), P waves per chunk.
+// items (chunk it % nch, row phase it / nch), P waves per chunk.  A chunk
+// is 128 bytes of a row, or the whole row when the leading dimension is
+// shorter (a power of two from 16 bytes): LPR lanes read 16 bytes each of
+// one row, a wave RPW rows per load.
 template <typename V>
 struct ProjSplit {
     static constexpr int QW = 16 / sizeof(V);
     static constexpr int CW = 128 / sizeof(V);
-    static constexpr int LPR = CW / QW;  // 8
-    static constexpr int RPW = 64 / LPR;  // 8
     static constexpr int NW = kT3 / 64;
-    int nch, P, items, step, q, rsub;
-    __device__ explicit ProjSplit(int nc) {
+    int cw, lpr, rpw, nch, P, items, step, q, rsub;
+    __device__ ProjSplit(int nc, int64_t ld) {
         const int lane = threadIdx.x & 63;
-        q = lane % LPR;
-        rsub = lane / LPR;
-        nch = (nc + CW - 1) / CW;
+        cw = ld < CW ? (int)ld : CW;
+        lpr = cw / QW;
+        rpw = 64 / lpr;
+        q = lane % lpr;
+        rsub = lane / lpr;
+        nch = (nc + cw - 1) / cw;
         P = nch < NW ? NW / nch : 1;
         items = P * nch;
-        step = RPW * P;
+        step = rpw * P;
     }
 };
 
-template <typename V, int UR>
+// FULL: rows of at least one 128-byte chunk (the chunk geometry is then
+// known at compile time).
+template <typename V, int UR, bool FULL>
 __device__ __forceinline__ void project_rows(const V* __restrict__ ACt, int64_t ld, int rows, int nc,
                                              const double* ss, const double* ws, double* tacc, double* vacc,
                                              double (*cred)[64], const ProjSplit<V>& g) {
     using G = ProjSplit<V>;
-    constexpr int QW = G::QW, CW = G::CW, LPR = G::LPR, RPW = G::RPW, NW = G::NW;
+    constexpr int QW = G::QW, NW = G::NW;
+    const int CW = FULL ? G::CW : g.cw, LPR = FULL ? G::CW / QW : g.lpr, RPW = FULL ? 64 / (G::CW / QW) : g.rpw;
     const int wave = threadIdx.x >> 6;
     const int q = g.q, rsub = g.rsub, nch = g.nch, P = g.P, items = g.items, step = g.step;
     for (int k0 = 0; k0 < items; k0 += NW) {
@@ -557,9 +566,11 @@ __device__ __forceinline__ void project_rows(const V* __restrict__ ACt, int64_t 
 #pragma unroll
         for (int e = 0; e < QW; ++e) {
 #pragma unroll
-            for (int off = LPR; off < 64; off <<= 1) {
-                at[e] += __shfl_xor(at[e], off, 64);
-                av[e] += __shfl_xor(av[e], off, 64);
+            for (int off = 1; off < 64; off <<= 1) {
+                if (off >= LPR) {
+                    at[e] += __shfl_xor(at[e], off, 64);
+                    av[e] += __shfl_xor(av[e], off, 64);
+                }
             }
         }
         if (rsub == 0 && act) {
@@ -863,7 +874,9 @@ constexpr int upd_pool() {
     return 2 * kT3 * B + kT3 + 2048 + kT3;
 }
 
-template <typename V, typename W, int B, bool FUSE, int UR>
+// SINGLE: the single-system kernel, which also instantiates the projection
+// with compile-time chunk geometry (same lanes and order as the general one).
+template <typename V, typename W, int B, bool FUSE, int UR, bool SINGLE = false>
 __device__ __forceinline__ void update_reduce_body(const SysView<V, W>& v, int64_t bid, int mode, double* pool) {
     DevState* st = v.st;
     const uint32_t mask = (mode == 2) ? M_REFINE : M_RUN;
@@ -886,7 +899,7 @@ __device__ __forceinline__ void update_reduce_body(const SysView<V, W>& v, int64
     }
     const int64_t pb = bid * v.geo.cb3;
     const int64_t pe = (pb + v.geo.cb3) < v.nb ? (pb + v.geo.cb3) : v.nb;
-    const ProjSplit<V> pg(nc);
+    const ProjSplit<V> pg(nc, v.ldac);
     bool tm = false;
     double rr = 0.0, rs = 0.0;
     double a = 0.0, gam = -1.0;
@@ -984,8 +997,12 @@ __device__ __forceinline__ void update_reduce_body(const SysView<V, W>& v, int64
         }
         if (nc > 0) {
             const int64_t pn = (ps + T) < pe ? (ps + T) : pe;
-            project_rows<V, UR>(v.AC + ps * B * v.ldac, v.ldac, (int)((pn - ps) * B), nc, ss, ws, tacc, vacc, cred,
-                                pg);
+            if (SINGLE && v.ldac >= ProjSplit<V>::CW)
+                project_rows<V, UR, true>(v.AC + ps * B * v.ldac, v.ldac, (int)((pn - ps) * B), nc, ss, ws, tacc,
+                                          vacc, cred, pg);
+            else
+                project_rows<V, UR, false>(v.AC + ps * B * v.ldac, v.ldac, (int)((pn - ps) * B), nc, ss, ws, tacc,
+                                           vacc, cred, pg);
         }
     }
     const int stride = 2 * nc + 2;
@@ -1320,12 +1337,12 @@ __global__ __launch_bounds__(256) void k_spmv_dot(SysView<V, W> v) {
 template <typename V, typename W, int B>
 __global__ __launch_bounds__(kT3, 2) void k_update_reduce(SysView<V, W> v, int mode) {
     __shared__ double pool[upd_pool<B>()];
-    update_reduce_body<V, W, B, false, kUrOne>(v, blockIdx.x, mode, pool);
+    update_reduce_body<V, W, B, false, kUrOne, true>(v, blockIdx.x, mode, pool);
 }
 template <typename V, typename W, int B>
 __global__ __launch_bounds__(kT3, 2) void k_update_fused(SysView<V, W> v, int mode) {
     __shared__ double pool[upd_pool<B>() > fin_pool() ? upd_pool<B>() : fin_pool()];
-    update_reduce_body<V, W, B, true, kUrOne>(v, blockIdx.x, mode, pool);
+    update_reduce_body<V, W, B, true, kUrOne, true>(v, blockIdx.x, mode, pool);
 }
 template <typename V, typename W>
 __global__ __launch_bounds__(kTF3) void k_finalize_update(SysView<V, W> v, int mode) {

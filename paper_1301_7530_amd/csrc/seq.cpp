@@ -439,7 +439,7 @@ template <typename V, typename W>
 krs_status SeqImpl<V, W>::coarse_pass(std::vector<double>& G) {
     const size_t nn = (size_t)nc * nc;
     const bool need_v = !std::is_same<V, double>::value;
-    ldac = std::max<int64_t>(32, ((int64_t)nc + 31) & ~(int64_t)31);
+    ldac = ac_leading_dim(nc);
     if (!d_AC64.reserve(ctx, (size_t)n * ldac * sizeof(double)) ||
         (need_v && !d_ACv.reserve(ctx, (size_t)n * ldac * sizeof(V))) || !d_G.reserve(ctx, nn * sizeof(double)) ||
         !d_Ginv.reserve(ctx, nn * sizeof(double)) || !d_mu.reserve(ctx, 3072 * sizeof(double))) {
@@ -554,7 +554,7 @@ int64_t SeqImpl<V, W>::working_bytes() const {
     if (desc.reuse == KRS_REUSE_SELECTIVE && history_needed())
         hist = desc.history_cap > 0 ? std::min(desc.history_cap, max_iter + 1) : max_iter + 1;
     const int ncmax = std::max(nc, desc.max_basis > 0 ? desc.max_basis : nc);
-    const int64_t ldm = std::max<int64_t>(32, ((int64_t)ncmax + 31) & ~(int64_t)31);
+    const int64_t ldm = ac_leading_dim(ncmax);
     const int64_t vsz = std::is_same<V, double>::value ? 0 : (int64_t)sizeof(V);
     int64_t b = ldc * hist * (int64_t)sizeof(V);                       // Z history
     b += n * ldm * (8 + vsz);                                          // A C (double and V)
@@ -827,7 +827,7 @@ krs_status SeqImpl<V, W>::end_solve(double* x, bool device_x, krs_solve_info* in
 
 template <typename V, typename W>
 int64_t SeqImpl<V, W>::model_bytes_per_iter() const {
-    // B_A + B_M + 11 n p_w + 2 n p_x + 2 n nc p (see the design notes);
+    // B_A + B_M + 11 n p_w + 2 n p_x + n (ldac + nc) p;
     // p: matrix / basis storage, p_w: Krylov vectors, p_x = 8
     const int64_t p = sizeof(V), pw = sizeof(W);
     const int64_t pa = op64() ? 8 : p;  // matrix value bytes
@@ -835,7 +835,9 @@ int64_t SeqImpl<V, W>::model_bytes_per_iter() const {
     const int64_t BA = (B == 1) ? nnz * (pa + 4) : nnz * pa + 4 * nnzb;
     const int64_t BM = (B == 1) ? n * p : 3 * n * p;
     const int64_t vec = 11 * n * pw + 2 * n * 8 - (desc.reuse == KRS_REUSE_SELECTIVE ? 0 : n * pw);
-    return BA + BM + vec + 2 * n * (int64_t)nc * p;
+    // the projector streams the padded rows of A C, the correction C
+    const int64_t basis = nc > 0 ? n * (ac_leading_dim(nc) + nc) * p : 0;
+    return BA + BM + vec + basis;
 }
 
 // ------------------------------------------------------------- recycle
