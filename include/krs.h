@@ -245,8 +245,9 @@ krs_status krs_batch_solve_recycle(krs_ctx* ctx, krs_seq* const* seqs, int32_t c
  * sequences overlap on the device.  Each result equals the one of
  * krs_seq_submit + krs_seq_solve + krs_seq_recycle on the same sequence.
  * While a server exists its worker owns the context's stream: the caller
- * must not use that context's sequences directly, and a sequence with
- * requests in flight cannot be destroyed (KRS_E_STATE). */
+ * must not use that context's sequences directly.  A sequence with requests
+ * in flight cannot be destroyed (KRS_E_STATE), and submit, solve, recycle,
+ * basis export and the batch calls refuse it (KRS_E_BUSY). */
 typedef struct krs_server krs_server;
 
 typedef struct {

@@ -3,6 +3,7 @@
 // this boundary.
 #include <cstring>
 #include <exception>
+#include <memory>
 #include <new>
 #include <string>
 #include <vector>
@@ -164,20 +165,25 @@ krs_status krs_seq_create(krs_ctx* ctx, const krs_seq_desc* d, const double* C0,
         set_error("hipSetDevice failed");
         return KRS_E_DEVICE;
     }
-    krs_seq* s = new krs_seq();
+    std::unique_ptr<krs_seq> s(new krs_seq());
     if (d->precision == KRS_MIXED || d->precision == KRS_FP32_BASIS) s->impl.reset(new krs::SeqImpl<float, double>());
     else if (d->precision == KRS_FP32) s->impl.reset(new krs::SeqImpl<float, float>());
     else s->impl.reset(new krs::SeqImpl<double, double>());
     s->impl->ctx = ctx;
-    krs_status st = s->impl->create(*d, C0, m0, ldc0);
+    krs_status st = KRS_OK;
+    try {
+        st = s->impl->create(*d, C0, m0, ldc0);
+    } catch (...) {
+        s->impl->destroy();  // device buffers of a creation that threw
+        throw;
+    }
     if (st != KRS_OK) {
         s->impl->destroy();
-        delete s;
         return st;
     }
     s->impl->nc = m0;
     ctx->live_seqs += 1;
-    *out = s;
+    *out = s.release();
     return KRS_OK;
     KRS_GUARD_END
 }
@@ -185,6 +191,10 @@ krs_status krs_seq_create(krs_ctx* ctx, const krs_seq_desc* d, const double* C0,
 krs_status krs_seq_submit(krs_seq* s, const double* values, const double* b) {
     KRS_GUARD_BEGIN
     if (!s) return KRS_E_INVALID;
+    if (s->impl->in_server.load() > 0) {
+        set_error("the sequence has server requests in flight");
+        return KRS_E_BUSY;
+    }
     return s->impl->submit(values, b, false);
     KRS_GUARD_END
 }
@@ -192,6 +202,10 @@ krs_status krs_seq_submit(krs_seq* s, const double* values, const double* b) {
 krs_status krs_seq_submit_device(krs_seq* s, const double* d_values, const double* d_b) {
     KRS_GUARD_BEGIN
     if (!s) return KRS_E_INVALID;
+    if (s->impl->in_server.load() > 0) {
+        set_error("the sequence has server requests in flight");
+        return KRS_E_BUSY;
+    }
     return s->impl->submit(d_values, d_b, true);
     KRS_GUARD_END
 }
@@ -199,6 +213,10 @@ krs_status krs_seq_submit_device(krs_seq* s, const double* d_values, const doubl
 krs_status krs_seq_solve(krs_seq* s, double* x, krs_solve_info* info) {
     KRS_GUARD_BEGIN
     if (!s) return KRS_E_INVALID;
+    if (s->impl->in_server.load() > 0) {
+        set_error("the sequence has server requests in flight");
+        return KRS_E_BUSY;
+    }
     return s->impl->solve(x, false, info);
     KRS_GUARD_END
 }
@@ -206,6 +224,10 @@ krs_status krs_seq_solve(krs_seq* s, double* x, krs_solve_info* info) {
 krs_status krs_seq_solve_device(krs_seq* s, double* d_x, krs_solve_info* info) {
     KRS_GUARD_BEGIN
     if (!s) return KRS_E_INVALID;
+    if (s->impl->in_server.load() > 0) {
+        set_error("the sequence has server requests in flight");
+        return KRS_E_BUSY;
+    }
     return s->impl->solve(d_x, true, info);
     KRS_GUARD_END
 }
@@ -213,6 +235,10 @@ krs_status krs_seq_solve_device(krs_seq* s, double* d_x, krs_solve_info* info) {
 krs_status krs_seq_recycle(krs_seq* s, int32_t* n_added) {
     KRS_GUARD_BEGIN
     if (!s) return KRS_E_INVALID;
+    if (s->impl->in_server.load() > 0) {
+        set_error("the sequence has server requests in flight");
+        return KRS_E_BUSY;
+    }
     return s->impl->recycle(n_added);
     KRS_GUARD_END
 }
@@ -256,6 +282,10 @@ krs_status krs_seq_coeffs(krs_seq* s, double* alpha, double* rho, double* gamma,
 krs_status krs_seq_basis(krs_seq* s, double* C, int64_t ldc, int32_t cap, int32_t* n_c) {
     KRS_GUARD_BEGIN
     if (!s) return KRS_E_INVALID;
+    if (s->impl->in_server.load() > 0) {
+        set_error("the sequence has server requests in flight");
+        return KRS_E_BUSY;
+    }
     return s->impl->basis(C, ldc, cap, n_c);
     KRS_GUARD_END
 }
@@ -365,6 +395,10 @@ static krs_status batch_common(krs_ctx* ctx, krs_seq* const* seqs, int32_t count
             set_error("every sequence must belong to ctx");
             return KRS_E_INVALID;
         }
+        if (seqs[i]->impl->in_server.load() > 0) {
+            set_error("a sequence of the batch has server requests in flight");
+            return KRS_E_BUSY;
+        }
         for (int j = 0; j < i; ++j)
             if (seqs[j] == seqs[i]) {
                 set_error("a sequence appears twice in the batch");
@@ -391,6 +425,10 @@ krs_status krs_batch_recycle(krs_ctx* ctx, krs_seq* const* seqs, int32_t count, 
         if (!seqs[i] || seqs[i]->impl->ctx != ctx) {
             set_error("every sequence must belong to ctx");
             return KRS_E_INVALID;
+        }
+        if (seqs[i]->impl->in_server.load() > 0) {
+            set_error("a sequence of the batch has server requests in flight");
+            return KRS_E_BUSY;
         }
         for (int j = 0; j < i; ++j)
             if (seqs[j] == seqs[i]) {

@@ -81,10 +81,21 @@ void ldl_eigenvalues_range(const std::vector<double>& d, const std::vector<doubl
         bisect_range(m, d.data(), l2d.data(), lo, hi, k0, k1, asc);
         return;
     }
+    // ranges whose thread cannot be started are bisected on this thread
     std::vector<std::thread> pool;
+    try {
+        pool.reserve(nt);
+    } catch (...) {
+    }
     for (int t = 0; t < nt; ++t) {
         const int a = k0 + (int)((int64_t)cnt * t / nt), b = k0 + (int)((int64_t)cnt * (t + 1) / nt);
-        pool.emplace_back(bisect_range, m, d.data(), l2d.data(), lo, hi, a, b, asc);
+        bool started = false;
+        try {
+            pool.emplace_back(bisect_range, m, d.data(), l2d.data(), lo, hi, a, b, asc);
+            started = true;
+        } catch (...) {
+        }
+        if (!started) bisect_range(m, d.data(), l2d.data(), lo, hi, a, b, asc);
     }
     for (auto& th : pool) th.join();
 }

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <thread>
@@ -1284,13 +1285,19 @@ krs_status batch_solve(krs_ctx* ctx, SeqBase* const* seqs, int count, double* co
         for (int i : idx)
             if (out[i] == KRS_OK || out[i] == KRS_E_MAXIT) ok.push_back(i);
         if (ok.empty()) return;
-        helpers.emplace_back([&, ok] {
-            std::vector<SeqBase*> m;
-            for (int i : ok) m.push_back(seqs[i]);
-            std::vector<krs_status> st(ok.size(), KRS_OK);
+        // everything the helper uses is allocated here: nothing on it can throw
+        std::vector<SeqBase*> m;
+        for (int i : ok) m.push_back(seqs[i]);
+        std::vector<krs_status> st(ok.size(), KRS_OK);
+        auto fn = [&pst, ok = std::move(ok), m = std::move(m), st = std::move(st)]() mutable {
             plan_all(m.data(), (int)m.size(), st.data());
             for (size_t j = 0; j < ok.size(); ++j) pst[ok[j]] = st[j];
-        });
+        };
+        try {
+            helpers.emplace_back(fn);
+        } catch (...) {
+            fn();  // no helper thread: plan here
+        }
     };
     // begin every member; group the begun ones by type
     std::map<int, std::vector<int>> groups;
@@ -1383,6 +1390,7 @@ krs_status batch_solve(krs_ctx* ctx, SeqBase* const* seqs, int count, double* co
             if ((out[i] == KRS_OK || out[i] == KRS_E_MAXIT) && ended[i]) {
                 krs_status r2 = pst[i];
                 if (r2 == KRS_OK) r2 = seqs[i]->recycle_apply(&a);
+                else set_error(seqs[i]->plan_msg);
                 if (r2 != KRS_OK) out[i] = r2;
                 else if (info) info[i].added = a;
             }
@@ -1397,26 +1405,45 @@ krs_status batch_solve(krs_ctx* ctx, SeqBase* const* seqs, int count, double* co
 
 void plan_all(SeqBase* const* seqs, int count, krs_status* st) {
     // Independent sequences: their host-side Ritz work runs on up to
-    // host_threads() threads, one sequence per thread, the threads left over
-    // shared out as bisection threads of each (all of them when there is a
-    // single sequence).  Host work only: no device calls.
+    // host_threads() threads (this one included), one sequence per thread,
+    // the threads left over shared out as bisection threads of each (all of
+    // them when there is a single sequence).  Host work only: no device
+    // calls.  Nothing escapes a thread: a plan that throws fails with a
+    // status, and threads that cannot be started leave their sequences to
+    // the ones that run.
     const int nt = std::max(1, std::min(count, host_threads()));
     const int per = std::max(1, host_threads() / nt);
     std::atomic<int> next{0};
-    auto work = [&]() {
+    auto work = [&]() noexcept {
         for (int i = next.fetch_add(1); i < count; i = next.fetch_add(1)) {
-            seqs[i]->recycle_threads = per;
-            st[i] = seqs[i]->recycle_plan();
-            seqs[i]->recycle_threads = 0;
+            SeqBase* s = seqs[i];
+            s->recycle_threads = per;
+            krs_status r = KRS_OK;
+            const char* msg = nullptr;
+            try {
+                r = s->recycle_plan();
+                if (r != KRS_OK) msg = krs_last_error();
+            } catch (const std::bad_alloc&) {
+                r = KRS_E_OOM;
+                msg = "host allocation failed in the Ritz analysis";
+            } catch (...) {
+                r = KRS_E_INVALID;
+                msg = "internal error in the Ritz analysis";
+            }
+            if (msg) std::snprintf(s->plan_msg, sizeof s->plan_msg, "%s", msg);
+            s->recycle_threads = 0;
+            st[i] = r;
         }
     };
-    if (nt == 1) {
-        work();
-    } else {
-        std::vector<std::thread> pool;
-        for (int t = 0; t < nt; ++t) pool.emplace_back(work);
-        for (auto& th : pool) th.join();
+    std::vector<std::thread> pool;
+    try {
+        pool.reserve(nt - 1);
+        for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+    } catch (...) {
+        // fewer threads: the started ones and this one take every sequence
     }
+    work();
+    for (auto& th : pool) th.join();
 }
 
 krs_status recycle_all(krs_ctx* ctx, SeqBase* const* seqs, int count, int32_t* added) {
@@ -1428,6 +1455,7 @@ krs_status recycle_all(krs_ctx* ctx, SeqBase* const* seqs, int count, int32_t* a
     for (int i = 0; i < count; ++i) {
         int32_t a = 0;
         if (st[i] == KRS_OK) st[i] = seqs[i]->recycle_apply(&a);
+        else if (first == KRS_OK) set_error(seqs[i]->plan_msg);
         if (added) added[i] = a;
         if (st[i] != KRS_OK && first == KRS_OK) first = st[i];
     }

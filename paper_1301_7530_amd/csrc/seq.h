@@ -18,8 +18,8 @@ struct krs_ctx {
     bool own_stream = false;
     bool has_alloc = false;
     krs_allocator alloc{};
-    int live_seqs = 0;
-    int live_servers = 0;
+    std::atomic<int> live_seqs{0};
+    std::atomic<int> live_servers{0};
     std::atomic<int64_t> bytes_live{0};
 };
 
@@ -60,6 +60,9 @@ struct SeqBase {
     // while the device is busy), then the device work on the stream
     virtual krs_status recycle_plan() = 0;
     virtual krs_status recycle_apply(int32_t* n_added) = 0;
+    // message of the last failed recycle_plan (the error text is per thread,
+    // and the plan may have run on a helper thread)
+    char plan_msg[256] = {0};
     virtual krs_status basis(double* C, int64_t ld, int32_t cap, int32_t* n_c) = 0;
     virtual void destroy() = 0;
     // live kernel timing (sampled iterations, device wall clock)

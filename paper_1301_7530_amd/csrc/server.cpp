@@ -20,8 +20,10 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <exception>
 #include <map>
 #include <mutex>
+#include <new>
 #include <set>
 #include <string>
 #include <thread>
@@ -69,7 +71,8 @@ struct krs_server {
     krs_status fatal = KRS_OK;
     std::string fatal_msg;
 
-    void post(Request& r, krs_status st, const krs_solve_info& info, int batch) {
+    // msg: the failure's message (null: this thread's last error)
+    void post(Request& r, krs_status st, const krs_solve_info& info, int batch, const char* msg = nullptr) {
         krs_completion c;
         std::memset(&c, 0, sizeof c);
         const auto now = Clock::now();
@@ -81,7 +84,7 @@ struct krs_server {
         c.queue_ms = ms_since(r.t_arrive, r.t_admit);
         c.info = info;
         if (st != KRS_OK) {
-            const char* m = krs_last_error();
+            const char* m = msg ? msg : krs_last_error();
             std::strncpy(c.message, m ? m : "", sizeof c.message - 1);
         }
         r.impl->in_server.fetch_sub(1);
@@ -96,10 +99,18 @@ struct krs_server {
     }
 
     void run();
+    void serve();
 };
 
+// The worker thread's body: nothing escapes it.  A host failure (an
+// allocation, a thread that cannot start) inside the loop stops the server
+// the way a device failure does.
 void krs_server::run() {
     (void)hipSetDevice(ctx->device);
+    serve();
+}
+
+void krs_server::serve() {
     struct Active {
         Request req;
         int64_t bytes;
@@ -114,6 +125,7 @@ void krs_server::run() {
         std::vector<krs::SeqBase*> rec;
         std::vector<size_t> rec_idx;
         std::vector<krs_status> pst;
+        std::vector<std::string> msgs;  // end_solve failures
         int batch = 0;
         std::atomic<bool> planned{false};
         std::thread th;
@@ -122,173 +134,209 @@ void krs_server::run() {
     int64_t used = 0;
     int nact = 0;
     std::vector<int32_t> stat;
+    // requests of the current admission round, and how many of them have
+    // been begun (or completed) so far
+    std::vector<Request> admit;
+    size_t admit_done = 0;
     // apply the planned recycles (in order), release and complete; with
-    // `block`, wait for the oldest plan first
-    auto finish_pending = [&](bool block, krs_status fail) {
+    // `block`, wait for the oldest plan first; with `fail`, complete them
+    // with that status and message instead
+    auto finish_pending = [&](bool block, krs_status fail, const char* fail_msg = nullptr) {
         while (!pending.empty()) {
             Pending& p = *pending.front();
             if (!block && !p.planned.load()) break;
             block = false;
-            p.th.join();
+            if (p.th.joinable()) p.th.join();
             for (size_t j = 0; j < p.rec.size(); ++j) {
+                const size_t i = p.rec_idx[j];
                 krs_status a = p.pst[j];
                 int32_t added = 0;
-                if (a == KRS_OK && fail == KRS_OK) a = p.rec[j]->recycle_apply(&added);
-                if (fail != KRS_OK) a = fail;
-                p.infos[p.rec_idx[j]].added = added;
-                if (a != KRS_OK && p.sts[p.rec_idx[j]] == KRS_OK) p.sts[p.rec_idx[j]] = a;
+                if (fail != KRS_OK) {
+                    a = fail;
+                } else if (a == KRS_OK) {
+                    a = p.rec[j]->recycle_apply(&added);
+                    if (a != KRS_OK) p.msgs[i] = krs_last_error();
+                } else {
+                    p.msgs[i] = p.rec[j]->plan_msg;
+                }
+                p.infos[i].added = added;
+                if (a != KRS_OK && p.sts[i] == KRS_OK) p.sts[i] = a;
             }
             for (size_t i = 0; i < p.fin.size(); ++i) {
                 p.fin[i].req.impl->trim();
                 used -= p.fin[i].bytes;
-                post(p.fin[i].req, p.sts[i], p.infos[i], p.batch);
+                post(p.fin[i].req, p.sts[i], p.infos[i], p.batch, fail != KRS_OK ? fail_msg : p.msgs[i].c_str());
             }
             pending.pop_front();
         }
     };
-    while (true) {
-        finish_pending(false, KRS_OK);
-        // ---- admission
-        std::vector<Request> admit;
-        {
-            std::unique_lock<std::mutex> lk(mu);
-            if (nact == 0 && queue.empty() && pending.empty()) {
-                if (stop) break;
-                cv_work.wait_for(lk, std::chrono::milliseconds(20));
-                continue;
-            }
-            std::set<krs::SeqBase*> seen;  // a sequence's later requests wait for its earlier ones
-            for (auto it = queue.begin(); it != queue.end();) {
-                if (nact + (int)admit.size() >= max_slots) break;
-                if (busy.count(it->impl) || seen.count(it->impl)) {
-                    seen.insert(it->impl);
-                    ++it;
-                    continue;
-                }
-                const int64_t bytes = it->impl->working_bytes();
-                const bool fits = budget == 0 || used + bytes <= (int64_t)budget;
-                if (!fits && (nact + admit.size()) > 0) break;  // in order: wait for memory
-                it->bytes = bytes;
-                it->t_admit = Clock::now();
-                used += bytes;
-                busy.insert(it->impl);
-                admit.push_back(std::move(*it));
-                it = queue.erase(it);
-            }
-            peak_bytes = std::max(peak_bytes, used);
-        }
-        std::set<int> dirty;
-        for (Request& r : admit) {
-            krs_status st = r.impl->submit(r.values.data(), r.b.data(), false);
-            if (st == KRS_OK) st = r.impl->begin_solve();
-            if (st != KRS_OK) {
+    // a failure of the device or the host: fail every request in flight and
+    // stop serving
+    auto fail_all = [&](krs_status st, const std::string& msg) {
+        while (!pending.empty()) finish_pending(true, st, msg.c_str());
+        for (auto& kv : members)
+            for (auto& a : kv.second) {
                 krs_solve_info none;
                 std::memset(&none, 0, sizeof none);
-                none.status = st;
-                used -= r.bytes;
-                r.impl->trim();
-                post(r, st, none, 0);
-                continue;
+                post(a.req, st, none, 0, msg.c_str());
             }
-            std::vector<double>().swap(r.values);
-            std::vector<double>().swap(r.b);
-            const int key = r.impl->type_key();
-            const int64_t bytes = r.bytes;
-            members[key].push_back(Active{std::move(r), bytes});
-            dirty.insert(key);
-            ++nact;
+        for (size_t i = admit_done; i < admit.size(); ++i) {
+            krs_solve_info none;
+            std::memset(&none, 0, sizeof none);
+            post(admit[i], st, none, 0, msg.c_str());
         }
-        krs_status st = KRS_OK;
-        for (int key : dirty) {
-            auto& rp = runners[key];
-            if (!rp) rp = krs::make_runner(ctx, key);
-            std::vector<krs::SeqBase*> m;
-            for (auto& a : members[key]) m.push_back(a.req.impl);
-            st = rp->set_members(m);
-            if (st != KRS_OK) break;
-        }
-        if (nact == 0 && st == KRS_OK) {
-            // nothing to iterate: the queued requests wait for recycles
-            finish_pending(true, KRS_OK);
-            continue;
-        }
-        // ---- one block of iterations for every member, all types
-        for (auto& kv : runners) {
-            if (st != KRS_OK) break;
-            if (kv.second->size() > 0) st = kv.second->launch(32, true);
-        }
-        if (st == KRS_OK) {
-            ++blocks;
-            member_blocks += nact;
-        }
-        // ---- completions
-        for (auto& kv : runners) {
-            if (st != KRS_OK) break;
-            if (kv.second->size() == 0) continue;
-            st = kv.second->read_status(stat);
-            if (st != KRS_OK) break;
-            auto& mem = members[kv.first];
-            std::vector<Active> keep, fin;
-            const int batch = (int)mem.size();
-            for (size_t i = 0; i < mem.size(); ++i) {
-                if (krs::finished_status(stat[2 * i])) fin.push_back(std::move(mem[i]));
-                else keep.push_back(std::move(mem[i]));
-            }
-            const bool changed = !fin.empty();
-            if (changed) {
-                // copy the solutions out; plan the recycles on a helper thread
-                auto p = std::make_unique<Pending>();
-                p->batch = batch;
-                p->fin = std::move(fin);
-                const size_t nf = p->fin.size();
-                p->infos.resize(nf);
-                p->sts.resize(nf);
-                for (size_t i = 0; i < nf; ++i) {
-                    std::memset(&p->infos[i], 0, sizeof p->infos[i]);
-                    p->sts[i] = p->fin[i].req.impl->end_solve(p->fin[i].req.x_out, false, &p->infos[i]);
-                    if (p->sts[i] == KRS_OK || p->sts[i] == KRS_E_MAXIT) {
-                        p->rec.push_back(p->fin[i].req.impl);
-                        p->rec_idx.push_back(i);
-                    }
+        admit.clear();
+        members.clear();
+        runners.clear();
+        std::lock_guard<std::mutex> g(mu);
+        fatal = st;
+        fatal_msg = msg;
+        for (auto& r : queue) r.impl->in_server.fetch_sub(1);
+        queue.clear();
+        busy.clear();
+        stop = true;
+        cv_done.notify_all();
+    };
+    try {
+        while (true) {
+            finish_pending(false, KRS_OK);
+            // ---- admission
+            admit.clear();
+            admit_done = 0;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                if (nact == 0 && queue.empty() && pending.empty()) {
+                    if (stop) break;
+                    cv_work.wait_for(lk, std::chrono::milliseconds(20));
+                    continue;
                 }
-                nact -= (int)nf;
-                p->pst.assign(p->rec.size(), KRS_OK);
-                Pending* pp = p.get();
-                pp->th = std::thread([pp] {
-                    krs::plan_all(pp->rec.data(), (int)pp->rec.size(), pp->pst.data());
-                    pp->planned.store(true);
-                });
-                pending.push_back(std::move(p));
+                std::set<krs::SeqBase*> seen;  // a sequence's later requests wait for its earlier ones
+                for (auto it = queue.begin(); it != queue.end();) {
+                    if (nact + (int)admit.size() >= max_slots) break;
+                    if (busy.count(it->impl) || seen.count(it->impl)) {
+                        seen.insert(it->impl);
+                        ++it;
+                        continue;
+                    }
+                    const int64_t bytes = it->impl->working_bytes();
+                    const bool fits = budget == 0 || used + bytes <= (int64_t)budget;
+                    if (!fits && (nact + admit.size()) > 0) break;  // in order: wait for memory
+                    it->bytes = bytes;
+                    it->t_admit = Clock::now();
+                    used += bytes;
+                    busy.insert(it->impl);
+                    admit.push_back(std::move(*it));
+                    it = queue.erase(it);
+                }
+                peak_bytes = std::max(peak_bytes, used);
             }
-            if (changed) {
-                mem = std::move(keep);
-                std::vector<krs::SeqBase*> m;
-                for (auto& a : mem) m.push_back(a.req.impl);
-                st = kv.second->set_members(m);
-            }
-        }
-        if (st != KRS_OK) {
-            // device failure: fail every request in flight and stop serving
-            std::string msg = krs_last_error() ? krs_last_error() : "";
-            while (!pending.empty()) finish_pending(true, st);
-            for (auto& kv : members)
-                for (auto& a : kv.second) {
+            std::set<int> dirty;
+            for (; admit_done < admit.size(); ++admit_done) {
+                Request& r = admit[admit_done];
+                krs_status st = r.impl->submit(r.values.data(), r.b.data(), false);
+                if (st == KRS_OK) st = r.impl->begin_solve();
+                if (st != KRS_OK) {
                     krs_solve_info none;
                     std::memset(&none, 0, sizeof none);
-                    post(a.req, st, none, 0);
+                    none.status = st;
+                    used -= r.bytes;
+                    r.impl->trim();
+                    post(r, st, none, 0);
+                    continue;
                 }
-            members.clear();
-            runners.clear();
-            std::lock_guard<std::mutex> g(mu);
-            fatal = st;
-            fatal_msg = msg;
-            for (auto& r : queue) r.impl->in_server.fetch_sub(1);
-            queue.clear();
-            busy.clear();
-            stop = true;
-            cv_done.notify_all();
-            break;
+                const int key = r.impl->type_key();
+                auto& mk = members[key];
+                mk.reserve(mk.size() + 1);  // the move below cannot fail half-way
+                std::vector<double>().swap(r.values);
+                std::vector<double>().swap(r.b);
+                const int64_t bytes = r.bytes;
+                mk.push_back(Active{std::move(r), bytes});
+                dirty.insert(key);
+                ++nact;
+            }
+            krs_status st = KRS_OK;
+            for (int key : dirty) {
+                auto& rp = runners[key];
+                if (!rp) rp = krs::make_runner(ctx, key);
+                std::vector<krs::SeqBase*> m;
+                for (auto& a : members[key]) m.push_back(a.req.impl);
+                st = rp->set_members(m);
+                if (st != KRS_OK) break;
+            }
+            if (nact == 0 && st == KRS_OK) {
+                // nothing to iterate: the queued requests wait for recycles
+                finish_pending(true, KRS_OK);
+                continue;
+            }
+            // ---- one block of iterations for every member, all types
+            for (auto& kv : runners) {
+                if (st != KRS_OK) break;
+                if (kv.second->size() > 0) st = kv.second->launch(32, true);
+            }
+            if (st == KRS_OK) {
+                ++blocks;
+                member_blocks += nact;
+            }
+            // ---- completions
+            for (auto& kv : runners) {
+                if (st != KRS_OK) break;
+                if (kv.second->size() == 0) continue;
+                st = kv.second->read_status(stat);
+                if (st != KRS_OK) break;
+                auto& mem = members[kv.first];
+                std::vector<Active> keep, fin;
+                const int batch = (int)mem.size();
+                for (size_t i = 0; i < mem.size(); ++i) {
+                    if (krs::finished_status(stat[2 * i])) fin.push_back(std::move(mem[i]));
+                    else keep.push_back(std::move(mem[i]));
+                }
+                const bool changed = !fin.empty();
+                if (changed) {
+                    // copy the solutions out; plan the recycles on a helper thread
+                    auto p = std::make_unique<Pending>();
+                    p->batch = batch;
+                    p->fin = std::move(fin);
+                    const size_t nf = p->fin.size();
+                    p->infos.resize(nf);
+                    p->sts.resize(nf);
+                    p->msgs.resize(nf);
+                    for (size_t i = 0; i < nf; ++i) {
+                        std::memset(&p->infos[i], 0, sizeof p->infos[i]);
+                        p->sts[i] = p->fin[i].req.impl->end_solve(p->fin[i].req.x_out, false, &p->infos[i]);
+                        if (p->sts[i] != KRS_OK) p->msgs[i] = krs_last_error();
+                        if (p->sts[i] == KRS_OK || p->sts[i] == KRS_E_MAXIT) {
+                            p->rec.push_back(p->fin[i].req.impl);
+                            p->rec_idx.push_back(i);
+                        }
+                    }
+                    nact -= (int)nf;
+                    p->pst.assign(p->rec.size(), KRS_OK);
+                    Pending* pp = p.get();
+                    pending.push_back(std::move(p));
+                    auto plan = [pp] {
+                        krs::plan_all(pp->rec.data(), (int)pp->rec.size(), pp->pst.data());
+                        pp->planned.store(true);
+                    };
+                    try {
+                        pp->th = std::thread(plan);
+                    } catch (...) {
+                        plan();  // no helper thread: plan here
+                    }
+                }
+                if (changed) {
+                    mem = std::move(keep);
+                    std::vector<krs::SeqBase*> m;
+                    for (auto& a : mem) m.push_back(a.req.impl);
+                    st = kv.second->set_members(m);
+                }
+            }
+            if (st != KRS_OK) {
+                fail_all(st, krs_last_error() ? krs_last_error() : "");
+                break;
+            }
         }
+    } catch (const std::exception& e) {
+        fail_all(KRS_E_OOM, std::string("server stopped on a host failure: ") + e.what());
     }
 }
 
@@ -301,17 +349,23 @@ krs_status krs_server_create(krs_ctx* ctx, size_t hbm_budget, int32_t max_slots,
             return KRS_E_INVALID;
         }
         *out = nullptr;
-        if (ctx->live_servers > 0) {
+        std::unique_ptr<krs_server> s(new krs_server());
+        int none = 0;
+        if (!ctx->live_servers.compare_exchange_strong(none, 1)) {
             krs::set_error("the context already has a server");
             return KRS_E_STATE;
         }
-        krs_server* s = new krs_server();
         s->ctx = ctx;
         s->budget = hbm_budget;
         s->max_slots = max_slots;
-        ctx->live_servers += 1;
-        s->worker = std::thread([s] { s->run(); });
-        *out = s;
+        krs_server* sp = s.get();
+        try {
+            s->worker = std::thread([sp] { sp->run(); });
+        } catch (...) {
+            ctx->live_servers -= 1;
+            throw;
+        }
+        *out = s.release();
         return KRS_OK;
     } catch (const std::exception& e) {
         krs::set_error(e.what());
@@ -407,7 +461,13 @@ krs_status krs_server_stats(krs_server* s, krs_server_report* out) {
     if (s->completed > 0 && s->started) {
         const double span = ms_since(s->t0, s->t_last);
         out->solves_per_s = span > 0 ? 1e3 * (double)s->completed / span : 0.0;
-        std::vector<double> l = s->lat_ms;
+        std::vector<double> l;
+        try {
+            l = s->lat_ms;
+        } catch (const std::bad_alloc&) {
+            krs::set_error("host allocation failed");
+            return KRS_E_OOM;
+        }
         auto pct = [&l](double q) {
             const size_t i = std::min(l.size() - 1, (size_t)(q * (double)(l.size() - 1) + 0.5));
             std::nth_element(l.begin(), l.begin() + i, l.end());
