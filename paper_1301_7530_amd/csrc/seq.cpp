@@ -661,7 +661,8 @@ krs_status SeqImpl<V, W>::begin_solve() {
     int hist = 0;
     trks_slots = 0;
     if (desc.reuse == KRS_REUSE_SELECTIVE && !history_needed()) {
-        // a full frozen basis takes nothing from this run: no history
+        // nothing is appended from this run (a full frozen basis, or the
+        // cost cap holds): no history
         d_Z.release(ctx);
         history_kept = 0;
     } else if (desc.reuse == KRS_REUSE_SELECTIVE) {
@@ -685,7 +686,7 @@ krs_status SeqImpl<V, W>::begin_solve() {
         if (desc.max_basis > 0) hist = std::min(hist, std::max(0, desc.max_basis - nc));
         if (desc.history_cap > 0) hist = std::min(hist, desc.history_cap);
         hist = std::min(hist, 1024 - nc);
-        if (hist < 0) hist = 0;
+        if (hist < 0 || cost_held()) hist = 0;
         if (!ensure_c_capacity(nc + hist)) return KRS_E_OOM;
         trks_slots = hist;
     }

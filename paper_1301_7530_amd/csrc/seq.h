@@ -99,9 +99,12 @@ struct SeqImpl : SeqBase {
     int dropped_last = 0;
     int history_kept = 0;
     int history_fit = 0;  // history length that fit after a longer one did not (0: none failed)
-    // SRKS needs the run's directions unless the basis is full and frozen
+    // the cost cap holds: the recycle after this solve appends nothing
+    bool cost_held() const { return desc.cap_policy == KRS_CAP_COST && cost_hold > 0 && nc <= nc0; }
+    // SRKS needs the run's directions unless nothing will be appended from
+    // them: the basis is full and frozen, or the cost cap holds
     bool history_needed() const {
-        return !(desc.cap_policy == KRS_CAP_FREEZE && desc.max_basis > 0 && nc >= desc.max_basis);
+        return !(desc.cap_policy == KRS_CAP_FREEZE && desc.max_basis > 0 && nc >= desc.max_basis) && !cost_held();
     }
     std::vector<double> h_F;  // host source of the last basis-update upload
     struct RecyclePlan {
