@@ -367,9 +367,24 @@ __device__ __forceinline__ X ell_row1(const V* __restrict__ val, const int32_t* 
 #pragma unroll
         for (int u = 0; u < UNR; ++u) acc += (X)a[u] * xs[u];
     }
-    for (; k < k1; ++k) {
-        const int64_t e = k * 64 + lane;
-        acc += (X)val[e] * x[col[e]];
+    // the last (fewer than UNR) slots as one group: every load issued at a
+    // clamped, valid slot before any is used, the sum in the same order
+    const int64_t r = k1 - k;
+    if (r > 0) {
+        int32_t cc[UNR];
+        V a[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const int64_t e = (k + (u < r ? u : r - 1)) * 64 + lane;
+            cc[u] = col[e];
+            a[u] = val[e];
+        }
+        X xs[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) xs[u] = x[cc[u]];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u)
+            if (u < r) acc += (X)a[u] * xs[u];
     }
     return acc;
 }
@@ -1410,6 +1425,64 @@ __global__ __launch_bounds__(256) void kb_correct_dir(const SysView<V, W>* __res
     const int2 e = map[blockIdx.x];
     correct_dir_body<V, W, 8>(views[e.x], e.y, first);
 }
+// The direction update of the members without a basis (n_c = 0): w = s +
+// beta w_old and z = s, the expressions correct_dir_body evaluates when there
+// is no column (so the same bits), without its LDS stage.  A workgroup takes
+// kDir0Group consecutive ranges b of that body's grid (blocks b, b + g5, ...)
+// with every load of a round issued before any store: with thousands of
+// small systems the per-workgroup latency, not the bytes, set the time of the
+// general kernel.
+template <typename V, typename W>
+__global__ __launch_bounds__(256) void kb_correct_dir0(const SysView<V, W>* __restrict__ views,
+                                                       const int2* __restrict__ map, int first) {
+    constexpr int G = kDir0Group;
+    const int2 e = map[blockIdx.x];
+    const SysView<V, W>& v = views[e.x];
+    const DevState* st = v.st;
+    if (!gate(st, M_RUN)) return;
+    if (first == 2 && st->pending_dir == 0) return;
+    const double beta = (first == 1) ? 0.0 : st->beta;
+    const int j = st->iter;
+    const int hist_cap = st->hist_cap;
+    const bool tm = first == 0 && ktime_sample(st, 2);
+    const int tid = threadIdx.x;
+    const int64_t nblk = (v.n + 255) / 256;
+    const int64_t g5 = v.geo.g5;
+    const int64_t b0 = e.y;
+    const int nb = (int)((b0 + G) < g5 ? G : g5 - b0);
+    for (int u = 0; u < nb; ++u) ktime_begin(v.kslots, 2, b0 + u, tm);
+    for (int64_t r0 = 0; r0 + b0 < nblk; r0 += g5) {
+        int64_t row[G];
+        W sv[G], wv0[G];
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int64_t blk = r0 + b0 + u;
+            row[u] = (u < nb && blk < nblk) ? blk * 256 + tid : v.n;
+            sv[u] = 0;
+            wv0[u] = 0;
+            if (row[u] < v.n) {
+                sv[u] = v.s[row[u]];
+                if (first != 1) wv0[u] = v.w[row[u]];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int64_t i = row[u];
+            if (i < v.n) {
+                const double s = (double)sv[u];
+                const double cz = 0.0, cw = 0.0;
+                const W zv = (W)(s - cz);
+                const W wv = (first == 1) ? zv : (W)(s - cw + beta * (double)wv0[u]);
+                v.w[i] = wv;
+                if (j < hist_cap) {
+                    if (v.zhist) v.zhist[(int64_t)j * v.ldh + i] = (V)zv;
+                    if (v.whist) v.whist[(int64_t)j * v.ldh + i] = (V)wv;
+                }
+            }
+        }
+    }
+    for (int u = 0; u < nb; ++u) ktime_end(v.kslots, 2, b0 + u, tm);
+}
 template <typename V, typename W, int B>
 __global__ __launch_bounds__(256) void kb_true_resid(const SysView<V, W>* __restrict__ views,
                                                      const int2* __restrict__ map, int final_only) {
@@ -1882,9 +1955,12 @@ void batch_update_reduce(const SysView<V, W>* views, const BatchMaps& m, int mod
 
 template <typename V, typename W>
 void batch_correct_dir(const SysView<V, W>* views, const BatchMaps& m, int first, hipStream_t stream) {
-    if (m.count[BK_DIR] <= 0) return;
-    hipLaunchKernelGGL((kb_correct_dir<V, W>), dim3((unsigned)m.count[BK_DIR]), dim3(256), 0, stream, views,
-                       m.map[BK_DIR], first);
+    if (m.count[BK_DIR] > 0)
+        hipLaunchKernelGGL((kb_correct_dir<V, W>), dim3((unsigned)m.count[BK_DIR]), dim3(256), 0, stream, views,
+                           m.map[BK_DIR], first);
+    if (m.count[BK_DIR0] > 0)
+        hipLaunchKernelGGL((kb_correct_dir0<V, W>), dim3((unsigned)m.count[BK_DIR0]), dim3(256), 0, stream, views,
+                           m.map[BK_DIR0], first);
 }
 
 template <typename V, typename W, int B>
