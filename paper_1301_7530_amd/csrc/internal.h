@@ -160,11 +160,14 @@ enum BatchKernel {
     BK_DOT,       // coarse dot (gd; systems with a basis)
     BK_ONEC,      // one workgroup per system with a basis
     BK_CC,        // coarse correction (gcc; systems with a basis)
-    BK_DIR0,      // direction update of systems without a basis (kDir0Group K5 ranges each)
+    BK_DIR0,      // direction update of systems without a basis (kDirFewGroup K5 ranges each)
+    BK_DIRF,      // direction update of systems with 1..kDirFewCols columns (kDirFewGroup K5 ranges each)
     BK_COUNT
 };
-// K5 workgroup ranges per workgroup of the basis-free direction update
-constexpr int kDir0Group = 4;
+// the direction update of systems with at most kDirFewCols basis columns:
+// K5 workgroup ranges per workgroup
+constexpr int kDirFewCols = 4;
+constexpr int kDirFewGroup = 4;
 struct BatchMaps {
     const int2* map[BK_COUNT];
     int64_t count[BK_COUNT];

@@ -1425,22 +1425,36 @@ __global__ __launch_bounds__(256) void kb_correct_dir(const SysView<V, W>* __res
     const int2 e = map[blockIdx.x];
     correct_dir_body<V, W, 8>(views[e.x], e.y, first);
 }
-// The direction update of the members without a basis (n_c = 0): w = s +
-// beta w_old and z = s, the expressions correct_dir_body evaluates when there
-// is no column (so the same bits), without its LDS stage.  A workgroup takes
-// kDir0Group consecutive ranges b of that body's grid (blocks b, b + g5, ...)
-// with every load of a round issued before any store: with thousands of
-// small systems the per-workgroup latency, not the bytes, set the time of the
-// general kernel.
-template <typename V, typename W>
-__global__ __launch_bounds__(256) void kb_correct_dir0(const SysView<V, W>* __restrict__ views,
-                                                       const int2* __restrict__ map, int first) {
-    constexpr int G = kDir0Group;
+// The direction update of the members with at most kDirFewCols basis
+// columns: z = s - C mu and w = s - C mu2 + beta w_old, without the general
+// kernel's LDS stage.  With so few columns the general kernel gives each
+// column to its own wave and adds the four waves' products in LDS in the
+// order ((c0 + c1) + c2) + c3 (missing columns as zeros); the same products
+// and the same order are formed here per row in registers, so the bits are
+// the same.  NC = 0 serves the members without a basis (no column loads,
+// fewer registers), NC = kDirFewCols the others.  A workgroup takes
+// kDirFewGroup consecutive ranges b of that
+// kernel's grid (blocks b, b + g5, ...) with every load of a round issued
+// before any store: with thousands of small systems the per-workgroup
+// latency, not the bytes, set the time of the general kernel.
+template <typename V, typename W, int NC>
+__global__ __launch_bounds__(256) void kb_correct_dir_few(const SysView<V, W>* __restrict__ views,
+                                                          const int2* __restrict__ map, int first) {
+    constexpr int G = kDirFewGroup;
+    static_assert(NC == 0 || NC == 4, "the general kernel's four waves hold one column each");
+    constexpr int NA = NC > 0 ? NC : 1;
     const int2 e = map[blockIdx.x];
     const SysView<V, W>& v = views[e.x];
     const DevState* st = v.st;
     if (!gate(st, M_RUN)) return;
     if (first == 2 && st->pending_dir == 0) return;
+    const int nc = v.nc;
+    double m1[NA], m2[NA];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        m1[k] = (k < nc) ? v.mu[k] : 0.0;
+        m2[k] = (k < nc) ? ((first == 1) ? v.mu[k] : v.mu2[k]) : 0.0;
+    }
     const double beta = (first == 1) ? 0.0 : st->beta;
     const int j = st->iter;
     const int hist_cap = st->hist_cap;
@@ -1454,23 +1468,38 @@ __global__ __launch_bounds__(256) void kb_correct_dir0(const SysView<V, W>* __re
     for (int64_t r0 = 0; r0 + b0 < nblk; r0 += g5) {
         int64_t row[G];
         W sv[G], wv0[G];
+        V cv[G][NA];
 #pragma unroll
         for (int u = 0; u < G; ++u) {
             const int64_t blk = r0 + b0 + u;
             row[u] = (u < nb && blk < nblk) ? blk * 256 + tid : v.n;
             sv[u] = 0;
             wv0[u] = 0;
+#pragma unroll
+            for (int k = 0; k < NA; ++k) cv[u][k] = 0;
             if (row[u] < v.n) {
                 sv[u] = v.s[row[u]];
                 if (first != 1) wv0[u] = v.w[row[u]];
+#pragma unroll
+                for (int k = 0; k < NC; ++k)
+                    if (k < nc) cv[u][k] = v.C[(int64_t)k * v.ldc + row[u]];
             }
         }
 #pragma unroll
         for (int u = 0; u < G; ++u) {
             const int64_t i = row[u];
             if (i < v.n) {
+                double az[4] = {0.0, 0.0, 0.0, 0.0}, aw[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int k = 0; k < NC; ++k) {
+                    if (k < nc) {
+                        az[k] += (double)cv[u][k] * m1[k];
+                        aw[k] += (double)cv[u][k] * m2[k];
+                    }
+                }
+                const double cz = ((az[0] + az[1]) + az[2]) + az[3];
+                const double cw = ((aw[0] + aw[1]) + aw[2]) + aw[3];
                 const double s = (double)sv[u];
-                const double cz = 0.0, cw = 0.0;
                 const W zv = (W)(s - cz);
                 const W wv = (first == 1) ? zv : (W)(s - cw + beta * (double)wv0[u]);
                 v.w[i] = wv;
@@ -1959,8 +1988,11 @@ void batch_correct_dir(const SysView<V, W>* views, const BatchMaps& m, int first
         hipLaunchKernelGGL((kb_correct_dir<V, W>), dim3((unsigned)m.count[BK_DIR]), dim3(256), 0, stream, views,
                            m.map[BK_DIR], first);
     if (m.count[BK_DIR0] > 0)
-        hipLaunchKernelGGL((kb_correct_dir0<V, W>), dim3((unsigned)m.count[BK_DIR0]), dim3(256), 0, stream, views,
-                           m.map[BK_DIR0], first);
+        hipLaunchKernelGGL((kb_correct_dir_few<V, W, 0>), dim3((unsigned)m.count[BK_DIR0]), dim3(256), 0, stream,
+                           views, m.map[BK_DIR0], first);
+    if (m.count[BK_DIRF] > 0)
+        hipLaunchKernelGGL((kb_correct_dir_few<V, W, kDirFewCols>), dim3((unsigned)m.count[BK_DIRF]), dim3(256), 0,
+                           stream, views, m.map[BK_DIRF], first);
 }
 
 template <typename V, typename W, int B>

@@ -1146,10 +1146,11 @@ struct BatchRunner : RunnerBase {
             for (int b = 0; b < v.geo.g1; ++b) lists[BK_SPMV].push_back(make_int2(i, b));
             for (int b = 0; b < v.geo.g3; ++b) lists[BK_UPD].push_back(make_int2(i, b));
             lists[BK_ONE].push_back(make_int2(i, 0));
-            if (basis) {
+            if (v.nc > kDirFewCols) {
                 for (int b = 0; b < v.geo.g5; ++b) lists[BK_DIR].push_back(make_int2(i, b));
             } else {
-                for (int b = 0; b < v.geo.g5; b += kDir0Group) lists[BK_DIR0].push_back(make_int2(i, b));
+                const int k = v.nc == 0 ? BK_DIR0 : BK_DIRF;
+                for (int b = 0; b < v.geo.g5; b += kDirFewGroup) lists[k].push_back(make_int2(i, b));
             }
             if (basis) {
                 for (int b = 0; b < v.geo.gd; ++b) lists[BK_DOT].push_back(make_int2(i, b));
