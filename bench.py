@@ -319,7 +319,7 @@ def run_batched(args, K, torch, data):
     ctx = K.Context(0)
     kw = dict(precision=args.precision, tol=1e-8, max_iter=args.max_iter, ritz_eps=args.eps or wl["eps"],
               max_basis=wl["max_basis"], cap_policy=wl.get("cap_policy", "freeze"), history_cap=args.history_cap,
-              refine_drop=args.refine_drop)
+              refine_drop=args.refine_drop, separate_finalize=args.separate_finalize)
     fused_rows = args.update_rows or wl["update_rows"]
 
     def phase(reuse, fused):
