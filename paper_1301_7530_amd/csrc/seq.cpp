@@ -251,6 +251,9 @@ void SeqImpl<V, W>::destroy() {
         b->release(ctx);
     if (h_st) (void)hipHostFree(h_st);
     h_st = nullptr;
+    if (h_coef) (void)hipHostFree(h_coef);
+    h_coef = nullptr;
+    h_coef_cap = 0;
     for (auto& e : ev)
         if (e) (void)hipEventDestroy(e);
     graph_release();
@@ -789,10 +792,24 @@ krs_status SeqImpl<V, W>::end_solve(double* x, bool device_x, krs_solve_info* in
     coef_rho.assign(mc, 0.0);
     coef_gamma.assign(mc, 0.0);
     if (mc > 0) {
+        // the three coefficient runs through pinned staging: one wait
+        // instead of a blocking copy each (a batch ends hundreds of solves)
+        if (h_coef_cap < 3 * (size_t)mc) {
+            if (h_coef) (void)hipHostFree(h_coef);
+            h_coef = nullptr;
+            h_coef_cap = 0;
+            const size_t want = 3 * (size_t)std::min(coef_cap, std::max(mc, 2 * mc));
+            KRS_HIP(hipHostMalloc((void**)&h_coef, want * sizeof(double), hipHostMallocDefault));
+            h_coef_cap = want;
+        }
         const double* base = (const double*)d_coef.p;
-        KRS_HIP(hipMemcpy(coef_alpha.data(), base, mc * sizeof(double), hipMemcpyDeviceToHost));
-        KRS_HIP(hipMemcpy(coef_rho.data(), base + coef_cap, mc * sizeof(double), hipMemcpyDeviceToHost));
-        KRS_HIP(hipMemcpy(coef_gamma.data(), base + 2 * coef_cap, mc * sizeof(double), hipMemcpyDeviceToHost));
+        for (int a = 0; a < 3; ++a)
+            KRS_HIP(hipMemcpyAsync(h_coef + (size_t)a * mc, base + (size_t)a * coef_cap, mc * sizeof(double),
+                                   hipMemcpyDeviceToHost, stream));
+        KRS_HIP(hipStreamSynchronize(stream));
+        std::memcpy(coef_alpha.data(), h_coef, mc * sizeof(double));
+        std::memcpy(coef_rho.data(), h_coef + mc, mc * sizeof(double));
+        std::memcpy(coef_gamma.data(), h_coef + 2 * (size_t)mc, mc * sizeof(double));
     }
     krs_solve_info inf = info_last;
     inf.iters = m;

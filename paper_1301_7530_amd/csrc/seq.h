@@ -94,6 +94,8 @@ struct SeqImpl : SeqBase {
     Buf d_col, d_slice_ptr, d_map, d_diag, d_val64, d_valV, d_minv, d_bad, d_in, d_b, d_x, d_r, d_s, d_w, d_q;
     Buf d_C, d_C0, d_AC64, d_ACv, d_G, d_Ginv, d_mu, d_Z, d_coef, d_partials, d_st, d_F, d_tmp, d_Ctmp, d_kslots;
     DevState* h_st = nullptr;
+    double* h_coef = nullptr;  // pinned staging of the CG coefficients read back by end_solve
+    size_t h_coef_cap = 0;     // doubles
     Geometry geo{};
     int tuned_nc = 0;
     int dropped_last = 0;
