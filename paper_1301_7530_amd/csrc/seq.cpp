@@ -9,6 +9,8 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <new>
+#include <stdexcept>
 #include <thread>
 
 namespace krs {
@@ -586,7 +588,7 @@ krs_status SeqImpl<V, W>::solve(double* x, bool device_x, krs_solve_info* info) 
     if (st != KRS_OK) return st;
     st = iterate();
     if (st != KRS_OK) return st;
-    return end_solve(x, device_x, info);
+    return end_solve(x, device_x, info, h_st->iter);
 }
 
 // Update-kernel tile choice: time the update kernel alone (mode 1 rewrites
@@ -764,11 +766,37 @@ krs_status SeqImpl<V, W>::iterate() {
     return KRS_OK;
 }
 
+// Pinned staging for the first mc coefficients of each of the three runs
+// (alpha, rho, gamma), then their asynchronous copies on the stream.
 template <typename V, typename W>
-krs_status SeqImpl<V, W>::end_solve(double* x, bool device_x, krs_solve_info* info) {
+void SeqImpl<V, W>::coef_readback(int mc) {
+    if (h_coef_cap < 3 * (size_t)mc) {
+        if (h_coef) (void)hipHostFree(h_coef);
+        h_coef = nullptr;
+        h_coef_cap = 0;
+        const size_t want = 3 * (size_t)std::min(coef_cap, 2 * mc);
+        if (hipHostMalloc((void**)&h_coef, want * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+            h_coef = nullptr;
+            throw std::bad_alloc();
+        }
+        h_coef_cap = want;
+    }
+    const double* base = (const double*)d_coef.p;
+    for (int a = 0; a < 3; ++a)
+        if (hipMemcpyAsync(h_coef + (size_t)a * mc, base + (size_t)a * coef_cap, mc * sizeof(double),
+                           hipMemcpyDeviceToHost, stream) != hipSuccess)
+            throw std::runtime_error("coefficient read-back failed");
+}
+
+template <typename V, typename W>
+krs_status SeqImpl<V, W>::end_solve(double* x, bool device_x, krs_solve_info* info, int iter_hint) {
     const SysView<V, W> v = cur;
     k_resid(v, 1);
     KRS_CHECK_LAUNCH();
+    // with the final iteration count known, the coefficients come back with
+    // the state (one wait); otherwise after it
+    const int mc_pre = iter_hint >= 0 ? std::min(iter_hint + 1, coef_cap) : -1;
+    if (mc_pre > 0) coef_readback(mc_pre);
     KRS_HIP(hipEventRecord(ev[2], stream));
     KRS_HIP(hipMemcpyAsync(h_st, d_st.p, sizeof(DevState), hipMemcpyDeviceToHost, stream));
     if (x) {
@@ -792,21 +820,12 @@ krs_status SeqImpl<V, W>::end_solve(double* x, bool device_x, krs_solve_info* in
     coef_rho.assign(mc, 0.0);
     coef_gamma.assign(mc, 0.0);
     if (mc > 0) {
-        // the three coefficient runs through pinned staging: one wait
-        // instead of a blocking copy each (a batch ends hundreds of solves)
-        if (h_coef_cap < 3 * (size_t)mc) {
-            if (h_coef) (void)hipHostFree(h_coef);
-            h_coef = nullptr;
-            h_coef_cap = 0;
-            const size_t want = 3 * (size_t)std::min(coef_cap, std::max(mc, 2 * mc));
-            KRS_HIP(hipHostMalloc((void**)&h_coef, want * sizeof(double), hipHostMallocDefault));
-            h_coef_cap = want;
+        // the three coefficient runs come through pinned staging (a batch
+        // ends hundreds of solves: no blocking copy each)
+        if (mc != mc_pre) {
+            coef_readback(mc);
+            KRS_HIP(hipStreamSynchronize(stream));
         }
-        const double* base = (const double*)d_coef.p;
-        for (int a = 0; a < 3; ++a)
-            KRS_HIP(hipMemcpyAsync(h_coef + (size_t)a * mc, base + (size_t)a * coef_cap, mc * sizeof(double),
-                                   hipMemcpyDeviceToHost, stream));
-        KRS_HIP(hipStreamSynchronize(stream));
         std::memcpy(coef_alpha.data(), h_coef, mc * sizeof(double));
         std::memcpy(coef_rho.data(), h_coef + mc, mc * sizeof(double));
         std::memcpy(coef_gamma.data(), h_coef + 2 * (size_t)mc, mc * sizeof(double));
@@ -1298,10 +1317,11 @@ krs_status batch_solve(krs_ctx* ctx, SeqBase* const* seqs, int count, double* co
                 if (th.joinable()) th.join();
         }
     } joiner{helpers};
+    std::vector<int> iter_of(count, -1);  // final iteration counts read from the status words
     auto end_member = [&](int i) {
         if (ended[i]) return;
         ended[i] = 1;
-        out[i] = seqs[i]->end_solve(x ? x[i] : nullptr, device_x, info ? &info[i] : nullptr);
+        out[i] = seqs[i]->end_solve(x ? x[i] : nullptr, device_x, info ? &info[i] : nullptr, iter_of[i]);
     };
     auto plan_members = [&](std::vector<int> idx) {
         std::vector<int> ok;
@@ -1362,6 +1382,7 @@ krs_status batch_solve(krs_ctx* ctx, SeqBase* const* seqs, int count, double* co
             for (size_t i = 0; i < act.size(); ++i) {
                 if (stat[2 * i + 1] != last[i]) progress = true;
                 if (finished_status(stat[2 * i])) {
+                    iter_of[act[i]] = stat[2 * i + 1];
                     if (rec && !ended[act[i]]) done_now.push_back(act[i]);
                     continue;
                 }

@@ -46,7 +46,10 @@ struct SeqBase {
     // solve() = begin_solve() + iterate() + end_solve(); a batch runs the
     // iterations of several begun systems in fused launches instead
     virtual krs_status begin_solve() = 0;
-    virtual krs_status end_solve(double* x, bool device_x, krs_solve_info* info) = 0;
+    // iter_hint: the solve's final iteration count when the caller has read
+    // it from the device status (lets the coefficient read-back start
+    // before the wait), or -1
+    virtual krs_status end_solve(double* x, bool device_x, krs_solve_info* info, int iter_hint = -1) = 0;
     virtual int type_key() const = 0;
     // device bytes a solve adds on top of the resident sequence (matrix,
     // vectors, basis): Krylov history, A C, staging and reduction scratch
@@ -138,7 +141,8 @@ struct SeqImpl : SeqBase {
     krs_status solve(double* x, bool device_x, krs_solve_info* info) override;
     krs_status begin_solve() override;
     krs_status iterate();
-    krs_status end_solve(double* x, bool device_x, krs_solve_info* info) override;
+    krs_status end_solve(double* x, bool device_x, krs_solve_info* info, int iter_hint = -1) override;
+    void coef_readback(int mc);  // enqueue the copies of the first mc CG coefficients into h_coef
     int type_key() const override;
     krs_status tune_update();
     int64_t working_bytes() const override;

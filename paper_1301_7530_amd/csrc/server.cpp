@@ -286,9 +286,14 @@ void krs_server::serve() {
                 auto& mem = members[kv.first];
                 std::vector<Active> keep, fin;
                 const int batch = (int)mem.size();
+                std::vector<int> fin_iter;  // their final iteration counts
                 for (size_t i = 0; i < mem.size(); ++i) {
-                    if (krs::finished_status(stat[2 * i])) fin.push_back(std::move(mem[i]));
-                    else keep.push_back(std::move(mem[i]));
+                    if (krs::finished_status(stat[2 * i])) {
+                        fin.push_back(std::move(mem[i]));
+                        fin_iter.push_back(stat[2 * i + 1]);
+                    } else {
+                        keep.push_back(std::move(mem[i]));
+                    }
                 }
                 const bool changed = !fin.empty();
                 if (changed) {
@@ -302,7 +307,8 @@ void krs_server::serve() {
                     p->msgs.resize(nf);
                     for (size_t i = 0; i < nf; ++i) {
                         std::memset(&p->infos[i], 0, sizeof p->infos[i]);
-                        p->sts[i] = p->fin[i].req.impl->end_solve(p->fin[i].req.x_out, false, &p->infos[i]);
+                        p->sts[i] =
+                            p->fin[i].req.impl->end_solve(p->fin[i].req.x_out, false, &p->infos[i], fin_iter[i]);
                         if (p->sts[i] != KRS_OK) p->msgs[i] = krs_last_error();
                         if (p->sts[i] == KRS_OK || p->sts[i] == KRS_E_MAXIT) {
                             p->rec.push_back(p->fin[i].req.impl);
