@@ -101,6 +101,34 @@ def test_batch_equals_alone_bitwise(gpu, precision, reuse):
             assert _relres(seqs[i].csr(k), rb["x"]) <= 1e-8
 
 
+@pytest.mark.parametrize("precision,reuse,cap", [("fp64", "selective", 3), ("mixed", "total", 4)])
+def test_batch_few_columns_equals_alone_bitwise(gpu, precision, reuse, cap):
+    """Members with one to four basis columns take the batch's light
+    direction-update kernel (no basis: its column-free instance); the single
+    solve takes the general one.  Both add the column products in the same
+    order, so every result is still identical bit for bit."""
+    n_sys = 3
+    seqs = _sequences(n_sys)
+    kw = dict(precision=precision, reuse=reuse, tol=1e-8, max_iter=3000, max_basis=cap, cap_policy="freeze",
+              ritz_eps=1e-8, history_cap=400)
+    print(f"batch vs alone, few columns: {precision} {reuse} cap {cap}", flush=True)
+    a = _alone(gpu, seqs, n_sys, **kw)
+    b = _batched(gpu, seqs, n_sys, **kw)
+    widths = set()
+    for i in range(len(seqs)):
+        for k in range(n_sys):
+            ra, rb = a[i][k], b[i][k]
+            assert ra["status"] == rb["status"] == 0, (i, k, ra["status"], rb["status"])
+            assert ra["iters"] == rb["iters"] and ra["n_c"] == rb["n_c"], (i, k)
+            assert np.array_equal(ra["x"], rb["x"]), (i, k)
+            for ca, cb in zip(ra["coef"], rb["coef"]):
+                assert np.array_equal(ca, cb)
+            assert np.array_equal(ra["C"], rb["C"])
+            assert _relres(seqs[i].csr(k), rb["x"]) <= 1e-8
+            widths.add(rb["n_c"])
+    assert 0 in widths and any(1 <= w <= 4 for w in widths), widths
+
+
 def _batched_solve_recycle(ctx, seqs, n_systems, **kw):
     import torch
 
