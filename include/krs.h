@@ -42,7 +42,7 @@ typedef enum {
     KRS_E_COARSE_SINGULAR = 4, /* every basis column was rejected by the rank guard */
     KRS_E_MAXIT = 5,           /* max_iter reached; krs_solve_info is still filled */
     KRS_E_DEVICE = 6,          /* HIP runtime error */
-    KRS_E_BUSY = 7,            /* resource temporarily unavailable (server queue full) */
+    KRS_E_BUSY = 7,            /* resource temporarily unavailable (server queue full, sequence held by a server) */
     KRS_E_STATE = 8            /* call not valid in the object's current state */
 } krs_status;
 
