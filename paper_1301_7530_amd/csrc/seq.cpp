@@ -66,7 +66,10 @@ bool Buf::grow_keep(krs_ctx* ctx, size_t nbytes, hipStream_t stream) {
             dev_free(ctx, q, nbytes);
             return false;
         }
-        if (hipStreamSynchronize(stream) != hipSuccess) return false;
+        if (hipStreamSynchronize(stream) != hipSuccess) {
+            dev_free(ctx, q, nbytes);
+            return false;
+        }
     }
     release(ctx);
     p = q;
