@@ -198,6 +198,12 @@ krs_status SeqImpl<V, W>::create(const krs_seq_desc& d, const double* C0, int32_
         set_error("device allocation failed while creating the sequence");
         return KRS_E_OOM;
     }
+    // the uploads below read these host vectors: every way out of this
+    // function waits for the stream before they are destroyed
+    struct WaitOnExit {
+        hipStream_t s;
+        ~WaitOnExit() { (void)hipStreamSynchronize(s); }
+    } wait_on_exit{stream};
     KRS_HIP(hipMemcpyAsync(d_col.p, col.data(), col.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
     KRS_HIP(hipMemcpyAsync(d_slice_ptr.p, slice_ptr.data(), slice_ptr.size() * sizeof(int64_t), hipMemcpyHostToDevice,
                            stream));
@@ -488,10 +494,12 @@ krs_status SeqImpl<V, W>::rebuild(int* dropped) {
     *dropped = 0;
     if (nc == 0) return KRS_OK;
     std::vector<double> G;
+    // source of an asynchronous upload: lives until the next pass has waited
+    std::vector<double> U;
     krs_status st = coarse_pass(G);
     if (st != KRS_OK) return st;
     {
-        std::vector<double> U((size_t)nc * nc);
+        U.assign((size_t)nc * nc, 0.0);
         std::vector<uint8_t> kept(nc, 1);
         const int nk = coarse_orthonormalizer(nc, G.data(), desc.rank_tol, U.data(), kept.data());
         *dropped += nc - nk;
