@@ -432,8 +432,8 @@ def main():
     if args.precision is None:
         args.precision = {"batched": "mixed", "diffusion20": "fp64"}.get(args.workload, "fp32basis")
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "multi-GPU sharding is not implemented", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); "
+              "sharding across GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
     if int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: one process / one GPU only", file=sys.stderr)
