@@ -45,21 +45,21 @@ HBM_PEAK = 8.0e12  # MI355X HBM3E, bytes/s
 TRAFFIC_K1 = {("elasticity40", "fp32basis"): 146268827}
 
 WORKLOADS = {
-    "elasticity40": dict(kind="elasticity", size=40, n_systems=20, config_id=2, max_basis=60, eps=1e-8),
+    "elasticity40": dict(kind="elasticity", size=40, n_systems=20, workload_id=2, max_basis=60, eps=1e-8),
     # the whole Krylov run is kept (16000 x 3.06 M single-precision vectors,
     # 196 GB): with a shorter history only the top of the spectrum stagnates
-    "elasticity100": dict(kind="elasticity", size=100, n_systems=30, config_id=3, max_basis=200, eps=1e-8,
+    "elasticity100": dict(kind="elasticity", size=100, n_systems=30, workload_id=3, max_basis=200, eps=1e-8,
                           history_cap=16000),
-    "diffusion20": dict(kind="diffusion", size=(20, 20, 20), n_systems=8, config_id=1, max_basis=0, eps=1e-14),
+    "diffusion20": dict(kind="diffusion", size=(20, 20, 20), n_systems=8, workload_id=1, max_basis=0, eps=1e-14),
     # many independent diffusion sequences (n ~ U[5e3, 2e5]) solved in fused launches
     # fused launches use wide update tiles (fewer, longer workgroups per
     # system); the one-at-a-time comparison keeps the default tile
-    "batched": dict(kind="batched", size=None, n_systems=10, config_id=4, max_basis=60, eps=1e-8, cap_policy="cost",
+    "batched": dict(kind="batched", size=None, n_systems=10, workload_id=4, max_basis=60, eps=1e-8, cap_policy="cost",
                     update_rows=4096),
     # clients with elasticity sequences (1e4..5e5 dofs) served with continuous batching
-    "serving": dict(kind="serving", size=None, n_systems=50, config_id=5, max_basis=200, eps=1e-8),
+    "serving": dict(kind="serving", size=None, n_systems=50, workload_id=5, max_basis=200, eps=1e-8),
     # calibration for hardware byte counters: device-to-device copies of a known size
-    "copy": dict(kind="copy", size=None, n_systems=0, config_id=0, max_basis=0, eps=0.0),
+    "copy": dict(kind="copy", size=None, n_systems=0, workload_id=0, max_basis=0, eps=0.0),
 }
 
 
@@ -469,7 +469,7 @@ def main():
         run_serving(args, K, torch, serving_data)
         return
     wl = WORKLOADS[args.workload]
-    seq = gen.make_sequence(wl["kind"], wl["size"], wl["n_systems"], wl["config_id"])
+    seq = gen.make_sequence(wl["kind"], wl["size"], wl["n_systems"], wl["workload_id"])
     total = args.warmup + args.steps
     order = [k % wl["n_systems"] for k in range(total)]
     _log(f"workload {args.workload}: n={seq.n} nnzb={seq.nnzb} block={seq.block}; generating {min(total, wl['n_systems'])} systems")

@@ -137,7 +137,7 @@ def test_elasticity100_sampled(gpu):
     the true residual of both solutions with the oracle's SpMV, and fewer
     iterations for the second system with the recycled basis."""
     K = _K()
-    seq = gen.config_elasticity(100, 2, config_id=3)
+    seq = gen.config_elasticity(100, 2, workload_id=3)
     print("elasticity 100^3: n", seq.n, flush=True)
     s = K.sequence_for(gpu, seq, precision="fp32basis", reuse="selective", ritz_eps=1e-8, max_basis=200,
                        cap_policy="freeze", tol=1e-8, max_iter=30000, history_cap=16000)
