@@ -342,21 +342,16 @@ krs_status krs_ritz_select(const double* alpha, const double* rho, int32_t m, do
         set_error("alpha and rho are required");
         return KRS_E_INVALID;
     }
-    std::vector<double> d(m), l2(m > 0 ? m - 1 : 0);
     for (int j = 0; j < m; ++j) {
         if (!(alpha[j] > 0.0) || !(rho[j] > 0.0)) {
             set_error("alpha and rho must be positive");
             return KRS_E_INVALID;
         }
-        d[j] = 1.0 / alpha[j];
     }
-    for (int j = 0; j + 1 < m; ++j) l2[j] = rho[j + 1] / rho[j];
+    const krs::QdArray z = krs::qd_from_cg(alpha, rho, m);
     std::vector<double> th, th1;
-    krs::ldl_eigenvalues(d, l2, th, 8);
-    if (m > 1) {
-        std::vector<double> d1(d.begin(), d.end() - 1), l21(l2.begin(), l2.begin() + (m - 2));
-        krs::ldl_eigenvalues(d1, l21, th1, 8);
-    }
+    krs::qd_eigenvalues_desc(z, th, 8);
+    if (m > 1) krs::qd_eigenvalues_desc(krs::qd_leading(z, m - 1), th1, 8);
     std::vector<int> sel = krs::stagnation_select(th, th1, eps);
     for (int i = 0; i < m; ++i) {
         if (theta) theta[i] = th[i];

@@ -235,17 +235,23 @@ template <typename V, typename W>
 void batch_status(const SysView<V, W>* views, int count, int32_t* out, hipStream_t stream);
 
 // ----------------------------------------------------------- host logic
-// Tridiagonal eigenvalues of H = L D L^T (d_j = 1/alpha_j, l_j^2 = beta_{j+1}),
-// descending, high relative accuracy (ritz.cpp).
-void ldl_eigenvalues(const std::vector<double>& d, const std::vector<double>& l2, std::vector<double>& theta,
-                     int threads);
-// Ascending eigenvalues k0..k1-1 (0 = smallest) of L D L^T into asc[k].
-void ldl_eigenvalues_range(const std::vector<double>& d, const std::vector<double>& l2, int k0, int k1,
-                           double* asc, int threads);
-// Number of eigenvalues of L D L^T below sigma.
-int ldl_count_below(const std::vector<double>& d, const std::vector<double>& l2, double sigma);
-// Whether L D L^T has an eigenvalue in [lo, hi]; l2d[i] = l2[i] * d[i].
-bool ldl_has_eigenvalue_in(const std::vector<double>& d, const std::vector<double>& l2d, double lo, double hi);
+// qd array of the Lanczos tridiagonal H_m = R^T R of the CG coefficients
+// (Section 4.1): q_j = R_jj^2 = 1/alpha_j, e_j = R_{j,j+1}^2 =
+// (rho_{j+1}/rho_j)/alpha_j.  The leading (m-1) x (m-1) block H_{m-1} is
+// the array cut to q[0..m-2], e[0..m-3] (ritz.cpp).
+struct QdArray {
+    std::vector<double> q, e;
+};
+QdArray qd_from_cg(const double* alpha, const double* rho, int m);
+QdArray qd_leading(const QdArray& z, int m1);
+// Number of eigenvalues below sigma (high relative accuracy).
+int qd_count_below(const QdArray& z, double sigma);
+// Whether the array has an eigenvalue in [lo, hi].
+bool qd_has_eigenvalue_in(const QdArray& z, double lo, double hi);
+// Eigenvalues of ascending ranks k0..k1-1 (0 = smallest) into out[k].
+void qd_eigenvalues_asc(const QdArray& z, int k0, int k1, double* out, int threads);
+// Every eigenvalue, descending.
+void qd_eigenvalues_desc(const QdArray& z, std::vector<double>& theta, int threads);
 // Eigenvector (unit 2-norm) of the explicit tridiagonal (diag, off) for eigenvalue theta.
 void tridiag_eigvec(const std::vector<double>& diag, const std::vector<double>& off, double theta,
                     std::vector<double>& v);

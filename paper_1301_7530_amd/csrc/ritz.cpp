@@ -1,16 +1,25 @@
 // Host-side Ritz analysis for selective reuse (Section 4.1 and 4.4).
 //
-// The Lanczos tridiagonal recovered from the CG coefficients is factored as
-// H_m = L D L^T with d_j = 1/alpha_j and l_j^2 = beta_{j+1} = rho_{j+1}/rho_j
-// (expanding L D L^T gives delta_j = d_j + l_{j-1}^2 d_{j-1} and
-// eta_j = l_j d_j, the entries of Section 4.1).  Eigenvalues are obtained by
-// bisection on the inertia of L D L^T - sigma I computed with the stationary
-// qd transform, which keeps high relative accuracy for the small Ritz values
-// that the 1e-14 stagnation test must resolve.  Eigenvectors of the few
-// selected values come from a twisted factorisation of T - theta I.
+// The Lanczos tridiagonal recovered from the CG coefficients is positive
+// definite and factors as H_m = R^T R with R upper bidiagonal,
+//   R_jj^2 = q_j = 1/alpha_j,   R_{j,j+1}^2 = e_j = beta_{j+1}/alpha_j,
+// beta_{j+1} = rho_{j+1}/rho_j (expanding R^T R gives the diagonal
+// q_j + e_{j-1} and the off-diagonal sqrt(q_j e_j) of Section 4.1).  The
+// pair (q, e) is the qd array of H_m; it determines the eigenvalues to high
+// relative accuracy, which the stagnation test needs for the small Ritz
+// values.  Eigenvalues are counted with the progressive differential qd
+// transform of R R^T - sigma I (same spectrum as R^T R): its pivots are the
+// LDL^T pivots of R R^T - sigma I, so by Sylvester's law of inertia the
+// number of negative pivots is the number of eigenvalues below sigma.
+// Ranks are isolated by splitting intervals whose end counts are known
+// (geometric midpoints once an interval is away from zero, so small values
+// converge in relative terms) and refined to adjacent doubles.  Eigenvectors
+// of the few selected values come from a twisted factorisation of
+// T - theta I.
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
+#include <limits>
 #include <thread>
 #include <vector>
 
@@ -20,68 +29,118 @@ namespace krs {
 
 namespace {
 
-// number of eigenvalues of L D L^T strictly below sigma
-inline int inertia_below(int m, const double* d, const double* l2d, double sigma) {
+// Eigenvalues of the qd array (q[0..m-1], e[0..m-2]) strictly below sigma.
+int pqd_negatives(const double* q, const double* e, int m, double sigma) {
+    if (m <= 0) return 0;
     int neg = 0;
-    double t = -sigma;
-    for (int i = 0; i < m; ++i) {
-        double piv = d[i] + t;
-        if (piv == 0.0) piv = -DBL_EPSILON * (std::fabs(d[i]) + std::fabs(t)) - DBL_MIN;
+    double d = q[0] - sigma;
+    for (int i = 0; i + 1 < m; ++i) {
+        double piv = d + e[i];
+        // a pivot that is exactly zero is taken as the smallest negative
+        // number (the count of a sigma perturbed by less than an ulp); the
+        // next pivot then overflows to +inf, whose limit is handled below
+        if (piv == 0.0) piv = -std::numeric_limits<double>::denorm_min();
         neg += piv < 0.0;
-        if (i + 1 < m) t = (l2d[i] / piv) * t - sigma;
+        d = std::isinf(piv) ? q[i + 1] - sigma : d * (q[i + 1] / piv) - sigma;
     }
+    neg += d < 0.0;
     return neg;
 }
 
-void bisect_range(int m, const double* d, const double* l2d, double lo, double hi, int k0, int k1, double* out) {
-    for (int k = k0; k < k1; ++k) {
-        double a = lo, b = hi;
-        while (true) {
-            const double mid = 0.5 * (a + b);
-            if (!(mid > a && mid < b)) break;
-            if (inertia_below(m, d, l2d, mid) <= k) a = mid;
-            else b = mid;
+// Upper bound of the spectrum: Gershgorin discs of R R^T, whose diagonal is
+// q_i + e_i and off-diagonal sqrt(e_i q_{i+1}); widened until every
+// eigenvalue counts below it.
+double qd_upper(const double* q, const double* e, int m) {
+    double hi = 0.0;
+    for (int i = 0; i < m; ++i) {
+        const double ei = (i + 1 < m) ? e[i] : 0.0;
+        double r = q[i] + ei;
+        if (i > 0) r += std::sqrt(e[i - 1] * q[i]);
+        if (i + 1 < m) r += std::sqrt(ei * q[i + 1]);
+        hi = std::max(hi, r);
+    }
+    hi = hi * (1.0 + 16.0 * DBL_EPSILON) + DBL_MIN;
+    for (int t = 0; t < 64 && pqd_negatives(q, e, m, hi) < m; ++t) hi *= 2.0;
+    return hi;
+}
+
+inline double split_point(double a, double b) {
+    // geometric midpoint while the interval spans more than a factor 2 away
+    // from zero (relative convergence of small values), arithmetic otherwise
+    if (a > 0.0 && b > 2.0 * a) return std::sqrt(a) * std::sqrt(b);
+    return a + 0.5 * (b - a);
+}
+
+// Eigenvalues of ascending ranks k0..k1-1 into out[k] (absolute index).
+void rank_range(const double* q, const double* e, int m, double hi, int k0, int k1, double* out) {
+    struct Interval {
+        double a, b;
+        int below_a, below_b;  // eigenvalues below a, below b: ranks [below_a, below_b) lie in [a, b)
+    };
+    std::vector<Interval> work;
+    work.push_back({0.0, hi, 0, m});
+    while (!work.empty()) {
+        const Interval iv = work.back();
+        work.pop_back();
+        if (iv.below_b <= k0 || iv.below_a >= k1 || iv.below_b == iv.below_a) continue;
+        const double mid = split_point(iv.a, iv.b);
+        if (!(mid > iv.a && mid < iv.b)) {
+            // adjacent doubles: every rank inside takes the interval's centre
+            const double v = iv.a + 0.5 * (iv.b - iv.a);
+            for (int k = std::max(iv.below_a, k0); k < std::min(iv.below_b, k1); ++k) out[k] = v;
+            continue;
         }
-        out[k] = 0.5 * (a + b);
+        const int c = std::min(std::max(pqd_negatives(q, e, m, mid), iv.below_a), iv.below_b);
+        work.push_back({mid, iv.b, c, iv.below_b});
+        work.push_back({iv.a, mid, iv.below_a, c});
     }
 }
 
 }  // namespace
 
-// Gershgorin interval of the explicit tridiagonal of L D L^T.
-static void ldl_bounds(const std::vector<double>& d, const std::vector<double>& l2, const std::vector<double>& l2d,
-                       double& lo, double& hi) {
-    const int m = (int)d.size();
-    lo = 0.0;
-    hi = 0.0;
-    for (int i = 0; i < m; ++i) {
-        const double diag = d[i] + (i > 0 ? l2d[i - 1] : 0.0);
-        double off = 0.0;
-        if (i > 0) off += std::sqrt(l2[i - 1]) * std::fabs(d[i - 1]);
-        if (i + 1 < m) off += std::sqrt(l2[i]) * std::fabs(d[i]);
-        if (i == 0 || diag - off < lo) lo = diag - off;
-        if (i == 0 || diag + off > hi) hi = diag + off;
-    }
-    lo = std::min(lo, 0.0);
-    hi = hi * (1.0 + 4.0 * DBL_EPSILON) + DBL_MIN;
+QdArray qd_from_cg(const double* alpha, const double* rho, int m) {
+    QdArray z;
+    z.q.resize(std::max(m, 0));
+    z.e.resize(std::max(m - 1, 0));
+    for (int j = 0; j < m; ++j) z.q[j] = 1.0 / alpha[j];
+    for (int j = 0; j + 1 < m; ++j) z.e[j] = (rho[j + 1] / rho[j]) * z.q[j];
+    return z;
 }
 
-void ldl_eigenvalues_range(const std::vector<double>& d, const std::vector<double>& l2, int k0, int k1,
-                           double* asc, int threads) {
-    const int m = (int)d.size();
-    if (k1 > m) k1 = m;
+QdArray qd_leading(const QdArray& z, int m1) {
+    QdArray t;
+    m1 = std::max(0, std::min(m1, (int)z.q.size()));
+    t.q.assign(z.q.begin(), z.q.begin() + m1);
+    t.e.assign(z.e.begin(), z.e.begin() + std::max(m1 - 1, 0));
+    return t;
+}
+
+int qd_count_below(const QdArray& z, double sigma) {
+    return pqd_negatives(z.q.data(), z.e.data(), (int)z.q.size(), sigma);
+}
+
+bool qd_has_eigenvalue_in(const QdArray& z, double lo, double hi) {
+    const int m = (int)z.q.size();
+    if (m == 0) return false;
+    return pqd_negatives(z.q.data(), z.e.data(), m, std::nextafter(hi, INFINITY)) >
+           pqd_negatives(z.q.data(), z.e.data(), m, lo);
+}
+
+void qd_eigenvalues_asc(const QdArray& z, int k0, int k1, double* out, int threads) {
+    const int m = (int)z.q.size();
+    k1 = std::min(k1, m);
+    k0 = std::max(k0, 0);
     if (k0 >= k1) return;
-    std::vector<double> l2d(m, 0.0);
-    for (int i = 0; i + 1 < m; ++i) l2d[i] = l2[i] * d[i];
-    double lo, hi;
-    ldl_bounds(d, l2, l2d, lo, hi);
+    const double* q = z.q.data();
+    const double* e = z.e.data();
+    const double hi = qd_upper(q, e, m);
     const int cnt = k1 - k0;
-    const int nt = std::max(1, std::min(threads, cnt / 4 + 1));
+    const int nt = std::max(1, std::min(threads, cnt / 8 + 1));
     if (nt == 1) {
-        bisect_range(m, d.data(), l2d.data(), lo, hi, k0, k1, asc);
+        rank_range(q, e, m, hi, k0, k1, out);
         return;
     }
-    // ranges whose thread cannot be started are bisected on this thread
+    // rank chunks on threads; a chunk whose thread cannot start runs here
     std::vector<std::thread> pool;
     try {
         pool.reserve(nt);
@@ -91,38 +150,21 @@ void ldl_eigenvalues_range(const std::vector<double>& d, const std::vector<doubl
         const int a = k0 + (int)((int64_t)cnt * t / nt), b = k0 + (int)((int64_t)cnt * (t + 1) / nt);
         bool started = false;
         try {
-            pool.emplace_back(bisect_range, m, d.data(), l2d.data(), lo, hi, a, b, asc);
+            pool.emplace_back(rank_range, q, e, m, hi, a, b, out);
             started = true;
         } catch (...) {
         }
-        if (!started) bisect_range(m, d.data(), l2d.data(), lo, hi, a, b, asc);
+        if (!started) rank_range(q, e, m, hi, a, b, out);
     }
     for (auto& th : pool) th.join();
 }
 
-int ldl_count_below(const std::vector<double>& d, const std::vector<double>& l2, double sigma) {
-    const int m = (int)d.size();
-    if (m == 0) return 0;
-    std::vector<double> l2d(m, 0.0);
-    for (int i = 0; i + 1 < m; ++i) l2d[i] = l2[i] * d[i];
-    return inertia_below(m, d.data(), l2d.data(), sigma);
-}
-
-bool ldl_has_eigenvalue_in(const std::vector<double>& d, const std::vector<double>& l2d, double lo, double hi) {
-    const int m = (int)d.size();
-    if (m == 0) return false;
-    // eigenvalues in [lo, hi]: count below the next double above hi, minus count below lo
-    return inertia_below(m, d.data(), l2d.data(), std::nextafter(hi, INFINITY)) >
-           inertia_below(m, d.data(), l2d.data(), lo);
-}
-
-void ldl_eigenvalues(const std::vector<double>& d, const std::vector<double>& l2, std::vector<double>& theta,
-                     int threads) {
-    const int m = (int)d.size();
+void qd_eigenvalues_desc(const QdArray& z, std::vector<double>& theta, int threads) {
+    const int m = (int)z.q.size();
     theta.assign(m, 0.0);
     if (m == 0) return;
     std::vector<double> asc(m);
-    ldl_eigenvalues_range(d, l2, 0, m, asc.data(), threads);
+    qd_eigenvalues_asc(z, 0, m, asc.data(), threads);
     for (int k = 0; k < m; ++k) theta[m - 1 - k] = asc[k];
 }
 

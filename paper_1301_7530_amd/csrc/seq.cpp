@@ -963,19 +963,17 @@ krs_status SeqImpl<V, W>::recycle_plan() {
         // before the first direction restart (after it H_m is block diagonal)
         const int mu = std::min(std::min(m, hist), h_st->first_restart);
         if (mu > 1) {
-            std::vector<double> dd(mu), l2(mu - 1);
-            for (int j = 0; j < mu; ++j) dd[j] = 1.0 / coef_alpha[j];
-            for (int j = 0; j + 1 < mu; ++j) l2[j] = coef_rho[j + 1] / coef_rho[j];
-            std::vector<double> d1(dd.begin(), dd.end() - 1);
-            std::vector<double> l21(l2.begin(), l2.begin() + (mu - 2));
+            // H_mu and its leading block H_{mu-1} as qd arrays (Section 4.1)
+            const QdArray zm = qd_from_cg(coef_alpha.data(), coef_rho.data(), mu);
+            const QdArray zm1 = qd_leading(zm, mu - 1);
             const int nt = recycle_threads > 0 ? recycle_threads : host_threads();
             const bool frozen = capped;
             std::vector<double> th_m(mu, 0.0);  // descending (Algorithm 3 order)
             std::vector<int> sel;               // descending indices, ascending order
             if (!frozen) {
                 std::vector<double> th_m1;
-                ldl_eigenvalues(dd, l2, th_m, nt);
-                ldl_eigenvalues(d1, l21, th_m1, nt);
+                qd_eigenvalues_desc(zm, th_m, nt);
+                qd_eigenvalues_desc(zm1, th_m1, nt);
                 sel = stagnation_select(th_m, th_m1, desc.ritz_eps);
                 last_theta = th_m;
                 last_sel.assign(mu, 0);
@@ -994,8 +992,6 @@ krs_status SeqImpl<V, W>::recycle_plan() {
                 // inertia counts instead of bisecting H_{m-1}'s spectrum.
                 const int room = std::max(0, desc.max_basis - nc);
                 std::vector<double> a(mu);
-                std::vector<double> l21d(mu - 1, 0.0);
-                for (int i = 0; i + 1 < mu - 1; ++i) l21d[i] = l21[i] * d1[i];
                 std::vector<int> sel_asc;
                 bool have_cut = false, stop = false;
                 double cut = 0.0;
@@ -1003,14 +999,14 @@ krs_status SeqImpl<V, W>::recycle_plan() {
                 const int CH = 128;
                 while (k < mu && !stop) {
                     const int k1 = std::min(mu, k + CH);
-                    ldl_eigenvalues_range(dd, l2, k, k1, a.data(), nt);
+                    qd_eigenvalues_asc(zm, k, k1, a.data(), nt);
                     for (int kk = k; kk < k1; ++kk) {
                         if (have_cut && a[kk] > cut) {
                             stop = true;
                             break;
                         }
                         const double e = desc.ritz_eps * std::fabs(a[kk]);
-                        if (ldl_has_eigenvalue_in(d1, l21d, a[kk] - e, a[kk] + e)) {
+                        if (qd_has_eigenvalue_in(zm1, a[kk] - e, a[kk] + e)) {
                             sel_asc.push_back(kk);
                             if (!have_cut && (int)sel_asc.size() >= room) {
                                 have_cut = true;
@@ -1044,10 +1040,12 @@ krs_status SeqImpl<V, W>::recycle_plan() {
             sel.resize(std::min<size_t>(sel.size(), (size_t)std::max(0, 1024 - nc)));
             const int s = (int)sel.size();
             if (s > 0) {
-                // F[j, t] = (-1)^j q_t[j] / (sqrt(rho_j) sqrt|theta_t|)
+                // F[j, t] = (-1)^j q_t[j] / (sqrt(rho_j) sqrt|theta_t|); the
+                // explicit tridiagonal R^T R: diagonal q_j + e_{j-1},
+                // off-diagonal sqrt(q_j e_j)
                 std::vector<double> diag(mu), off(mu - 1);
-                for (int j = 0; j < mu; ++j) diag[j] = dd[j] + (j > 0 ? l2[j - 1] * dd[j - 1] : 0.0);
-                for (int j = 0; j + 1 < mu; ++j) off[j] = std::sqrt(l2[j]) * dd[j];
+                for (int j = 0; j < mu; ++j) diag[j] = zm.q[j] + (j > 0 ? zm.e[j - 1] : 0.0);
+                for (int j = 0; j + 1 < mu; ++j) off[j] = std::sqrt(zm.q[j] * zm.e[j]);
                 std::vector<double>& F = h_F;  // kept alive: the copy in the apply step is asynchronous
                 F.assign((size_t)mu * s, 0.0);
                 std::vector<double> q;

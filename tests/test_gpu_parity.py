@@ -12,6 +12,7 @@ import pytest
 
 import gen
 import oracle as O
+from ritz_compare import assert_ritz_close, selection_flips
 
 pytestmark = pytest.mark.gpu
 
@@ -123,10 +124,13 @@ def test_srks_elasticity_sequence_fp64(gpu):
                 # fill it are computed: compare that (descending) tail
                 th_o, th_o1 = O.ritz_values(alpha, rho)
                 L = len(th_gpu)
-                assert np.array_equal(th_gpu, th_o[len(th_o) - L:])
+                assert_ritz_close(th_gpu, th_o[len(th_o) - L:])
                 sel_o = np.zeros(len(th_o), dtype=bool)
                 sel_o[O.srks_select(th_o, th_o1, eps)] = True
-                assert np.array_equal(sel_gpu, sel_o[len(th_o) - L:])
+                off = len(th_o) - L
+                flips = selection_flips(np.nonzero(sel_gpu)[0] + off, np.nonzero(sel_o[off:])[0] + off,
+                                        th_o, th_o1, eps)
+                assert len(flips) <= 2, (k, flips)
             if added:
                 C_out = s.basis()
                 new_gpu = C_out[:, C_out.shape[1] - added:]
