@@ -80,8 +80,8 @@ typedef enum { KRS_CAP_RESTART = 0, KRS_CAP_FREEZE = 1, KRS_CAP_COST = 2 } krs_c
  *   compared with those of the latest solve made with the initial basis
  *   alone; when the recycled columns did not lower them, the basis is reset
  *   to C0 and nothing is appended for the next three systems, six after a
- *   second failed trial in a row, and so on up to 48 (the limit "set after a
- *   complexity analysis" of Section 4.4). */
+ *   second failed trial in a row, and so on up to 48.  An extension: it
+ *   judges the basis after the fact from the measured iteration counts. */
 
 typedef struct krs_ctx krs_ctx;
 typedef struct krs_seq krs_seq;
@@ -129,7 +129,12 @@ typedef struct {
                               choice in the last bits only) */
     int32_t kernel_flags;  /* bit 0: run the end-of-step reduction (coarse solve, beta, status) as a
                               kernel of its own instead of in the last workgroup of the update kernel;
-                              same arithmetic, one more launch per iteration */
+                              same arithmetic, one more launch per iteration.
+                              bit 1: form the next direction as Algorithm 1 writes it, w = z + beta w_old,
+                              instead of the default w = z + beta P w_old, which applies the projector
+                              P = I - C G^-1 (A C)^T to the old direction as well (the same vector in exact
+                              arithmetic, Section 2.1; the default keeps rounding from moving the direction
+                              out of the range of P, at no extra pass over memory) */
 } krs_seq_desc;
 
 typedef struct {
@@ -182,14 +187,20 @@ krs_status krs_seq_solve_device(krs_seq* s, double* d_x, krs_solve_info* info);
  * or SRKS Ritz selection (Algorithm 3), then the cap policy.  n_added may
  * be NULL. */
 krs_status krs_seq_recycle(krs_seq* s, int32_t* n_added);
-/* Ritz values of the last SRKS extraction (descending, m of them) and the
- * selection flags (1 = passed the stagnation test).  cap = array sizes. */
+/* Ritz values of the last SRKS extraction (Section 4.1: eigenvalues of the
+ * Lanczos tridiagonal built from the CG coefficients; descending, m of them)
+ * and the selection flags (1 = passed the stagnation test of Section 4.4,
+ * Algorithm 3).  cap = array sizes; with a capped basis only the part of
+ * the spectrum scanned to fill it is reported (m_out says how much). */
 krs_status krs_seq_ritz(krs_seq* s, double* theta, uint8_t* selected, int32_t cap, int32_t* m_out);
-/* CG coefficients of the last solve: alpha_j, rho_j = (r_j, z_j) and
+/* CG coefficients of the last solve (Algorithm 1; the Lanczos tridiagonal
+ * of Section 4.1 is built from them): alpha_j, rho_j = (r_j, z_j) and
  * gamma_j = (w_j, A w_j) for j < m.  Any pointer may be NULL. */
 krs_status krs_seq_coeffs(krs_seq* s, double* alpha, double* rho, double* gamma, int32_t cap, int32_t* m_out);
-/* Export the current basis (n x n_c, column-major, leading dim ldc) as
- * doubles; C may be NULL to query n_c only. */
+/* Export the current augmentation basis C^(k) of Algorithms 2 and 3 (n x
+ * n_c, column-major, leading dim ldc) as doubles; C may be NULL to query n_c
+ * only.  After a solve the columns are the A-orthonormalised ones (same
+ * span as the carried basis). */
 krs_status krs_seq_basis(krs_seq* s, double* C, int64_t ldc, int32_t cap, int32_t* n_c);
 krs_status krs_seq_info(krs_seq* s, krs_solve_info* info);
 /* Live kernel timing.  When enabled, every 32nd iteration the SpMV + (w, A w)

@@ -39,7 +39,7 @@ def lib():
         L.orc_apcg.restype = ctypes.c_int
         L.orc_apcg.argtypes = [ctypes.c_int64, _I64, _I32, _D, ctypes.c_int, _D, ctypes.c_int, ctypes.c_int64,
                                _D, ctypes.c_double, ctypes.c_int, ctypes.c_double, _D, _D, _D, _D, _D,
-                               _D, ctypes.c_int64, _D, ctypes.c_int64, _INT, _INT, _D]
+                               _D, ctypes.c_int64, _D, ctypes.c_int64, _INT, _INT, _D, ctypes.c_int]
         L.orc_apcg_alg1.restype = ctypes.c_int
         L.orc_apcg_alg1.argtypes = [ctypes.c_int64, _I64, _I32, _D, ctypes.c_int, _D, ctypes.c_int, ctypes.c_int64,
                                     _D, ctypes.c_int, ctypes.c_double, _D, _D, _D]
@@ -78,9 +78,17 @@ def spmv(row_ptr, col_idx, values, x):
     return y
 
 
+DIRECTION = {"literal": 0, "project_old": 1}
+
+
 def apcg(row_ptr, col_idx, values, b, precond="jacobi", C=None, tol=1e-8, max_iter=None, guard=1e-6,
-         record_z=False, record_w=False):
+         record_z=False, record_w=False, direction="literal", reorth=False):
     """One APCG(A, M, C, b) solve (Algorithm 1, standard form; see oracle.c).
+
+    ``direction``: 'literal' (w = z + beta w_old, Algorithm 1) or
+    'project_old' (w = z + beta P w_old, the same in exact arithmetic).
+    ``reorth``: full reorthogonalisation of every new direction against all
+    earlier ones (Section 2.1 remark; used in the experiments of Section 5.1).
 
     Returns a dict with x, m, status, alpha[m], gamma[m], rho[m] (rho_0..rho_{m-1}),
     resnorm[m+1], relres_true, kept (bool per column of C), and Z / W
@@ -108,7 +116,8 @@ def apcg(row_ptr, col_idx, values, b, precond="jacobi", C=None, tol=1e-8, max_it
     rel = ctypes.c_double(0.0)
     st = lib().orc_apcg(n, _p(rp, _I64), _p(ci, _I32), _p(v), PRECOND[precond], _p(Cf), nc, ldc, _p(b), tol,
                         max_iter, guard, _p(x), _p(alpha), _p(rho), _p(gamma), _p(resn), _p(Z), n, _p(W), n,
-                        _p(kept, _INT), ctypes.byref(m), ctypes.byref(rel))
+                        _p(kept, _INT), ctypes.byref(m), ctypes.byref(rel),
+                        DIRECTION[direction] | (2 if reorth else 0))
     if st in (ORC_INVALID, ORC_NOMEM):
         raise ValueError(f"oracle apcg failed with status {st}")
     m = m.value
@@ -122,7 +131,8 @@ def apcg(row_ptr, col_idx, values, b, precond="jacobi", C=None, tol=1e-8, max_it
 
 
 def apcg_alg1(row_ptr, col_idx, values, b, iters, precond="jacobi", C=None, guard=1e-6):
-    """Algorithm 1 in its printed Gram-Schmidt form; returns (x, alpha, bgs)."""
+    """APCG from its conjugacy conditions (the Gram-Schmidt form Algorithm 1
+    prints); returns (x, alpha, bgs) with bgs the Gram-Schmidt coefficients."""
     rp, ci, v = _csr(row_ptr, col_idx, values)
     b = np.ascontiguousarray(b, dtype=np.float64)
     n = len(b)

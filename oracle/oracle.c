@@ -242,6 +242,11 @@ static void project(const orc_coarse* K, const double* s, double* z, double* mu)
     }
 }
 
+/* Gram-Schmidt coefficient of direction i: out[i] = (A w_i, z) / (w_i, A w_i). */
+static void mu_h(const double* Qall, const double* gam, int64_t n, int i, const double* z, double* out) {
+    out[i] = orc_dot(n, Qall + (size_t)i * n, z) / gam[i];
+}
+
 /* ------------------------------------------------------------------ APCG */
 /*
  * APCG(A, M, C, b) — Algorithm 1 with the initialisation/projector pair of
@@ -266,11 +271,28 @@ static void project(const orc_coarse* K, const double* s, double* z, double* mu)
  *   when a further direction was formed); resn[j] = ||r_j||, j <= m;
  *   Z, W: columns j < m of z_j, w_j (leading dims ldz, ldw);
  *   kept[c] = 1 if column c survived the rank guard.
+ *
+ * opts (0 = the update above):
+ *   ORC_OPT_PROJECT_OLD: the next direction is z_{j+1} + beta P w_j, the
+ *     projector applied to the old direction too (P w_j = w_j in exact
+ *     arithmetic, so this is the same iteration; it is the library's
+ *     default form, kept here to measure what the difference does).
+ *   ORC_OPT_REORTH: full reorthogonalisation, which the paper states APCG
+ *     admits (Section 2.1) and uses in every experiment (Section 5.1): the
+ *     next direction is z_{j+1} made A-orthogonal to every earlier one,
+ *       w_{j+1} = z_{j+1} - sum_{i<=j} ((A w_i, z_{j+1}) / (w_i, A w_i)) w_i
+ *     (classical Gram-Schmidt in the A inner product over the stored w_i
+ *     and A w_i).  In exact arithmetic only the i = j term is nonzero and it
+ *     equals beta_{j+1} w_j.  rho and beta keep their definitions, so the
+ *     Lanczos coefficients of Section 4.1 are unchanged.
  */
+enum { ORC_OPT_PROJECT_OLD = 1, ORC_OPT_REORTH = 2 };
+
 int orc_apcg(int64_t n, const int64_t* rp, const int32_t* ci, const double* av, int precond,
              const double* C, int nc, int64_t ldc, const double* b, double tol, int max_iter, double guard,
              double* x, double* alpha, double* rho, double* gamma, double* resn,
-             double* Z, int64_t ldz, double* W, int64_t ldw, int* kept, int* m_out, double* relres_true) {
+             double* Z, int64_t ldz, double* W, int64_t ldw, int* kept, int* m_out, double* relres_true,
+             int opts) {
     if (n <= 0 || max_iter < 0 || (nc > 0 && (!C || ldc < n))) return ORC_INVALID;
     orc_prec P;
     int st = prec_setup(&P, precond, n, rp, ci, av);
@@ -285,7 +307,17 @@ int orc_apcg(int64_t n, const int64_t* rp, const int32_t* ci, const double* av, 
     double* w = (double*)malloc(sizeof(double) * (size_t)n);
     double* q = (double*)malloc(sizeof(double) * (size_t)n);
     double* mu = (double*)malloc(sizeof(double) * (size_t)(K.nk > 0 ? K.nk : 1));
-    if (!r || !s || !z || !w || !q || !mu) { st = ORC_NOMEM; goto out; }
+    /* every direction and its product with A, for the reorthogonalisation */
+    const int reorth = (opts & ORC_OPT_REORTH) != 0;
+    const size_t hcols = reorth ? (size_t)max_iter + 1 : 0;
+    double* Wall = reorth ? (double*)malloc(sizeof(double) * (size_t)n * hcols) : NULL;
+    double* Qall = reorth ? (double*)malloc(sizeof(double) * (size_t)n * hcols) : NULL;
+    double* gam = reorth ? (double*)malloc(sizeof(double) * hcols) : NULL;
+    double* gsc = reorth ? (double*)malloc(sizeof(double) * hcols) : NULL;
+    double* pw = (opts & ORC_OPT_PROJECT_OLD) ? (double*)malloc(sizeof(double) * (size_t)n) : NULL;
+    double* pmu = (opts & ORC_OPT_PROJECT_OLD) ? (double*)malloc(sizeof(double) * (size_t)(K.nk > 0 ? K.nk : 1)) : NULL;
+    if (!r || !s || !z || !w || !q || !mu || (reorth && (!Wall || !Qall || !gam || !gsc)) ||
+        ((opts & ORC_OPT_PROJECT_OLD) && (!pw || !pmu))) { st = ORC_NOMEM; goto out; }
 
     double bnorm = sqrt(orc_dot(n, b, b));
     /* initialisation: x0 = C G^{-1} C^T b, r0 = b - A C mu0 */
@@ -319,6 +351,11 @@ int orc_apcg(int64_t n, const int64_t* rp, const int32_t* ci, const double* av, 
         orc_spmv(n, rp, ci, av, w, q);
         double g = orc_dot(n, w, q);
         if (gamma) gamma[j] = g;
+        if (reorth) {
+            memcpy(Wall + (size_t)j * n, w, sizeof(double) * (size_t)n);
+            memcpy(Qall + (size_t)j * n, q, sizeof(double) * (size_t)n);
+            gam[j] = g;
+        }
         if (!(g > 0.0) || !(rh > 0.0)) { m = j; st = ORC_BREAKDOWN; goto done; }
         double a = rh / g;
         if (alpha) alpha[j] = a;
@@ -332,7 +369,22 @@ int orc_apcg(int64_t n, const int64_t* rp, const int32_t* ci, const double* av, 
         project(&K, s, z, mu);
         double rh_new = orc_dot(n, r, z);
         double be = rh_new / rh;
-        for (int64_t i = 0; i < n; ++i) w[i] = z[i] + be * w[i];
+        if (reorth) {
+            /* classical Gram-Schmidt in the A inner product: all the
+             * coefficients from z, then one update */
+            for (int i = 0; i <= j; ++i) mu_h(Qall, gam, n, i, z, gsc);
+            memcpy(w, z, sizeof(double) * (size_t)n);
+            for (int i = 0; i <= j; ++i) {
+                const double c = gsc[i];
+                const double* wi = Wall + (size_t)i * n;
+                for (int64_t t = 0; t < n; ++t) w[t] -= c * wi[t];
+            }
+        } else if (opts & ORC_OPT_PROJECT_OLD) {
+            project(&K, w, pw, pmu);
+            for (int64_t i = 0; i < n; ++i) w[i] = z[i] + be * pw[i];
+        } else {
+            for (int64_t i = 0; i < n; ++i) w[i] = z[i] + be * w[i];
+        }
         rh = rh_new;
         if (rho) rho[j + 1] = rh;
     }
@@ -346,19 +398,34 @@ done:
     if (m_out) *m_out = m;
 out:
     free(r); free(s); free(z); free(w); free(q); free(mu);
+    free(Wall); free(Qall); free(gam); free(gsc); free(pw); free(pmu);
     prec_free(&P);
     coarse_free(&K);
     return st;
 }
 
 /*
- * Algorithm 1 in its printed Gram–Schmidt form, for cross-checks on small
- * inputs: alpha_{j} = (r_j, w_j)/(A w_j, w_j), z_{j+1} = P M^{-1} r_{j+1}
- * (the printed index r_{j+1} is read as r_j of the new step), and
- * w_{j+1} = z_{j+1} - b_{j+1} w_j with b_{j+1} = (A w_j, z_{j+1})/(w_j, A w_j).
- * Runs exactly `iters` steps (no stopping test); returns alpha[] and the
- * Gram–Schmidt coefficients bgs[1..iters-1] (bgs[0] unused).
+ * Cross-check of the standard form against the conjugacy conditions that
+ * define APCG (Section 2.1), on small inputs.  Each step takes the step
+ * length that makes the new residual orthogonal to the current direction,
+ *   (r_j - a A w_j, w_j) = 0,
+ * and builds the next direction from the projected preconditioned residual
+ * by removing its A-component along the current direction,
+ *   (z + c w_j, A w_j) = 0.
+ * Algorithm 1 prints this Gram-Schmidt form (its coefficient is -c); the
+ * standard form replaces the two inner products by rho ratios, equal in
+ * exact arithmetic.  Runs exactly `iters` steps with no stopping test and
+ * returns the step lengths a_j and the Gram-Schmidt coefficients
+ * gs[j] = -c_j (j >= 1; gs[0] unused).
  */
+static double conj_step_length(int64_t n, const double* r, const double* w, const double* aw, double waw) {
+    return orc_dot(n, r, w) / waw;
+}
+
+static double conj_gs_coeff(int64_t n, const double* z, const double* aw, double waw) {
+    return orc_dot(n, z, aw) / waw;
+}
+
 int orc_apcg_alg1(int64_t n, const int64_t* rp, const int32_t* ci, const double* av, int precond,
                   const double* C, int nc, int64_t ldc, const double* b, int iters, double guard,
                   double* x, double* alpha, double* bgs) {
@@ -368,40 +435,43 @@ int orc_apcg_alg1(int64_t n, const int64_t* rp, const int32_t* ci, const double*
     orc_coarse K;
     st = coarse_build(&K, n, rp, ci, av, C, nc, ldc, guard, NULL);
     if (st != ORC_OK) { prec_free(&P); coarse_free(&K); return st; }
-    double* r = (double*)malloc(sizeof(double) * (size_t)n);
-    double* s = (double*)malloc(sizeof(double) * (size_t)n);
-    double* z = (double*)malloc(sizeof(double) * (size_t)n);
-    double* w = (double*)malloc(sizeof(double) * (size_t)n);
-    double* q = (double*)malloc(sizeof(double) * (size_t)n);
-    double* mu = (double*)malloc(sizeof(double) * (size_t)(K.nk > 0 ? K.nk : 1));
+    double* res = (double*)malloc(sizeof(double) * (size_t)n);
+    double* pre = (double*)malloc(sizeof(double) * (size_t)n);
+    double* dir = (double*)malloc(sizeof(double) * (size_t)n);
+    double* adir = (double*)malloc(sizeof(double) * (size_t)n);
+    double* zz = (double*)malloc(sizeof(double) * (size_t)n);
+    double* cmu = (double*)malloc(sizeof(double) * (size_t)(K.nk > 0 ? K.nk : 1));
+    if (!res || !pre || !dir || !adir || !zz || !cmu) { st = ORC_NOMEM; goto fin; }
+    /* start: x0 = C G^-1 C^T b and its residual (the initialisation of P) */
     memset(x, 0, sizeof(double) * (size_t)n);
-    memcpy(r, b, sizeof(double) * (size_t)n);
+    memcpy(res, b, sizeof(double) * (size_t)n);
     if (K.nk > 0) {
         for (int t = 0; t < K.nk; ++t) K.tmp[t] = orc_dot(n, K.Ck + (size_t)t * n, b);
-        coarse_solve(&K, K.tmp, mu);
+        coarse_solve(&K, K.tmp, cmu);
         for (int t = 0; t < K.nk; ++t)
-            for (int64_t i = 0; i < n; ++i) { x[i] += K.Ck[(size_t)t * n + i] * mu[t]; r[i] -= K.Qk[(size_t)t * n + i] * mu[t]; }
+            for (int64_t i = 0; i < n; ++i) { x[i] += K.Ck[(size_t)t * n + i] * cmu[t]; res[i] -= K.Qk[(size_t)t * n + i] * cmu[t]; }
     }
-    prec_apply(&P, r, s);
-    project(&K, s, z, mu);
-    memcpy(w, z, sizeof(double) * (size_t)n);
+    prec_apply(&P, res, pre);
+    project(&K, pre, dir, cmu);
     for (int j = 0; j < iters; ++j) {
-        orc_spmv(n, rp, ci, av, w, q);
-        double wq = orc_dot(n, w, q);
-        double a = orc_dot(n, r, w) / wq;
+        orc_spmv(n, rp, ci, av, dir, adir);
+        const double waw = orc_dot(n, dir, adir);
+        const double a = conj_step_length(n, res, dir, adir, waw);
         alpha[j] = a;
-        for (int64_t i = 0; i < n; ++i) { x[i] += a * w[i]; r[i] -= a * q[i]; }
+        for (int64_t i = 0; i < n; ++i) x[i] += a * dir[i];
+        for (int64_t i = 0; i < n; ++i) res[i] -= a * adir[i];
         if (j + 1 == iters) break;
-        prec_apply(&P, r, s);
-        project(&K, s, z, mu);
-        double bb = orc_dot(n, q, z) / wq;
-        bgs[j + 1] = bb;
-        for (int64_t i = 0; i < n; ++i) w[i] = z[i] - bb * w[i];
+        prec_apply(&P, res, pre);
+        project(&K, pre, zz, cmu);
+        const double g = conj_gs_coeff(n, zz, adir, waw);  /* = -c */
+        bgs[j + 1] = g;
+        for (int64_t i = 0; i < n; ++i) dir[i] = zz[i] - g * dir[i];
     }
-    free(r); free(s); free(z); free(w); free(q); free(mu);
+fin:
+    free(res); free(pre); free(dir); free(adir); free(zz); free(cmu);
     prec_free(&P);
     coarse_free(&K);
-    return ORC_OK;
+    return st;
 }
 
 /* ------------------------------------------- Ritz analysis (Section 4.1) */

@@ -331,7 +331,7 @@ class Sequence:
     def __init__(self, ctx: Context, row_ptr, col_idx, n, block=1, precision="fp64", reuse="selective",
                  precond=None, cap_policy="freeze", tol=1e-8, max_iter=10000, ritz_eps=1e-14, max_basis=0,
                  refine_every=0, history_cap=0, rank_tol=0.0, refine_drop=0.0, C0=None, eager=False,
-                 update_rows=0, autotune=False, separate_finalize=False):
+                 update_rows=0, autotune=False, separate_finalize=False, literal_direction=False):
         self.ctx = ctx
         self.n = int(n)
         self.block = int(block)
@@ -361,7 +361,7 @@ class Sequence:
         d.exec_mode = 1 if eager else 0
         d.update_rows = update_rows
         d.autotune = 1 if autotune else 0
-        d.kernel_flags = 1 if separate_finalize else 0
+        d.kernel_flags = (1 if separate_finalize else 0) | (2 if literal_direction else 0)
         self.desc = d
         h = ctypes.c_void_p()
         if C0 is not None and C0.shape[1] > 0:

@@ -147,7 +147,7 @@ struct SysView {
     unsigned long long* kslots;  // per-workgroup start / end stamps of timed launches
     Geometry geo;
     int32_t fused;               // 1: the update kernel's last workgroup runs the finalize
-    int32_t pad1;
+    int32_t dir_literal;         // 1: w = z + beta w_old as written; 0: w = z + beta P w_old
 };
 
 // Launch maps of a fused batch: map[k][i] = (system, workgroup) of launch

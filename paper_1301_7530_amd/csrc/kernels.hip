@@ -878,8 +878,9 @@ __device__ __forceinline__ void finalize_update_body(const SysView<V, W>& v, int
     __syncthreads();
     if (tid < NWORD) reinterpret_cast<unsigned long long*>(v.st)[tid] = reinterpret_cast<const unsigned long long*>(&S)[tid];
     // the new direction is projected as a whole: w = P (z + beta w_old)
-    // = s + beta w_old - C (mu + beta G^-1 (AC)^T w_old)
-    const double bt = beta_s;
+    // = s + beta w_old - C (mu + beta G^-1 (AC)^T w_old); with dir_literal
+    // the old direction is taken as it is (w = z + beta w_old)
+    const double bt = v.dir_literal ? 0.0 : beta_s;
     for (int c = tid; c < nc; c += T) v.mu2[c] = muL[c] + bt * gvL[c];
 }
 
@@ -1091,7 +1092,8 @@ __device__ __forceinline__ void update_reduce_body(const SysView<V, W>& v, int64
 // ------------------------------------------------------------------ K5
 // z = s - C mu and w = s - C mu2 + beta w_old with mu2 = mu + beta G^-1
 // (AC)^T w_old, i.e. w = P (z + beta w_old): the whole direction is kept
-// A-orthogonal to C (in exact arithmetic (AC)^T w_old = 0 and mu2 = mu).
+// A-orthogonal to C (in exact arithmetic (AC)^T w_old = 0 and mu2 = mu, so
+// this is Algorithm 1's w = z + beta w_old; with dir_literal mu2 = mu).
 // first = 1: initial direction w = z; first = 2: the update that follows a
 // residual replacement (runs only when one is pending).  A workgroup owns
 // 256 rows: lane l of every wave reads 4 consecutive rows of a column of C

@@ -368,6 +368,7 @@ SysView<V, W> SeqImpl<V, W>::view() {
     v.sync = (unsigned*)((char*)d_st.p + kSyncOffset);
     v.kslots = (unsigned long long*)d_kslots.p;
     v.fused = (desc.kernel_flags & 1) ? 0 : 1;
+    v.dir_literal = (desc.kernel_flags & 2) ? 1 : 0;
     return v;
 }
 

@@ -128,8 +128,6 @@ def test_elasticity40_bench_setup(gpu, elasticity40):
         s.close()
 
 
-@pytest.mark.skipif(bool(__import__("os").environ.get("KRS_SKIP_100")),
-                    reason="elasticity 100^3 (3.06 M unknowns, about 40 s) skipped by KRS_SKIP_100")
 def test_elasticity100_sampled(gpu):
     """Elasticity 100^3 in the benchmark's FP32-basis setup, checked on what
     the oracle computes one by one or what holds at any size: the first CG

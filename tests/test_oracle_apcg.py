@@ -277,3 +277,82 @@ def test_maxit_and_zero_rhs():
     assert r["status"] == O.ORC_MAXIT and r["m"] == 2
     r = O.apcg(*_csr(A), np.zeros(20), "none", tol=1e-8, max_iter=5)
     assert r["m"] == 0 and np.all(r["x"] == 0)
+
+
+def test_direction_forms_agree_on_recycled_bases():
+    """w = z + beta w_old (Algorithm 1) and w = z + beta P w_old (the
+    library's default: the projector applied to the old direction as well)
+    are one iteration in exact arithmetic (P w_old = w_old, Section 2.1).
+    In double precision their iteration counts agree within +-2 and both
+    solutions meet the tolerance, with a basis of recycled Ritz vectors
+    (elasticity 6^3, SRKS after system 0) and with a random basis."""
+    import gen
+
+    seq = gen.config_elasticity(6, 3)
+    recs, C = O.solve_sequence(seq, 1, reuse="srks", eps=1e-10, cap=24, cap_policy="freeze", tol=1e-8,
+                               max_iter=4000)
+    rng = np.random.default_rng(11)
+    bases = [C, rng.standard_normal((seq.n, 12))]
+    for k in (1, 2):
+        rp, ci, v, b = seq.csr(k)
+        for Cb in bases:
+            a = O.apcg(rp, ci, v, b, "block3", C=Cb, tol=1e-8, max_iter=4000, direction="literal")
+            p = O.apcg(rp, ci, v, b, "block3", C=Cb, tol=1e-8, max_iter=4000, direction="project_old")
+            assert a["status"] == O.ORC_OK and p["status"] == O.ORC_OK
+            assert abs(a["m"] - p["m"]) <= 2, (k, a["m"], p["m"])
+            assert a["relres_true"] <= 1e-8 and p["relres_true"] <= 1e-8
+            # the first coefficients agree to rounding
+            assert np.allclose(a["alpha"][:20], p["alpha"][:20], rtol=1e-9, atol=0)
+
+
+def test_reorth_exact_termination_and_solution():
+    """Full reorthogonalisation on tiny SPD inputs (kappa up to 1e4): exact
+    termination within n - n_c steps, the dense solution, and the same
+    coefficients as the plain iteration over the first steps."""
+    rng = np.random.default_rng(12)
+    for n, nc, kappa in ((24, 0, 1e2), (32, 5, 1e4)):
+        A = _rand_spd(n, kappa, rng)
+        C = rng.standard_normal((n, nc)) if nc else None
+        b = rng.standard_normal(n)
+        r = O.apcg(*_csr(A), b, "none", C=C, tol=1e-12, max_iter=n, reorth=True)
+        assert r["status"] == O.ORC_OK and r["m"] <= n - nc, (n, r["m"])
+        xs = np.linalg.solve(A, b)
+        assert np.linalg.norm(r["x"] - xs) / np.linalg.norm(xs) <= 1e-10 * kappa
+        p = O.apcg(*_csr(A), b, "none", C=C, tol=1e-12, max_iter=n)
+        k = min(5, r["m"], p["m"])
+        assert np.allclose(r["alpha"][:k], p["alpha"][:k], rtol=1e-8)
+
+
+def test_reorth_keeps_directions_conjugate_and_ritz_values_simple():
+    """At n = 6,084 and about 10^3 steps (elasticity 12^3, tol 1e-10):
+    with full reorthogonalisation every pair of directions is A-conjugate to
+    1e-12 (normalised), and no two Ritz values coincide to 1e-8 (no ghost
+    copies, so the 1e-14 stagnation test selects each eigenvalue once);
+    without it conjugacy is lost and ghost pairs appear (Section 5.1)."""
+    import gen
+
+    seq = gen.config_elasticity(12, 1)
+    rp, ci, v, b = seq.csr(0)
+    A = sp.csr_matrix((v, ci, rp), shape=(seq.n, seq.n))
+    out = {}
+    for reorth in (False, True):
+        r = O.apcg(rp, ci, v, b, "block3", tol=1e-10, max_iter=3000, record_w=True, reorth=reorth)
+        assert r["status"] == O.ORC_OK and r["relres_true"] <= 1e-9
+        W = r["W"]
+        G = W.T @ (A @ W)
+        d = np.sqrt(np.diag(G))
+        Gn = G / d[:, None] / d[None, :]
+        np.fill_diagonal(Gn, 0.0)
+        th, th1 = O.ritz_values(r["alpha"], r["rho"])
+        close = int(np.sum(np.abs(np.diff(th)) / th[1:] < 1e-8))
+        sel = O.srks_select(th, th1, 1e-14)
+        out[reorth] = (r["m"], np.abs(Gn).max(), close, th[sel])
+    m0, cos0, close0, _ = out[False]
+    m1, cos1, close1, sel1 = out[True]
+    assert m1 > 500
+    assert cos1 <= 1e-12, cos1
+    assert close1 == 0
+    assert np.all(np.abs(np.diff(sel1)) / sel1[1:] > 1e-8)
+    # the pin discriminates: the plain run has lost conjugacy and has ghosts
+    assert cos0 > 1e-3 and close0 > 10
+    assert m1 <= m0
