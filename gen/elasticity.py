@@ -86,8 +86,40 @@ def _pattern(E: int):
     return row_ptr, col_idx, valid
 
 
+_asm_lib = None
+
+
+def _asm():
+    global _asm_lib
+    if _asm_lib is None:
+        import ctypes
+
+        from .build import ensure_built
+
+        L = ctypes.CDLL(ensure_built())
+        D = ctypes.POINTER(ctypes.c_double)
+        L.gen_elasticity_blocks.restype = None
+        L.gen_elasticity_blocks.argtypes = [ctypes.c_int, D, D, D]
+        _asm_lib = L
+    return _asm_lib
+
+
+def elasticity_blocks(moduli: np.ndarray, kref: np.ndarray, nnzb: int) -> np.ndarray:
+    """Blocks float64[nnzb, 3, 3] in block-CSR order, assembled by the C
+    helper (same sums, same rounding as ``elasticity_matrix``)."""
+    import ctypes
+
+    mod = np.ascontiguousarray(moduli, dtype=np.float64)
+    kr = np.ascontiguousarray(kref, dtype=np.float64)
+    out = np.empty((nnzb, 3, 3), dtype=np.float64)
+    D = ctypes.POINTER(ctypes.c_double)
+    _asm().gen_elasticity_blocks(mod.shape[0], mod.ctypes.data_as(D), kr.ctypes.data_as(D), out.ctypes.data_as(D))
+    return out
+
+
 def elasticity_matrix(moduli: np.ndarray, nu: float = 0.3, kref: np.ndarray | None = None):
-    """Assemble for element moduli of shape (E, E, E) indexed [ez, ey, ex].
+    """Assemble for element moduli of shape (E, E, E) indexed [ez, ey, ex]
+    (vectorised numpy; the reference for the C helper).
 
     Returns (block_row_ptr int64[nb+1], block_col int32[nnzb],
     blocks float64[nnzb, 3, 3]) with nb = E*(E+1)^2 free nodes.
@@ -198,7 +230,7 @@ class ElasticitySequence:
 
     def system(self, k):
         """(blocks float64[nnzb*9] row-major 3x3, b float64[n]) of system k."""
-        _, _, blocks = elasticity_matrix(self.moduli(k), self.nu, self._kref)
+        blocks = elasticity_blocks(self.moduli(k), self._kref, self.nnzb)
         return blocks.reshape(-1), self.rhs(k)
 
     def csr(self, k):

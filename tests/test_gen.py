@@ -116,3 +116,16 @@ def test_batched_and_serving_sizes():
     Es = gen.serving_elasticity_sizes()
     dofs = np.array([3 * E * (E + 1) ** 2 for E in Es])
     assert len(Es) == 64 and dofs.min() > 5e3 and dofs.max() < 6e5
+
+
+def test_elasticity_c_assembly_matches_numpy_bitwise():
+    """The C assembly helper and the vectorised numpy assembly produce the
+    same blocks bit for bit (same sums in the same order)."""
+    from gen.elasticity import elasticity_blocks, elasticity_matrix
+
+    for E in (2, 5, 9):
+        sq = gen.config_elasticity(E, 2)
+        for k in range(2):
+            _, _, ref = elasticity_matrix(sq.moduli(k), sq.nu, sq._kref)
+            got = elasticity_blocks(sq.moduli(k), sq._kref, sq.nnzb)
+            assert np.array_equal(ref, got), (E, k)
