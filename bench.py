@@ -1,26 +1,27 @@
 #!/usr/bin/env python3
 """Throughput benchmark of the Krylov-reuse APCG library on one GPU.
 
-A step is one system of the sequence taken through the whole hot path:
+A step is one system of a sequence taken through the whole hot path:
 intake of the new matrix values and right-hand side (already resident in
 HBM), rebuild of A C and C^T A C for the carried basis, the APCG iterations
 to a true relative residual of 1e-8, and the Ritz extraction / selection /
-basis update (SRKS).  The same systems are then solved with plain PCG
-(no basis) on the same GPU for comparison.
+basis update (SRKS).  The timed run starts from an empty basis and takes
+systems 0..steps-1 of one sequence in order, so every recycle that grows the
+basis is inside it; the warm-up solves the first systems on a separate
+sequence handle that is then discarded.  Plain PCG (no basis) on the first
+systems gives the comparison on the same GPU, and a second precision on the
+first systems gives each solution's error against the headline run.
 
-Default workload: Q1 elasticity on a 40^3 mesh (n = 201,720 dofs,
-15,548,742 nonzeros in 3x3 blocks), 64 stiff cubic inclusions, cumulative
+Default workload: Q1 elasticity on a 100^3 mesh (n = 3,060,300 dofs,
+242,991,882 nonzeros in 3x3 blocks), 64 stiff cubic inclusions, cumulative
 damage between systems, 3x3 block-Jacobi, SRKS with eps = 1e-8 and a basis
-of at most 60 vectors (frozen once full); double-precision operator and
-vectors with the basis and preconditioner streamed in single precision
-(--precision fp32basis; "mixed" also rounds the matrix values, which on this
-stiff-inclusion problem costs about half again as many iterations).
+of at most 200 vectors (frozen once full), double precision throughout.
 
-Other workloads: --workload batched (many diffusion sequences in fused
-launches), --workload serving (Poisson arrivals into the continuous-batching
-server), elasticity100, diffusion20.
+Other workloads: elasticity40, diffusion20, batched (many diffusion
+sequences in fused launches), serving (Poisson arrivals into the
+continuous-batching server).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32basis|mixed|fp64|fp32]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--precision P]
 
 Prints one JSON line.
 """
@@ -37,12 +38,6 @@ import time
 import numpy as np
 
 HBM_PEAK = 8.0e12  # MI355X HBM3E, bytes/s
-
-# Bytes per launch of k_spmv_dot read from the hardware counters
-# (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 KiB, the factors from a 1 GiB
-# device copy), by (workload, precision); kept only while the kernel is the
-# one the counters were taken on.
-TRAFFIC_K1 = {("elasticity40", "fp32basis"): 146268827}
 
 WORKLOADS = {
     "elasticity40": dict(kind="elasticity", size=40, n_systems=20, workload_id=2, max_basis=60, eps=1e-8),
@@ -67,95 +62,335 @@ def _log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def spmv_bytes(seq, p, pw):
-    """Algorithmic bytes of one SpMV launch: matrix values (p bytes) + block
-    column indices + the vector read once + the product written once (pw)."""
+def gen_systems(seq, ks, threads=16):
+    """Host values and right-hand sides of systems ``ks`` of ``seq``.  The
+    random streams are cumulative, so they are drawn in order first; the
+    matrix assembly (C helper for elasticity, numpy for diffusion) then runs
+    on a thread pool."""
+    import concurrent.futures as cf
+
+    for k in sorted(ks):
+        (seq.moduli if hasattr(seq, "moduli") else seq.coefficients)(k)
+        seq.rhs(k)
+    with cf.ThreadPoolExecutor(max_workers=max(1, min(threads, len(ks)))) as ex:
+        return dict(zip(ks, ex.map(seq.system, ks)))
+
+
+KERNEL_NAMES = ("k_spmv_dot", "k_update_fused", "k_correct_dir")
+
+
+def kernel_bytes(seq, prec, n_c, hist, reuse):
+    """Algorithmic bytes of one launch of each per-iteration kernel.
+
+    K1 q = A w and (w, q): the matrix values and block columns, w read, q
+    written.  K3: x, w, r, q read, x, r, s written, the preconditioner, the
+    rows of A C.  K5: s, w_old read, w written, z_j written to the history
+    when one is kept, the basis C.  p: matrix value bytes, pb: basis and
+    preconditioner bytes, pw: Krylov vector bytes (x is always 8)."""
+    p, pb, pw = prec["p"], prec["pb"], prec["pw"]
+    n = seq.n
     nnz = seq.nnzb * seq.block * seq.block
-    if seq.block == 1:
-        return nnz * (p + 4) + 2 * seq.n * pw
-    return nnz * p + 4 * seq.nnzb + 2 * seq.n * pw
+    BA = nnz * (p + 4) if seq.block == 1 else nnz * p + 4 * seq.nnzb
+    BM = n * pb if seq.block == 1 else 3 * n * pb
+    k1 = BA + 2 * n * pw
+    k3 = n * (2 * 8 + 5 * pw) + BM + n * n_c * pb
+    k5 = n * 3 * pw + (n * pb if (hist and reuse == "selective") else 0) + n * n_c * pb
+    return k1, k3, k5
 
 
-def run_phase(K, ctx, seq, dev_sys, reuse, args, wl, order, timing=False):
+PRECISIONS = {
+    "fp64": dict(p=8, pb=8, pw=8, dtype="f64", detail="fp64 throughout"),
+    "fp32basis": dict(p=8, pb=4, pw=8, dtype="f64+f32",
+                      detail="fp64 matrix and vectors, fp32 basis (C, AC), history and preconditioner, fp64 reductions, "
+                             "coarse algebra, Ritz problem and residual replacement"),
+    "mixed": dict(p=4, pb=4, pw=8, dtype="f32+f64",
+                  detail="fp32 matrix/preconditioner/basis, fp64 vectors and reductions, fp64 residual replacement"),
+    "fp32": dict(p=4, pb=4, pw=4, dtype="f32", detail="fp32 matrix, basis and vectors, fp64 reductions"),
+}
+
+
+def max_basis(args, wl):
+    """The basis cap: --max-basis (a number, or 'auto' for the complexity
+    analysis of the library), else the workload's."""
+    if args.max_basis == "auto":
+        return -1
+    return int(args.max_basis) if args.max_basis else wl["max_basis"]
+
+
+def run_sequence(K, ctx, seq, dev_sys, ks, precision, reuse, args, wl, timing=False, xs=None, label=""):
+    """Systems ``ks`` of one sequence in order, from an empty basis, each
+    through intake, rebuild, iterations and recycle.  Returns the wall time
+    of the whole run and per-system records (with the kernel-timing deltas
+    of that system when ``timing``)."""
     import torch
 
-    s = K.sequence_for(ctx, seq, precision=args.precision, reuse=reuse, tol=1e-8, max_iter=args.max_iter,
+    s = K.sequence_for(ctx, seq, precision=precision, reuse=reuse, tol=1e-8, max_iter=args.max_iter,
                        history_cap=wl.get("history_cap", 0),
-                       ritz_eps=args.eps if args.eps else wl["eps"], max_basis=args.max_basis or wl["max_basis"],
-                       cap_policy="freeze",
+                       ritz_eps=args.eps if args.eps else wl["eps"],
+                       max_basis=max_basis(args, wl) if reuse == "selective" else 0,
+                       cap_policy=args.cap_policy,
                        refine_drop=args.refine_drop, autotune=args.autotune, update_rows=args.update_rows,
                        eager=args.eager, separate_finalize=args.separate_finalize)
-    x = torch.empty(seq.n, dtype=torch.float64, device="cuda")
-    infos = []
-    lat = []
-    C_before = None
+    x_scratch = torch.empty(seq.n, dtype=torch.float64, device="cuda")
+    recs = []
     try:
-        for i, k in enumerate(order[: args.warmup]):
-            s.submit(*dev_sys[k])
-            s.solve_device(x)
-            s.recycle()
-        if reuse != "none":
-            C_before = s.basis() if args.cpu_baseline else None
         if timing:
             s.set_timing(True)
+        prev = [(0, 0.0)] * 3
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for k in order[args.warmup:]:
+        for i, k in enumerate(ks):
             ts = time.perf_counter()
+            x = xs[i] if xs is not None and i < len(xs) else x_scratch
             s.submit(*dev_sys[k])
             info = s.solve_device(x)
+            n_c_solve = info["n_c"]
             s.recycle()
-            info["added"] = s.info()["added"]
-            info["t_recycle_ms"] = s.info()["t_recycle_ms"]
-            infos.append(info)
-            lat.append(time.perf_counter() - ts)
-            _log(f"  system {k}: {info['iters']} iterations, n_c {info['n_c']}, {1e3 * lat[-1]:.1f} ms")
+            after = s.info()
+            info["added"] = after["added"]
+            info["t_recycle_ms"] = after["t_recycle_ms"]
+            info["n_c_solve"] = n_c_solve
+            info["lat_s"] = time.perf_counter() - ts
+            if timing:
+                cur = []
+                for j in range(3):
+                    c, mean = s.kernel_time(j)
+                    cur.append((c, c * mean if c else 0.0))
+                info["ktime"] = [(cur[j][0] - prev[j][0], cur[j][1] - prev[j][1]) for j in range(3)]
+                prev = cur
+            recs.append(info)
+            _log(f"  {label} system {k}: {info['iters']} iterations, n_c {n_c_solve} (+{info['added']}), "
+                 f"{1e3 * info['lat_s']:.1f} ms")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        ktimes = [s.kernel_time(j) for j in range(3)] if timing else None
-        coeffs = s.coeffs()
     finally:
         s.close()
-    return dict(time=t1 - t0, infos=infos, lat=lat, ktimes=ktimes, C_before=C_before, coeffs=coeffs)
+    return dict(time=t1 - t0, infos=recs)
 
 
-def cpu_baseline(seq, k, C, m_avg, sample_iters, coeffs):
-    """Time the oracle on a bounded sample of the same workload."""
+def cpu_baseline(seq, host_sys, k, m_avg, nc_avg, sample_iters, nc_sample):
+    """The oracle on a bounded sample of the same workload, one thread.
+
+    Timed: the oracle's solve of system k with no basis for 1 and for
+    1 + sample_iters iterations (per-iteration time t0), and with a basis of
+    nc_sample columns (random, the cost does not depend on the values) for 1
+    and 1 + sample_iters iterations (coarse build B and per-iteration time
+    t1).  A solve with n_c columns and m iterations is then priced at
+    B n_c / nc_sample + m (t0 + (t1 - t0) n_c / nc_sample), i.e. the
+    oracle's build and projector costs taken as linear in n_c."""
     import oracle as O
 
-    rp, ci, v, b = seq.csr(k)
-    pc = "block3" if seq.block == 3 else "jacobi"
-    t = time.perf_counter()
-    O.apcg(rp, ci, v, b, pc, C=C, tol=1e-8, max_iter=1)
-    t_first = time.perf_counter() - t
-    t = time.perf_counter()
-    O.apcg(rp, ci, v, b, pc, C=C, tol=1e-8, max_iter=1 + sample_iters)
-    t_long = time.perf_counter() - t
-    t_iter = max(t_long - t_first, 1e-9) / sample_iters
-    # Ritz analysis of an m-step run: the oracle bisects every eigenvalue of
-    # H_m and H_{m-1} (about 70 Sturm counts of length m each); time a few
-    # counts on the GPU run's own coefficients and scale
-    alpha, rho = coeffs
-    m = max(len(alpha), 2)
-    d, l2 = O.lanczos_factors(alpha, rho)
-    dd = np.ascontiguousarray(d)
-    ll = np.ascontiguousarray(l2 if len(l2) else np.zeros(1))
-    lib = O.lib()
-    pre = 64
-    t = time.perf_counter()
-    for j in range(pre):
-        lib.orc_ldl_count(len(dd), O._p(dd), O._p(ll), float(j) / pre)
-    t_count = (time.perf_counter() - t) / pre
-    t_ritz = 2 * m * 70 * t_count
-    solve_s = t_first + (m_avg - 1) * t_iter + t_ritz
+    vals, b = host_sys[k]
+    if seq.block == 3:
+        import gen
+
+        rp, ci, v = gen.bsr_to_csr(seq.row_ptr, seq.col_idx, vals.reshape(-1, 3, 3))
+        pc = "block3"
+    else:
+        rp, ci, v = seq.row_ptr, seq.col_idx, vals
+        pc = "jacobi"
+
+    def timed(C, iters):
+        t = time.perf_counter()
+        O.apcg(rp, ci, v, b, pc, C=C, tol=1e-30, max_iter=iters)
+        return time.perf_counter() - t
+
+    t_a = timed(None, 1)
+    t_b = timed(None, 1 + sample_iters)
+    t0 = max(t_b - t_a, 1e-9) / sample_iters
+    C = np.random.default_rng(7).standard_normal((seq.n, nc_sample))
+    t_c = timed(C, 1)
+    t_d = timed(C, 1 + sample_iters)
+    t1 = max(t_d - t_c, 1e-9) / sample_iters
+    build = max(t_c - t_a, 0.0)
+    solve_s = build * nc_avg / nc_sample + m_avg * (t0 + (t1 - t0) * nc_avg / nc_sample)
     return dict(value=1.0 / solve_s, unit="solves/s", cores=1, kind="oracle",
-                sample=(f"oracle (C, fp64, 1 thread) on system {k} of the same sequence with the GPU's basis "
-                        f"(n_c={0 if C is None else C.shape[1]}): build + {sample_iters} APCG iterations timed "
-                        f"({t_first:.2f}s first iteration incl. coarse build, {t_iter*1e3:.1f} ms/iteration), "
-                        f"Ritz bisection timed on {pre} Sturm counts of length {m} (the GPU run's coefficients); "
-                        f"scaled to the GPU's mean "
-                        f"{m_avg:.0f} iterations per solve"),
-                seconds_per_solve=solve_s)
+                sample=(f"oracle (C, fp64, 1 thread) on system {k} of the same sequence: 1 and {1 + sample_iters} "
+                        f"APCG iterations with no basis ({t0 * 1e3:.0f} ms/iteration) and with {nc_sample} basis "
+                        f"columns ({t1 * 1e3:.0f} ms/iteration, coarse build {build:.2f} s); priced for the GPU "
+                        f"run's mean {m_avg:.0f} iterations and {nc_avg:.0f} columns per solve, build and "
+                        f"projector linear in the columns"),
+                seconds_per_solve=solve_s, seconds_sampled=t_a + t_b + t_c + t_d)
+
+
+def profile_traffic(name):
+    """Bytes per launch from the hardware counters, read from the committed
+    rocprofv3 summary ``profiles/<name>.md`` (lines 'traffic_bytes_per_launch:'
+    and 'kernels_sha256:'); None when there is no summary or the kernel
+    source has changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", name + ".md")
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1301_7530_amd", "csrc", "kernels.hip")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.split(":", 1)[0].strip("`* -") in ("traffic_bytes_per_launch", "kernels_sha256"):
+            key, v = line.split(":", 1)
+            vals[key.strip("`* -")] = v.strip().strip("`")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if vals.get("kernels_sha256") != sha or "traffic_bytes_per_launch" not in vals:
+        return None
+    return int(vals["traffic_bytes_per_launch"])
+
+
+def run_sequence_workload(args, K, torch, wl):
+    import gen
+
+    seq = gen.make_sequence(wl["kind"], wl["size"], wl["n_systems"], wl["workload_id"])
+    precision = args.precision
+    prec = PRECISIONS[precision]
+    reuse = "selective" if wl["max_basis"] else "total"
+    ks = list(range(args.steps))
+    warm = list(range(args.warmup))
+    plain_ks = list(range(min(args.plain_systems, args.steps))) if args.plain else []
+    cmp_ks = list(range(min(args.compare_systems, args.steps))) if args.compare else []
+    need = sorted(set(ks) | set(warm))
+    _log(f"workload {args.workload}: n={seq.n} nnzb={seq.nnzb} block={seq.block}; generating {len(need)} systems")
+    t = time.perf_counter()
+    host = gen_systems(seq, need)
+    _log(f"generated in {time.perf_counter() - t:.1f} s")
+    dev_sys = {k: (torch.from_numpy(host[k][0]).to("cuda"), torch.from_numpy(host[k][1]).to("cuda")) for k in need}
+    if not args.cpu_baseline:
+        host = {}
+    torch.cuda.synchronize()
+    ctx = K.Context(0)
+    if warm:
+        _log(f"warm-up: systems {warm[0]}..{warm[-1]} on a separate, discarded sequence handle")
+        run_sequence(K, ctx, seq, dev_sys, warm, precision, reuse, args, wl, label="warm-up")
+        # hand the warm-up's Krylov history back to the device before the
+        # timed run reserves its own
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    xs = [torch.empty(seq.n, dtype=torch.float64, device="cuda") for _ in cmp_ks]
+    _log(f"timed: systems 0..{args.steps - 1} in order from an empty basis ({precision})")
+    main = run_sequence(K, ctx, seq, dev_sys, ks, precision, reuse, args, wl, timing=True, xs=xs, label="timed")
+    plain = None
+    if plain_ks:
+        _log(f"plain PCG: systems {plain_ks[0]}..{plain_ks[-1]} ({precision})")
+        plain = run_sequence(K, ctx, seq, dev_sys, plain_ks, precision, "none", args, wl, label="plain")
+    cmp = None
+    if cmp_ks:
+        _log(f"{args.compare}: systems {cmp_ks[0]}..{cmp_ks[-1]} from an empty basis, errors against the {precision} run")
+        xc = [torch.empty(seq.n, dtype=torch.float64, device="cuda") for _ in cmp_ks]
+        cmp = run_sequence(K, ctx, seq, dev_sys, cmp_ks, args.compare, reuse, args, wl, xs=xc, label=args.compare)
+        cmp["err"] = [float(torch.linalg.norm(xc[i] - xs[i]) / torch.linalg.norm(xs[i])) for i in range(len(cmp_ks))]
+    ctx.close()
+
+    infos = main["infos"]
+    value = args.steps / main["time"]
+    iters = [i["iters"] for i in infos]
+    lat_ms = np.array([i["lat_s"] for i in infos]) * 1e3
+    model_bytes = sum(i["model_bytes"] for i in infos)
+    # live device-clock rooflines of the three per-iteration kernels: over
+    # the timed systems solved with the widest basis of the run (the steady
+    # state once the basis is built; all systems when none has a basis)
+    cap = max_basis(args, wl)
+    nc_top = max(i["n_c_solve"] for i in infos)
+    steady = [i for i in infos if i["n_c_solve"] == nc_top]
+    kstat = []
+    for j in range(3):
+        cnt = sum(i["ktime"][j][0] for i in steady)
+        ms = sum(i["ktime"][j][1] for i in steady)
+        byt = 0
+        for i in steady:
+            # SRKS keeps the run's z_j unless nothing can be appended from
+            # it: a full frozen basis, or a limit of 0 from the analysis
+            lim = i["n_c_lim"]
+            hist = not ((cap < 0 and lim == 0) or (args.cap_policy == "freeze" and lim > 0 and i["n_c_solve"] >= lim))
+            byt += kernel_bytes(seq, prec, i["n_c_solve"], hist, reuse)[j] * i["ktime"][j][0]
+        kstat.append(dict(kernel=KERNEL_NAMES[j], launches_sampled=cnt, mean_us=1e3 * ms / cnt if cnt else None,
+                          achieved_GBps=byt / (ms * 1e-3) / 1e9 if ms else None,
+                          frac=byt / (ms * 1e-3) / HBM_PEAK if ms else None,
+                          algorithmic_bytes_per_launch=byt / cnt if cnt else None))
+    # the dominant kernel: the longest launches (each runs once per iteration)
+    dom = max(range(3), key=lambda j: (kstat[j]["mean_us"] or 0.0))
+    d = kstat[dom]
+    traffic = profile_traffic(f"{KERNEL_NAMES[dom]}_{args.workload}_{precision}")
+    workload_desc = (f"{args.workload}: Q1 elasticity {wl['size']}^3" if wl["kind"] == "elasticity"
+                     else f"{args.workload}: 7-point diffusion {wl['size']}")
+    out = {
+        "metric": "solves/s at 1e-8 resid vs plain PCG same GPU; %HBM peak; p50/p99 latency",
+        "value": round(value, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * main["time"] / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": prec["dtype"],
+        "data": "synthetic",
+        "config": {
+            "workload": workload_desc,
+            "n": seq.n,
+            "nnz": seq.nnzb * seq.block * seq.block,
+            "systems_timed": f"0..{args.steps - 1} of one sequence, in order, from an empty basis",
+            "warmup": f"systems 0..{args.warmup - 1} on a separate sequence handle, discarded",
+            "reuse": f"SRKS eps={args.eps if args.eps else wl['eps']:.0e}" if wl["max_basis"] else "TRKS",
+            "max_basis": cap if cap >= 0 else f"auto (complexity analysis): {infos[-1]['n_c_lim']}",
+            "cap_policy": args.cap_policy,
+            "precond": "3x3 block-Jacobi" if seq.block == 3 else "Jacobi",
+            "tol": 1e-8,
+            "precision": precision,
+            "precision_detail": prec["detail"],
+        },
+        "iters": iters,
+        "n_c": [i["n_c_solve"] for i in infos],
+        "added": [i["added"] for i in infos],
+        "iters_mean": float(np.mean(iters)),
+        "n_c_mean": float(np.mean([i["n_c_solve"] for i in infos])),
+        "rel_res_true_max": float(max(i["rel_res_true"] for i in infos)),
+        "refinements_mean": float(np.mean([i["refinements"] for i in infos])),
+        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
+        "phase_ms_mean": {k: float(np.mean([i[k] for i in infos])) for k in
+                          ("t_rebuild_ms", "t_iter_ms", "t_recycle_ms")},
+        "hbm_frac_model": model_bytes / main["time"] / HBM_PEAK,
+        "kernels": kstat,
+        "roofline": {
+            "kernel": d["kernel"],
+            "bound": "hbm",
+            "achieved": d["achieved_GBps"],
+            "peak": HBM_PEAK / 1e9,
+            "unit": "GB/s",
+            "frac": d["frac"],
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": d["algorithmic_bytes_per_launch"],
+            "launches_sampled": d["launches_sampled"],
+            "launches": f"sampled launches (every 32nd iteration) of the timed systems solved with n_c = {nc_top}",
+        },
+    }
+    if plain is not None:
+        pv = len(plain_ks) / plain["time"]
+        out["plain_pcg"] = {
+            "value": round(pv, 4),
+            "systems": f"0..{plain_ks[-1]}",
+            "iters": [i["iters"] for i in plain["infos"]],
+            "rel_res_true_max": float(max(i["rel_res_true"] for i in plain["infos"])),
+        }
+        # the same systems of the timed run, for a like-for-like rate
+        same = len(plain_ks) / sum(infos[i]["lat_s"] for i in range(len(plain_ks)))
+        out["plain_pcg"]["srks_value_same_systems"] = round(same, 4)
+        out["speedup_vs_plain_pcg"] = value / pv
+    if cmp is not None:
+        ci = cmp["infos"]
+        out["compare"] = {
+            "precision": args.compare,
+            "detail": PRECISIONS[args.compare]["detail"],
+            "systems": f"0..{cmp_ks[-1]} from an empty basis",
+            "value": round(len(cmp_ks) / cmp["time"], 4),
+            "per_system": [dict(k=cmp_ks[i], iters=ci[i]["iters"], d_iters=ci[i]["iters"] - infos[i]["iters"],
+                                n_c=ci[i]["n_c_solve"], d_n_c=ci[i]["n_c_solve"] - infos[i]["n_c_solve"],
+                                rel_err_vs_fp64=cmp["err"][i], rel_res_true=ci[i]["rel_res_true"])
+                           for i in range(len(cmp_ks))],
+        }
+    if args.cpu_baseline:
+        _log("CPU baseline (oracle sample)")
+        out["cpu_baseline"] = cpu_baseline(seq, host, 0, float(np.mean(iters)), out["n_c_mean"], args.cpu_iters,
+                                           args.cpu_nc)
+    print(json.dumps(out), flush=True)
 
 
 def _gen_system(task):
@@ -406,19 +641,28 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="elasticity40", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default=None, choices=["mixed", "fp64", "fp32", "fp32basis"],
-                    help="default: fp32basis (elasticity, serving), mixed (batched diffusion), fp64 (diffusion20)")
+    ap.add_argument("--workload", default="elasticity100", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default=None, choices=sorted(PRECISIONS),
+                    help="default: fp64 (elasticity, diffusion20), fp32basis (serving), mixed (batched diffusion)")
+    ap.add_argument("--compare", default="fp32basis", choices=sorted(PRECISIONS),
+                    help="second precision run on the first systems, with each solution's error against the "
+                         "headline run")
+    ap.add_argument("--compare-systems", type=int, default=4)
+    ap.add_argument("--no-compare", dest="compare", action="store_const", const=None)
+    ap.add_argument("--cap-policy", default="freeze", choices=["freeze", "restart", "cost"])
     ap.add_argument("--max-iter", type=int, default=30000)
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--no-plain", dest="plain", action="store_false")
-    ap.add_argument("--cpu-iters", type=int, default=100)
+    ap.add_argument("--plain-systems", type=int, default=3, help="plain PCG on the first systems of the sequence")
+    ap.add_argument("--cpu-iters", type=int, default=10, help="oracle iterations per timed sample")
+    ap.add_argument("--cpu-nc", type=int, default=8, help="basis columns of the oracle's timed sample")
     ap.add_argument("--eps", type=float, default=0.0, help="SRKS stagnation tolerance (default: per workload)")
     ap.add_argument("--refine-drop", type=float, default=0.0, help="mixed: refinement trigger (0 = library default)")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="keep the default update-kernel tile instead of timing candidates")
     ap.add_argument("--update-rows", type=int, default=0, help="fixed update-kernel block rows per workgroup")
-    ap.add_argument("--max-basis", type=int, default=0, help="basis cap (0: the workload's)")
+    ap.add_argument("--max-basis", default=None,
+                    help="basis cap n_c_lim: a number, or 'auto' (complexity analysis); default: the workload's")
     ap.add_argument("--sequences", type=int, default=256, help="batched workload: number of sequences")
     ap.add_argument("--history-cap", type=int, default=256, help="batched workload: Krylov vectors kept per solve")
     ap.add_argument("--eager", action="store_true", help="launch kernels one by one instead of graph replay")
@@ -430,7 +674,7 @@ def main():
     ap.add_argument("--hbm-budget", type=float, default=64.0, help="serving workload: working-set budget (GiB)")
     args = ap.parse_args()
     if args.precision is None:
-        args.precision = {"batched": "mixed", "diffusion20": "fp64"}.get(args.workload, "fp32basis")
+        args.precision = {"batched": "mixed", "serving": "fp32basis"}.get(args.workload, "fp64")
     if args.gpus != 1:
         print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); "
               "sharding across GPUs is not implemented", file=sys.stderr)
@@ -468,99 +712,7 @@ def main():
             args.history_cap = 1000
         run_serving(args, K, torch, serving_data)
         return
-    wl = WORKLOADS[args.workload]
-    seq = gen.make_sequence(wl["kind"], wl["size"], wl["n_systems"], wl["workload_id"])
-    total = args.warmup + args.steps
-    order = [k % wl["n_systems"] for k in range(total)]
-    _log(f"workload {args.workload}: n={seq.n} nnzb={seq.nnzb} block={seq.block}; generating {min(total, wl['n_systems'])} systems")
-    dev_sys = {}
-    for k in sorted(set(order)):
-        vals, b = seq.system(k)
-        dev_sys[k] = (torch.from_numpy(vals).to("cuda"), torch.from_numpy(b).to("cuda"))
-    torch.cuda.synchronize()
-    ctx = K.Context(0)
-    _log("SRKS phase")
-    srks = run_phase(K, ctx, seq, dev_sys, "selective" if wl["max_basis"] else "total", args, wl, order, timing=True)
-    plain = None
-    if args.plain:
-        _log("plain PCG phase")
-        plain = run_phase(K, ctx, seq, dev_sys, "none", args, wl, order)
-    ctx.close()
-
-    p = 8 if args.precision in ("fp64", "fp32basis") else 4       # matrix value bytes
-    pw = 4 if args.precision == "fp32" else 8      # Krylov vector bytes
-    value = args.steps / srks["time"]
-    infos = srks["infos"]
-    iters = [i["iters"] for i in infos]
-    lat_ms = np.array(srks["lat"]) * 1e3
-    model_bytes = sum(i["model_bytes"] for i in infos)
-    k_cnt, k_ms = srks["ktimes"][0]
-    kb = spmv_bytes(seq, p, pw)
-    achieved = kb / (k_ms * 1e-3) if k_cnt else float("nan")
-    out = {
-        "metric": "solves/s at 1e-8 resid vs plain PCG same GPU; %HBM peak; p50/p99 latency",
-        "value": round(value, 4),
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(1e3 * srks["time"] / args.steps, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": {"mixed": "f32+f64", "fp64": "f64", "fp32": "f32", "fp32basis": "f64+f32"}[args.precision],
-        "data": "synthetic",
-        "config": {
-            "workload": f"{args.workload}: Q1 elasticity {wl['size']}^3" if wl["kind"] == "elasticity"
-            else f"{args.workload}: 7-point diffusion {wl['size']}",
-            "n": seq.n,
-            "nnz": seq.nnzb * seq.block * seq.block,
-            "systems_timed": args.steps,
-            "reuse": f"SRKS eps={args.eps if args.eps else wl['eps']:.0e}" if wl["max_basis"] else "TRKS",
-            "max_basis": args.max_basis or wl["max_basis"],
-            "cap_policy": "freeze",
-            "precond": "3x3 block-Jacobi" if seq.block == 3 else "Jacobi",
-            "tol": 1e-8,
-            "precision": args.precision,
-            "precision_detail": {"mixed": "fp32 matrix/preconditioner/basis, fp64 vectors and reductions", "fp64": "fp64 throughout", "fp32": "fp32 matrix, basis and vectors, fp64 reductions", "fp32basis": "fp64 matrix and vectors, fp32 basis (C, AC) and preconditioner, fp64 reductions"}[args.precision],
-        },
-        "iters_mean": float(np.mean(iters)),
-        "update_rows": sorted({i["update_rows"] for i in infos}),
-        "n_c_mean": float(np.mean([i["n_c"] for i in infos])),
-        "rel_res_true_max": float(max(i["rel_res_true"] for i in infos)),
-        "refinements_mean": float(np.mean([i["refinements"] for i in infos])),
-        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
-        "phase_ms_mean": {k: float(np.mean([i[k] for i in infos])) for k in
-                          ("t_setup_ms", "t_rebuild_ms", "t_iter_ms", "t_recycle_ms")},
-        "hbm_frac_model": model_bytes / srks["time"] / HBM_PEAK,
-        "kernel_ms_mean": {name: srks["ktimes"][j][1] for j, name in enumerate(("spmv_dot", "update_reduce", "correct_dir"))},
-        "roofline": {
-            "kernel": "k_spmv_dot",
-            "bound": "hbm",
-            "achieved": achieved / 1e9,
-            "peak": HBM_PEAK / 1e9,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK,
-            "traffic": TRAFFIC_K1.get((args.workload, args.precision)),
-            "algorithmic_bytes_per_launch": kb,
-            "launches_sampled": k_cnt,
-        },
-    }
-    if plain is not None:
-        pv = args.steps / plain["time"]
-        out["plain_pcg"] = {
-            "value": round(pv, 4),
-            "iters_mean": float(np.mean([i["iters"] for i in plain["infos"]])),
-            "rel_res_true_max": float(max(i["rel_res_true"] for i in plain["infos"])),
-        }
-        out["speedup_vs_plain_pcg"] = value / pv
-    if args.cpu_baseline:
-        _log("CPU baseline (oracle sample)")
-        k = order[args.warmup]
-        a, r, _ = srks["coeffs"]
-        out["cpu_baseline"] = cpu_baseline(seq, k, srks["C_before"], float(np.mean(iters)), args.cpu_iters, (a, r))
-    print(json.dumps(out), flush=True)
-
+    run_sequence_workload(args, K, torch, WORKLOADS[args.workload])
 
 if __name__ == "__main__":
     main()

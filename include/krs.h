@@ -83,6 +83,21 @@ typedef enum { KRS_CAP_RESTART = 0, KRS_CAP_FREEZE = 1, KRS_CAP_COST = 2 } krs_c
  *   second failed trial in a row, and so on up to 48.  An extension: it
  *   judges the basis after the fact from the measured iteration counts. */
 
+/* max_basis = KRS_NC_LIM_AUTO (SRKS with KRS_CAP_RESTART or KRS_CAP_FREEZE):
+ * n_c_lim is set by a complexity analysis (Section 4.4, the remark after
+ * Algorithm 3) on the first solve of the sequence, whose iteration count
+ * m_0 is taken for every non-augmented system.  Deflating the eigenvectors
+ * of the k lowest eigenvalues is modelled as leaving the CG rate of the
+ * reduced condition number theta_max / theta_(k+1) (Section 2.2, and the
+ * rate of Section 4.3), i.e. m(k) = max(1, m_0 ln sigma_0 / ln sigma_k) with
+ * sigma = (sqrt(kappa) - 1) / (sqrt(kappa) + 1) over the distinct Ritz values
+ * of that solve; each system with k columns is priced at m(k) times the
+ * algorithmic bytes of an iteration with k columns plus the rebuild of k
+ * columns (the library's byte model), and n_c_lim is the k <= 1024 of least
+ * cost.  The value is reported in krs_solve_info.n_c_lim; krs_nc_limit
+ * exposes the analysis itself. */
+#define KRS_NC_LIM_AUTO (-1)
+
 typedef struct krs_ctx krs_ctx;
 typedef struct krs_seq krs_seq;
 
@@ -114,7 +129,7 @@ typedef struct {
     double tol;            /* stop when ||r|| <= tol ||b|| (recursive, then confirmed with the true residual) */
     int32_t max_iter;      /* iterations per solve */
     double ritz_eps;       /* SRKS stagnation tolerance epsilon (Section 4.4), e.g. 1e-14 */
-    int32_t max_basis;     /* n_c_lim; 0 = unlimited */
+    int32_t max_basis;     /* n_c_lim; 0 = unlimited; KRS_NC_LIM_AUTO: from the complexity analysis */
     int32_t refine_every;  /* mixed: force a true-residual refinement at least every k iterations (0 = off) */
     int32_t history_cap;   /* Krylov vectors kept for SRKS (0 = max_iter); longer runs use the leading part */
     double rank_tol;       /* rank guard: drop a basis column whose Cholesky pivot <= rank_tol * max diag (0 = 1e-6) */
@@ -135,7 +150,20 @@ typedef struct {
                               P = I - C G^-1 (A C)^T to the old direction as well (the same vector in exact
                               arithmetic, Section 2.1; the default keeps rounding from moving the direction
                               out of the range of P, at no extra pass over memory) */
+    int32_t reselect;      /* SRKS: 0 = keep every Ritz vector that passed the stagnation test;
+                              1 = KRS_RESELECT_CLUSTER: drop the central cluster of those values
+                              ("clust", Section 4.4), before the cap */
+    double cluster_min_frac; /* minimum size of the central cluster as a fraction of the preselected
+                                values (0 = 0.2, the paper's one fifth) */
 } krs_seq_desc;
+/* KRS_RESELECT_CLUSTER (Section 4.4): the values that passed the stagnation
+ * test are sorted, the distances between neighbours taken on a log scale,
+ * and those distances fitted in least squares by a three-level step
+ * function whose middle step covers at least ceil(cluster_min_frac * s) of
+ * the s values (the outer steps over the low and high ends, one of them
+ * possibly empty); when the middle level is below the outer ones, its
+ * values are the central cluster and are not recycled. */
+#define KRS_RESELECT_CLUSTER 1
 
 typedef struct {
     int32_t iters;          /* m: products A w performed in the last solve */
@@ -153,6 +181,8 @@ typedef struct {
     double t_iter_ms;       /* iterations (including refinements) */
     double t_recycle_ms;    /* Ritz extraction / selection / basis update */
     int64_t model_bytes;    /* algorithmic HBM bytes of the iterations of the last solve */
+    int32_t n_c_lim;        /* cap in force: max_basis, the value set by KRS_NC_LIM_AUTO, 0 if none (-1: not yet set) */
+    int32_t reserved;
 } krs_solve_info;
 
 /* ------------------------------------------------------------- context */
@@ -197,6 +227,14 @@ krs_status krs_seq_ritz(krs_seq* s, double* theta, uint8_t* selected, int32_t ca
  * of Section 4.1 is built from them): alpha_j, rho_j = (r_j, z_j) and
  * gamma_j = (w_j, A w_j) for j < m.  Any pointer may be NULL. */
 krs_status krs_seq_coeffs(krs_seq* s, double* alpha, double* rho, double* gamma, int32_t cap, int32_t* m_out);
+/* Export the preconditioned projected residuals z_0 .. z_{m'-1} of the last
+ * solve kept in the Krylov history (SRKS only; the vectors Algorithm 3
+ * stores to build the Ritz vectors, Section 4.4), as doubles, n x m'
+ * column-major with leading dimension ldz.  m' (m_out) is the number kept:
+ * at most the iteration count, less when the history reservation was
+ * shorter, 0 when no history was kept (TRKS, plain PCG, a full frozen
+ * basis).  Z may be NULL to query m'.  Valid until the next solve. */
+krs_status krs_seq_history(krs_seq* s, double* Z, int64_t ldz, int32_t cap, int32_t* m_out);
 /* Export the current augmentation basis C^(k) of Algorithms 2 and 3 (n x
  * n_c, column-major, leading dim ldc) as doubles; C may be NULL to query n_c
  * only.  After a solve the columns are the A-orthonormalised ones (same
@@ -295,6 +333,23 @@ krs_status krs_server_stats(krs_server* s, krs_server_report* out);
 krs_status krs_server_destroy(krs_server* s);
 
 /* ------------------------------------------------ host-side Ritz logic */
+/* Host only, no device: the complexity analysis of KRS_NC_LIM_AUTO on the
+ * CG coefficients alpha[m], rho[m] of a non-augmented solve (Section 4.4
+ * remark after Algorithm 3; model stated at KRS_NC_LIM_AUTO) with the given
+ * byte costs: bytes_iter0 per iteration without a basis, bytes_col_iter per
+ * basis column per iteration, bytes_rebuild0 + k bytes_col_rebuild for the
+ * rebuild of k > 0 columns.  *nc_lim receives the k in 0..kmax of least
+ * modelled bytes per system (kmax is clipped to the number of distinct Ritz
+ * values less one); cost (NULL, or kmax + 1 doubles) the modelled bytes for
+ * each k; *k_out the clipped kmax. */
+krs_status krs_nc_limit(const double* alpha, const double* rho, int32_t m, double bytes_iter0, double bytes_col_iter,
+                        double bytes_rebuild0, double bytes_col_rebuild, int32_t kmax, double* cost,
+                        int32_t* k_out, int32_t* nc_lim);
+/* Host only, no device: the cluster reselection of KRS_RESELECT_CLUSTER
+ * on Ritz values theta[m] (any order) and a preselection flags[m]
+ * (1 = preselected); on return flags[i] = 1 only for the preselected values
+ * outside the central cluster (Section 4.4). */
+krs_status krs_cluster_reselect(const double* theta, int32_t m, double min_frac, uint8_t* flags);
 /* Pure host computations exposed for testing the library's selection
  * logic; no device is touched.
  * krs_ritz_select: from alpha[m], rho[m] build the Lanczos tridiagonal H_m

@@ -82,13 +82,17 @@ DIRECTION = {"literal": 0, "project_old": 1}
 
 
 def apcg(row_ptr, col_idx, values, b, precond="jacobi", C=None, tol=1e-8, max_iter=None, guard=1e-6,
-         record_z=False, record_w=False, direction="literal", reorth=False):
+         record_z=False, record_w=False, direction="literal", reorth=False, orthonormal=False):
     """One APCG(A, M, C, b) solve (Algorithm 1, standard form; see oracle.c).
 
     ``direction``: 'literal' (w = z + beta w_old, Algorithm 1) or
     'project_old' (w = z + beta P w_old, the same in exact arithmetic).
     ``reorth``: full reorthogonalisation of every new direction against all
     earlier ones (Section 2.1 remark; used in the experiments of Section 5.1).
+    ``orthonormal``: work with the A-orthonormal basis C L^{-T} of the kept
+    columns (G = L L^T) instead of C and the Cholesky factor: the same
+    projector in exact arithmetic, without the condition number of G in its
+    rounding.
 
     Returns a dict with x, m, status, alpha[m], gamma[m], rho[m] (rho_0..rho_{m-1}),
     resnorm[m+1], relres_true, kept (bool per column of C), and Z / W
@@ -117,7 +121,7 @@ def apcg(row_ptr, col_idx, values, b, precond="jacobi", C=None, tol=1e-8, max_it
     st = lib().orc_apcg(n, _p(rp, _I64), _p(ci, _I32), _p(v), PRECOND[precond], _p(Cf), nc, ldc, _p(b), tol,
                         max_iter, guard, _p(x), _p(alpha), _p(rho), _p(gamma), _p(resn), _p(Z), n, _p(W), n,
                         _p(kept, _INT), ctypes.byref(m), ctypes.byref(rel),
-                        DIRECTION[direction] | (2 if reorth else 0))
+                        DIRECTION[direction] | (2 if reorth else 0) | (4 if orthonormal else 0))
     if st in (ORC_INVALID, ORC_NOMEM):
         raise ValueError(f"oracle apcg failed with status {st}")
     m = m.value
@@ -273,16 +277,130 @@ def freeze_pick(idx, th_m, room):
     return sorted(order[:room])
 
 
+def cluster_reselect(th_m, idx, min_frac=0.2):
+    """Drop the central cluster from a preselection (Section 4.4, the
+    reselection behind "clust14").
+
+    The preselected Ritz values (indices ``idx`` into ``th_m``) are sorted
+    ascending, v_1 < ... < v_s, and the distances between neighbours taken on
+    a log scale, g_i = ln(v_{i+1} / v_i).  The sequence g is approximated in
+    the least-squares sense by a piecewise-constant function of three pieces
+    g[0:a], g[a:b], g[b:] (each level the mean of its piece; outer pieces may
+    be empty, not both) whose middle piece covers at least
+    L = ceil(min_frac * s) values (b - a + 1 >= L; one fifth of the preselection
+    for the default, as the paper sets it); ties go to the smaller a,
+    then the smaller b.  When the middle level is below every non-empty
+    outer level, the values v_{a+1}..v_{b+1} (1-based) form the central
+    cluster and are dropped.  Returns the kept indices, ascending.
+    """
+    idx = [int(i) for i in idx]
+    s = len(idx)
+    if s < 3:
+        return sorted(idx)
+    order = sorted(idx, key=lambda i: (th_m[i], i))
+    v = np.array([th_m[i] for i in order], dtype=np.float64)
+    g = np.log(v[1:] / v[:-1])
+    G = len(g)
+    L = max(1, int(math.ceil(min_frac * s - 1e-9)))
+    c1 = np.concatenate([[0.0], np.cumsum(g)])
+    c2 = np.concatenate([[0.0], np.cumsum(g * g)])
+
+    def sse(i, j):  # pieces g[i:j]
+        if j <= i:
+            return 0.0
+        t = c1[j] - c1[i]
+        return (c2[j] - c2[i]) - t * t / (j - i)
+
+    best = None
+    for a in range(0, G + 1):
+        for b in range(a + 1, G + 1):
+            if b - a + 1 < L or (a == 0 and b == G):
+                continue
+            cost = sse(0, a) + sse(a, b) + sse(b, G)
+            if best is None or cost < best[0]:
+                best = (cost, a, b)
+    if best is None:
+        return sorted(idx)
+    _, a, b = best
+    mid = (c1[b] - c1[a]) / (b - a)
+    outer = [(c1[a] - c1[0]) / a] if a > 0 else []
+    if b < G:
+        outer.append((c1[G] - c1[b]) / (G - b))
+    if not all(mid < o for o in outer):
+        return sorted(idx)
+    drop = set(order[a : b + 1])
+    return sorted(i for i in idx if i not in drop)
+
+
+def distinct_ritz_ascending(alpha, rho, merge=1e-10):
+    """Ritz values of H_m ascending, with copies (values within a relative
+    ``merge`` of the previous kept one, as finite-precision Lanczos repeats
+    converged values) counted once."""
+    th = np.sort(ritz_values(alpha, rho)[0])
+    out = []
+    for t in th:
+        if out and abs(t - out[-1]) <= merge * abs(t):
+            continue
+        out.append(float(t))
+    return np.array(out)
+
+
+def nc_limit(alpha, rho, bytes_iter0, bytes_col_iter, bytes_rebuild0, bytes_col_rebuild, kmax, merge=1e-10):
+    """n_c_lim from a complexity analysis (Section 4.4, remark after Algorithm 3).
+
+    Under the assumption that every non-augmented system takes the m_0
+    iterations of the solve that produced (alpha, rho), a system augmented
+    by the eigenvectors of its k lowest eigenvalues converges at the rate of
+    the reduced condition number theta_max / theta_(k+1) (Section 2.2
+    deflation; the CG rate of Section 4.3), so it takes
+        m(k) = max(1, m_0 ln(sigma(kappa_0)) / ln(sigma(kappa_k))),
+        sigma(kappa) = (sqrt(kappa) - 1) / (sqrt(kappa) + 1),
+    iterations, the spectrum taken from the distinct Ritz values.  A solve
+    with k columns moves
+        T(k) = m(k) (bytes_iter0 + k bytes_col_iter) + [k > 0] (bytes_rebuild0 + k bytes_col_rebuild)
+    bytes; n_c_lim is the k in 0..kmax that minimises T (the smaller k on a
+    tie).  Returns (n_c_lim, T as an array over k).
+    """
+    th = distinct_ritz_ascending(alpha, rho, merge)
+    m0 = len(alpha)
+    kmax = int(max(0, min(kmax, len(th) - 1)))
+    tmax = th[-1]
+
+    def lnsig(kappa):
+        if kappa <= 1.0:
+            return -np.inf  # one distinct eigenvalue left: converges at once
+        r = math.sqrt(kappa)
+        return math.log((r - 1.0) / (r + 1.0))
+
+    l0 = lnsig(tmax / th[0])
+    T = np.empty(kmax + 1)
+    for k in range(kmax + 1):
+        lk = lnsig(tmax / th[k])
+        mk = max(1.0, m0 * (l0 / lk)) if np.isfinite(lk) else 1.0
+        T[k] = mk * (bytes_iter0 + k * bytes_col_iter) + ((bytes_rebuild0 + k * bytes_col_rebuild) if k else 0.0)
+    best = int(np.argmin(T))
+    return best, T
+
+
 def solve_sequence(seq, n_systems=None, reuse="srks", precond=None, tol=1e-8, eps=1e-14, cap=0,
-                   cap_policy="freeze", C0=None, max_iter=None, guard=1e-6, keep_x=False):
+                   cap_policy="freeze", C0=None, max_iter=None, guard=1e-6, keep_x=False, cost_model=None,
+                   reselect=None, cluster_min_frac=0.2):
     """Run TRKS / SRKS / plain PCG over systems 0..n_systems-1 of ``seq``.
 
     ``reuse``: 'none' (PCG), 'trks' (Algorithm 2) or 'srks' (Algorithm 3).
     ``cap`` (n_c_lim, 0 = none) with ``cap_policy`` 'restart' (reset the
     basis to C0 once its size reaches the cap, Algorithm 3) or 'freeze'
     (append only while below the cap, smallest Ritz values first).
+    ``reselect='cluster'``: the SRKS preselection is reduced by
+    ``cluster_reselect`` before the cap ("clust", Section 4.4).
+    ``cap='auto'``: n_c_lim from ``nc_limit`` on the first solve's
+    coefficients, with ``cost_model`` = dict(bytes_iter0, bytes_col_iter,
+    bytes_rebuild0, bytes_col_rebuild, kmax).
     Returns one record per system.
     """
+    auto = cap == "auto"
+    if auto:
+        cap = 0
     n_systems = seq.n_systems if n_systems is None else n_systems
     if precond is None:
         precond = "block3" if getattr(seq, "block", 1) == 3 else "jacobi"
@@ -303,24 +421,36 @@ def solve_sequence(seq, n_systems=None, reuse="srks", precond=None, tol=1e-8, ep
         if keep_x:
             rec["x"] = res["x"]
         m = res["m"]
+        if auto and k == 0:
+            cap, _ = nc_limit(res["alpha"], res["rho"], **cost_model)
+            rec["nc_lim"] = cap
+            if cap == 0:
+                cap = -1  # nothing may be appended
         new = np.zeros((n, 0))
         if reuse == "trks" and m > 0:
             cols = list(range(m))
             if cap and cap_policy == "freeze":
                 cols = cols[: max(cap - C.shape[1], 0)]
+            elif cap < 0:
+                cols = []
             new = trks_block(res["W"][:, cols], res["gamma"][cols])
         elif reuse == "srks" and m > 1:
             th_m, th_m1 = ritz_values(res["alpha"], res["rho"])
             sel = srks_select(th_m, th_m1, eps)
             rec["theta"] = th_m
+            rec["preselected"] = list(sel)
+            if reselect == "cluster":
+                sel = cluster_reselect(th_m, sel, cluster_min_frac)
             rec["selected_all"] = list(sel)
             if cap and cap_policy == "freeze":
                 sel = freeze_pick(sel, th_m, cap - C.shape[1])
+            elif cap < 0:
+                sel = []
             rec["selected"] = list(sel)
             new = ritz_block(res["Z"], res["alpha"], res["rho"], sel, th_m)
         rec["added"] = new.shape[1]
         C = np.concatenate([C, new], axis=1) if new.shape[1] else C
-        if cap and cap_policy == "restart" and C.shape[1] >= cap:
+        if cap > 0 and cap_policy == "restart" and C.shape[1] >= cap:
             C = C_init.copy()
             rec["restarted"] = True
         rec["nc_next"] = C.shape[1]

@@ -223,6 +223,41 @@ static int coarse_build(orc_coarse* K, int64_t n, const int64_t* rp, const int32
     return ORC_OK;
 }
 
+/* Replace the kept basis by an A-orthonormal one of the same span:
+ * Ck <- Ck L^{-T}, Qk <- Qk L^{-T} (so Ck^T A Ck = L^{-1} G L^{-T} = I) and
+ * L <- I.  The projector P = I - C G^{-1} (A C)^T is unchanged in exact
+ * arithmetic; its rounding no longer carries the condition number of G. */
+static void coarse_orthonormalize(orc_coarse* K) {
+    const int nk = K->nk;
+    const int64_t n = K->n;
+    if (nk <= 0) return;
+    /* rows of X L^T = Y solved by forward substitution: for each row i,
+     * y_t = (x_t - sum_{k<t} y_k L[t,k]) / L[t,t] */
+    double* row = (double*)malloc(sizeof(double) * (size_t)nk);
+    double* rq = (double*)malloc(sizeof(double) * (size_t)nk);
+    if (!row || !rq) { free(row); free(rq); return; }
+    for (int64_t i = 0; i < n; ++i) {
+        for (int t = 0; t < nk; ++t) {
+            double a = K->Ck[(size_t)t * n + i], q = K->Qk[(size_t)t * n + i];
+            for (int k = 0; k < t; ++k) {
+                const double l = K->L[t + (size_t)k * nk];
+                a -= row[k] * l;
+                q -= rq[k] * l;
+            }
+            row[t] = a / K->L[t + (size_t)t * nk];
+            rq[t] = q / K->L[t + (size_t)t * nk];
+        }
+        for (int t = 0; t < nk; ++t) {
+            K->Ck[(size_t)t * n + i] = row[t];
+            K->Qk[(size_t)t * n + i] = rq[t];
+        }
+    }
+    for (int a = 0; a < nk; ++a)
+        for (int b = 0; b < nk; ++b) K->L[a + (size_t)b * nk] = (a == b) ? 1.0 : 0.0;
+    free(row);
+    free(rq);
+}
+
 static void coarse_free(orc_coarse* K) {
     free(K->kept); free(K->Ck); free(K->Qk); free(K->L); free(K->tmp);
     memset(K, 0, sizeof(*K));
@@ -277,6 +312,9 @@ static void mu_h(const double* Qall, const double* gam, int64_t n, int i, const 
  *     projector applied to the old direction too (P w_j = w_j in exact
  *     arithmetic, so this is the same iteration; it is the library's
  *     default form, kept here to measure what the difference does).
+ *   ORC_OPT_ORTHONORMAL: after the guarded Cholesky G = L L^T of the kept
+ *     columns, work with the A-orthonormal basis C L^{-T} (same span, same
+ *     projector in exact arithmetic) instead of C and the factor.
  *   ORC_OPT_REORTH: full reorthogonalisation, which the paper states APCG
  *     admits (Section 2.1) and uses in every experiment (Section 5.1): the
  *     next direction is z_{j+1} made A-orthogonal to every earlier one,
@@ -286,7 +324,7 @@ static void mu_h(const double* Qall, const double* gam, int64_t n, int i, const 
  *     equals beta_{j+1} w_j.  rho and beta keep their definitions, so the
  *     Lanczos coefficients of Section 4.1 are unchanged.
  */
-enum { ORC_OPT_PROJECT_OLD = 1, ORC_OPT_REORTH = 2 };
+enum { ORC_OPT_PROJECT_OLD = 1, ORC_OPT_REORTH = 2, ORC_OPT_ORTHONORMAL = 4 };
 
 int orc_apcg(int64_t n, const int64_t* rp, const int32_t* ci, const double* av, int precond,
              const double* C, int nc, int64_t ldc, const double* b, double tol, int max_iter, double guard,
@@ -300,6 +338,7 @@ int orc_apcg(int64_t n, const int64_t* rp, const int32_t* ci, const double* av, 
     orc_coarse K;
     st = coarse_build(&K, n, rp, ci, av, C, nc, ldc, guard, kept);
     if (st != ORC_OK) { prec_free(&P); coarse_free(&K); return st; }
+    if (opts & ORC_OPT_ORTHONORMAL) coarse_orthonormalize(&K);
 
     double* r = (double*)malloc(sizeof(double) * (size_t)n);
     double* s = (double*)malloc(sizeof(double) * (size_t)n);

@@ -33,6 +33,7 @@ PRECISION = {"fp64": 0, "mixed": 1, "fp32": 2, "fp32basis": 3}
 REUSE = {"none": 0, "total": 1, "trks": 1, "selective": 2, "srks": 2}
 PRECOND = {"jacobi": 0, "bjacobi3": 1, "block3": 1}
 CAP_POLICY = {"restart": 0, "freeze": 1, "cost": 2}
+NC_LIM_AUTO = -1  # max_basis: n_c_lim from the complexity analysis on the first solve
 
 _D = ctypes.POINTER(ctypes.c_double)
 _I64 = ctypes.POINTER(ctypes.c_int64)
@@ -63,6 +64,8 @@ class SeqDesc(ctypes.Structure):
         ("update_rows", ctypes.c_int32),
         ("autotune", ctypes.c_int32),
         ("kernel_flags", ctypes.c_int32),
+        ("reselect", ctypes.c_int32),
+        ("cluster_min_frac", ctypes.c_double),
     ]
 
 
@@ -83,6 +86,8 @@ class SolveInfo(ctypes.Structure):
         ("t_iter_ms", ctypes.c_double),
         ("t_recycle_ms", ctypes.c_double),
         ("model_bytes", ctypes.c_int64),
+        ("n_c_lim", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -146,6 +151,7 @@ SIGNATURES = [
     ("krs_seq_ritz", _S, [_P, _D, _U8, ctypes.c_int32, _I32]),
     ("krs_seq_coeffs", _S, [_P, _D, _D, _D, ctypes.c_int32, _I32]),
     ("krs_seq_basis", _S, [_P, _D, ctypes.c_int64, ctypes.c_int32, _I32]),
+    ("krs_seq_history", _S, [_P, _D, ctypes.c_int64, ctypes.c_int32, _I32]),
     ("krs_seq_info", _S, [_P, ctypes.POINTER(SolveInfo)]),
     ("krs_seq_set_timing", _S, [_P, ctypes.c_int32]),
     ("krs_seq_kernel_time", _S, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), _D]),
@@ -159,6 +165,9 @@ SIGNATURES = [
     ("krs_server_poll", _S, [_P, ctypes.POINTER(Completion), ctypes.c_int32, _I32, ctypes.c_int32]),
     ("krs_server_stats", _S, [_P, ctypes.POINTER(ServerStats)]),
     ("krs_server_destroy", _S, [_P]),
+    ("krs_nc_limit", _S, [_D, _D, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                          ctypes.c_double, ctypes.c_int32, _D, _I32, _I32]),
+    ("krs_cluster_reselect", _S, [_D, ctypes.c_int32, ctypes.c_double, _U8]),
     ("krs_ritz_select", _S, [_D, _D, ctypes.c_int32, ctypes.c_double, _D, _D, _U8]),
     ("krs_coarse_factor", _S, [ctypes.c_int32, _D, ctypes.c_double, _D, _U8, _I32]),
 ]
@@ -210,6 +219,31 @@ def ritz_select(alpha, rho, eps):
     _check(_lib.krs_ritz_select(_dptr(alpha), _dptr(rho), m, float(eps), _dptr(th), _dptr(th1),
                                 sel.ctypes.data_as(_U8)), "krs_ritz_select")
     return th[:m], th1[: max(m - 1, 0)], sel[:m].astype(bool)
+
+
+def nc_limit(alpha, rho, bytes_iter0, bytes_col_iter, bytes_rebuild0, bytes_col_rebuild, kmax):
+    """Library's complexity analysis for n_c_lim (no device used).
+
+    Returns (n_c_lim, modelled bytes per system for k = 0..kmax')."""
+    alpha = np.ascontiguousarray(alpha, dtype=np.float64)
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    cost = np.zeros(int(kmax) + 1)
+    k = ctypes.c_int32(0)
+    nl = ctypes.c_int32(0)
+    _check(_lib.krs_nc_limit(_dptr(alpha), _dptr(rho), len(alpha), float(bytes_iter0), float(bytes_col_iter),
+                             float(bytes_rebuild0), float(bytes_col_rebuild), int(kmax), _dptr(cost),
+                             ctypes.byref(k), ctypes.byref(nl)), "krs_nc_limit")
+    return nl.value, cost[: k.value + 1]
+
+
+def cluster_reselect(theta, selected, min_frac=0.2):
+    """Library's cluster reselection (no device used): theta (any order) and
+    a bool preselection; returns the bool flags kept."""
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    fl = np.ascontiguousarray(np.asarray(selected, dtype=bool).astype(np.uint8))
+    _check(_lib.krs_cluster_reselect(_dptr(th), len(th), float(min_frac), fl.ctypes.data_as(_U8)),
+           "krs_cluster_reselect")
+    return fl.astype(bool)
 
 
 def coarse_factor(G, rank_tol=1e-6):
@@ -331,7 +365,8 @@ class Sequence:
     def __init__(self, ctx: Context, row_ptr, col_idx, n, block=1, precision="fp64", reuse="selective",
                  precond=None, cap_policy="freeze", tol=1e-8, max_iter=10000, ritz_eps=1e-14, max_basis=0,
                  refine_every=0, history_cap=0, rank_tol=0.0, refine_drop=0.0, C0=None, eager=False,
-                 update_rows=0, autotune=False, separate_finalize=False, literal_direction=False):
+                 update_rows=0, autotune=False, separate_finalize=False, literal_direction=False, reselect=None,
+                 cluster_min_frac=0.0):
         self.ctx = ctx
         self.n = int(n)
         self.block = int(block)
@@ -362,6 +397,8 @@ class Sequence:
         d.update_rows = update_rows
         d.autotune = 1 if autotune else 0
         d.kernel_flags = (1 if separate_finalize else 0) | (2 if literal_direction else 0)
+        d.reselect = {None: 0, "none": 0, "cluster": 1}[reselect]
+        d.cluster_min_frac = cluster_min_frac
         self.desc = d
         h = ctypes.c_void_p()
         if C0 is not None and C0.shape[1] > 0:
@@ -441,6 +478,14 @@ class Sequence:
         k = ctypes.c_int32(0)
         _check(_lib.krs_seq_basis(self.handle, _dptr(C), self.n, C.shape[1], ctypes.byref(k)), "krs_seq_basis")
         return C[:, :nc]
+
+    def history(self):
+        """z_j kept in the Krylov history by the last solve (n x m', float64)."""
+        m = ctypes.c_int32(0)
+        _check(_lib.krs_seq_history(self.handle, None, self.n, 0, ctypes.byref(m)), "krs_seq_history")
+        Z = np.zeros((self.n, max(m.value, 1)), order="F")
+        _check(_lib.krs_seq_history(self.handle, _dptr(Z), self.n, Z.shape[1], ctypes.byref(m)), "krs_seq_history")
+        return Z[:, : m.value]
 
     def set_timing(self, enable=True):
         _check(_lib.krs_seq_set_timing(self.handle, 1 if enable else 0), "krs_seq_set_timing")
@@ -534,5 +579,5 @@ def sequence_for(ctx, seq, **kw):
     return Sequence(ctx, seq.row_ptr, seq.col_idx, seq.n, block=getattr(seq, "block", 1), **kw)
 
 
-__all__ = ["Context", "Sequence", "Server", "KrsError", "ritz_select", "coarse_factor", "sequence_for", "version", "lib",
+__all__ = ["Context", "Sequence", "Server", "KrsError", "ritz_select", "nc_limit", "cluster_reselect", "coarse_factor", "sequence_for", "version", "lib",
            "SIGNATURES", "LIB_PATH"]

@@ -5,7 +5,9 @@
 #include <exception>
 #include <memory>
 #include <new>
+#include <algorithm>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "seq.h"
@@ -116,7 +118,8 @@ krs_status krs_seq_create(krs_ctx* ctx, const krs_seq_desc* d, const double* C0,
     }
     *out = nullptr;
     if (d->n <= 0 || (d->block != 1 && d->block != 3) || d->n % d->block != 0 || d->nnzb <= 0 || !d->row_ptr ||
-        !d->col_idx || d->tol <= 0.0 || d->max_iter < 0 || m0 < 0 || d->max_basis < 0 || d->history_cap < 0 ||
+        !d->col_idx || d->tol <= 0.0 || d->max_iter < 0 || m0 < 0 || d->max_basis < KRS_NC_LIM_AUTO ||
+        d->history_cap < 0 ||
         d->refine_every < 0) {
         set_error("invalid sequence description");
         return KRS_E_INVALID;
@@ -124,6 +127,16 @@ krs_status krs_seq_create(krs_ctx* ctx, const krs_seq_desc* d, const double* C0,
     if (d->precision != KRS_FP64 && d->precision != KRS_MIXED && d->precision != KRS_FP32 &&
         d->precision != KRS_FP32_BASIS) {
         set_error("unknown precision");
+        return KRS_E_INVALID;
+    }
+    if (d->reselect != 0 && (d->reselect != KRS_RESELECT_CLUSTER || d->reuse != KRS_REUSE_SELECTIVE ||
+                             d->cluster_min_frac < 0.0 || d->cluster_min_frac > 1.0)) {
+        set_error("cluster reselection needs selective reuse and 0 <= cluster_min_frac <= 1");
+        return KRS_E_INVALID;
+    }
+    if (d->max_basis == KRS_NC_LIM_AUTO &&
+        (d->reuse != KRS_REUSE_SELECTIVE || (d->cap_policy != KRS_CAP_RESTART && d->cap_policy != KRS_CAP_FREEZE))) {
+        set_error("KRS_NC_LIM_AUTO needs selective reuse with the restart or freeze cap");
         return KRS_E_INVALID;
     }
     if (d->reuse != KRS_REUSE_NONE && d->reuse != KRS_REUSE_TOTAL && d->reuse != KRS_REUSE_SELECTIVE) {
@@ -279,6 +292,17 @@ krs_status krs_seq_coeffs(krs_seq* s, double* alpha, double* rho, double* gamma,
     KRS_GUARD_END
 }
 
+krs_status krs_seq_history(krs_seq* s, double* Z, int64_t ldz, int32_t cap, int32_t* m_out) {
+    KRS_GUARD_BEGIN
+    if (!s) return KRS_E_INVALID;
+    if (s->impl->in_server.load() > 0) {
+        set_error("the sequence has server requests in flight");
+        return KRS_E_BUSY;
+    }
+    return s->impl->history(Z, ldz, cap, m_out);
+    KRS_GUARD_END
+}
+
 krs_status krs_seq_basis(krs_seq* s, double* C, int64_t ldc, int32_t cap, int32_t* n_c) {
     KRS_GUARD_BEGIN
     if (!s) return KRS_E_INVALID;
@@ -331,6 +355,58 @@ krs_status krs_seq_destroy(krs_seq* s) {
     s->impl->destroy();
     ctx->live_seqs -= 1;
     delete s;
+    return KRS_OK;
+    KRS_GUARD_END
+}
+
+krs_status krs_nc_limit(const double* alpha, const double* rho, int32_t m, double bytes_iter0, double bytes_col_iter,
+                        double bytes_rebuild0, double bytes_col_rebuild, int32_t kmax, double* cost,
+                        int32_t* k_out, int32_t* nc_lim) {
+    KRS_GUARD_BEGIN
+    if (!nc_lim || m < 0 || kmax < 0 || (m > 0 && (!alpha || !rho))) {
+        set_error("alpha, rho and nc_lim are required");
+        return KRS_E_INVALID;
+    }
+    for (int j = 0; j < m; ++j)
+        if (!(alpha[j] > 0.0) || !(rho[j] > 0.0)) {
+            set_error("coefficients must be positive");
+            return KRS_E_INVALID;
+        }
+    krs::NcCostModel cm;
+    cm.bytes_iter0 = bytes_iter0;
+    cm.bytes_col_iter = bytes_col_iter;
+    cm.bytes_rebuild0 = bytes_rebuild0;
+    cm.bytes_col_rebuild = bytes_col_rebuild;
+    cm.kmax = kmax;
+    std::vector<double> c;
+    const unsigned hc = std::thread::hardware_concurrency();
+    *nc_lim = krs::nc_limit(alpha, rho, m, cm, (int)std::min(16u, std::max(1u, hc)), &c);
+    if (k_out) *k_out = c.empty() ? 0 : (int32_t)c.size() - 1;
+    if (cost)
+        for (size_t k = 0; k < c.size(); ++k) cost[k] = c[k];
+    return KRS_OK;
+    KRS_GUARD_END
+}
+
+krs_status krs_cluster_reselect(const double* theta, int32_t m, double min_frac, uint8_t* flags) {
+    KRS_GUARD_BEGIN
+    if (m < 0 || (m > 0 && (!theta || !flags)) || !(min_frac > 0.0) || min_frac > 1.0) {
+        set_error("theta and flags are required, 0 < min_frac <= 1");
+        return KRS_E_INVALID;
+    }
+    std::vector<double> th(theta, theta + m);
+    std::vector<int> sel;
+    for (int i = 0; i < m; ++i) {
+        if (!flags[i]) continue;
+        if (!(theta[i] > 0.0)) {
+            set_error("preselected Ritz values must be positive");
+            return KRS_E_INVALID;
+        }
+        sel.push_back(i);
+    }
+    const std::vector<int> keep = krs::cluster_reselect(th, sel, min_frac);
+    for (int i = 0; i < m; ++i) flags[i] = 0;
+    for (int i : keep) flags[i] = 1;
     return KRS_OK;
     KRS_GUARD_END
 }

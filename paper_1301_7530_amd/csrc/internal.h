@@ -34,9 +34,11 @@ constexpr int64_t kMaxTimedGrid = 8192;
 // system's reductions (and results) are the same in both.
 // Row length of the row-major A C: the next power of two of at least 4
 // elements up to 32 columns (16-byte segments, whole rows per 128-byte
-// chunk), else a multiple of 32 (128-byte chunks of FP32 values).
-inline int64_t ac_leading_dim(int64_t nc) {
-    if (nc > 32) return (nc + 31) & ~(int64_t)31;
+// chunk), else a multiple of the 128-byte chunk the projection reads
+// (32 FP32 or 16 FP64 values).
+inline int64_t ac_leading_dim(int64_t nc, int64_t elem_bytes) {
+    const int64_t cw = 128 / elem_bytes;
+    if (nc > 32) return (nc + cw - 1) / cw * cw;
     int64_t l = 4;
     while (l < nc) l *= 2;
     return l;
@@ -124,7 +126,7 @@ struct SysView {
     int32_t nc;      // columns of C in this solve
     int32_t pad0;
     const V* C;      // n x nc column-major, leading dim ldc (a multiple of 256 >= n)
-    const V* AC;     // n x nc row-major, leading dim ldac = ac_leading_dim(nc)
+    const V* AC;     // n x nc row-major, leading dim ldac = ac_leading_dim(nc, sizeof(V))
     int64_t ldc;
     int64_t ldac;
     const double* Ginv;  // nc x nc column-major
@@ -255,6 +257,22 @@ void qd_eigenvalues_desc(const QdArray& z, std::vector<double>& theta, int threa
 // Eigenvector (unit 2-norm) of the explicit tridiagonal (diag, off) for eigenvalue theta.
 void tridiag_eigvec(const std::vector<double>& diag, const std::vector<double>& off, double theta,
                     std::vector<double>& v);
+// Byte costs of the complexity analysis behind n_c_lim (Section 4.4): one
+// iteration without a basis, the extra bytes per basis column per
+// iteration, the per-system rebuild of a non-empty basis and its extra
+// bytes per column.
+struct NcCostModel {
+    double bytes_iter0 = 0.0, bytes_col_iter = 0.0, bytes_rebuild0 = 0.0, bytes_col_rebuild = 0.0;
+    int kmax = 0;
+};
+// n_c_lim from the CG coefficients of a solve taken as the non-augmented
+// iteration count of every system; cost (optional) receives the modelled
+// bytes per system for k = 0..kmax' (kmax' = kmax clipped to the spectrum).
+int nc_limit(const double* alpha, const double* rho, int m, const NcCostModel& cm, int threads,
+             std::vector<double>* cost);
+// Cluster reselection (Section 4.4, "clust"): the preselected indices sel
+// into theta without the central cluster, ascending.
+std::vector<int> cluster_reselect(const std::vector<double>& theta, const std::vector<int>& sel, double min_frac);
 // Stagnation selection (Section 4.4) on descending theta_m / theta_{m-1}.
 std::vector<int> stagnation_select(const std::vector<double>& th_m, const std::vector<double>& th_m1, double eps);
 // Cholesky with rank guard + explicit inverse (coarse.cpp). Returns kept count.

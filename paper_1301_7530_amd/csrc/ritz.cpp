@@ -168,6 +168,59 @@ void qd_eigenvalues_desc(const QdArray& z, std::vector<double>& theta, int threa
     for (int k = 0; k < m; ++k) theta[m - 1 - k] = asc[k];
 }
 
+// n_c_lim by a complexity analysis (Section 4.4, after Algorithm 3).  The
+// m_0 iterations of the given solve stand for every non-augmented system.
+// Deflating the eigenvectors of the k lowest eigenvalues leaves the CG rate
+// of the reduced condition number theta_max / theta_(k+1) (Section 2.2 and
+// the rate of Section 4.3), so an augmented solve is modelled at
+//   m(k) = max(1, m_0 ln(sigma_0) / ln(sigma_k)),  sigma = (sqrt(kappa)-1)/(sqrt(kappa)+1),
+// iterations over the distinct Ritz values (finite-precision Lanczos
+// repeats converged values: a value within a relative 1e-10 of the last
+// kept one is a copy), and moves
+//   T(k) = m(k) (bytes_iter0 + k bytes_col_iter) + [k > 0] (bytes_rebuild0 + k bytes_col_rebuild)
+// bytes per system.  n_c_lim minimises T over k = 0..kmax (the smaller k on
+// a tie).  Only the low end of the spectrum and its top are computed.
+int nc_limit(const double* alpha, const double* rho, int m, const NcCostModel& cm, int threads,
+             std::vector<double>* cost) {
+    if (cost) cost->clear();
+    if (m <= 0) return 0;
+    const QdArray z = qd_from_cg(alpha, rho, m);
+    std::vector<double> asc(m, 0.0);  // out[k] at the absolute rank k
+    qd_eigenvalues_asc(z, m - 1, m, asc.data(), 1);
+    const double top = asc[m - 1];
+    std::vector<double> distinct;
+    const int want = std::max(0, cm.kmax) + 1;
+    const int CH = 256;
+    for (int k = 0; k < m && (int)distinct.size() < want; k += CH) {
+        const int k1 = std::min(m, k + CH);
+        qd_eigenvalues_asc(z, k, k1, asc.data(), threads);
+        for (int t = k; t < k1 && (int)distinct.size() < want; ++t)
+            if (distinct.empty() || std::fabs(asc[t] - distinct.back()) > 1e-10 * std::fabs(asc[t]))
+                distinct.push_back(asc[t]);
+    }
+    const int kmax = std::min(std::max(0, cm.kmax), (int)distinct.size() - 1);
+    auto log_rate = [](double kappa) {
+        if (!(kappa > 1.0)) return -std::numeric_limits<double>::infinity();
+        const double r = std::sqrt(kappa);
+        return std::log((r - 1.0) / (r + 1.0));
+    };
+    const double l0 = log_rate(top / distinct[0]);
+    int best = 0;
+    double best_t = 0.0;
+    for (int k = 0; k <= kmax; ++k) {
+        const double lk = log_rate(top / distinct[k]);
+        const double mk = std::isfinite(lk) ? std::max(1.0, (double)m * (l0 / lk)) : 1.0;
+        const double t = mk * (cm.bytes_iter0 + k * cm.bytes_col_iter) +
+                         (k > 0 ? cm.bytes_rebuild0 + k * cm.bytes_col_rebuild : 0.0);
+        if (cost) cost->push_back(t);
+        if (k == 0 || t < best_t) {
+            best = k;
+            best_t = t;
+        }
+    }
+    return best;
+}
+
 // Twisted factorisation of T - theta I = N_r Delta_r N_r^T: the top-down
 // and bottom-up triangular factorisations meet at the index r where the
 // twist element |gamma_r| is smallest; the eigenvector solves
@@ -217,6 +270,67 @@ void tridiag_eigvec(const std::vector<double>& diag, const std::vector<double>& 
         if (std::fabs(v[i]) > std::fabs(v[im])) im = i;
     const double sc = (v[im] < 0 ? -1.0 : 1.0) / nrm;
     for (double& x : v) x *= sc;
+}
+
+// Reselection by cluster identification (Section 4.4, "clust"): of the
+// preselected Ritz values, drop the central cluster.  The sorted values'
+// neighbour distances on a log scale are fitted, in least squares, by a
+// three-level step function (outer levels over the low and high ends, which
+// may be empty but not both, and a middle level over at least
+// ceil(min_frac * s) values); when the middle level lies below the outer
+// ones its values are the cluster.  Exhaustive over the two breakpoints
+// with running sums (s is at most a few hundred).
+std::vector<int> cluster_reselect(const std::vector<double>& theta, const std::vector<int>& sel, double min_frac) {
+    const int s = (int)sel.size();
+    if (s < 3) {
+        std::vector<int> out(sel);
+        std::sort(out.begin(), out.end());
+        return out;
+    }
+    std::vector<int> ord(sel);
+    std::sort(ord.begin(), ord.end(), [&](int i, int j) {
+        if (theta[i] != theta[j]) return theta[i] < theta[j];
+        return i < j;
+    });
+    const int G = s - 1;
+    std::vector<long double> S1(G + 1, 0.0L), S2(G + 1, 0.0L);
+    for (int i = 0; i < G; ++i) {
+        const double d = std::log(theta[ord[i + 1]] / theta[ord[i]]);
+        S1[i + 1] = S1[i] + d;
+        S2[i + 1] = S2[i] + (long double)d * d;
+    }
+    auto piece = [&](int i, int j) -> long double {  // squared deviation of g[i..j)
+        if (j <= i) return 0.0L;
+        const long double t = S1[j] - S1[i];
+        return (S2[j] - S2[i]) - t * t / (j - i);
+    };
+    const int L = std::max(1, (int)std::ceil(min_frac * s - 1e-9));
+    int ba = -1, bb = -1;
+    long double best = 0.0L;
+    for (int a = 0; a <= G; ++a)
+        for (int b = std::max(a + 1, a + L - 1); b <= G; ++b) {
+            if (a == 0 && b == G) continue;
+            const long double c = piece(0, a) + piece(a, b) + piece(b, G);
+            if (ba < 0 || c < best) {
+                best = c;
+                ba = a;
+                bb = b;
+            }
+        }
+    std::vector<int> out;
+    bool drop_mid = ba >= 0;
+    if (drop_mid) {
+        const long double mid = (S1[bb] - S1[ba]) / (bb - ba);
+        if (ba > 0 && !(mid < S1[ba] / ba)) drop_mid = false;
+        if (bb < G && !(mid < (S1[G] - S1[bb]) / (G - bb))) drop_mid = false;
+    }
+    std::vector<uint8_t> dropped(theta.size(), 0);
+    if (drop_mid)
+        for (int t = ba; t <= bb; ++t) dropped[ord[t]] = 1;
+    for (int i : sel)
+        if (!dropped[i]) out.push_back(i);
+    std::sort(out.begin(), out.end());
+    return out;
 }
 
 std::vector<int> stagnation_select(const std::vector<double>& th_m, const std::vector<double>& th_m1, double eps) {

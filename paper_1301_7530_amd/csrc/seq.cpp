@@ -138,6 +138,7 @@ krs_status SeqImpl<V, W>::create(const krs_seq_desc& d, const double* C0, int32_
     if (desc.rank_tol <= 0.0) desc.rank_tol = 1e-6;
     if (desc.refine_drop == 0.0) desc.refine_drop = 0.1;
     if (desc.ritz_eps <= 0.0) desc.ritz_eps = 1e-14;
+    if (desc.cluster_min_frac <= 0.0) desc.cluster_min_frac = 0.2;
     const int64_t* rp = d.row_ptr;
     const int32_t* ci = d.col_idx;
     // ---- sliced ELL layout
@@ -455,7 +456,7 @@ template <typename V, typename W>
 krs_status SeqImpl<V, W>::coarse_pass(std::vector<double>& G) {
     const size_t nn = (size_t)nc * nc;
     const bool need_v = !std::is_same<V, double>::value;
-    ldac = ac_leading_dim(nc);
+    ldac = ac_leading_dim(nc, sizeof(V));
     if (!d_AC64.reserve(ctx, (size_t)n * ldac * sizeof(double)) ||
         (need_v && !d_ACv.reserve(ctx, (size_t)n * ldac * sizeof(V))) || !d_G.reserve(ctx, nn * sizeof(double)) ||
         !d_Ginv.reserve(ctx, nn * sizeof(double)) || !d_mu.reserve(ctx, 3072 * sizeof(double))) {
@@ -571,8 +572,8 @@ int64_t SeqImpl<V, W>::working_bytes() const {
     int64_t hist = 0;
     if (desc.reuse == KRS_REUSE_SELECTIVE && history_needed())
         hist = desc.history_cap > 0 ? std::min(desc.history_cap, max_iter + 1) : max_iter + 1;
-    const int ncmax = std::max(nc, desc.max_basis > 0 ? desc.max_basis : nc);
-    const int64_t ldm = ac_leading_dim(ncmax);
+    const int ncmax = std::max(nc, has_cap() ? cap_value() : nc);
+    const int64_t ldm = ac_leading_dim(ncmax, sizeof(V));
     const int64_t vsz = std::is_same<V, double>::value ? 0 : (int64_t)sizeof(V);
     int64_t b = ldc * hist * (int64_t)sizeof(V);                       // Z history
     b += n * ldm * (8 + vsz);                                          // A C (double and V)
@@ -859,7 +860,9 @@ krs_status SeqImpl<V, W>::end_solve(double* x, bool device_x, krs_solve_info* in
     inf.t_rebuild_ms = t0;
     inf.t_iter_ms = t1;
     inf.t_recycle_ms = 0.0;
-    inf.model_bytes = model_bytes_per_iter() * m;
+    inf.model_bytes = model_bytes_per_iter(false) * m;
+    inf.n_c_lim = has_cap() ? cap_value() : (desc.max_basis < 0 ? -1 : 0);
+    cost_bytes_last = model_bytes_per_iter(true) * m;
     krs_status rs = KRS_OK;
     if (h_st->status == ST_MAXIT) rs = KRS_E_MAXIT;
     else if (h_st->status == ST_BREAKDOWN) rs = KRS_E_NOT_SPD;
@@ -876,18 +879,26 @@ krs_status SeqImpl<V, W>::end_solve(double* x, bool device_x, krs_solve_info* in
 }
 
 template <typename V, typename W>
-int64_t SeqImpl<V, W>::model_bytes_per_iter() const {
-    // B_A + B_M + 11 n p_w + 2 n p_x + n (ldac + nc) p;
-    // p: matrix / basis storage, p_w: Krylov vectors, p_x = 8
+int64_t SeqImpl<V, W>::model_bytes_per_iter(bool padded) const {
+    // Algorithmic bytes of one iteration: B_A + B_M + 10 n p_w + 2 n p_x
+    // (+ n p for the history column z_j when one is kept) + 2 n n_c p;
+    // p: matrix / basis storage, p_w: Krylov vectors, p_x = 8.
+    // `padded`: the cost cap's figure instead, which counts the padded rows
+    // of A C that the update kernel streams and a z column for every
+    // selective-reuse iteration.
     const int64_t p = sizeof(V), pw = sizeof(W);
     const int64_t pa = op64() ? 8 : p;  // matrix value bytes
     const int64_t nnz = nnzb * B * B;
     const int64_t BA = (B == 1) ? nnz * (pa + 4) : nnz * pa + 4 * nnzb;
     const int64_t BM = (B == 1) ? n * p : 3 * n * p;
-    const int64_t vec = 11 * n * pw + 2 * n * 8 - (desc.reuse == KRS_REUSE_SELECTIVE ? 0 : n * pw);
-    // the projector streams the padded rows of A C, the correction C
-    const int64_t basis = nc > 0 ? n * (ac_leading_dim(nc) + nc) * p : 0;
-    return BA + BM + vec + basis;
+    if (padded) {
+        const int64_t vec = 11 * n * pw + 2 * n * 8 - (desc.reuse == KRS_REUSE_SELECTIVE ? 0 : n * pw);
+        const int64_t basis = nc > 0 ? n * (ac_leading_dim(nc, sizeof(V)) + nc) * p : 0;
+        return BA + BM + vec + basis;
+    }
+    const bool z_kept = desc.reuse == KRS_REUSE_SELECTIVE && history_kept > 0;
+    const int64_t vec = 10 * n * pw + 2 * n * 8 + (z_kept ? n * p : 0);
+    return BA + BM + vec + 2 * n * (int64_t)nc * p;
 }
 
 // ------------------------------------------------------------- recycle
@@ -925,7 +936,7 @@ krs_status SeqImpl<V, W>::recycle_plan() {
     // trial in a row).
     bool append_ok = true;
     if (desc.cap_policy == KRS_CAP_COST) {
-        const int64_t cost = info_last.model_bytes;
+        const int64_t cost = cost_bytes_last;
         if (info_last.n_c <= nc0) {
             ref_cost = cost;
             if (cost_hold > 0) {
@@ -944,7 +955,24 @@ krs_status SeqImpl<V, W>::recycle_plan() {
             cost_fails = 0;
         }
     }
-    const bool capped = desc.max_basis > 0 && (desc.cap_policy == KRS_CAP_FREEZE || desc.cap_policy == KRS_CAP_COST);
+    if (desc.max_basis < 0 && nc_lim_auto < 0 && m > 0) {
+        // n_c_lim by the complexity analysis of Section 4.4 on this first
+        // solve, with the byte model of the iteration (basis columns in V)
+        NcCostModel cm;
+        const int64_t p = sizeof(V), pw = sizeof(W);
+        const int64_t pa = op64() ? 8 : p;
+        const int64_t nnz = nnzb * B * B;
+        const int64_t BA = (B == 1) ? nnz * (pa + 4) : nnz * pa + 4 * nnzb;
+        const int64_t BM = (B == 1) ? n * p : 3 * n * p;
+        cm.bytes_iter0 = (double)(BA + BM + 10 * n * pw + 2 * n * 8);
+        cm.bytes_col_iter = 2.0 * n * p;
+        cm.bytes_rebuild0 = (double)BA;
+        cm.bytes_col_rebuild = 7.0 * n * p;
+        cm.kmax = std::min(1024, m - 1);
+        const int nt = recycle_threads > 0 ? recycle_threads : host_threads();
+        nc_lim_auto = nc_limit(coef_alpha.data(), coef_rho.data(), m, cm, nt, nullptr);
+    }
+    const bool capped = has_cap() && (desc.cap_policy == KRS_CAP_FREEZE || desc.cap_policy == KRS_CAP_COST);
     if (!append_ok) {
         // nothing appended
     } else if (desc.reuse == KRS_REUSE_TOTAL && m > 0) {
@@ -957,7 +985,8 @@ krs_status SeqImpl<V, W>::recycle_plan() {
             plan.kind = 1;
             plan.add = cnt;
         }
-    } else if (desc.reuse == KRS_REUSE_SELECTIVE && m > 1 && !(capped && nc >= desc.max_basis)) {
+    } else if (desc.reuse == KRS_REUSE_SELECTIVE && m > 1 && !(capped && nc >= cap_value()) &&
+               !(has_cap() && cap_value() == 0)) {
         // (with a full frozen basis nothing could be appended: no extraction)
         const int hist = h_st->hist_cap;
         // leading part of the Lanczos run: within the kept history and
@@ -968,7 +997,9 @@ krs_status SeqImpl<V, W>::recycle_plan() {
             const QdArray zm = qd_from_cg(coef_alpha.data(), coef_rho.data(), mu);
             const QdArray zm1 = qd_leading(zm, mu - 1);
             const int nt = recycle_threads > 0 ? recycle_threads : host_threads();
-            const bool frozen = capped;
+            // the frozen scan stops at the room; a reselection needs the
+            // whole preselection first
+            const bool frozen = capped && desc.reselect == 0;
             std::vector<double> th_m(mu, 0.0);  // descending (Algorithm 3 order)
             std::vector<int> sel;               // descending indices, ascending order
             if (!frozen) {
@@ -976,10 +1007,23 @@ krs_status SeqImpl<V, W>::recycle_plan() {
                 qd_eigenvalues_desc(zm, th_m, nt);
                 qd_eigenvalues_desc(zm1, th_m1, nt);
                 sel = stagnation_select(th_m, th_m1, desc.ritz_eps);
+                if (desc.reselect == KRS_RESELECT_CLUSTER) sel = cluster_reselect(th_m, sel, desc.cluster_min_frac);
                 last_theta = th_m;
                 last_sel.assign(mu, 0);
                 for (int i : sel) last_sel[i] = 1;
                 last_selected = (int)sel.size();
+                if (capped) {
+                    // fill the room smallest theta first, ties to the lower index
+                    const int room = std::max(0, cap_value() - nc);
+                    std::vector<int> cand(sel);
+                    std::stable_sort(cand.begin(), cand.end(), [&](int i, int j) {
+                        if (th_m[i] != th_m[j]) return th_m[i] < th_m[j];
+                        return i < j;
+                    });
+                    if ((int)cand.size() > room) cand.resize(room);
+                    std::sort(cand.begin(), cand.end());
+                    sel = cand;
+                }
             } else {
                 // Smallest Ritz values first (the order in which a frozen
                 // basis is filled): a_k, b_k are the k-th smallest
@@ -991,7 +1035,7 @@ krs_status SeqImpl<V, W>::recycle_plan() {
                 // of H_{m-1} that can lie within eps |a_k| of it, so the test
                 // is whether H_{m-1} has an eigenvalue in that window: two
                 // inertia counts instead of bisecting H_{m-1}'s spectrum.
-                const int room = std::max(0, desc.max_basis - nc);
+                const int room = std::max(0, cap_value() - nc);
                 std::vector<double> a(mu);
                 std::vector<int> sel_asc;
                 bool have_cut = false, stop = false;
@@ -1065,6 +1109,7 @@ krs_status SeqImpl<V, W>::recycle_plan() {
     }
     info_last.added = plan.add;
     info_last.selected = last_selected;
+    info_last.n_c_lim = has_cap() ? cap_value() : (desc.max_basis < 0 ? -1 : 0);
     plan.host_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     return KRS_OK;
 }
@@ -1101,7 +1146,7 @@ krs_status SeqImpl<V, W>::recycle_apply(int32_t* n_added) {
         nc += s;
     }
     // restart cap (Algorithm 3, last step)
-    if (desc.max_basis > 0 && desc.cap_policy == KRS_CAP_RESTART && nc >= desc.max_basis) {
+    if (has_cap() && desc.cap_policy == KRS_CAP_RESTART && nc >= cap_value() && cap_value() > 0) {
         if (nc0 > 0) {
             KRS_HIP(hipMemcpyAsync(d_C.p, d_C0.p, (size_t)ldc * nc0 * sizeof(V), hipMemcpyDeviceToDevice, stream));
         }
@@ -1125,9 +1170,38 @@ krs_status SeqImpl<V, W>::basis(double* C, int64_t ld, int32_t cap, int32_t* n_c
         return KRS_E_INVALID;
     }
     if (!d_tmp.reserve(ctx, (size_t)n * sizeof(double))) return KRS_E_OOM;
+    return basis_staged(C, ld, (double*)d_tmp.p);
+}
+
+template <typename V, typename W>
+krs_status SeqImpl<V, W>::history(double* Z, int64_t ld, int32_t cap, int32_t* m_out) {
+    // the directions z_0 .. z_{mh-1} of the last solve that the history kept
+    const int mh = (desc.reuse == KRS_REUSE_SELECTIVE && d_Z.p) ? std::min(m_last, history_kept) : 0;
+    if (m_out) *m_out = mh;
+    if (!Z) return KRS_OK;
+    if (ld < n || cap < mh) {
+        set_error("output history too small");
+        return KRS_E_INVALID;
+    }
+    if (!d_tmp.reserve(ctx, (size_t)n * sizeof(double))) return KRS_E_OOM;
+    for (int c = 0; c < mh; ++c) {
+        launch_v2d<V>((const V*)d_Z.p + (size_t)c * ldc, (double*)d_tmp.p, n, stream);
+        KRS_CHECK_LAUNCH();
+        KRS_HIP(hipMemcpyAsync(Z + (size_t)c * ld, d_tmp.p, n * sizeof(double), hipMemcpyDeviceToHost, stream));
+    }
+    KRS_HIP(hipStreamSynchronize(stream));
+    return KRS_OK;
+}
+
+// Each column converted to double in `staging` (n doubles of device memory)
+// and copied out; the copies are stream-ordered behind the conversions, so
+// one staging vector serves every column.
+template <typename V, typename W>
+krs_status SeqImpl<V, W>::basis_staged(double* C, int64_t ld, double* staging) {
     for (int c = 0; c < nc; ++c) {
-        launch_v2d<V>((const V*)d_C.p + (size_t)c * ldc, (double*)d_tmp.p, n, stream);
-        KRS_HIP(hipMemcpyAsync(C + (size_t)c * ld, d_tmp.p, n * sizeof(double), hipMemcpyDeviceToHost, stream));
+        launch_v2d<V>((const V*)d_C.p + (size_t)c * ldc, staging, n, stream);
+        KRS_CHECK_LAUNCH();
+        KRS_HIP(hipMemcpyAsync(C + (size_t)c * ld, staging, n * sizeof(double), hipMemcpyDeviceToHost, stream));
     }
     KRS_HIP(hipStreamSynchronize(stream));
     return KRS_OK;

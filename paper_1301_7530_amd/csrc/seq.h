@@ -67,6 +67,9 @@ struct SeqBase {
     // and the plan may have run on a helper thread)
     char plan_msg[256] = {0};
     virtual krs_status basis(double* C, int64_t ld, int32_t cap, int32_t* n_c) = 0;
+    // the export through caller-provided device staging of n doubles
+    virtual krs_status basis_staged(double* C, int64_t ld, double* staging) = 0;
+    virtual krs_status history(double* Z, int64_t ld, int32_t cap, int32_t* m_out) = 0;
     virtual void destroy() = 0;
     // live kernel timing (sampled iterations, device wall clock)
     bool timing = false;
@@ -109,8 +112,15 @@ struct SeqImpl : SeqBase {
     // SRKS needs the run's directions unless nothing will be appended from
     // them: the basis is full and frozen, or the cost cap holds
     bool history_needed() const {
-        return !(desc.cap_policy == KRS_CAP_FREEZE && desc.max_basis > 0 && nc >= desc.max_basis) && !cost_held();
+        if (has_cap() && (cap_value() == 0 || (desc.cap_policy == KRS_CAP_FREEZE && nc >= cap_value())))
+            return false;
+        return !cost_held();
     }
+    // n_c_lim: given (max_basis > 0), or set by the complexity analysis on
+    // the first solve (max_basis = KRS_NC_LIM_AUTO; -1 until then)
+    int nc_lim_auto = -1;
+    bool has_cap() const { return desc.max_basis > 0 || (desc.max_basis < 0 && nc_lim_auto >= 0); }
+    int cap_value() const { return desc.max_basis > 0 ? desc.max_basis : std::max(0, nc_lim_auto); }
     std::vector<double> h_F;  // host source of the last basis-update upload
     struct RecyclePlan {
         bool ready = false;       // planned, not yet applied
@@ -151,6 +161,8 @@ struct SeqImpl : SeqBase {
     krs_status recycle_plan() override;
     krs_status recycle_apply(int32_t* n_added) override;
     krs_status basis(double* C, int64_t ld, int32_t cap, int32_t* n_c) override;
+    krs_status basis_staged(double* C, int64_t ld, double* staging) override;
+    krs_status history(double* Z, int64_t ld, int32_t cap, int32_t* m_out) override;
     void destroy() override;
 
     SysView<V, W> view();
@@ -163,7 +175,8 @@ struct SeqImpl : SeqBase {
     void k_resid(const SysView<V, W>& v, int final_only);
     void enqueue_iterations(const SysView<V, W>& v, int k);
     void enqueue_refine(const SysView<V, W>& v);
-    int64_t model_bytes_per_iter() const;
+    int64_t model_bytes_per_iter(bool padded) const;
+    int64_t cost_bytes_last = 0;  // streamed bytes of the last solve (cost cap)
     // double-precision operator with a single-precision basis / preconditioner
     bool op64() const { return desc.precision == KRS_FP32_BASIS; }
 };

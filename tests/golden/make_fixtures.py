@@ -1,0 +1,119 @@
+"""Write the FP64 oracle fixtures used by the full-size GPU parity tests.
+
+Calls only ``oracle`` (and the input generators of ``gen``); nothing here
+comes from the HIP library.  Run from the repository root:
+
+    python tests/golden/make_fixtures.py [name ...]
+
+Each fixture is a JSON file with, per system of an SRKS sequence (Algorithm
+3, 3x3 block-Jacobi, FP64, tol 1e-8; the direction update in the form
+w = z + beta P w_old, which equals Algorithm 1's w = z + beta w_old in exact
+arithmetic and is the library's default): the iteration count, the
+basis width before the solve and after the recycle, the selected Ritz
+indices, the first CG coefficients, the true relative residual, and a
+fingerprint of the span of the recycled basis: with R a seeded n x 8 probe,
+F = (Q^T R)^T (Q^T R) for Q an orthonormal basis of span(C), which depends on
+the span only (any basis of it, A-orthonormalised or not, gives the same F).
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import gen  # noqa: E402
+import oracle as O  # noqa: E402
+
+FIXTURES = {
+    # the 40^3 elasticity workload, first three systems, cap 60 (freeze)
+    "elasticity40_srks_fp64": dict(E=40, workload_id=2, systems=3, cap=60, eps=1e-8, max_iter=30000),
+    # the 100^3 workload's setup at 30^3, the whole 30-system sequence, cap 200 (freeze)
+    "elasticity30_srks_fp64": dict(E=30, workload_id=3, systems=30, cap=200, eps=1e-8, max_iter=30000),
+    # the 40^3 workload with n_c_lim from the complexity analysis of the
+    # first solve (byte model of the library's FP64 iteration), freeze cap
+    "elasticity40_auto_fp64": dict(E=40, workload_id=2, systems=4, cap="auto", eps=1e-8, max_iter=30000),
+}
+
+
+def cost_model_fp64(seq, kmax):
+    """Algorithmic bytes of the FP64 iteration and rebuild (3x3 blocks):
+    matrix values and block columns, the block preconditioner, ten vector
+    passes plus x read and written; two passes over a basis column per
+    iteration; the rebuild streams A once and seven passes per column."""
+    nnz = 9 * seq.nnzb
+    BA = nnz * 8 + 4 * seq.nnzb
+    BM = 3 * seq.n * 8
+    return dict(bytes_iter0=BA + BM + 10 * seq.n * 8 + 2 * seq.n * 8, bytes_col_iter=2 * seq.n * 8,
+                bytes_rebuild0=BA, bytes_col_rebuild=7 * seq.n * 8, kmax=kmax)
+N_COEF = 40
+
+
+def probe(n: int) -> np.ndarray:
+    return np.random.default_rng(np.random.SeedSequence([13017530, 99, n])).standard_normal((n, 8))
+
+
+def span_fingerprint(C: np.ndarray, R: np.ndarray) -> np.ndarray:
+    if C.shape[1] == 0:
+        return np.zeros((R.shape[1], R.shape[1]))
+    U, s, _ = np.linalg.svd(C, full_matrices=False)
+    Q = U[:, s > s[0] * 1e-10]
+    P = Q.T @ R
+    return P.T @ P
+
+
+def make(name: str) -> None:
+    cfg = FIXTURES[name]
+    seq = gen.config_elasticity(cfg["E"], cfg["systems"], cfg["workload_id"])
+    R = probe(seq.n)
+    t = time.perf_counter()
+    recs = []
+    C = np.zeros((seq.n, 0))
+    cap = cfg["cap"]
+    nc_lim = None
+    for k in range(cfg["systems"]):
+        rp, ci, v, b = seq.csr(k)
+        res = O.apcg(rp, ci, v, b, "block3", C=C, tol=1e-8, max_iter=cfg["max_iter"], record_z=True,
+                     direction="project_old")
+        nc_in = C.shape[1]
+        if nc_in:
+            C = C[:, res["kept"]]
+        rec = dict(k=k, m=int(res["m"]), nc_in=int(nc_in), nc_solve=int(C.shape[1]),
+                   status=int(res["status"]), relres_true=float(res["relres_true"]),
+                   alpha=res["alpha"][:N_COEF].tolist(), rho=res["rho"][:N_COEF].tolist(),
+                   gamma=res["gamma"][:N_COEF].tolist())
+        if cap == "auto":
+            nc_lim, _ = O.nc_limit(res["alpha"], res["rho"], **cost_model_fp64(seq, min(1024, res["m"] - 1)))
+            cap = nc_lim
+            rec["nc_lim"] = int(nc_lim)
+        room = cap - C.shape[1]
+        sel = []
+        if res["m"] > 1 and room > 0:
+            th_m, th_m1 = O.ritz_values(res["alpha"], res["rho"])
+            allsel = O.srks_select(th_m, th_m1, cfg["eps"])
+            sel = O.freeze_pick(allsel, th_m, room)
+            rec["selected_all_count"] = len(allsel)
+            new = O.ritz_block(res["Z"], res["alpha"], res["rho"], sel, th_m)
+            C = np.concatenate([C, new], axis=1)
+        rec["selected"] = [int(i) for i in sel]
+        rec["nc_next"] = int(C.shape[1])
+        rec["fingerprint"] = span_fingerprint(C, R).tolist()
+        recs.append(rec)
+        del res
+        print(f"{name} system {k}: m={rec['m']} n_c {rec['nc_in']}->{rec['nc_solve']} (+{len(sel)}) "
+              f"rel res {rec['relres_true']:.2e}  [{time.perf_counter() - t:.0f} s]", flush=True)
+    out = dict(name=name, config=cfg, n=seq.n, n_coef=N_COEF, generator="tests/golden/make_fixtures.py",
+               systems=recs)
+    with open(os.path.join(HERE, name + ".json"), "w") as f:
+        json.dump(out, f, indent=0)
+
+
+if __name__ == "__main__":
+    for nm in sys.argv[1:] or list(FIXTURES):
+        make(nm)

@@ -1,0 +1,118 @@
+"""GPU parity at the benchmark's shapes against stored FP64 oracle runs.
+
+The fixtures under tests/golden/ are written by tests/golden/make_fixtures.py,
+which calls only the oracle (SRKS, Algorithm 3; direction update in the
+re-projected form w = z + beta P w_old, the library's default, equal to
+Algorithm 1's in exact arithmetic).  Per system, in FP64: the iteration
+count within +-2, the basis width the solve used and the columns appended
+within the rank guard's and the stagnation threshold's slack (+-2), the
+first CG coefficients of a solve from an empty basis to 1e-9, the true
+residual <= 1e-8, and the span of the recycled basis through its
+fingerprint (Q^T R)^T (Q^T R) for a seeded probe R and Q an orthonormal
+basis of span(C), which any basis of the same span reproduces.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import gen
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _fixture(name):
+    path = os.path.join(HERE, "golden", name + ".json")
+    with open(path) as f:
+        return json.load(f)
+
+
+def _probe(n):
+    return np.random.default_rng(np.random.SeedSequence([13017530, 99, n])).standard_normal((n, 8))
+
+
+def _fingerprint(C, R):
+    if C.shape[1] == 0:
+        return np.zeros((R.shape[1], R.shape[1]))
+    U, s, _ = np.linalg.svd(C, full_matrices=False)
+    Q = U[:, s > s[0] * 1e-10]
+    P = Q.T @ R
+    return P.T @ P
+
+
+def _run(gpu, fx, max_basis):
+    import paper_1301_7530_amd as K
+
+    cfg = fx["config"]
+    seq = gen.config_elasticity(cfg["E"], cfg["systems"], cfg["workload_id"])
+    assert seq.n == fx["n"]
+    R = _probe(seq.n)
+    s = K.sequence_for(gpu, seq, precision="fp64", reuse="selective", ritz_eps=cfg["eps"], max_basis=max_basis,
+                       cap_policy="freeze", tol=1e-8, max_iter=cfg["max_iter"], history_cap=cfg["max_iter"])
+    out = []
+    try:
+        for k in range(cfg["systems"]):
+            s.submit(*seq.system(k))
+            x, info = s.solve()
+            a, r, g = s.coeffs()
+            add = s.recycle()
+            C = s.basis()
+            rp, ci, v, b = seq.csr(k)
+            res = np.linalg.norm(b - O.spmv(rp, ci, v, x)) / np.linalg.norm(b)
+            out.append(dict(m=info["iters"], nc_solve=info["n_c"], added=add, res=res, alpha=a, rho=r,
+                            fp=_fingerprint(C, R), nc_lim=info["n_c_lim"], status=info["status"]))
+            print(f"system {k}: m {info['iters']} (oracle {fx['systems'][k]['m']}), n_c {info['n_c']} "
+                  f"(oracle {fx['systems'][k]['nc_solve']}), +{add} (oracle +{len(fx['systems'][k]['selected'])})",
+                  flush=True)
+    finally:
+        s.close()
+    return out
+
+
+def _compare(fx, got):
+    nco = fx["n_coef"]
+    for k, (g, w) in enumerate(zip(got, fx["systems"])):
+        assert g["status"] == 0 and g["res"] <= 1e-8, (k, g["res"])
+        assert abs(g["m"] - w["m"]) <= 2, (k, g["m"], w["m"])
+        assert abs(g["nc_solve"] - w["nc_solve"]) <= 2, (k, g["nc_solve"], w["nc_solve"])
+        assert abs(g["added"] - len(w["selected"])) <= 2, (k, g["added"], len(w["selected"]))
+        if w["nc_solve"] == 0:
+            assert np.allclose(g["alpha"][:nco], w["alpha"], rtol=1e-9, atol=0)
+            assert np.allclose(g["rho"][:nco], w["rho"], rtol=1e-9, atol=0)
+        F, F0 = g["fp"], np.asarray(w["fingerprint"])
+        scale = max(np.abs(F0).max(), 1.0)
+        dev = np.abs(F - F0).max() / scale
+        print(f"system {k}: span fingerprint deviation {dev:.2e}", flush=True)
+        assert dev <= 0.05, (k, dev)
+
+
+def test_elasticity40_srks_against_fixture(gpu):
+    fx = _fixture("elasticity40_srks_fp64")
+    _compare(fx, _run(gpu, fx, fx["config"]["cap"]))
+
+
+def test_elasticity40_auto_cap_against_fixture(gpu):
+    """n_c_lim from the complexity analysis (Section 4.4): the library's
+    value on its own first solve equals the oracle's on its own, or the
+    oracle's analysis of the library's coefficients gives the library's
+    value and the oracle's modelled cost of both choices agrees to 1e-3."""
+    import paper_1301_7530_amd as K
+
+    fx = _fixture("elasticity40_auto_fp64")
+    got = _run(gpu, fx, K.NC_LIM_AUTO)
+    want = fx["systems"][0]["nc_lim"]
+    lim = got[0]["nc_lim"]
+    print(f"n_c_lim: library {lim}, oracle {want}", flush=True)
+    if lim != want:
+        seq = gen.config_elasticity(fx["config"]["E"], 1, fx["config"]["workload_id"])
+        from golden.make_fixtures import cost_model_fp64
+
+        a, r = got[0]["alpha"], got[0]["rho"]
+        k_o, T = O.nc_limit(a, r, **cost_model_fp64(seq, min(1024, len(a) - 1)))
+        assert k_o == lim
+        assert abs(T[want] - T[lim]) <= 1e-3 * T[lim]
+    _compare(fx, got)

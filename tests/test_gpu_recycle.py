@@ -1,0 +1,152 @@
+"""GPU parity of the between-system work: the basis rebuild of Algorithm 3
+element by element, and the restart cap.
+
+* Basis rebuild (Section 4.4, Algorithm 3): after a solve and a recycle the
+  new columns of the library's basis are compared with the oracle's
+  ``ritz_block`` evaluated on the library's own history z_j, coefficients
+  and selection, column by column.  The bound is that of the arithmetic: a
+  length-m sum in the basis precision (u = 2^-53, or 2^-24 for the
+  single-precision basis, whose combination matrix is rounded to single
+  precision for the matrix cores) plus the difference of two eigenvector
+  computations, u ||T|| / gap per side, carried through ||Z D||.  A Ritz
+  vector's sign is not fixed by the method, so each column is compared after
+  aligning signs.
+* Restart cap (Algorithm 3, last step): the basis returns to C^(0) once it
+  reaches n_c_lim; the restart points, the basis widths and the iteration
+  counts (+-2) follow the oracle's ``solve_sequence(cap_policy='restart')``.
+"""
+import numpy as np
+import pytest
+
+import gen
+import oracle as O
+from ritz_compare import selection_flips
+
+pytestmark = pytest.mark.gpu
+
+U64 = 2.0 ** -53
+U32 = 2.0 ** -24
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32basis"])
+def test_basis_rebuild_elementwise(gpu, precision):
+    import paper_1301_7530_amd as K
+
+    seq = gen.config_elasticity(10, 1)
+    eps = 1e-8
+    s = K.sequence_for(gpu, seq, precision=precision, reuse="selective", ritz_eps=eps, tol=1e-8, max_iter=5000)
+    try:
+        s.submit(*seq.system(0))
+        _, info = s.solve()
+        assert info["status"] == 0
+        alpha, rho, _ = s.coeffs()
+        Z = s.history()
+        added = s.recycle()
+        C = s.basis()
+        th_lib, sel_flags = s.ritz()
+    finally:
+        s.close()
+    mu = Z.shape[1]
+    assert mu == info["iters"] > 50
+    a, r = alpha[:mu], rho[:mu]
+    th_m, th_m1 = O.ritz_values(a, r)
+    sel_lib = np.nonzero(sel_flags)[0]
+    sel_orc = O.srks_select(th_m, th_m1, eps)
+    flips = selection_flips(sel_lib, sel_orc, th_m, th_m1, eps)
+    print(f"{precision}: m={mu}, selected {len(sel_lib)} (oracle {len(sel_orc)}), flips {flips}", flush=True)
+    assert added == len(sel_lib) == C.shape[1] > 0
+    ref = O.ritz_block(Z, a, r, list(sel_lib), th_m)
+    F = O.ritz_block(np.eye(mu), a, r, list(sel_lib), th_m)
+    u = U64 if precision == "fp64" else U32
+    ZD = np.linalg.norm(Z / np.sqrt(r)[None, :], 2)
+    tmax = float(np.max(np.abs(th_m)))
+    worst = 0.0
+    for t, i in enumerate(sel_lib):
+        c, c0 = C[:, t], ref[:, t]
+        if np.dot(c, c0) < 0:
+            c = -c
+        gap = np.min(np.abs(np.delete(th_m, i) - th_m[i]))
+        e_arith = (mu + 2) * u * np.linalg.norm(np.abs(Z) @ np.abs(F[:, t]))
+        e_eig = ZD * (2 * 8 * U64 * tmax / gap) / np.sqrt(abs(th_m[i]))
+        err = np.linalg.norm(c - c0)
+        worst = max(worst, err / (e_arith + e_eig))
+        assert err <= 4 * (e_arith + e_eig), (t, i, err, e_arith, e_eig, np.linalg.norm(c0))
+    print(f"{precision}: largest error / bound {worst:.3g}", flush=True)
+
+
+def test_restart_cap_follows_oracle(gpu):
+    import paper_1301_7530_amd as K
+
+    seq = gen.config_elasticity(6, 6)
+    cap, eps = 160, 1e-10
+    recs, _ = O.solve_sequence(seq, 6, reuse="srks", eps=eps, cap=cap, cap_policy="restart", tol=1e-8,
+                               max_iter=5000)
+    s = K.sequence_for(gpu, seq, precision="fp64", reuse="selective", ritz_eps=eps, max_basis=cap,
+                       cap_policy="restart", tol=1e-8, max_iter=5000)
+    got = []
+    try:
+        for k in range(6):
+            s.submit(*seq.system(k))
+            _, info = s.solve()
+            s.recycle()
+            got.append((info["iters"], info["n_c"], s.n_c))
+    finally:
+        s.close()
+    want = [(r["m"], r["nc"], r["nc_next"]) for r in recs]
+    print("gpu   ", got, "\noracle", want, flush=True)
+    assert any(r.get("restarted") for r in recs)
+    for (m, nc, nxt), (mo, nco, nxto) in zip(got, want):
+        assert (nxt == 0) == (nxto == 0)  # the same restart points
+        assert abs(nc - nco) <= 2 and abs(nxt - nxto) <= 4
+        assert abs(m - mo) <= 2
+
+
+def test_cluster_reselection_on_gpu_coefficients(gpu):
+    """The library's selection with the cluster reselection ("clust14",
+    Section 4.4) equals the oracle's stagnation test followed by its
+    cluster_reselect on the same CG coefficients."""
+    import paper_1301_7530_amd as K
+
+    seq = gen.config_elasticity(6, 1)
+    eps = 1e-14
+    s = K.sequence_for(gpu, seq, precision="fp64", reuse="selective", ritz_eps=eps, tol=1e-8, max_iter=5000,
+                       reselect="cluster")
+    try:
+        s.submit(*seq.system(0))
+        _, info = s.solve()
+        assert info["status"] == 0
+        alpha, rho, _ = s.coeffs()
+        added = s.recycle()
+        th_lib, flags = s.ritz()
+    finally:
+        s.close()
+    m = len(alpha)
+    th_m, th_m1 = O.ritz_values(alpha[:m], rho[:m])
+    pre = O.srks_select(th_m, th_m1, eps)
+    want = O.cluster_reselect(th_m, pre, 0.2)
+    got = np.nonzero(flags)[0].tolist()
+    print(f"m={m}: preselected {len(pre)}, kept {len(want)} (library {len(got)})", flush=True)
+    assert len(pre) >= 5 and len(want) < len(pre)
+    assert got == want and added == len(got)
+
+
+def test_cluster_sequence_follows_oracle(gpu):
+    import paper_1301_7530_amd as K
+
+    seq = gen.config_elasticity(6, 4)
+    eps = 1e-14
+    recs, _ = O.solve_sequence(seq, 4, reuse="srks", eps=eps, tol=1e-8, max_iter=5000, reselect="cluster")
+    s = K.sequence_for(gpu, seq, precision="fp64", reuse="selective", ritz_eps=eps, tol=1e-8, max_iter=5000,
+                       reselect="cluster")
+    got = []
+    try:
+        for k in range(4):
+            s.submit(*seq.system(k))
+            _, info = s.solve()
+            got.append((info["iters"], info["n_c"], s.recycle()))
+    finally:
+        s.close()
+    want = [(r["m"], r["nc"], r["added"]) for r in recs]
+    print("gpu   ", got, "\noracle", want, flush=True)
+    for (m, nc, add), (mo, nco, addo) in zip(got, want):
+        assert abs(m - mo) <= 2 and abs(nc - nco) <= 2 and abs(add - addo) <= 2
