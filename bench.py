@@ -46,11 +46,12 @@ WORKLOADS = {
     "elasticity100": dict(kind="elasticity", size=100, n_systems=30, workload_id=3, max_basis=200, eps=1e-8,
                           history_cap=16000),
     "diffusion20": dict(kind="diffusion", size=(20, 20, 20), n_systems=8, workload_id=1, max_basis=0, eps=1e-14),
+    # secant loop of a damaging cube: each matrix from the previous solution's strains
+    "newton40": dict(kind="newton", size=40, n_systems=20, workload_id=6, max_basis=60, eps=1e-8),
     # many independent diffusion sequences (n ~ U[5e3, 2e5]) solved in fused launches
-    # fused launches use wide update tiles (fewer, longer workgroups per
-    # system); the one-at-a-time comparison keeps the default tile
-    "batched": dict(kind="batched", size=None, n_systems=10, workload_id=4, max_basis=60, eps=1e-8, cap_policy="cost",
-                    update_rows=4096),
+    # (the fused phases let the library's batch autotuner pick the update
+    # tile; the one-at-a-time comparison keeps the default tile)
+    "batched": dict(kind="batched", size=None, n_systems=10, workload_id=4, max_basis=60, eps=1e-8, cap_policy="cost"),
     # clients with elasticity sequences (1e4..5e5 dofs) served with continuous batching
     "serving": dict(kind="serving", size=None, n_systems=50, workload_id=5, max_basis=200, eps=1e-8),
     # calibration for hardware byte counters: device-to-device copies of a known size
@@ -130,7 +131,7 @@ def run_sequence(K, ctx, seq, dev_sys, ks, precision, reuse, args, wl, timing=Fa
                        max_basis=max_basis(args, wl) if reuse == "selective" else 0,
                        cap_policy=args.cap_policy,
                        refine_drop=args.refine_drop, autotune=args.autotune, update_rows=args.update_rows,
-                       eager=args.eager, separate_finalize=args.separate_finalize)
+                       eager=args.eager, separate_finalize=args.separate_finalize, spmv_variant=args.spmv_variant)
     x_scratch = torch.empty(seq.n, dtype=torch.float64, device="cuda")
     recs = []
     try:
@@ -233,6 +234,75 @@ def profile_traffic(name):
     if vals.get("kernels_sha256") != sha or "traffic_bytes_per_launch" not in vals:
         return None
     return int(vals["traffic_bytes_per_launch"])
+
+
+def run_newton_workload(args, K, torch, wl):
+    """Secant loop of a damaging cube (gen.NewtonSequence): system k+1 is
+    assembled on the host from the strains of solution k, so inputs cannot
+    be resident before the run.  value = steps / (time on the device path:
+    upload of the values, intake, rebuild, iterations, recycle, solution
+    copy-back); the host assembly time is reported beside it.  Plain PCG
+    runs the same loop (its own solutions drive its own matrices)."""
+    import gen
+
+    def loop(reuse, steps, label):
+        seq = gen.NewtonSequence(wl["size"], steps, (gen.SEED_ROOT, wl["workload_id"], 0))
+        ctx = K.Context(0)
+        s = K.sequence_for(ctx, seq, precision=args.precision, reuse=reuse, tol=1e-8, max_iter=args.max_iter,
+                           ritz_eps=args.eps or wl["eps"],
+                           max_basis=max_basis(args, wl) if reuse == "selective" else 0, cap_policy=args.cap_policy)
+        x = torch.empty(seq.n, dtype=torch.float64, device="cuda")
+        t_dev = t_host = 0.0
+        iters, ncs = [], []
+        try:
+            for k in range(steps):
+                th = time.perf_counter()
+                vals, b = seq.system(k)
+                t_host += time.perf_counter() - th
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                dv, db = torch.from_numpy(vals).to("cuda"), torch.from_numpy(b).to("cuda")
+                s.submit(dv, db)
+                info = s.solve_device(x)
+                if reuse != "none":
+                    s.recycle()
+                xh = x.cpu().numpy()
+                t_dev += time.perf_counter() - t0
+                if info["status"] != 0 or info["rel_res_true"] > 1e-8:
+                    raise RuntimeError(f"{label} system {k}: {info}")
+                th = time.perf_counter()
+                seq.advance(xh)
+                t_host += time.perf_counter() - th
+                iters.append(info["iters"])
+                ncs.append(info["n_c"])
+                _log(f"  {label} system {k}: {info['iters']} iterations, n_c {info['n_c']}")
+        finally:
+            s.close()
+            ctx.close()
+        soft = float((seq.moduli(steps - 1) < seq.moduli(0)).mean())
+        return dict(value=steps / t_dev, t_dev=t_dev, t_host=t_host, iters=iters, n_c=ncs, softened=soft)
+
+    if args.warmup:
+        loop("selective", min(args.warmup, 2), "warm-up")
+    main = loop("selective", args.steps, "SRKS")
+    plain = loop("none", args.steps, "plain") if args.plain else None
+    out = {
+        "metric": "solves/s at 1e-8 resid vs plain PCG same GPU; %HBM peak; p50/p99 latency",
+        "value": round(main["value"], 4), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * main["t_dev"] / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": PRECISIONS[args.precision]["dtype"], "data": "synthetic",
+        "config": {"workload": f"newton{wl['size']}: secant loop of a damaging Q1 elasticity cube {wl['size']}^3, "
+                               "each matrix from the previous solution's strains",
+                   "precision": args.precision, "reuse": f"SRKS eps={args.eps or wl['eps']:.0e}",
+                   "max_basis": max_basis(args, wl), "cap_policy": args.cap_policy},
+        "iters": main["iters"], "n_c": main["n_c"], "host_assembly_s": round(main["t_host"], 3),
+        "elements_softened_at_end": main["softened"],
+    }
+    if plain:
+        out["plain_pcg"] = {"value": round(plain["value"], 4), "iters": plain["iters"]}
+        out["speedup_vs_plain_pcg"] = main["value"] / plain["value"]
+    print(json.dumps(out), flush=True)
 
 
 def run_sequence_workload(args, K, torch, wl):
@@ -542,6 +612,123 @@ def run_serving(args, K, torch, data):
     print(json.dumps(out), flush=True)
 
 
+def _gen_client_systems(task):
+    E, cid, ks, n_systems = task
+    import gen
+
+    sq = gen.make_sequence("elasticity", E, n_systems, 5, cid)
+    for k in range(max(ks) + 1 if ks else 0):
+        sq.moduli(k)
+        sq.rhs(k)
+    return cid, {k: sq.system(k) for k in ks}
+
+
+def run_serving_sweep(args, K, torch):
+    """The serving workload (64 clients, 50 elasticity systems each, per-client
+    bases resident) under open-loop Poisson arrivals at each rate of
+    --sweep (per client), a window of --window seconds per rate: arrivals
+    stop at the window's end, the requests in flight drain, and solves/s,
+    p50/p99 latency and the mean batch are reported per rate.  Each client's
+    requests are its next systems, so the bases carry over from one rate to
+    the next (50 per client at most)."""
+    import concurrent.futures as cf
+    import threading
+
+    import gen
+
+    wl = WORKLOADS["serving"]
+    Es = gen.serving_elasticity_sizes(64)[: args.clients]
+    seqs = [gen.make_sequence("elasticity", E, wl["n_systems"], 5, c) for c, E in enumerate(Es)]
+    rates = [float(r) for r in args.sweep.split(",")]
+    rng = np.random.default_rng(np.random.SeedSequence((13017530, 5, 1 << 22)))
+    plans, nxt = [], [0] * len(seqs)
+    for lam in rates:
+        arr = []
+        for c in range(len(seqs)):
+            t = 0.0
+            while True:
+                t += rng.exponential(1.0 / lam)
+                if t >= args.window or nxt[c] >= wl["n_systems"]:
+                    break
+                arr.append((t, c, nxt[c]))
+                nxt[c] += 1
+        arr.sort()
+        plans.append(arr)
+    ctx = K.Context(0)
+    kw = dict(precision=args.precision, reuse="selective", tol=1e-8, max_iter=args.max_iter,
+              ritz_eps=args.eps or wl["eps"], max_basis=wl["max_basis"], cap_policy="freeze",
+              history_cap=args.history_cap, refine_drop=args.refine_drop)
+    hs = [K.sequence_for(ctx, sq, **kw) for sq in seqs]
+    out_rates = []
+    try:
+        for lam, arr in zip(rates, plans):
+            need = {}
+            for _, c, k in arr:
+                need.setdefault(c, []).append(k)
+            _log(f"rate {lam}/s per client: {len(arr)} requests in {args.window:.0f} s; generating")
+            host = {}
+            # threads (the matrix assembly runs in C without the GIL): this
+            # process already holds the GPU, so no worker processes
+            with cf.ThreadPoolExecutor(max_workers=16) as ex:
+                for cid, systems in ex.map(_gen_client_systems,
+                                           [(Es[c], c, ks, wl["n_systems"]) for c, ks in need.items()]):
+                    host[cid] = systems
+            srv = K.Server(ctx, hbm_budget=int(args.hbm_budget * (1 << 30)), max_slots=args.clients)
+            done = []
+            try:
+                def producer():
+                    t0 = time.perf_counter()
+                    for t, c, k in arr:
+                        dt = t - (time.perf_counter() - t0)
+                        if dt > 0:
+                            time.sleep(dt)
+                        srv.enqueue(hs[c], *host[c][k], tag=c * 1000 + k)
+
+                th = threading.Thread(target=producer)
+                t_start = time.perf_counter()
+                th.start()
+                while len(done) < len(arr):
+                    got = srv.poll(timeout_ms=60000)
+                    if not got:
+                        raise RuntimeError("server made no progress for 60 s")
+                    done += got
+                th.join()
+                wall = time.perf_counter() - t_start
+                st = srv.stats()
+            finally:
+                srv.close()
+            bad = [c for c in done if c["status"] != 0 or c["info"]["rel_res_true"] > 1e-8]
+            if bad:
+                raise RuntimeError(f"{len(bad)} requests missed the tolerance: {bad[0]['message']}")
+            lat = np.array([c["latency_ms"] for c in done])
+            rec = dict(rate_per_client=lam, offered_per_s=lam * len(seqs), requests=len(arr),
+                       solves_per_s=len(done) / wall, wall_s=wall, p50_ms=float(np.percentile(lat, 50)),
+                       p99_ms=float(np.percentile(lat, 99)), mean_batch=st["mean_batch"],
+                       iters_mean=float(np.mean([c["info"]["iters"] for c in done])),
+                       n_c_mean=float(np.mean([c["info"]["n_c"] for c in done])))
+            _log(f"  {rec}")
+            out_rates.append(rec)
+    finally:
+        for h in hs:
+            h.close()
+        ctx.close()
+    top = max(out_rates, key=lambda r: r["solves_per_s"])
+    out = {
+        "metric": "solves/s at 1e-8 resid vs plain PCG same GPU; %HBM peak; p50/p99 latency",
+        "value": round(top["solves_per_s"], 4), "unit": "solves/s", "n_gpus": 1,
+        "steps": sum(r["requests"] for r in out_rates), "warmup": 0,
+        "ms_per_step": round(1e3 / top["solves_per_s"], 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": PRECISIONS[args.precision]["dtype"], "data": "synthetic",
+        "config": {"workload": f"serving sweep: {len(seqs)} clients, Q1 elasticity {min(s.n for s in seqs)}.."
+                               f"{max(s.n for s in seqs)} dofs, up to {wl['n_systems']} systems each, Poisson "
+                               f"arrivals swept over {rates} per client, {args.window:.0f} s windows",
+                   "clients": len(seqs), "hbm_budget_gib": args.hbm_budget, "precision": args.precision},
+        "latency_ms": {"p50": top["p50_ms"], "p99": top["p99_ms"]},
+        "per_rate": out_rates,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def run_batched(args, K, torch, data):
     """Fused multi-sequence solves (one batch_solve per step over every
     sequence) against the same sequences solved one after the other, and
@@ -555,12 +742,13 @@ def run_batched(args, K, torch, data):
     kw = dict(precision=args.precision, tol=1e-8, max_iter=args.max_iter, ritz_eps=args.eps or wl["eps"],
               max_basis=wl["max_basis"], cap_policy=wl.get("cap_policy", "freeze"), history_cap=args.history_cap,
               refine_drop=args.refine_drop, separate_finalize=args.separate_finalize)
-    fused_rows = args.update_rows or wl["update_rows"]
+    fused_rows = args.update_rows
 
     def phase(reuse, fused):
-        hs = [K.sequence_for(ctx, sq, reuse=reuse, update_rows=fused_rows if fused else 0, **kw) for sq in seqs]
+        hs = [K.sequence_for(ctx, sq, reuse=reuse, update_rows=fused_rows if fused else 0,
+                             autotune=fused and not fused_rows, **kw) for sq in seqs]
         xs = [torch.empty(sq.n, dtype=torch.float64, device="cuda") for sq in seqs]
-        iters, t_steps, t_rec, ncs = [], [], [], []
+        iters, t_steps, t_rec, ncs, tiles = [], [], [], [], []
         try:
             for step, k in enumerate(ks):
                 torch.cuda.synchronize()
@@ -583,6 +771,7 @@ def run_batched(args, K, torch, data):
                     t_steps.append(time.perf_counter() - t0)
                     t_rec.append(time.perf_counter() - t1)
                     iters.append([inf["iters"] for inf in infos])
+                    tiles.append(sorted({inf["update_rows"] for inf in infos}))
                     ncs.append(float(np.mean([inf["n_c"] for inf in infos])))
                     bad = [inf for inf in infos if inf["rel_res_true"] > 1e-8 or inf["status"] != 0]
                     if bad:
@@ -593,7 +782,7 @@ def run_batched(args, K, torch, data):
         t = sum(t_steps)
         return dict(value=len(hs) * len(t_steps) / t, time=t, iters_mean=float(np.mean(iters)),
                     step_ms=[round(1e3 * x, 2) for x in t_steps], recycle_ms=[round(1e3 * x, 2) for x in t_rec],
-                    n_c_mean=[round(x, 2) for x in ncs])
+                    n_c_mean=[round(x, 2) for x in ncs], tiles=tiles)
 
     _log("fused SRKS")
     fused = phase("selective", True)
@@ -619,7 +808,9 @@ def run_batched(args, K, torch, data):
                                f"SRKS eps={kw['ritz_eps']:.0e} cap {wl['max_basis']} ({kw['cap_policy']}), "
                                f"fused launches",
                    "sequences": len(seqs), "sum_n": n_tot, "precision": args.precision,
-                   "history_cap": args.history_cap, "update_rows_fused": fused_rows},
+                   "history_cap": args.history_cap,
+                   "update_rows_fused": fused_rows or "batch autotuner"},
+        "update_rows_per_step": fused["tiles"],
         "iters_mean": fused["iters_mean"],
         "step_ms": fused["step_ms"],
         "recycle_ms": fused["recycle_ms"],
@@ -666,12 +857,17 @@ def main():
     ap.add_argument("--sequences", type=int, default=256, help="batched workload: number of sequences")
     ap.add_argument("--history-cap", type=int, default=256, help="batched workload: Krylov vectors kept per solve")
     ap.add_argument("--eager", action="store_true", help="launch kernels one by one instead of graph replay")
+    ap.add_argument("--spmv-variant", type=int, default=0,
+                    help="block SpMV load schedule bits: 1 four blocks in flight, 2 non-temporal matrix loads, "
+                         "4 up to 4096 workgroups")
     ap.add_argument("--separate-finalize", action="store_true",
                     help="run the end-of-step reduction as its own kernel")
     ap.add_argument("--clients", type=int, default=64, help="serving workload: clients (sequences)")
     ap.add_argument("--systems", type=int, default=3, help="serving workload: systems per client")
     ap.add_argument("--rate", type=float, default=1.0, help="serving workload: arrivals per second per client")
     ap.add_argument("--hbm-budget", type=float, default=64.0, help="serving workload: working-set budget (GiB)")
+    ap.add_argument("--sweep", default="", help="serving workload: per-client arrival rates to sweep, e.g. 0.01,0.02")
+    ap.add_argument("--window", type=float, default=60.0, help="serving sweep: seconds of arrivals per rate")
     args = ap.parse_args()
     if args.precision is None:
         args.precision = {"batched": "mixed", "serving": "fp32basis"}.get(args.workload, "fp64")
@@ -684,7 +880,7 @@ def main():
         sys.exit(2)
 
     batched_data = gen_batched(args) if args.workload == "batched" else None
-    serving_data = gen_serving(args) if args.workload == "serving" else None
+    serving_data = gen_serving(args) if args.workload == "serving" and not args.sweep else None
 
     import torch
 
@@ -710,9 +906,16 @@ def main():
     if args.workload == "serving":
         if args.history_cap == 256:
             args.history_cap = 1000
+        if args.sweep:
+            run_serving_sweep(args, K, torch)
+            return
         run_serving(args, K, torch, serving_data)
         return
-    run_sequence_workload(args, K, torch, WORKLOADS[args.workload])
+    wl = WORKLOADS[args.workload]
+    if wl["kind"] == "newton":
+        run_newton_workload(args, K, torch, wl)
+        return
+    run_sequence_workload(args, K, torch, wl)
 
 if __name__ == "__main__":
     main()

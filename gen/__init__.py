@@ -15,6 +15,9 @@ assumes):
   coefficients, one unknown per cell (scalar CSR).
 * ``elasticity``: Q1 hexahedral linear elasticity on a cube with one clamped
   face and stiff random inclusions (3x3 nodal block CSR, i.e. BSR).
+* ``newton``: the elasticity cube in a secant loop, each matrix built from
+  the strains of the previous solution (the nonlinear sequences of the
+  paper's Sections 5.2 and 5.3, made synthetic).
 
 Sequences perturb a random subset of cells/elements at every step
 (cumulative "damage"), and draw a fresh Gaussian right-hand side per system.
@@ -22,6 +25,7 @@ Sequences perturb a random subset of cells/elements at every step
 
 from .diffusion import diffusion_matrix, DiffusionSequence
 from .elasticity import q1_reference_stiffness, elasticity_matrix, ElasticitySequence, bsr_to_csr
+from .newton import NewtonSequence, centre_strain, softening
 from .workloads import (
     SEED_ROOT,
     make_sequence,
@@ -38,6 +42,9 @@ __all__ = [
     "elasticity_matrix",
     "ElasticitySequence",
     "bsr_to_csr",
+    "NewtonSequence",
+    "centre_strain",
+    "softening",
     "SEED_ROOT",
     "make_sequence",
     "config_diffusion_20",

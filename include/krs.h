@@ -149,7 +149,17 @@ typedef struct {
                               instead of the default w = z + beta P w_old, which applies the projector
                               P = I - C G^-1 (A C)^T to the old direction as well (the same vector in exact
                               arithmetic, Section 2.1; the default keeps rounding from moving the direction
-                              out of the range of P, at no extra pass over memory) */
+                              out of the range of P, at no extra pass over memory).
+                              bit 2: full reorthogonalisation (Section 2.1 remark, used in the experiments
+                              of Section 5.1): each new direction is z made A-orthogonal to every kept
+                              earlier direction, w = z - sum_i ((A w_i, z) / (w_i, A w_i)) w_i (classical
+                              Gram-Schmidt in the A inner product); the first min(history_cap or max_iter,
+                              4096) directions and their products with A are kept (2 n doubles each).
+                              KRS_FP64 only; not in fused batches or the server (KRS_E_INVALID).
+                              bits 3-5: load schedule of the double-precision block SpMV (same results up
+                              to the grouping of the (w, A w) partial sums): bit 3 four blocks of a row in
+                              flight instead of two, bit 4 non-temporal loads of the matrix, bit 5 up to
+                              4096 SpMV workgroups instead of 2048. */
     int32_t reselect;      /* SRKS: 0 = keep every Ritz vector that passed the stagnation test;
                               1 = KRS_RESELECT_CLUSTER: drop the central cluster of those values
                               ("clust", Section 4.4), before the cap */

@@ -384,13 +384,16 @@ def nc_limit(alpha, rho, bytes_iter0, bytes_col_iter, bytes_rebuild0, bytes_col_
 
 def solve_sequence(seq, n_systems=None, reuse="srks", precond=None, tol=1e-8, eps=1e-14, cap=0,
                    cap_policy="freeze", C0=None, max_iter=None, guard=1e-6, keep_x=False, cost_model=None,
-                   reselect=None, cluster_min_frac=0.2):
+                   reselect=None, cluster_min_frac=0.2, direction="literal", reorth=False):
     """Run TRKS / SRKS / plain PCG over systems 0..n_systems-1 of ``seq``.
 
     ``reuse``: 'none' (PCG), 'trks' (Algorithm 2) or 'srks' (Algorithm 3).
     ``cap`` (n_c_lim, 0 = none) with ``cap_policy`` 'restart' (reset the
     basis to C0 once its size reaches the cap, Algorithm 3) or 'freeze'
     (append only while below the cap, smallest Ritz values first).
+    A sequence with an ``advance(x)`` method (gen.NewtonSequence) receives
+    each solution before its next system is built.  ``direction``, ``reorth``:
+    the direction-update form and full reorthogonalisation of ``apcg``.
     ``reselect='cluster'``: the SRKS preselection is reduced by
     ``cluster_reselect`` before the cap ("clust", Section 4.4).
     ``cap='auto'``: n_c_lim from ``nc_limit`` on the first solve's
@@ -411,7 +414,9 @@ def solve_sequence(seq, n_systems=None, reuse="srks", precond=None, tol=1e-8, ep
     for k in range(n_systems):
         rp, ci, v, b = seq.csr(k)
         res = apcg(rp, ci, v, b, precond, C, tol, max_iter, guard, record_z=(reuse == "srks"),
-                   record_w=(reuse == "trks"))
+                   record_w=(reuse == "trks"), direction=direction, reorth=reorth)
+        if hasattr(seq, "advance"):
+            seq.advance(res["x"])  # a sequence whose next matrix depends on this solution
         nc_in = C.shape[1]
         if nc_in:
             C = C[:, res["kept"]]

@@ -365,7 +365,8 @@ class Sequence:
     def __init__(self, ctx: Context, row_ptr, col_idx, n, block=1, precision="fp64", reuse="selective",
                  precond=None, cap_policy="freeze", tol=1e-8, max_iter=10000, ritz_eps=1e-14, max_basis=0,
                  refine_every=0, history_cap=0, rank_tol=0.0, refine_drop=0.0, C0=None, eager=False,
-                 update_rows=0, autotune=False, separate_finalize=False, literal_direction=False, reselect=None,
+                 update_rows=0, autotune=False, separate_finalize=False, literal_direction=False, reorth=False,
+                 spmv_variant=0, reselect=None,
                  cluster_min_frac=0.0):
         self.ctx = ctx
         self.n = int(n)
@@ -396,7 +397,8 @@ class Sequence:
         d.exec_mode = 1 if eager else 0
         d.update_rows = update_rows
         d.autotune = 1 if autotune else 0
-        d.kernel_flags = (1 if separate_finalize else 0) | (2 if literal_direction else 0)
+        d.kernel_flags = ((1 if separate_finalize else 0) | (2 if literal_direction else 0) | (4 if reorth else 0)
+                          | ((int(spmv_variant) & 7) << 3))
         d.reselect = {None: 0, "none": 0, "cluster": 1}[reselect]
         d.cluster_min_frac = cluster_min_frac
         self.desc = d

@@ -129,6 +129,10 @@ krs_status krs_seq_create(krs_ctx* ctx, const krs_seq_desc* d, const double* C0,
         set_error("unknown precision");
         return KRS_E_INVALID;
     }
+    if ((d->kernel_flags & 4) && d->precision != KRS_FP64) {
+        set_error("full reorthogonalisation (kernel_flags bit 2) runs in double precision only");
+        return KRS_E_INVALID;
+    }
     if (d->reselect != 0 && (d->reselect != KRS_RESELECT_CLUSTER || d->reuse != KRS_REUSE_SELECTIVE ||
                              d->cluster_min_frac < 0.0 || d->cluster_min_frac > 1.0)) {
         set_error("cluster reselection needs selective reuse and 0 <= cluster_min_frac <= 1");
@@ -470,6 +474,10 @@ static krs_status batch_common(krs_ctx* ctx, krs_seq* const* seqs, int32_t count
             set_error("a sequence of the batch has server requests in flight");
             return KRS_E_BUSY;
         }
+        if (seqs[i]->impl->desc.kernel_flags & 4) {
+            set_error("full reorthogonalisation is not available in fused batches (solve the sequence alone)");
+            return KRS_E_INVALID;
+        }
         for (int j = 0; j < i; ++j)
             if (seqs[j] == seqs[i]) {
                 set_error("a sequence appears twice in the batch");
@@ -500,6 +508,10 @@ krs_status krs_batch_recycle(krs_ctx* ctx, krs_seq* const* seqs, int32_t count, 
         if (seqs[i]->impl->in_server.load() > 0) {
             set_error("a sequence of the batch has server requests in flight");
             return KRS_E_BUSY;
+        }
+        if (seqs[i]->impl->desc.kernel_flags & 4) {
+            set_error("full reorthogonalisation is not available in fused batches (solve the sequence alone)");
+            return KRS_E_INVALID;
         }
         for (int j = 0; j < i; ++j)
             if (seqs[j] == seqs[i]) {

@@ -109,7 +109,7 @@ struct SysView {
     const int64_t* slice_ptr;  // [nslices+1] slot offsets
     const V* val;              // values in V precision (planar per slot)
     int32_t op64;              // 1: the SpMV streams val64 (double-precision operator)
-    int32_t pad_op;
+    int32_t spmv_var;          // SpMV load schedule: bit 0 four blocks in flight, bit 1 non-temporal matrix loads
     const double* val64;       // values in double (for true residuals / A C)
     const V* minv;             // preconditioner inverse: n (Jacobi) or 9*nb (3x3 blocks)
     int64_t n;                 // scalar rows
@@ -150,7 +150,20 @@ struct SysView {
     Geometry geo;
     int32_t fused;               // 1: the update kernel's last workgroup runs the finalize
     int32_t dir_literal;         // 1: w = z + beta w_old as written; 0: w = z + beta P w_old
+    // full reorthogonalisation (null Wr: off): every direction and its
+    // product with A kept row-major (n x ldr, columns j < rcap); the next
+    // direction is z made A-orthogonal to all of them
+    W* Wr;
+    W* Qr;
+    int64_t ldr;
+    int32_t rcap;
+    int32_t gr;       // row ranges (workgroups) of the coefficient partials
+    double* rpart;    // gr x ldr partial sums (A w_i, z)
+    double* rc;       // ldr coefficients (A w_i, z) / (w_i, A w_i)
+    W* zr;            // z of the current step, written by the direction update
 };
+// largest number of directions a reorthogonalised solve keeps
+constexpr int kReorthMax = 4096;
 
 // Launch maps of a fused batch: map[k][i] = (system, workgroup) of launch
 // k's workgroup i; count[k] = total workgroups.
@@ -178,7 +191,8 @@ struct BatchMaps {
 
 // ------------------------------------------------------------ launchers
 // All launch on `stream`; the grid shapes come from the view's geometry.
-Geometry make_geometry(int64_t n, int64_t nslices, int block, int64_t cb3_req);
+// spmv_grid: cap on the SpMV workgroups (0: 2048)
+Geometry make_geometry(int64_t n, int64_t nslices, int block, int64_t cb3_req, int spmv_grid = 0);
 // doubles of reduction scratch (after kPart1) a solve with nc columns needs
 int64_t partial_doubles(const Geometry& g, int nc);
 
@@ -189,6 +203,10 @@ void launch_update_reduce(const SysView<V, W>& v, int mode, hipStream_t stream);
 template <typename V, typename W, int B>
 void launch_update_only(const SysView<V, W>& v, int mode, hipStream_t stream);
 template <typename V, typename W> void launch_correct_dir(const SysView<V, W>& v, int first, hipStream_t stream);
+// full reorthogonalisation: the store after the SpMV; the coefficients and
+// the update of w after the direction update
+template <typename V, typename W> void launch_reorth_store(const SysView<V, W>& v, hipStream_t stream);
+template <typename V, typename W> void launch_reorth(const SysView<V, W>& v, hipStream_t stream);
 template <typename V, typename W, int B>
 void launch_true_resid(const SysView<V, W>& v, int final_only, hipStream_t stream);
 template <typename V, typename W>
@@ -223,6 +241,8 @@ template <typename V, typename W, int B>
 void batch_spmv_dot(const SysView<V, W>* views, const BatchMaps& m, hipStream_t stream);
 template <typename V, typename W, int B>
 void batch_update_reduce(const SysView<V, W>* views, const BatchMaps& m, int mode, hipStream_t stream);
+template <typename V, typename W, int B>
+void batch_update_only(const SysView<V, W>* views, const BatchMaps& m, int mode, hipStream_t stream);
 template <typename V, typename W>
 void batch_correct_dir(const SysView<V, W>* views, const BatchMaps& m, int first, hipStream_t stream);
 template <typename V, typename W, int B>

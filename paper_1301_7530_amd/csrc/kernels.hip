@@ -392,10 +392,18 @@ __device__ __forceinline__ X ell_row1(const V* __restrict__ val, const int32_t* 
 // A whole 3x3-block ELL row (one lane): the three sub-rows at once, so the
 // block column index and the three entries of x are loaded once per block
 // and all nine value planes stream in lane order.  UNR blocks in flight.
-template <typename V, typename X>
+// UNR: blocks whose loads are issued together; NT: the matrix streams
+// with non-temporal loads (read once per launch), leaving the caches to the
+// gathered x.  Neither changes the order of the sums.
+template <typename T, bool NT>
+__device__ __forceinline__ T ld_stream(const T* p) {
+    if (NT) return __builtin_nontemporal_load(p);
+    return *p;
+}
+
+template <typename V, typename X, int UNR = 2, bool NT = false>
 __device__ __forceinline__ void ell_row3all(const V* __restrict__ val, const int32_t* __restrict__ col,
                                             const X* __restrict__ x, int64_t k0, int64_t k1, int lane, X out[3]) {
-    constexpr int UNR = 2;
     X a0 = 0, a1 = 0, a2 = 0;
     int64_t k = k0;
     for (; k + UNR <= k1; k += UNR) {
@@ -403,10 +411,10 @@ __device__ __forceinline__ void ell_row3all(const V* __restrict__ val, const int
         V a[UNR][9];
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
-            cc[u] = col[(k + u) * 64 + lane];
+            cc[u] = ld_stream<int32_t, NT>(col + (k + u) * 64 + lane);
             const V* vb = val + (k + u) * 9 * 64 + lane;
 #pragma unroll
-            for (int e = 0; e < 9; ++e) a[u][e] = vb[e * 64];
+            for (int e = 0; e < 9; ++e) a[u][e] = ld_stream<V, NT>(vb + e * 64);
         }
         X xs[UNR][3];
 #pragma unroll
@@ -463,11 +471,18 @@ __device__ __forceinline__ void spmv_dot_body(const SysView<V, W>& v, int64_t bi
         }
     } else {
         // two slices per workgroup step, one per wave; a lane owns a block row
+        const int var = v.spmv_var;
         for (int64_t sl = bid * 2 + wave; sl < v.nslices; sl += nblk * 2) {
             const int64_t k0 = v.slice_ptr[sl], k1 = v.slice_ptr[sl + 1];
             W acc[3];
-            if (v.op64) ell_row3all<double, W>(v.val64, v.col, v.w, k0, k1, lane, acc);
-            else ell_row3all<V, W>(v.val, v.col, v.w, k0, k1, lane, acc);
+            if (v.op64) {
+                if ((var & 3) == 0) ell_row3all<double, W, 2, false>(v.val64, v.col, v.w, k0, k1, lane, acc);
+                else if ((var & 3) == 1) ell_row3all<double, W, 4, false>(v.val64, v.col, v.w, k0, k1, lane, acc);
+                else if ((var & 3) == 2) ell_row3all<double, W, 2, true>(v.val64, v.col, v.w, k0, k1, lane, acc);
+                else ell_row3all<double, W, 4, true>(v.val64, v.col, v.w, k0, k1, lane, acc);
+            } else {
+                ell_row3all<V, W>(v.val, v.col, v.w, k0, k1, lane, acc);
+            }
             const int64_t p = sl * 64 + lane;
             if (p < v.nb) {
 #pragma unroll
@@ -1187,6 +1202,7 @@ __device__ __forceinline__ void correct_dir_body(const SysView<V, W>& v, int64_t
             const W zv = (W)(s - cz);
             const W wv = (first == 1) ? zv : (W)(s - cw + beta * (double)wv0);
             v.w[i] = wv;
+            if (v.zr) v.zr[i] = zv;
             if (j < hist_cap) {
                 if (v.zhist) v.zhist[(int64_t)j * v.ldh + i] = (V)zv;
                 if (v.whist) v.whist[(int64_t)j * v.ldh + i] = (V)wv;
@@ -1194,6 +1210,92 @@ __device__ __forceinline__ void correct_dir_body(const SysView<V, W>& v, int64_t
         }
     }
     ktime_end(v.kslots, 2, bid, tm);
+}
+
+// ------------------------------------------------------- reorthogonalisation
+// Full reorthogonalisation (Section 2.1 remark; the experiments of Section
+// 5.1): after the direction update of step j, the new direction is
+//   w = z - sum_{i < j'} ((A w_i, z) / (w_i, A w_i)) w_i,  j' = min(j, rcap),
+// classical Gram-Schmidt in the A inner product over the kept directions
+// (in exact arithmetic only the last term is nonzero and equals beta w_old).
+// Four launches per step: the store of w_j and A w_j after the SpMV, then
+// the partial sums (A w_i, z) per row range, their reduction to the
+// coefficients, and the update of w.  The kept vectors are row-major so
+// that a row's coefficients stream contiguously.
+
+// after the SpMV of step j: row i of W_r and Q_r gets w_j[i] and (A w_j)[i]
+template <typename V, typename W>
+__global__ __launch_bounds__(256) void k_reorth_store(SysView<V, W> v) {
+    const DevState* st = v.st;
+    if (!gate(st, M_RUN)) return;
+    const int j = st->iter;
+    if (j >= v.rcap) return;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < v.n; i += (int64_t)gridDim.x * 256) {
+        v.Wr[i * v.ldr + j] = v.w[i];
+        v.Qr[i * v.ldr + j] = v.q[i];
+    }
+}
+
+// partial sums over the workgroup's row range of (A w_i, z), i < j'; thread
+// t takes the columns t, t + 256, ...; rows in order
+template <typename V, typename W>
+__global__ __launch_bounds__(256) void k_reorth_dot(SysView<V, W> v) {
+    const DevState* st = v.st;
+    if (!gate(st, M_RUN)) return;
+    const int jn = st->iter < v.rcap ? st->iter : v.rcap;
+    __shared__ double zs[256];
+    const int64_t per = (v.n + gridDim.x - 1) / gridDim.x;
+    const int64_t r0 = (int64_t)blockIdx.x * per;
+    const int64_t r1 = (r0 + per < v.n) ? r0 + per : v.n;
+    for (int i0 = 0; i0 < jn; i0 += 256) {
+        const int i = i0 + (int)threadIdx.x;
+        double acc = 0.0;
+        for (int64_t rb = r0; rb < r1; rb += 256) {
+            __syncthreads();
+            if (rb + threadIdx.x < r1) zs[threadIdx.x] = (double)v.zr[rb + threadIdx.x];
+            __syncthreads();
+            const int cnt = (r1 - rb < 256) ? (int)(r1 - rb) : 256;
+            if (i < jn) {
+                const W* q = v.Qr + rb * v.ldr + i;
+                for (int t = 0; t < cnt; ++t) acc += (double)q[(int64_t)t * v.ldr] * zs[t];
+            }
+        }
+        if (i < jn) v.rpart[(int64_t)blockIdx.x * v.ldr + i] = acc;
+    }
+}
+
+// coefficients c_i = (sum over row ranges, in order) / (w_i, A w_i)
+template <typename V, typename W>
+__global__ __launch_bounds__(256) void k_reorth_reduce(SysView<V, W> v) {
+    const DevState* st = v.st;
+    if (!gate(st, M_RUN)) return;
+    const int jn = st->iter < v.rcap ? st->iter : v.rcap;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < jn; i += gridDim.x * 256) {
+        double sum = 0.0;
+        for (int g = 0; g < v.gr; ++g) sum += v.rpart[(int64_t)g * v.ldr + i];
+        v.rc[i] = sum / v.gamma_h[i];
+    }
+}
+
+// w = z - sum_i c_i w_i: one wave per row, lanes over i, a fixed shuffle tree
+template <typename V, typename W>
+__global__ __launch_bounds__(256) void k_reorth_apply(SysView<V, W> v) {
+    const DevState* st = v.st;
+    if (!gate(st, M_RUN)) return;
+    const int jn = st->iter < v.rcap ? st->iter : v.rcap;
+    __shared__ double cs[kReorthMax];
+    for (int i = threadIdx.x; i < jn; i += 256) cs[i] = v.rc[i];
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = (int64_t)gridDim.x * 4;
+    for (int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); row < v.n; row += waves) {
+        const W* wr = v.Wr + row * v.ldr;
+        double acc = 0.0;
+        for (int i = lane; i < jn; i += 64) acc += cs[i] * (double)wr[i];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if (lane == 0) v.w[row] = (W)((double)v.zr[row] - acc);
+    }
 }
 
 // ----------------------------------------------------------------- K11
@@ -1888,12 +1990,14 @@ inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b);
 
 // ------------------------------------------------------------ geometry
 
-Geometry make_geometry(int64_t n, int64_t nslices, int block, int64_t cb3_req) {
+Geometry make_geometry(int64_t n, int64_t nslices, int block, int64_t cb3_req, int spmv_grid) {
     Geometry g{};
     const int64_t nb = n / block;
     const int64_t per = (block == 1) ? 4 : 2;  // slices per workgroup step (one per wave)
     int64_t g1 = (nslices + per - 1) / per;
-    g.g1 = (int32_t)std::min<int64_t>(std::max<int64_t>(g1, 1), 2048);
+    // at most kPart1 workgroups: each writes its (w, A w) partial there
+    const int64_t cap1 = spmv_grid > 0 ? std::min<int64_t>(spmv_grid, kPart1) : 2048;
+    g.g1 = (int32_t)std::min<int64_t>(std::max<int64_t>(g1, 1), cap1);
     // K3: contiguous ranges of cb3 block rows; by default one range per CU
     int64_t cb = cb3_req > 0 ? cb3_req : (nb + 255) / 256;
     if (cb < 64) cb = 64;
@@ -1982,6 +2086,15 @@ void batch_update_reduce(const SysView<V, W>* views, const BatchMaps& m, int mod
     if (m.count[BK_ONE] > 0)
         hipLaunchKernelGGL((kb_finalize_update<V, W>), dim3((unsigned)m.count[BK_ONE]), dim3(kTF3), 0, stream, views,
                            m.map[BK_ONE], mode);
+}
+
+// the update kernel of every member alone (no end-of-step reduction): the
+// batch autotuner times it in the initial mode
+template <typename V, typename W, int B>
+void batch_update_only(const SysView<V, W>* views, const BatchMaps& m, int mode, hipStream_t stream) {
+    if (m.count[BK_UPD] > 0)
+        hipLaunchKernelGGL((kb_update_reduce<V, W, B>), dim3((unsigned)m.count[BK_UPD]), dim3(kT3), 0, stream, views,
+                           m.map[BK_UPD], mode);
 }
 
 template <typename V, typename W>
@@ -2111,6 +2224,20 @@ void launch_d2v(const double* in, V* out, int64_t n, hipStream_t stream) {
     hipLaunchKernelGGL((k_d2v<V>), dim3(cdiv(n, 256)), dim3(256), 0, stream, in, out, n);
 }
 
+template <typename V, typename W>
+void launch_reorth_store(const SysView<V, W>& v, hipStream_t stream) {
+    const int g = (int)std::min<int64_t>(cdiv(v.n, 256), 2048);
+    hipLaunchKernelGGL((k_reorth_store<V, W>), dim3(g), dim3(256), 0, stream, v);
+}
+
+template <typename V, typename W>
+void launch_reorth(const SysView<V, W>& v, hipStream_t stream) {
+    hipLaunchKernelGGL((k_reorth_dot<V, W>), dim3(v.gr), dim3(256), 0, stream, v);
+    hipLaunchKernelGGL((k_reorth_reduce<V, W>), dim3(cdiv(kReorthMax, 256)), dim3(256), 0, stream, v);
+    const int g = (int)std::min<int64_t>(cdiv(v.n, 4), 2048);
+    hipLaunchKernelGGL((k_reorth_apply<V, W>), dim3(g), dim3(256), 0, stream, v);
+}
+
 template <typename V>
 void launch_v2d(const V* in, double* out, int64_t n, hipStream_t stream) {
     hipLaunchKernelGGL((k_v2d<V>), dim3(cdiv(n, 256)), dim3(256), 0, stream, in, out, n);
@@ -2125,10 +2252,13 @@ void launch_v2d(const V* in, double* out, int64_t n, hipStream_t stream) {
                                        hipStream_t);                                                              \
     template void batch_spmv_dot<V, W, B>(const SysView<V, W>*, const BatchMaps&, hipStream_t);                  \
     template void batch_update_reduce<V, W, B>(const SysView<V, W>*, const BatchMaps&, int, hipStream_t);        \
+    template void batch_update_only<V, W, B>(const SysView<V, W>*, const BatchMaps&, int, hipStream_t);          \
     template void batch_true_resid<V, W, B>(const SysView<V, W>*, const BatchMaps&, int, hipStream_t);
 
 #define KRS_INST_VW(V, W)                                                                                         \
     template void launch_correct_dir<V, W>(const SysView<V, W>&, int, hipStream_t);                              \
+    template void launch_reorth_store<V, W>(const SysView<V, W>&, hipStream_t);                                  \
+    template void launch_reorth<V, W>(const SysView<V, W>&, hipStream_t);                                        \
     template void launch_coarse_dot<V, W>(const SysView<V, W>&, int, int, uint32_t, hipStream_t);                \
     template void launch_coarse_correct<V, W>(const SysView<V, W>&, int, uint32_t, hipStream_t);                 \
     template void batch_correct_dir<V, W>(const SysView<V, W>*, const BatchMaps&, int, hipStream_t);             \

@@ -217,7 +217,7 @@ krs_status SeqImpl<V, W>::create(const krs_seq_desc& d, const double* C0, int32_
     std::memset(h_st, 0, sizeof(DevState));
     // ---- initial basis C0
     ldc = (n + 255) & ~(int64_t)255;
-    geo = make_geometry(n, nslices, B, desc.update_rows);
+    geo = make_geometry(n, nslices, B, desc.update_rows, spmv_grid_cap());
     nc = 0;
     if (m0 > 0) {
         if (!C0 || ldc0 < n) {
@@ -259,7 +259,7 @@ template <typename V, typename W>
 void SeqImpl<V, W>::destroy() {
     for (Buf* b : {&d_col, &d_slice_ptr, &d_map, &d_diag, &d_val64, &d_valV, &d_minv, &d_bad, &d_in, &d_b, &d_x,
                    &d_r, &d_s, &d_w, &d_q, &d_C, &d_C0, &d_AC64, &d_ACv, &d_G, &d_Ginv, &d_mu, &d_Z, &d_coef,
-                   &d_partials, &d_st, &d_F, &d_tmp, &d_Ctmp, &d_kslots})
+                   &d_partials, &d_st, &d_F, &d_tmp, &d_Ctmp, &d_kslots, &d_Wr, &d_Qr, &d_rpart, &d_rc, &d_zr})
         b->release(ctx);
     if (h_st) (void)hipHostFree(h_st);
     h_st = nullptr;
@@ -370,6 +370,17 @@ SysView<V, W> SeqImpl<V, W>::view() {
     v.kslots = (unsigned long long*)d_kslots.p;
     v.fused = (desc.kernel_flags & 1) ? 0 : 1;
     v.dir_literal = (desc.kernel_flags & 2) ? 1 : 0;
+    v.spmv_var = (desc.kernel_flags >> 3) & 3;
+    if (reorth() && rcap > 0) {
+        v.Wr = (W*)d_Wr.p;
+        v.Qr = (W*)d_Qr.p;
+        v.ldr = ldr;
+        v.rcap = rcap;
+        v.gr = rgr;
+        v.rpart = (double*)d_rpart.p;
+        v.rc = (double*)d_rc.p;
+        v.zr = (W*)d_zr.p;
+    }
     return v;
 }
 
@@ -395,8 +406,10 @@ template <typename V, typename W>
 void SeqImpl<V, W>::enqueue_iterations(const SysView<V, W>& v, int k) {
     for (int i = 0; i < k; ++i) {
         k_spmv(v);
+        if (v.Wr) launch_reorth_store<V, W>(v, stream);
         k_update(v, 0);
         launch_correct_dir<V, W>(v, 0, stream);
+        if (v.Wr) launch_reorth<V, W>(v, stream);
     }
 }
 
@@ -579,13 +592,19 @@ int64_t SeqImpl<V, W>::working_bytes() const {
     b += n * ldm * (8 + vsz);                                          // A C (double and V)
     b += ldc * (int64_t)ncmax * (int64_t)sizeof(V);                    // basis change staging
     b += nnzb * B * B * 8;                                             // value staging
-    b += (kPart1 + partial_doubles(make_geometry(n, nslices, B, desc.update_rows), ncmax)) * 8;
+    b += (kPart1 + partial_doubles(make_geometry(n, nslices, B, desc.update_rows, spmv_grid_cap()), ncmax)) * 8;
+    if (reorth()) {
+        const int64_t rc = std::min<int64_t>(std::min<int64_t>(desc.max_iter + 1, kReorthMax), 1 << 30);
+        b += 2 * n * ((rc + 15) / 16 * 16) * (int64_t)sizeof(W) + n * (int64_t)sizeof(W);
+    }
     return b;
 }
 
 template <typename V, typename W>
 void SeqImpl<V, W>::trim() {
-    for (Buf* b : {&d_Z, &d_AC64, &d_ACv, &d_partials, &d_F, &d_Ctmp, &d_tmp, &d_in, &d_kslots}) b->release(ctx);
+    for (Buf* b : {&d_Z, &d_AC64, &d_ACv, &d_partials, &d_F, &d_Ctmp, &d_tmp, &d_in, &d_kslots, &d_Wr, &d_Qr, &d_rpart,
+                   &d_rc, &d_zr})
+        b->release(ctx);
     graph_release();
 }
 
@@ -615,7 +634,7 @@ krs_status SeqImpl<V, W>::tune_update() {
                                  (nb + 127) / 128};
     std::vector<Geometry> geos;
     for (int64_t c : cand) {
-        const Geometry g = make_geometry(n, nslices, B, c);
+        const Geometry g = make_geometry(n, nslices, B, c, spmv_grid_cap());
         bool seen = false;
         for (const auto& h : geos) seen = seen || h.cb3 == g.cb3;
         if (!seen) geos.push_back(g);
@@ -649,6 +668,18 @@ krs_status SeqImpl<V, W>::tune_update() {
     }
     geo = bg;
     tuned_nc = nc;
+    return KRS_OK;
+}
+
+template <typename V, typename W>
+krs_status SeqImpl<V, W>::set_update_rows(int64_t rows) {
+    desc.update_rows = (int32_t)rows;
+    geo = make_geometry(n, nslices, B, rows, spmv_grid_cap());
+    if (!ensure_partials(0)) return KRS_E_OOM;
+    cur = view();
+    tuned_nc = std::max(nc, 1);
+    batch_tuned = true;
+    batch_tuned_nc = nc;
     return KRS_OK;
 }
 
@@ -708,6 +739,19 @@ krs_status SeqImpl<V, W>::begin_solve() {
         if (!ensure_c_capacity(nc + hist)) return KRS_E_OOM;
         trks_slots = hist;
     }
+    if (reorth()) {
+        // every direction of the run up to kReorthMax (and the history cap)
+        rcap = std::min(std::min(max_iter + 1, kReorthMax), desc.history_cap > 0 ? desc.history_cap : kReorthMax);
+        rcap = std::min(rcap, coef_cap);
+        ldr = ((int64_t)rcap + 15) / 16 * 16;
+        rgr = (int)std::max<int64_t>(1, std::min<int64_t>(512, (n + 4095) / 4096));
+        if (!d_Wr.reserve(ctx, (size_t)n * ldr * sizeof(W)) || !d_Qr.reserve(ctx, (size_t)n * ldr * sizeof(W)) ||
+            !d_rpart.reserve(ctx, (size_t)rgr * ldr * sizeof(double)) || !d_rc.reserve(ctx, (size_t)ldr * sizeof(double)) ||
+            !d_zr.reserve(ctx, (size_t)n * sizeof(W))) {
+            set_error("device allocation failed for the reorthogonalisation vectors");
+            return KRS_E_OOM;
+        }
+    }
     if (!ensure_partials(0)) return KRS_E_OOM;
     // device state
     std::memset(h_st, 0, sizeof(DevState));
@@ -727,7 +771,8 @@ krs_status SeqImpl<V, W>::begin_solve() {
     if (timing && !d_kslots.reserve(ctx, (size_t)3 * 2 * kMaxTimedGrid * sizeof(unsigned long long))) return KRS_E_OOM;
     KRS_HIP(hipMemcpyAsync(d_st.p, h_st, sizeof(DevState), hipMemcpyHostToDevice, stream));
     h_st->iter = 0;
-    if (desc.autotune && nc > 0 && (tuned_nc == 0 || 2 * nc > 3 * tuned_nc || 3 * nc < 2 * tuned_nc)) {
+    if (desc.autotune && !batch_tuned && nc > 0 &&
+        (tuned_nc == 0 || 2 * nc > 3 * tuned_nc || 3 * nc < 2 * tuned_nc)) {
         st = tune_update();
         if (st != KRS_OK) return st;
         if (!ensure_partials(0)) return KRS_E_OOM;
@@ -1310,6 +1355,32 @@ struct BatchRunner : RunnerBase {
         if (B == 1) batch_spmv_dot<V, W, 1>(views(), maps, stream);
         else batch_spmv_dot<V, W, 3>(views(), maps, stream);
     }
+    krs_status time_update(int reps, float* ms) override {
+        *ms = 0.f;
+        if (mem.empty()) return KRS_OK;
+        BatchMaps m = maps;
+        m.fused = 0;  // the update kernel alone, no end-of-step reduction
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        KRS_HIP(hipEventCreate(&e0));
+        KRS_HIP(hipEventCreate(&e1));
+        krs_status st = KRS_OK;
+        auto launch = [&] {
+            if (m.count[BK_UPD] <= 0) return;
+            if (B == 1) batch_update_only<V, W, 1>(views(), m, 1, stream);
+            else batch_update_only<V, W, 3>(views(), m, 1, stream);
+        };
+        launch();
+        if (hipEventRecord(e0, stream) != hipSuccess) st = KRS_E_DEVICE;
+        for (int r = 0; r < reps && st == KRS_OK; ++r) launch();
+        if (st == KRS_OK && (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(ms, e0, e1) != hipSuccess))
+            st = KRS_E_DEVICE;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (st != KRS_OK) set_error("timing the fused update failed");
+        *ms /= std::max(reps, 1);
+        return st;
+    }
     void update(int mode) {
         if (B == 1) batch_update_reduce<V, W, 1>(views(), maps, mode, stream);
         else batch_update_reduce<V, W, 3>(views(), maps, mode, stream);
@@ -1445,6 +1516,32 @@ krs_status batch_solve(krs_ctx* ctx, SeqBase* const* seqs, int count, double* co
             return m;
         };
         krs_status st = r->set_members(members(act));
+        // Batch autotuner: members that ask for it and have not been tuned
+        // in a batch (or whose basis width changed by half since) get the update tile (block rows per workgroup) whose
+        // fused launch over the whole group is fastest; the tile then stays
+        // with each sequence (it fixes the grouping of its partial sums).
+        bool tune = false;
+        for (int i : act) tune = tune || (seqs[i]->desc.autotune && seqs[i]->batch_tune_due());
+        if (st == KRS_OK && tune) {
+            const int64_t cand[] = {512, 1024, 2048, 4096, 8192, 16384};
+            float best = 0.f;
+            int64_t pick = 0;
+            for (int64_t c : cand) {
+                for (int i : act)
+                    if (st == KRS_OK) st = seqs[i]->set_update_rows(c);
+                if (st == KRS_OK) st = r->set_members(members(act));
+                float ms = 0.f;
+                if (st == KRS_OK) st = r->time_update(3, &ms);
+                if (st != KRS_OK) break;
+                if (pick == 0 || ms < best) {
+                    best = ms;
+                    pick = c;
+                }
+            }
+            for (int i : act)
+                if (st == KRS_OK) st = seqs[i]->set_update_rows(pick);
+            if (st == KRS_OK) st = r->set_members(members(act));
+        }
         // Short blocks: a member whose residual replacement is due waits
         // (gated) until the end of the block, and the gated workgroups of a
         // large batch still cost their dispatch.  The block length changes

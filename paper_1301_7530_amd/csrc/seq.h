@@ -67,6 +67,15 @@ struct SeqBase {
     // and the plan may have run on a helper thread)
     char plan_msg[256] = {0};
     virtual krs_status basis(double* C, int64_t ld, int32_t cap, int32_t* n_c) = 0;
+    // a begun solve's update tile (block rows per update workgroup), fixed
+    // from here on for the sequence (the batch autotuner sets it)
+    virtual krs_status set_update_rows(int64_t rows) = 0;
+    bool batch_tuned = false;
+    int batch_tuned_nc = 0;
+    bool batch_tune_due() const {
+        const int t = std::max(batch_tuned_nc, 1), c = std::max(nc, 1);
+        return !batch_tuned || 2 * c > 3 * t || 3 * c < 2 * t;
+    }
     // the export through caller-provided device staging of n doubles
     virtual krs_status basis_staged(double* C, int64_t ld, double* staging) = 0;
     virtual krs_status history(double* Z, int64_t ld, int32_t cap, int32_t* m_out) = 0;
@@ -99,6 +108,15 @@ struct SeqImpl : SeqBase {
     bool submitted = false, solved = false;
     Buf d_col, d_slice_ptr, d_map, d_diag, d_val64, d_valV, d_minv, d_bad, d_in, d_b, d_x, d_r, d_s, d_w, d_q;
     Buf d_C, d_C0, d_AC64, d_ACv, d_G, d_Ginv, d_mu, d_Z, d_coef, d_partials, d_st, d_F, d_tmp, d_Ctmp, d_kslots;
+    // full reorthogonalisation (kernel_flags bit 2): kept directions, their
+    // A-products, partial sums, coefficients, the current z
+    Buf d_Wr, d_Qr, d_rpart, d_rc, d_zr;
+    int rcap = 0, rgr = 0;
+    int64_t ldr = 0;
+    bool reorth() const { return (desc.kernel_flags & 4) != 0; }
+    // SpMV workgroup cap: kernel_flags bit 5 raises it from 2048 to 4096
+    // (the size of the region of its partial sums, kPart1)
+    int spmv_grid_cap() const { return (desc.kernel_flags & 32) ? (int)kPart1 : 0; }
     DevState* h_st = nullptr;
     double* h_coef = nullptr;  // pinned staging of the CG coefficients read back by end_solve
     size_t h_coef_cap = 0;     // doubles
@@ -161,6 +179,7 @@ struct SeqImpl : SeqBase {
     krs_status recycle_plan() override;
     krs_status recycle_apply(int32_t* n_added) override;
     krs_status basis(double* C, int64_t ld, int32_t cap, int32_t* n_c) override;
+    krs_status set_update_rows(int64_t rows) override;
     krs_status basis_staged(double* C, int64_t ld, double* staging) override;
     krs_status history(double* Z, int64_t ld, int32_t cap, int32_t* m_out) override;
     void destroy() override;
@@ -192,6 +211,10 @@ struct RunnerBase {
     // wait for the last launch; out[2 i] = status, out[2 i + 1] = iteration of member i
     virtual krs_status read_status(std::vector<int32_t>& out) = 0;
     virtual size_t size() const = 0;
+    // time `reps` launches of the update kernel alone (initial mode: it
+    // rewrites s and the partial sums, which the next step recomputes) over
+    // every member; *ms receives the mean per launch
+    virtual krs_status time_update(int reps, float* ms) = 0;
 };
 std::unique_ptr<RunnerBase> make_runner(krs_ctx* ctx, int type_key);
 bool finished_status(int device_status);

@@ -390,6 +390,10 @@ krs_status krs_server_enqueue(krs_server* s, krs_seq* seq, const double* values,
             krs::set_error("the sequence belongs to another context");
             return KRS_E_INVALID;
         }
+        if (seq->impl->desc.kernel_flags & 4) {
+            krs::set_error("full reorthogonalisation is not available in the server's fused batches");
+            return KRS_E_INVALID;
+        }
         Request r;
         r.seq = seq;
         r.impl = seq->impl.get();

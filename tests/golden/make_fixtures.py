@@ -34,8 +34,11 @@ import oracle as O  # noqa: E402
 FIXTURES = {
     # the 40^3 elasticity workload, first three systems, cap 60 (freeze)
     "elasticity40_srks_fp64": dict(E=40, workload_id=2, systems=3, cap=60, eps=1e-8, max_iter=30000),
-    # the 100^3 workload's setup at 30^3, the whole 30-system sequence, cap 200 (freeze)
-    "elasticity30_srks_fp64": dict(E=30, workload_id=3, systems=30, cap=200, eps=1e-8, max_iter=30000),
+    # the 100^3 workload's setup at 30^3, its first eight systems, cap 200
+    # (freeze), the paper's eps = 1e-14 (at 1e-8 the first system's 200
+    # smallest stagnated values include copies whose vectors stall the next
+    # solve near 4e-7 on the oracle)
+    "elasticity30_srks_fp64": dict(E=30, workload_id=3, systems=8, cap=200, eps=1e-14, max_iter=30000),
     # the 40^3 workload with n_c_lim from the complexity analysis of the
     # first solve (byte model of the library's FP64 iteration), freeze cap
     "elasticity40_auto_fp64": dict(E=40, workload_id=2, systems=4, cap="auto", eps=1e-8, max_iter=30000),
@@ -84,6 +87,7 @@ def make(name: str) -> None:
         nc_in = C.shape[1]
         if nc_in:
             C = C[:, res["kept"]]
+        C_solve = C  # the basis this solve used (after the guard), for the perturbed solves
         rec = dict(k=k, m=int(res["m"]), nc_in=int(nc_in), nc_solve=int(C.shape[1]),
                    status=int(res["status"]), relres_true=float(res["relres_true"]),
                    alpha=res["alpha"][:N_COEF].tolist(), rho=res["rho"][:N_COEF].tolist(),
@@ -101,12 +105,22 @@ def make(name: str) -> None:
             rec["selected_all_count"] = len(allsel)
             new = O.ritz_block(res["Z"], res["alpha"], res["rho"], sel, th_m)
             C = np.concatenate([C, new], axis=1)
+        # the oracle's own sensitivity: the same solve with b perturbed at
+        # the rounding level (relative 1e-15, two draws); the spread of
+        # these iteration counts is what rounding alone moves
+        prng = np.random.default_rng(np.random.SeedSequence([13017530, 98, k]))
+        pm = []
+        for _ in range(2):
+            bp = b * (1.0 + 1e-15 * prng.standard_normal(b.shape))
+            pm.append(int(O.apcg(rp, ci, v, bp, "block3", C=C_solve, tol=1e-8, max_iter=cfg["max_iter"],
+                                 direction="project_old")["m"]))
+        rec["m_perturbed"] = pm
         rec["selected"] = [int(i) for i in sel]
         rec["nc_next"] = int(C.shape[1])
         rec["fingerprint"] = span_fingerprint(C, R).tolist()
         recs.append(rec)
         del res
-        print(f"{name} system {k}: m={rec['m']} n_c {rec['nc_in']}->{rec['nc_solve']} (+{len(sel)}) "
+        print(f"{name} system {k}: m={rec['m']} (perturbed {pm}) n_c {rec['nc_in']}->{rec['nc_solve']} (+{len(sel)}) "
               f"rel res {rec['relres_true']:.2e}  [{time.perf_counter() - t:.0f} s]", flush=True)
     out = dict(name=name, config=cfg, n=seq.n, n_coef=N_COEF, generator="tests/golden/make_fixtures.py",
                systems=recs)

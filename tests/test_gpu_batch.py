@@ -256,6 +256,44 @@ def test_update_tile_choices_agree(gpu):
         assert np.linalg.norm(x - sols[0]) / np.linalg.norm(sols[0]) <= 1e-5
 
 
+def test_batch_autotuner_picks_one_tile(gpu):
+    """The batch autotuner (members created with autotune) times the fused
+    update over the whole group for each candidate tile and gives every
+    member the fastest; members then solve to the tolerance, and a member
+    solved alone with the tile it was given reproduces its batched result bit
+    for bit (the tile is all that the tuning changes)."""
+    K = _K()
+    seqs = _sequences(2)
+    kw = dict(precision="mixed", reuse="selective", tol=1e-8, max_iter=3000, ritz_eps=1e-8, max_basis=16,
+              cap_policy="freeze")
+    hs = [K.sequence_for(gpu, sq, autotune=True, **kw) for sq in seqs]
+    tiles, res = [], []
+    try:
+        for k in range(2):
+            for h, sq in zip(hs, seqs):
+                h.submit(*sq.system(k))
+            xs, infos = gpu.batch_solve(hs)
+            gpu.batch_recycle(hs)
+            tiles.append([inf["update_rows"] for inf in infos])
+            for i, inf in enumerate(infos):
+                assert inf["status"] == 0 and _relres(seqs[i].csr(k), xs[i]) <= 1e-8
+            res.append(xs)
+    finally:
+        for h in hs:
+            h.close()
+    print("tiles per batch:", tiles, flush=True)
+    assert all(len(set(t)) == 1 for t in tiles)
+    assert tiles[0][0] in (512, 1024, 2048, 4096, 8192, 16384) or tiles[0][0] >= 64
+    # the first member alone with the tiles it was given: the same bits
+    s = K.sequence_for(gpu, seqs[0], update_rows=tiles[0][0], **kw)
+    try:
+        s.submit(*seqs[0].system(0))
+        x0, _ = s.solve()
+    finally:
+        s.close()
+    assert np.array_equal(x0, res[0][0])
+
+
 def test_batched_full_size_sampled(gpu):
     """The batched workload at its full size (256 diffusion sequences,
     n ~ U[5e3, 2e5], sum n = 26.5 M) in the benchmark's setup, two systems:

@@ -157,14 +157,42 @@ def test_srks_sequence_drift_bounded(gpu):
         assert abs(res[k]["iters"] - recs[k]["m"]) <= max(2, 0.1 * recs[k]["m"]), (k, res[k]["iters"], recs[k]["m"])
 
 
-def test_mixed_precision_elasticity(gpu):
+def _dense(csr):
+    rp, ci, v, _ = csr
+    n = len(rp) - 1
+    A = np.zeros((n, n))
+    for i in range(n):
+        A[i, ci[rp[i]:rp[i + 1]]] = v[rp[i]:rp[i + 1]]
+    return A
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp32basis"])
+def test_mixed_precision_elasticity(gpu, precision):
+    """Each result of a reduced-precision mode against the FP64 oracle: the
+    device's true residual <= 1e-8; the host's recomputation of it within
+    the rounding of that recomputation, (max row length + 2) u
+    ||(|b| + |A||x|)|| / ||b||; and the error to the oracle's FP64 solution
+    within what two residuals of 1e-8 allow, 2e-8 kappa(A)."""
     seq = gen.config_elasticity(6, 2)
-    res = _run_gpu(gpu, seq, 2, precision="mixed", reuse="selective", ritz_eps=1e-10, max_basis=24,
+    res = _run_gpu(gpu, seq, 2, precision=precision, reuse="selective", ritz_eps=1e-10, max_basis=24,
                    cap_policy="freeze", tol=1e-8, max_iter=6000)
     for k in range(2):
+        csr = seq.csr(k)
+        rp, ci, v, b = csr
+        A = _dense(csr)
+        x = res[k]["x"]
         assert res[k]["status"] == 0
         assert res[k]["rel_res_true"] <= 1e-8
-        assert _relres(seq.csr(k), res[k]["x"]) <= 1e-8 * 1.05
+        rowmax = int(np.max(np.diff(rp)))
+        slack = (rowmax + 2) * 2.0 ** -53 * np.linalg.norm(np.abs(b) + np.abs(A) @ np.abs(x)) / np.linalg.norm(b)
+        assert _relres(csr, x) <= 1e-8 + slack
+        ref = O.apcg(rp, ci, v, b, "block3", tol=1e-10, max_iter=6000)
+        err = np.linalg.norm(x - ref["x"]) / np.linalg.norm(ref["x"])
+        kappa = np.linalg.cond(A)
+        print(f"{precision} system {k}: iterations {res[k]['iters']} (oracle {ref['m']} at 1e-10), "
+              f"|x - x_fp64|/|x_fp64| {err:.2e} (bound {2e-8 * kappa:.1e}), refinements {res[k]['refinements']}",
+              flush=True)
+        assert err <= 2e-8 * kappa
         assert res[k]["refinements"] >= 1
 
 
