@@ -250,6 +250,17 @@ krs_status krs_seq_history(krs_seq* s, double* Z, int64_t ldz, int32_t cap, int3
  * only.  After a solve the columns are the A-orthonormalised ones (same
  * span as the carried basis). */
 krs_status krs_seq_basis(krs_seq* s, double* C, int64_t ldc, int32_t cap, int32_t* n_c);
+/* krs_seq_basis for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments, result and errors, but the double-precision staging of
+ * each column lives in a static 32 MiB device array (one per GPU, held until
+ * the process ends) instead of a library allocation, so the call makes no
+ * hipMalloc/hipFree or other allocating call.  n * 8 bytes must fit the
+ * array (n <= 4,194,304), else KRS_E_INVALID with the limit in the message.
+ * Every call on one GPU shares that array: calls that overlap in time on one
+ * GPU (other threads, other contexts of the same device) race and must be
+ * serialised by the caller.  Synchronous like krs_seq_basis. */
+krs_status krs_seq_basis_noalloc(krs_seq* s, double* C, int64_t ldc, int32_t cap, int32_t* n_c);
 krs_status krs_seq_info(krs_seq* s, krs_solve_info* info);
 /* Live kernel timing.  When enabled, every 32nd iteration the SpMV + (w, A w)
  * kernel (0), the update / preconditioner / projector-reduction kernel (1)

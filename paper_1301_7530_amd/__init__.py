@@ -152,6 +152,7 @@ SIGNATURES = [
     ("krs_seq_coeffs", _S, [_P, _D, _D, _D, ctypes.c_int32, _I32]),
     ("krs_seq_basis", _S, [_P, _D, ctypes.c_int64, ctypes.c_int32, _I32]),
     ("krs_seq_history", _S, [_P, _D, ctypes.c_int64, ctypes.c_int32, _I32]),
+    ("krs_seq_basis_noalloc", _S, [_P, _D, ctypes.c_int64, ctypes.c_int32, _I32]),
     ("krs_seq_info", _S, [_P, ctypes.POINTER(SolveInfo)]),
     ("krs_seq_set_timing", _S, [_P, ctypes.c_int32]),
     ("krs_seq_kernel_time", _S, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), _D]),
@@ -488,6 +489,15 @@ class Sequence:
         Z = np.zeros((self.n, max(m.value, 1)), order="F")
         _check(_lib.krs_seq_history(self.handle, _dptr(Z), self.n, Z.shape[1], ctypes.byref(m)), "krs_seq_history")
         return Z[:, : m.value]
+
+    def basis_noalloc(self):
+        """The basis through krs_seq_basis_noalloc (no device allocation)."""
+        nc = self.n_c
+        C = np.zeros((self.n, max(nc, 1)), order="F")
+        k = ctypes.c_int32(0)
+        _check(_lib.krs_seq_basis_noalloc(self.handle, _dptr(C), self.n, C.shape[1], ctypes.byref(k)),
+               "krs_seq_basis_noalloc")
+        return C[:, :nc]
 
     def set_timing(self, enable=True):
         _check(_lib.krs_seq_set_timing(self.handle, 1 if enable else 0), "krs_seq_set_timing")

@@ -21,7 +21,7 @@ OUT = os.path.join(HERE, "_build")
 SO = os.path.join(HERE, "libkrs.so")
 ARCH = os.environ.get("KRS_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["kernels.hip", "seq.cpp", "ritz.cpp", "coarse.cpp", "abi.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "seq.cpp", "ritz.cpp", "coarse.cpp", "abi.cpp", "server.cpp", "noalloc.cpp"]
 
 
 def _hipcc():

@@ -75,6 +75,11 @@ krs_status krs_ctx_create(int device, void* hip_stream, const krs_allocator* a, 
         set_error("hipSetDevice failed");
         return KRS_E_DEVICE;
     }
+    {
+        // the device address of the allocation-free entry point's scratch
+        const krs_status st = krs::noalloc_init(device);
+        if (st != KRS_OK) return st;
+    }
     krs_ctx* c = new krs_ctx();
     c->device = device;
     if (hip_stream) {
@@ -315,6 +320,40 @@ krs_status krs_seq_basis(krs_seq* s, double* C, int64_t ldc, int32_t cap, int32_
         return KRS_E_BUSY;
     }
     return s->impl->basis(C, ldc, cap, n_c);
+    KRS_GUARD_END
+}
+
+krs_status krs_seq_basis_noalloc(krs_seq* s, double* C, int64_t ldc, int32_t cap, int32_t* n_c) {
+    KRS_GUARD_BEGIN
+    if (!s) return KRS_E_INVALID;
+    if (s->impl->in_server.load() > 0) {
+        set_error("the sequence has server requests in flight");
+        return KRS_E_BUSY;
+    }
+    krs::SeqBase* q = s->impl.get();
+    int32_t nc = 0;
+    krs_status st = q->basis(nullptr, ldc, 0, &nc);  // count only: no device work
+    if (st != KRS_OK) return st;
+    if (n_c) *n_c = nc;
+    if (!C) return KRS_OK;
+    const int64_t n = q->desc.n;
+    if (ldc < n || cap < nc) {
+        set_error("output basis too small");
+        return KRS_E_INVALID;
+    }
+    if ((size_t)n * sizeof(double) > krs::noalloc_scratch_bytes()) {
+        set_error("krs_seq_basis_noalloc: n = " + std::to_string(n) + " needs " +
+                  std::to_string((size_t)n * sizeof(double)) + " bytes of staging, beyond the " +
+                  std::to_string(krs::noalloc_scratch_bytes()) + "-byte scratch (n <= " +
+                  std::to_string(krs::noalloc_scratch_bytes() / sizeof(double)) + ")");
+        return KRS_E_INVALID;
+    }
+    void* staging = krs::noalloc_scratch(q->ctx->device);
+    if (!staging) {
+        set_error("krs_seq_basis_noalloc: scratch address unknown on this device");
+        return KRS_E_DEVICE;
+    }
+    return q->basis_staged(C, ldc, (double*)staging);
     KRS_GUARD_END
 }
 

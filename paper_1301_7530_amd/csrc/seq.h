@@ -231,6 +231,13 @@ void plan_all(SeqBase* const* seqs, int count, krs_status* st);
 krs_status batch_solve(krs_ctx* ctx, SeqBase* const* seqs, int count, double* const* x, bool device_x,
                        krs_solve_info* info, int32_t* added = nullptr);
 
+// The allocation-free entry point's static device scratch (noalloc.cpp):
+// looked up once per device with that device current; the address kept
+// per device (nullptr before noalloc_init succeeded on it).
+krs_status noalloc_init(int device);
+size_t noalloc_scratch_bytes();
+void* noalloc_scratch(int device);
+
 }  // namespace krs
 
 struct krs_seq {
