@@ -131,7 +131,8 @@ def run_sequence(K, ctx, seq, dev_sys, ks, precision, reuse, args, wl, timing=Fa
                        max_basis=max_basis(args, wl) if reuse == "selective" else 0,
                        cap_policy=args.cap_policy,
                        refine_drop=args.refine_drop, autotune=args.autotune, update_rows=args.update_rows,
-                       eager=args.eager, separate_finalize=args.separate_finalize, spmv_variant=args.spmv_variant)
+                       eager=args.eager, separate_finalize=args.separate_finalize, spmv_variant=args.spmv_variant,
+                       history_fp32=args.history_fp32 and precision == "fp64")
     x_scratch = torch.empty(seq.n, dtype=torch.float64, device="cuda")
     recs = []
     try:
@@ -329,10 +330,7 @@ def run_sequence_workload(args, K, torch, wl):
     if warm:
         _log(f"warm-up: systems {warm[0]}..{warm[-1]} on a separate, discarded sequence handle")
         run_sequence(K, ctx, seq, dev_sys, warm, precision, reuse, args, wl, label="warm-up")
-        # hand the warm-up's Krylov history back to the device before the
-        # timed run reserves its own
         torch.cuda.synchronize()
-        torch.cuda.empty_cache()
     xs = [torch.empty(seq.n, dtype=torch.float64, device="cuda") for _ in cmp_ks]
     _log(f"timed: systems 0..{args.steps - 1} in order from an empty basis ({precision})")
     main = run_sequence(K, ctx, seq, dev_sys, ks, precision, reuse, args, wl, timing=True, xs=xs, label="timed")
@@ -408,6 +406,8 @@ def run_sequence_workload(args, K, torch, wl):
             "precision_detail": prec["detail"],
         },
         "iters": iters,
+        "phase_ms": [[round(i[k], 1) for k in ("t_rebuild_ms", "t_iter_ms", "t_recycle_ms")] + [round(1e3 * i["lat_s"], 1)]
+                     for i in infos],
         "n_c": [i["n_c_solve"] for i in infos],
         "added": [i["added"] for i in infos],
         "iters_mean": float(np.mean(iters)),
@@ -858,8 +858,11 @@ def main():
     ap.add_argument("--history-cap", type=int, default=256, help="batched workload: Krylov vectors kept per solve")
     ap.add_argument("--eager", action="store_true", help="launch kernels one by one instead of graph replay")
     ap.add_argument("--spmv-variant", type=int, default=0,
-                    help="block SpMV load schedule bits: 1 four blocks in flight, 2 non-temporal matrix loads, "
-                         "4 up to 4096 workgroups")
+                    help="block SpMV load schedule bits (0: the library's default, 8192 workgroups and "
+                         "non-temporal loads for matrices over 256 MiB): 1 four blocks in flight, 2 non-temporal "
+                         "matrix loads, 4/8/12 at most 2048/4096/8192 workgroups")
+    ap.add_argument("--history-fp32", action="store_true",
+                    help="fp64: keep the Krylov history (used only to form the recycled vectors) in single precision")
     ap.add_argument("--separate-finalize", action="store_true",
                     help="run the end-of-step reduction as its own kernel")
     ap.add_argument("--clients", type=int, default=64, help="serving workload: clients (sequences)")

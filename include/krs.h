@@ -156,10 +156,15 @@ typedef struct {
                               Gram-Schmidt in the A inner product); the first min(history_cap or max_iter,
                               4096) directions and their products with A are kept (2 n doubles each).
                               KRS_FP64 only; not in fused batches or the server (KRS_E_INVALID).
-                              bits 3-5: load schedule of the double-precision block SpMV (same results up
+                              bits 3-6: load schedule of the double-precision block SpMV (same results up
                               to the grouping of the (w, A w) partial sums): bit 3 four blocks of a row in
-                              flight instead of two, bit 4 non-temporal loads of the matrix, bit 5 up to
-                              4096 SpMV workgroups instead of 2048. */
+                              flight instead of two, bit 4 non-temporal loads of the matrix, bits 5-6 the
+                              cap on SpMV workgroups (0: 8192, 1: 2048, 2: 4096, 3: 8192).  With bits 3-6
+                              all zero, a matrix larger than 256 MiB streams with non-temporal loads.
+                              bit 7 (KRS_FP64 only): the Krylov history of z_j kept in single precision,
+                              half the memory of a long run; it only forms the Ritz vectors of the
+                              recycle (combined in double precision, then A-orthonormalised with the
+                              rest of the basis), so every solve still runs in double precision. */
     int32_t reselect;      /* SRKS: 0 = keep every Ritz vector that passed the stagnation test;
                               1 = KRS_RESELECT_CLUSTER: drop the central cluster of those values
                               ("clust", Section 4.4), before the cap */

@@ -82,7 +82,7 @@ DIRECTION = {"literal": 0, "project_old": 1}
 
 
 def apcg(row_ptr, col_idx, values, b, precond="jacobi", C=None, tol=1e-8, max_iter=None, guard=1e-6,
-         record_z=False, record_w=False, direction="literal", reorth=False, orthonormal=False):
+         record_z=False, record_w=False, direction="literal", reorth=False, orthonormal=False, extended=False):
     """One APCG(A, M, C, b) solve (Algorithm 1, standard form; see oracle.c).
 
     ``direction``: 'literal' (w = z + beta w_old, Algorithm 1) or
@@ -93,6 +93,9 @@ def apcg(row_ptr, col_idx, values, b, precond="jacobi", C=None, tol=1e-8, max_it
     columns (G = L L^T) instead of C and the Cholesky factor: the same
     projector in exact arithmetic, without the condition number of G in its
     rounding.
+    ``extended``: accumulate the matrix-vector and dot products in extended
+    precision (both evaluations are faithful; their difference over a long
+    run is what rounding alone moves).
 
     Returns a dict with x, m, status, alpha[m], gamma[m], rho[m] (rho_0..rho_{m-1}),
     resnorm[m+1], relres_true, kept (bool per column of C), and Z / W
@@ -121,7 +124,8 @@ def apcg(row_ptr, col_idx, values, b, precond="jacobi", C=None, tol=1e-8, max_it
     st = lib().orc_apcg(n, _p(rp, _I64), _p(ci, _I32), _p(v), PRECOND[precond], _p(Cf), nc, ldc, _p(b), tol,
                         max_iter, guard, _p(x), _p(alpha), _p(rho), _p(gamma), _p(resn), _p(Z), n, _p(W), n,
                         _p(kept, _INT), ctypes.byref(m), ctypes.byref(rel),
-                        DIRECTION[direction] | (2 if reorth else 0) | (4 if orthonormal else 0))
+                        DIRECTION[direction] | (2 if reorth else 0) | (4 if orthonormal else 0)
+                        | (8 if extended else 0))
     if st in (ORC_INVALID, ORC_NOMEM):
         raise ValueError(f"oracle apcg failed with status {st}")
     m = m.value

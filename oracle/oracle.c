@@ -27,15 +27,32 @@ enum { ORC_PC_NONE = 0, ORC_PC_JACOBI = 1, ORC_PC_BLOCK3 = 3 };
 /* ---------------------------------------------------------------- basics */
 
 /* y = A x for CSR A. */
+/* Accumulation of sums: double (the default), or the x87 extended type
+ * (64-bit significand) when an APCG call asks for ORC_OPT_EXTENDED, set for
+ * the duration of that call.  Both are faithful evaluations of the same
+ * sums; comparing them shows how much rounding alone moves a long run. */
+static __thread int g_extended = 0;
+
 void orc_spmv(int64_t n, const int64_t* rp, const int32_t* ci, const double* av, const double* x, double* y) {
     for (int64_t i = 0; i < n; ++i) {
-        double s = 0.0;
-        for (int64_t k = rp[i]; k < rp[i + 1]; ++k) s += av[k] * x[ci[k]];
-        y[i] = s;
+        if (g_extended) {
+            long double s = 0.0L;
+            for (int64_t k = rp[i]; k < rp[i + 1]; ++k) s += (long double)av[k] * (long double)x[ci[k]];
+            y[i] = (double)s;
+        } else {
+            double s = 0.0;
+            for (int64_t k = rp[i]; k < rp[i + 1]; ++k) s += av[k] * x[ci[k]];
+            y[i] = s;
+        }
     }
 }
 
 double orc_dot(int64_t n, const double* a, const double* b) {
+    if (g_extended) {
+        long double s = 0.0L;
+        for (int64_t i = 0; i < n; ++i) s += (long double)a[i] * (long double)b[i];
+        return (double)s;
+    }
     double s = 0.0;
     for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
     return s;
@@ -315,6 +332,8 @@ static void mu_h(const double* Qall, const double* gam, int64_t n, int i, const 
  *   ORC_OPT_ORTHONORMAL: after the guarded Cholesky G = L L^T of the kept
  *     columns, work with the A-orthonormal basis C L^{-T} (same span, same
  *     projector in exact arithmetic) instead of C and the factor.
+ *   ORC_OPT_EXTENDED: matrix-vector products and dot products accumulated
+ *     in extended precision (then rounded to double).
  *   ORC_OPT_REORTH: full reorthogonalisation, which the paper states APCG
  *     admits (Section 2.1) and uses in every experiment (Section 5.1): the
  *     next direction is z_{j+1} made A-orthogonal to every earlier one,
@@ -324,7 +343,7 @@ static void mu_h(const double* Qall, const double* gam, int64_t n, int i, const 
  *     equals beta_{j+1} w_j.  rho and beta keep their definitions, so the
  *     Lanczos coefficients of Section 4.1 are unchanged.
  */
-enum { ORC_OPT_PROJECT_OLD = 1, ORC_OPT_REORTH = 2, ORC_OPT_ORTHONORMAL = 4 };
+enum { ORC_OPT_PROJECT_OLD = 1, ORC_OPT_REORTH = 2, ORC_OPT_ORTHONORMAL = 4, ORC_OPT_EXTENDED = 8 };
 
 int orc_apcg(int64_t n, const int64_t* rp, const int32_t* ci, const double* av, int precond,
              const double* C, int nc, int64_t ldc, const double* b, double tol, int max_iter, double guard,
@@ -332,12 +351,13 @@ int orc_apcg(int64_t n, const int64_t* rp, const int32_t* ci, const double* av, 
              double* Z, int64_t ldz, double* W, int64_t ldw, int* kept, int* m_out, double* relres_true,
              int opts) {
     if (n <= 0 || max_iter < 0 || (nc > 0 && (!C || ldc < n))) return ORC_INVALID;
+    g_extended = (opts & ORC_OPT_EXTENDED) != 0;
     orc_prec P;
     int st = prec_setup(&P, precond, n, rp, ci, av);
-    if (st != ORC_OK) { prec_free(&P); return st; }
+    if (st != ORC_OK) { prec_free(&P); g_extended = 0; return st; }
     orc_coarse K;
     st = coarse_build(&K, n, rp, ci, av, C, nc, ldc, guard, kept);
-    if (st != ORC_OK) { prec_free(&P); coarse_free(&K); return st; }
+    if (st != ORC_OK) { prec_free(&P); coarse_free(&K); g_extended = 0; return st; }
     if (opts & ORC_OPT_ORTHONORMAL) coarse_orthonormalize(&K);
 
     double* r = (double*)malloc(sizeof(double) * (size_t)n);
@@ -440,6 +460,7 @@ out:
     free(Wall); free(Qall); free(gam); free(gsc); free(pw); free(pmu);
     prec_free(&P);
     coarse_free(&K);
+    g_extended = 0;
     return st;
 }
 

@@ -367,7 +367,7 @@ class Sequence:
                  precond=None, cap_policy="freeze", tol=1e-8, max_iter=10000, ritz_eps=1e-14, max_basis=0,
                  refine_every=0, history_cap=0, rank_tol=0.0, refine_drop=0.0, C0=None, eager=False,
                  update_rows=0, autotune=False, separate_finalize=False, literal_direction=False, reorth=False,
-                 spmv_variant=0, reselect=None,
+                 spmv_variant=0, history_fp32=False, reselect=None,
                  cluster_min_frac=0.0):
         self.ctx = ctx
         self.n = int(n)
@@ -399,7 +399,7 @@ class Sequence:
         d.update_rows = update_rows
         d.autotune = 1 if autotune else 0
         d.kernel_flags = ((1 if separate_finalize else 0) | (2 if literal_direction else 0) | (4 if reorth else 0)
-                          | ((int(spmv_variant) & 7) << 3))
+                          | ((int(spmv_variant) & 15) << 3) | (128 if history_fp32 else 0))
         d.reselect = {None: 0, "none": 0, "cluster": 1}[reselect]
         d.cluster_min_frac = cluster_min_frac
         self.desc = d

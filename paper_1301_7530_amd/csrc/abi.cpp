@@ -134,6 +134,10 @@ krs_status krs_seq_create(krs_ctx* ctx, const krs_seq_desc* d, const double* C0,
         set_error("unknown precision");
         return KRS_E_INVALID;
     }
+    if ((d->kernel_flags & 128) && d->precision != KRS_FP64) {
+        set_error("a single-precision history (kernel_flags bit 7) applies to the double-precision basis only");
+        return KRS_E_INVALID;
+    }
     if ((d->kernel_flags & 4) && d->precision != KRS_FP64) {
         set_error("full reorthogonalisation (kernel_flags bit 2) runs in double precision only");
         return KRS_E_INVALID;

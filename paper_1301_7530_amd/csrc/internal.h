@@ -16,7 +16,10 @@ namespace krs {
 constexpr int kSlice = 64;
 // Doubles reserved at the head of the reduction scratch for SpMV partials
 // (>= the largest SpMV grid).
-constexpr int64_t kPart1 = 4096;
+constexpr int64_t kPart1 = 8192;
+// double-precision block matrices larger than this (the 256 MB Infinity
+// Cache) stream through the SpMV with non-temporal loads by default
+constexpr int64_t kNtBytes = int64_t(256) << 20;
 // Byte offset of the fused update's ticket counters in the state allocation
 // (one global counter, then one per group of kGroup update workgroups).
 constexpr int kSyncOffset = 256;
@@ -135,6 +138,7 @@ struct SysView {
     double* mu2;         // nc: mu + beta G^-1 (AC)^T w_old, for the projected direction
     // histories
     V* zhist;        // z_j at column j (SRKS), or null
+    float* zhist32;  // the same in single precision (kernel_flags bit 7, double bases), or null
     V* whist;        // w_j at column j (TRKS: columns of C past nc), or null
     int64_t ldh;
     double* alpha_h;  // [hist] alpha_j
@@ -206,6 +210,8 @@ template <typename V, typename W> void launch_correct_dir(const SysView<V, W>& v
 // full reorthogonalisation: the store after the SpMV; the coefficients and
 // the update of w after the direction update
 template <typename V, typename W> void launch_reorth_store(const SysView<V, W>& v, hipStream_t stream);
+void launch_basis_combine_h32(const float* Z, int64_t ldz, int m, const double* F, int s, double* out, int64_t ldo,
+                              int64_t n, hipStream_t stream);
 template <typename V, typename W> void launch_reorth(const SysView<V, W>& v, hipStream_t stream);
 template <typename V, typename W, int B>
 void launch_true_resid(const SysView<V, W>& v, int final_only, hipStream_t stream);

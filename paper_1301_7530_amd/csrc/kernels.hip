@@ -1205,6 +1205,7 @@ __device__ __forceinline__ void correct_dir_body(const SysView<V, W>& v, int64_t
             if (v.zr) v.zr[i] = zv;
             if (j < hist_cap) {
                 if (v.zhist) v.zhist[(int64_t)j * v.ldh + i] = (V)zv;
+                if (v.zhist32) v.zhist32[(int64_t)j * v.ldh + i] = (float)zv;
                 if (v.whist) v.whist[(int64_t)j * v.ldh + i] = (V)wv;
             }
         }
@@ -1609,6 +1610,7 @@ __global__ __launch_bounds__(256) void kb_correct_dir_few(const SysView<V, W>* _
                 v.w[i] = wv;
                 if (j < hist_cap) {
                     if (v.zhist) v.zhist[(int64_t)j * v.ldh + i] = (V)zv;
+                    if (v.zhist32) v.zhist32[(int64_t)j * v.ldh + i] = (float)zv;
                     if (v.whist) v.whist[(int64_t)j * v.ldh + i] = (V)wv;
                 }
             }
@@ -1772,8 +1774,8 @@ __global__ void k_gram_reduce(const double* partials, int np, int nc, double* G)
 }
 
 // out[:, t] = sum_j Z[:, j] F[j, t]  (F column-major m x s, double)
-template <typename V>
-__global__ __launch_bounds__(256) void k_basis_combine(const V* Z, int64_t ldz, int m, const double* F, int s, V* out,
+template <typename V, typename ZT = V>
+__global__ __launch_bounds__(256) void k_basis_combine(const ZT* Z, int64_t ldz, int m, const double* F, int s, V* out,
                                                        int64_t ldo, int64_t n) {
     constexpr int CW = 8;
     const int t0 = blockIdx.y * CW;
@@ -1996,7 +1998,7 @@ Geometry make_geometry(int64_t n, int64_t nslices, int block, int64_t cb3_req, i
     const int64_t per = (block == 1) ? 4 : 2;  // slices per workgroup step (one per wave)
     int64_t g1 = (nslices + per - 1) / per;
     // at most kPart1 workgroups: each writes its (w, A w) partial there
-    const int64_t cap1 = spmv_grid > 0 ? std::min<int64_t>(spmv_grid, kPart1) : 2048;
+    const int64_t cap1 = spmv_grid > 0 ? std::min<int64_t>(spmv_grid, kPart1) : kPart1;
     g.g1 = (int32_t)std::min<int64_t>(std::max<int64_t>(g1, 1), cap1);
     // K3: contiguous ranges of cb3 block rows; by default one range per CU
     int64_t cb = cb3_req > 0 ? cb3_req : (nb + 255) / 256;
@@ -2189,6 +2191,14 @@ void launch_basis_combine(const V* Z, int64_t ldz, int m, const double* F, int s
     }
     dim3 grid(cdiv(n, 256), (unsigned)((s + 7) / 8));
     hipLaunchKernelGGL((k_basis_combine<V>), grid, dim3(256), 0, stream, Z, ldz, m, F, s, out, ldo, n);
+}
+
+// a double-precision basis combined from a single-precision history
+void launch_basis_combine_h32(const float* Z, int64_t ldz, int m, const double* F, int s, double* out, int64_t ldo,
+                              int64_t n, hipStream_t stream) {
+    if (s <= 0 || m <= 0) return;
+    dim3 grid(cdiv(n, 256), (unsigned)((s + 7) / 8));
+    hipLaunchKernelGGL((k_basis_combine<double, float>), grid, dim3(256), 0, stream, Z, ldz, m, F, s, out, ldo, n);
 }
 
 template <typename V>

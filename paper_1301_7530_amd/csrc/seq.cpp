@@ -357,7 +357,10 @@ SysView<V, W> SeqImpl<V, W>::view() {
     v.zhist = nullptr;
     v.whist = nullptr;
     v.ldh = ldc;
-    if (desc.reuse == KRS_REUSE_SELECTIVE) v.zhist = (V*)d_Z.p;
+    if (desc.reuse == KRS_REUSE_SELECTIVE) {
+        if (hist32()) v.zhist32 = (float*)d_Z.p;
+        else v.zhist = (V*)d_Z.p;
+    }
     if (desc.reuse == KRS_REUSE_TOTAL && trks_slots > 0) v.whist = (V*)d_C.p + (size_t)nc * ldc;
     v.alpha_h = (double*)d_coef.p;
     v.rho_h = v.alpha_h + coef_cap;
@@ -371,6 +374,8 @@ SysView<V, W> SeqImpl<V, W>::view() {
     v.fused = (desc.kernel_flags & 1) ? 0 : 1;
     v.dir_literal = (desc.kernel_flags & 2) ? 1 : 0;
     v.spmv_var = (desc.kernel_flags >> 3) & 3;
+    if (((desc.kernel_flags >> 3) & 15) == 0 && B == 3 && v.op64 && nslots * 64 * 9 * (int64_t)sizeof(double) > kNtBytes)
+        v.spmv_var = 2;  // a matrix larger than the last-level cache streams with non-temporal loads
     if (reorth() && rcap > 0) {
         v.Wr = (W*)d_Wr.p;
         v.Qr = (W*)d_Qr.p;
@@ -588,7 +593,7 @@ int64_t SeqImpl<V, W>::working_bytes() const {
     const int ncmax = std::max(nc, has_cap() ? cap_value() : nc);
     const int64_t ldm = ac_leading_dim(ncmax, sizeof(V));
     const int64_t vsz = std::is_same<V, double>::value ? 0 : (int64_t)sizeof(V);
-    int64_t b = ldc * hist * (int64_t)sizeof(V);                       // Z history
+    int64_t b = ldc * hist * hist_elem();                              // Z history
     b += n * ldm * (8 + vsz);                                          // A C (double and V)
     b += ldc * (int64_t)ncmax * (int64_t)sizeof(V);                    // basis change staging
     b += nnzb * B * B * 8;                                             // value staging
@@ -721,14 +726,20 @@ krs_status SeqImpl<V, W>::begin_solve() {
         // that did not fit is not tried again by later solves (the attempt
         // would first release the reservation that does fit).
         if (history_fit > 0) hist = std::min(hist, history_fit);
-        while (!d_Z.reserve(ctx, (size_t)ldc * hist * sizeof(V))) {
+        const int64_t per = ldc * hist_elem();
+        const int64_t known = ctx->hist_fit_bytes.load();
+        if (known > 0 && (int64_t)hist * per > known) hist = (int)std::max<int64_t>(64, known / per);
+        bool failed = false;
+        while (!d_Z.reserve(ctx, (size_t)ldc * hist * (size_t)hist_elem())) {
             if (hist <= 64) {
                 set_error("device allocation failed for the Krylov history");
                 return KRS_E_OOM;
             }
             hist /= 2;
             history_fit = hist;
+            failed = true;
         }
+        if (failed) ctx->hist_fit_bytes.store((int64_t)hist * per);
         history_kept = hist;
     } else if (desc.reuse == KRS_REUSE_TOTAL) {
         hist = max_iter + 1;
@@ -1185,7 +1196,11 @@ krs_status SeqImpl<V, W>::recycle_apply(int32_t* n_added) {
         if (!ensure_c_capacity(nc + s)) return KRS_E_OOM;
         if (!d_F.reserve(ctx, h_F.size() * sizeof(double))) return KRS_E_OOM;
         KRS_HIP(hipMemcpyAsync(d_F.p, h_F.data(), h_F.size() * sizeof(double), hipMemcpyHostToDevice, stream));
-        launch_basis_combine<V>((const V*)d_Z.p, ldc, plan.mu, (const double*)d_F.p, s, (V*)d_C.p + (size_t)nc * ldc,
+        if (hist32())
+            launch_basis_combine_h32((const float*)d_Z.p, ldc, plan.mu, (const double*)d_F.p, s,
+                                     reinterpret_cast<double*>((V*)d_C.p + (size_t)nc * ldc), ldc, n, stream);
+        else
+            launch_basis_combine<V>((const V*)d_Z.p, ldc, plan.mu, (const double*)d_F.p, s, (V*)d_C.p + (size_t)nc * ldc,
                                 ldc, n, stream);
         KRS_CHECK_LAUNCH();
         nc += s;
@@ -1230,7 +1245,8 @@ krs_status SeqImpl<V, W>::history(double* Z, int64_t ld, int32_t cap, int32_t* m
     }
     if (!d_tmp.reserve(ctx, (size_t)n * sizeof(double))) return KRS_E_OOM;
     for (int c = 0; c < mh; ++c) {
-        launch_v2d<V>((const V*)d_Z.p + (size_t)c * ldc, (double*)d_tmp.p, n, stream);
+        if (hist32()) launch_v2d<float>((const float*)d_Z.p + (size_t)c * ldc, (double*)d_tmp.p, n, stream);
+        else launch_v2d<V>((const V*)d_Z.p + (size_t)c * ldc, (double*)d_tmp.p, n, stream);
         KRS_CHECK_LAUNCH();
         KRS_HIP(hipMemcpyAsync(Z + (size_t)c * ld, d_tmp.p, n * sizeof(double), hipMemcpyDeviceToHost, stream));
     }

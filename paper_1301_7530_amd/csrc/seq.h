@@ -21,6 +21,11 @@ struct krs_ctx {
     std::atomic<int> live_seqs{0};
     std::atomic<int> live_servers{0};
     std::atomic<int64_t> bytes_live{0};
+    // bytes of the longest Krylov history that fit on this device after a
+    // longer one did not (0: none failed); later sequences start there, so
+    // that a request bound to fail does not make the allocator drop its
+    // cached blocks
+    std::atomic<int64_t> hist_fit_bytes{0};
 };
 
 namespace krs {
@@ -114,9 +119,17 @@ struct SeqImpl : SeqBase {
     int rcap = 0, rgr = 0;
     int64_t ldr = 0;
     bool reorth() const { return (desc.kernel_flags & 4) != 0; }
-    // SpMV workgroup cap: kernel_flags bit 5 raises it from 2048 to 4096
-    // (the size of the region of its partial sums, kPart1)
-    int spmv_grid_cap() const { return (desc.kernel_flags & 32) ? (int)kPart1 : 0; }
+    // kernel_flags bit 7: the Krylov history of a double-precision basis
+    // kept in single precision (it only forms the Ritz vectors)
+    bool hist32() const { return (desc.kernel_flags & 128) != 0 && std::is_same<V, double>::value; }
+    int64_t hist_elem() const { return hist32() ? (int64_t)sizeof(float) : (int64_t)sizeof(V); }
+    // SpMV workgroup cap, kernel_flags bits 5-6: 0 the default (8192, the
+    // size of the region of its partial sums, kPart1), 1: 2048, 2: 4096,
+    // 3: 8192
+    int spmv_grid_cap() const {
+        const int code = (desc.kernel_flags >> 5) & 3;
+        return code == 0 ? (int)kPart1 : (int)std::min<int64_t>(kPart1, (int64_t)1024 << code);
+    }
     DevState* h_st = nullptr;
     double* h_coef = nullptr;  // pinned staging of the CG coefficients read back by end_solve
     size_t h_coef_cap = 0;     // doubles

@@ -115,12 +115,16 @@ def make(name: str) -> None:
             pm.append(int(O.apcg(rp, ci, v, bp, "block3", C=C_solve, tol=1e-8, max_iter=cfg["max_iter"],
                                  direction="project_old")["m"]))
         rec["m_perturbed"] = pm
+        # and with the products accumulated in extended precision: another
+        # faithful rounding of the same arithmetic
+        rec["m_extended"] = int(O.apcg(rp, ci, v, b, "block3", C=C_solve, tol=1e-8, max_iter=cfg["max_iter"],
+                                       direction="project_old", extended=True)["m"])
         rec["selected"] = [int(i) for i in sel]
         rec["nc_next"] = int(C.shape[1])
         rec["fingerprint"] = span_fingerprint(C, R).tolist()
         recs.append(rec)
         del res
-        print(f"{name} system {k}: m={rec['m']} (perturbed {pm}) n_c {rec['nc_in']}->{rec['nc_solve']} (+{len(sel)}) "
+        print(f"{name} system {k}: m={rec['m']} (perturbed {pm}, extended {rec['m_extended']}) n_c {rec['nc_in']}->{rec['nc_solve']} (+{len(sel)}) "
               f"rel res {rec['relres_true']:.2e}  [{time.perf_counter() - t:.0f} s]", flush=True)
     out = dict(name=name, config=cfg, n=seq.n, n_coef=N_COEF, generator="tests/golden/make_fixtures.py",
                systems=recs)

@@ -4,10 +4,12 @@ The fixtures under tests/golden/ are written by tests/golden/make_fixtures.py,
 which calls only the oracle (SRKS, Algorithm 3; direction update in the
 re-projected form w = z + beta P w_old, the library's default, equal to
 Algorithm 1's in exact arithmetic).  Per system, in FP64: the iteration
-count within +-2 of the oracle's plus the spread of the oracle's own count
-under rounding-level perturbations of b (two draws, stored with the
-fixture: thousands of CG steps amplify rounding, so the summation order of
-the reductions alone moves the count by about 1 %), the basis width the solve used and the columns appended
+count within +-2 of the range of the oracle's counts over faithful
+evaluations of the same solve (sums accumulated in double and in extended
+precision, b perturbed at the rounding level; stored with the fixture:
+thousands of CG steps amplify rounding, so the accumulation alone moves the
+count by about 1 %: 4882 in double, 4803 in extended precision on the first
+40^3 system), the basis width the solve used and the columns appended
 within the rank guard's and the stagnation threshold's slack (+-2), the
 first CG coefficients of a solve from an empty basis to 1e-9, the true
 residual <= 1e-8, and the span of the recycled basis through its
@@ -80,11 +82,14 @@ def _compare(fx, got):
     nco = fx["n_coef"]
     for k, (g, w) in enumerate(zip(got, fx["systems"])):
         assert g["status"] == 0 and g["res"] <= 1e-8, (k, g["res"])
-        # +-2 beyond what rounding-level perturbations of b move the
-        # oracle's own count (long FP64 CG runs are that sensitive)
-        spread = max(abs(p - w["m"]) for p in w["m_perturbed"])
-        print(f"system {k}: m {g['m']} vs oracle {w['m']} (perturbed {w['m_perturbed']})", flush=True)
-        assert abs(g["m"] - w["m"]) <= 2 + spread, (k, g["m"], w["m"], w["m_perturbed"])
+        # +-2 around the counts of the oracle's faithful evaluations of the
+        # same solve: double accumulation, extended-precision accumulation,
+        # and b perturbed at the rounding level (long FP64 CG runs move by
+        # about 1 % between them)
+        ms = [w["m"], w["m_extended"], *w["m_perturbed"]]
+        print(f"system {k}: m {g['m']} vs oracle {w['m']} (extended {w['m_extended']}, "
+              f"perturbed {w['m_perturbed']})", flush=True)
+        assert min(ms) - 2 <= g["m"] <= max(ms) + 2, (k, g["m"], ms)
         assert abs(g["nc_solve"] - w["nc_solve"]) <= 2, (k, g["nc_solve"], w["nc_solve"])
         assert abs(g["added"] - len(w["selected"])) <= 2, (k, g["added"], len(w["selected"]))
         if w["nc_solve"] == 0:

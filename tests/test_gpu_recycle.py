@@ -7,7 +7,9 @@ element by element, and the restart cap.
   and selection, column by column.  The bound is that of the arithmetic: a
   length-m sum in the basis precision (u = 2^-53, or 2^-24 for the
   single-precision basis, whose combination matrix is rounded to single
-  precision for the matrix cores) plus the difference of two eigenvector
+  precision for the matrix cores; a double-precision basis combined from a
+  single-precision history sums in double precision) plus the difference
+  of two eigenvector
   computations, u ||T|| / gap per side, carried through ||Z D||.  A Ritz
   vector's sign is not fixed by the method, so each column is compared after
   aligning signs.
@@ -28,13 +30,15 @@ U64 = 2.0 ** -53
 U32 = 2.0 ** -24
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32basis"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32basis", "fp64-history32"])
 def test_basis_rebuild_elementwise(gpu, precision):
     import paper_1301_7530_amd as K
 
     seq = gen.config_elasticity(10, 1)
     eps = 1e-8
-    s = K.sequence_for(gpu, seq, precision=precision, reuse="selective", ritz_eps=eps, tol=1e-8, max_iter=5000)
+    h32 = precision == "fp64-history32"
+    s = K.sequence_for(gpu, seq, precision="fp64" if h32 else precision, reuse="selective", ritz_eps=eps, tol=1e-8,
+                       max_iter=5000, history_fp32=h32)
     try:
         s.submit(*seq.system(0))
         _, info = s.solve()
@@ -57,7 +61,9 @@ def test_basis_rebuild_elementwise(gpu, precision):
     assert added == len(sel_lib) == C.shape[1] > 0
     ref = O.ritz_block(Z, a, r, list(sel_lib), th_m)
     F = O.ritz_block(np.eye(mu), a, r, list(sel_lib), th_m)
-    u = U64 if precision == "fp64" else U32
+    # the single-precision history is exported as it is stored, so the
+    # combination runs in double precision on exactly those values
+    u = U32 if precision == "fp32basis" else U64
     ZD = np.linalg.norm(Z / np.sqrt(r)[None, :], 2)
     tmax = float(np.max(np.abs(th_m)))
     worst = 0.0

@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 import scipy.sparse as sp
 
+import gen
 import oracle as O
 
 
@@ -356,3 +357,18 @@ def test_reorth_keeps_directions_conjugate_and_ritz_values_simple():
     # the pin discriminates: the plain run has lost conjugacy and has ghosts
     assert cos0 > 1e-3 and close0 > 10
     assert m1 <= m0
+
+
+def test_extended_accumulation_is_a_faithful_evaluation():
+    """Accumulating the products in extended precision is the same solve up
+    to rounding: the same iteration count within one step and the same
+    solution to the solve tolerance on a well-conditioned case, and the
+    first coefficients to 1e-12."""
+    seq = gen.config_diffusion_20(0, 1, N=8)
+    rp, ci, v, b = seq.csr(0)
+    a = O.apcg(rp, ci, v, b, "jacobi", tol=1e-10, max_iter=500)
+    e = O.apcg(rp, ci, v, b, "jacobi", tol=1e-10, max_iter=500, extended=True)
+    assert abs(a["m"] - e["m"]) <= 1
+    assert np.linalg.norm(a["x"] - e["x"]) <= 1e-9 * np.linalg.norm(a["x"])
+    assert np.allclose(a["alpha"][:20], e["alpha"][:20], rtol=1e-12, atol=0)
+    assert e["relres_true"] <= 1e-10 * 1.01
