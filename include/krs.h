@@ -91,7 +91,9 @@ typedef enum { KRS_CAP_RESTART = 0, KRS_CAP_FREEZE = 1, KRS_CAP_COST = 2 } krs_c
  * reduced condition number theta_max / theta_(k+1) (Section 2.2, and the
  * rate of Section 4.3), i.e. m(k) = max(1, m_0 ln sigma_0 / ln sigma_k) with
  * sigma = (sqrt(kappa) - 1) / (sqrt(kappa) + 1) over the distinct Ritz values
- * of that solve; each system with k columns is priced at m(k) times the
+ * of that solve, k running over the prefix of the ascending values that
+ * passed the stagnation test (ritz_eps: only converged Ritz vectors
+ * approximate eigenvectors; further columns are modelled as gaining nothing); each system with k columns is priced at m(k) times the
  * algorithmic bytes of an iteration with k columns plus the rebuild of k
  * columns (the library's byte model), and n_c_lim is the k <= 1024 of least
  * cost.  The value is reported in krs_solve_info.n_c_lim; krs_nc_limit
@@ -361,15 +363,16 @@ krs_status krs_server_destroy(krs_server* s);
 /* ------------------------------------------------ host-side Ritz logic */
 /* Host only, no device: the complexity analysis of KRS_NC_LIM_AUTO on the
  * CG coefficients alpha[m], rho[m] of a non-augmented solve (Section 4.4
- * remark after Algorithm 3; model stated at KRS_NC_LIM_AUTO) with the given
- * byte costs: bytes_iter0 per iteration without a basis, bytes_col_iter per
+ * remark after Algorithm 3; model stated at KRS_NC_LIM_AUTO), with eps the
+ * stagnation tolerance that marks a Ritz value converged, and the given byte
+ * costs: bytes_iter0 per iteration without a basis, bytes_col_iter per
  * basis column per iteration, bytes_rebuild0 + k bytes_col_rebuild for the
  * rebuild of k > 0 columns.  *nc_lim receives the k in 0..kmax of least
  * modelled bytes per system (kmax is clipped to the number of distinct Ritz
  * values less one); cost (NULL, or kmax + 1 doubles) the modelled bytes for
  * each k; *k_out the clipped kmax. */
 krs_status krs_nc_limit(const double* alpha, const double* rho, int32_t m, double bytes_iter0, double bytes_col_iter,
-                        double bytes_rebuild0, double bytes_col_rebuild, int32_t kmax, double* cost,
+                        double bytes_rebuild0, double bytes_col_rebuild, int32_t kmax, double eps, double* cost,
                         int32_t* k_out, int32_t* nc_lim);
 /* Host only, no device: the cluster reselection of KRS_RESELECT_CLUSTER
  * on Ritz values theta[m] (any order) and a preselection flags[m]

@@ -349,7 +349,8 @@ def distinct_ritz_ascending(alpha, rho, merge=1e-10):
     return np.array(out)
 
 
-def nc_limit(alpha, rho, bytes_iter0, bytes_col_iter, bytes_rebuild0, bytes_col_rebuild, kmax, merge=1e-10):
+def nc_limit(alpha, rho, bytes_iter0, bytes_col_iter, bytes_rebuild0, bytes_col_rebuild, kmax, eps=1e-8,
+             merge=1e-10):
     """n_c_lim from a complexity analysis (Section 4.4, remark after Algorithm 3).
 
     Under the assumption that every non-augmented system takes the m_0
@@ -359,13 +360,31 @@ def nc_limit(alpha, rho, bytes_iter0, bytes_col_iter, bytes_rebuild0, bytes_col_
     deflation; the CG rate of Section 4.3), so it takes
         m(k) = max(1, m_0 ln(sigma(kappa_0)) / ln(sigma(kappa_k))),
         sigma(kappa) = (sqrt(kappa) - 1) / (sqrt(kappa) + 1),
-    iterations, the spectrum taken from the distinct Ritz values.  A solve
-    with k columns moves
+    iterations, the spectrum taken from the distinct Ritz values.  Only
+    converged Ritz vectors approximate eigenvectors (Section 4.4: those whose
+    values pass the stagnation test at ``eps``), so k runs over the
+    converged prefix of the ascending Ritz values: past the first value
+    that has not converged, more columns are modelled as gaining nothing.
+    A solve with k columns moves
         T(k) = m(k) (bytes_iter0 + k bytes_col_iter) + [k > 0] (bytes_rebuild0 + k bytes_col_rebuild)
     bytes; n_c_lim is the k in 0..kmax that minimises T (the smaller k on a
     tie).  Returns (n_c_lim, T as an array over k).
     """
-    th = distinct_ritz_ascending(alpha, rho, merge)
+    th_m, th_m1 = ritz_values(alpha, rho)
+    conv = set(srks_select(th_m, th_m1, eps)) if len(alpha) > 1 else set()
+    order = sorted(range(len(th_m)), key=lambda i: (th_m[i], i))
+    th, ok = [], []
+    for i in order:  # distinct values ascending; a value converged if any copy passed
+        t = float(th_m[i])
+        if th and abs(t - th[-1]) <= merge * abs(t):
+            ok[-1] = ok[-1] or (i in conv)
+            continue
+        th.append(t)
+        ok.append(i in conv)
+    th = np.array(th)
+    kconv = 0
+    while kconv < len(ok) and ok[kconv]:
+        kconv += 1
     m0 = len(alpha)
     kmax = int(max(0, min(kmax, len(th) - 1)))
     tmax = th[-1]
@@ -379,7 +398,8 @@ def nc_limit(alpha, rho, bytes_iter0, bytes_col_iter, bytes_rebuild0, bytes_col_
     l0 = lnsig(tmax / th[0])
     T = np.empty(kmax + 1)
     for k in range(kmax + 1):
-        lk = lnsig(tmax / th[k])
+        kd = min(k, kconv)  # columns past the converged prefix deflate nothing more
+        lk = lnsig(tmax / th[kd])
         mk = max(1.0, m0 * (l0 / lk)) if np.isfinite(lk) else 1.0
         T[k] = mk * (bytes_iter0 + k * bytes_col_iter) + ((bytes_rebuild0 + k * bytes_col_rebuild) if k else 0.0)
     best = int(np.argmin(T))
@@ -431,7 +451,7 @@ def solve_sequence(seq, n_systems=None, reuse="srks", precond=None, tol=1e-8, ep
             rec["x"] = res["x"]
         m = res["m"]
         if auto and k == 0:
-            cap, _ = nc_limit(res["alpha"], res["rho"], **cost_model)
+            cap, _ = nc_limit(res["alpha"], res["rho"], eps=eps, **cost_model)
             rec["nc_lim"] = cap
             if cap == 0:
                 cap = -1  # nothing may be appended

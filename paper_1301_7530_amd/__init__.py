@@ -167,7 +167,7 @@ SIGNATURES = [
     ("krs_server_stats", _S, [_P, ctypes.POINTER(ServerStats)]),
     ("krs_server_destroy", _S, [_P]),
     ("krs_nc_limit", _S, [_D, _D, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                          ctypes.c_double, ctypes.c_int32, _D, _I32, _I32]),
+                          ctypes.c_double, ctypes.c_int32, ctypes.c_double, _D, _I32, _I32]),
     ("krs_cluster_reselect", _S, [_D, ctypes.c_int32, ctypes.c_double, _U8]),
     ("krs_ritz_select", _S, [_D, _D, ctypes.c_int32, ctypes.c_double, _D, _D, _U8]),
     ("krs_coarse_factor", _S, [ctypes.c_int32, _D, ctypes.c_double, _D, _U8, _I32]),
@@ -222,7 +222,7 @@ def ritz_select(alpha, rho, eps):
     return th[:m], th1[: max(m - 1, 0)], sel[:m].astype(bool)
 
 
-def nc_limit(alpha, rho, bytes_iter0, bytes_col_iter, bytes_rebuild0, bytes_col_rebuild, kmax):
+def nc_limit(alpha, rho, bytes_iter0, bytes_col_iter, bytes_rebuild0, bytes_col_rebuild, kmax, eps=1e-8):
     """Library's complexity analysis for n_c_lim (no device used).
 
     Returns (n_c_lim, modelled bytes per system for k = 0..kmax')."""
@@ -232,7 +232,7 @@ def nc_limit(alpha, rho, bytes_iter0, bytes_col_iter, bytes_rebuild0, bytes_col_
     k = ctypes.c_int32(0)
     nl = ctypes.c_int32(0)
     _check(_lib.krs_nc_limit(_dptr(alpha), _dptr(rho), len(alpha), float(bytes_iter0), float(bytes_col_iter),
-                             float(bytes_rebuild0), float(bytes_col_rebuild), int(kmax), _dptr(cost),
+                             float(bytes_rebuild0), float(bytes_col_rebuild), int(kmax), float(eps), _dptr(cost),
                              ctypes.byref(k), ctypes.byref(nl)), "krs_nc_limit")
     return nl.value, cost[: k.value + 1]
 

@@ -407,7 +407,7 @@ krs_status krs_seq_destroy(krs_seq* s) {
 }
 
 krs_status krs_nc_limit(const double* alpha, const double* rho, int32_t m, double bytes_iter0, double bytes_col_iter,
-                        double bytes_rebuild0, double bytes_col_rebuild, int32_t kmax, double* cost,
+                        double bytes_rebuild0, double bytes_col_rebuild, int32_t kmax, double eps, double* cost,
                         int32_t* k_out, int32_t* nc_lim) {
     KRS_GUARD_BEGIN
     if (!nc_lim || m < 0 || kmax < 0 || (m > 0 && (!alpha || !rho))) {
@@ -425,6 +425,7 @@ krs_status krs_nc_limit(const double* alpha, const double* rho, int32_t m, doubl
     cm.bytes_rebuild0 = bytes_rebuild0;
     cm.bytes_col_rebuild = bytes_col_rebuild;
     cm.kmax = kmax;
+    cm.eps = eps;
     std::vector<double> c;
     const unsigned hc = std::thread::hardware_concurrency();
     *nc_lim = krs::nc_limit(alpha, rho, m, cm, (int)std::min(16u, std::max(1u, hc)), &c);

@@ -289,6 +289,7 @@ void tridiag_eigvec(const std::vector<double>& diag, const std::vector<double>& 
 // bytes per column.
 struct NcCostModel {
     double bytes_iter0 = 0.0, bytes_col_iter = 0.0, bytes_rebuild0 = 0.0, bytes_col_rebuild = 0.0;
+    double eps = 1e-8;  // stagnation tolerance that marks a Ritz value converged
     int kmax = 0;
 };
 // n_c_lim from the CG coefficients of a solve taken as the non-augmented

@@ -176,7 +176,9 @@ void qd_eigenvalues_desc(const QdArray& z, std::vector<double>& theta, int threa
 //   m(k) = max(1, m_0 ln(sigma_0) / ln(sigma_k)),  sigma = (sqrt(kappa)-1)/(sqrt(kappa)+1),
 // iterations over the distinct Ritz values (finite-precision Lanczos
 // repeats converged values: a value within a relative 1e-10 of the last
-// kept one is a copy), and moves
+// kept one is a copy); only converged Ritz vectors approximate
+// eigenvectors (the stagnation test at eps), so k deflates the converged
+// prefix of the ascending values and columns past it gain nothing.  It moves
 //   T(k) = m(k) (bytes_iter0 + k bytes_col_iter) + [k > 0] (bytes_rebuild0 + k bytes_col_rebuild)
 // bytes per system.  n_c_lim minimises T over k = 0..kmax (the smaller k on
 // a tie).  Only the low end of the spectrum and its top are computed.
@@ -185,19 +187,36 @@ int nc_limit(const double* alpha, const double* rho, int m, const NcCostModel& c
     if (cost) cost->clear();
     if (m <= 0) return 0;
     const QdArray z = qd_from_cg(alpha, rho, m);
+    const QdArray z1 = qd_leading(z, std::max(m - 1, 0));
     std::vector<double> asc(m, 0.0);  // out[k] at the absolute rank k
     qd_eigenvalues_asc(z, m - 1, m, asc.data(), 1);
     const double top = asc[m - 1];
+    // distinct values ascending (a value within a relative 1e-10 of the
+    // last kept one is a Lanczos copy), each marked converged if it or a
+    // copy passes the stagnation test: H_{m-1} has an eigenvalue within
+    // eps |theta| (one of its interlacing neighbours)
     std::vector<double> distinct;
+    std::vector<uint8_t> conv;
     const int want = std::max(0, cm.kmax) + 1;
     const int CH = 256;
     for (int k = 0; k < m && (int)distinct.size() < want; k += CH) {
         const int k1 = std::min(m, k + CH);
         qd_eigenvalues_asc(z, k, k1, asc.data(), threads);
-        for (int t = k; t < k1 && (int)distinct.size() < want; ++t)
-            if (distinct.empty() || std::fabs(asc[t] - distinct.back()) > 1e-10 * std::fabs(asc[t]))
-                distinct.push_back(asc[t]);
+        for (int t = k; t < k1; ++t) {
+            const double a = asc[t];
+            const double e = cm.eps * std::fabs(a);
+            const bool c = m > 1 && qd_has_eigenvalue_in(z1, a - e, a + e);
+            if (!distinct.empty() && std::fabs(a - distinct.back()) <= 1e-10 * std::fabs(a)) {
+                conv.back() = conv.back() || c;
+                continue;
+            }
+            if ((int)distinct.size() >= want) break;
+            distinct.push_back(a);
+            conv.push_back(c);
+        }
     }
+    int kconv = 0;
+    while (kconv < (int)conv.size() && conv[kconv]) ++kconv;
     const int kmax = std::min(std::max(0, cm.kmax), (int)distinct.size() - 1);
     auto log_rate = [](double kappa) {
         if (!(kappa > 1.0)) return -std::numeric_limits<double>::infinity();
@@ -208,7 +227,8 @@ int nc_limit(const double* alpha, const double* rho, int m, const NcCostModel& c
     int best = 0;
     double best_t = 0.0;
     for (int k = 0; k <= kmax; ++k) {
-        const double lk = log_rate(top / distinct[k]);
+        // columns past the converged prefix deflate nothing more
+        const double lk = log_rate(top / distinct[std::min(k, kconv)]);
         const double mk = std::isfinite(lk) ? std::max(1.0, (double)m * (l0 / lk)) : 1.0;
         const double t = mk * (cm.bytes_iter0 + k * cm.bytes_col_iter) +
                          (k > 0 ? cm.bytes_rebuild0 + k * cm.bytes_col_rebuild : 0.0);

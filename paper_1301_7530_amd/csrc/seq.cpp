@@ -1025,6 +1025,7 @@ krs_status SeqImpl<V, W>::recycle_plan() {
         cm.bytes_rebuild0 = (double)BA;
         cm.bytes_col_rebuild = 7.0 * n * p;
         cm.kmax = std::min(1024, m - 1);
+        cm.eps = desc.ritz_eps;
         const int nt = recycle_threads > 0 ? recycle_threads : host_threads();
         nc_lim_auto = nc_limit(coef_alpha.data(), coef_rho.data(), m, cm, nt, nullptr);
     }

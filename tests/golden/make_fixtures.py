@@ -93,7 +93,8 @@ def make(name: str) -> None:
                    alpha=res["alpha"][:N_COEF].tolist(), rho=res["rho"][:N_COEF].tolist(),
                    gamma=res["gamma"][:N_COEF].tolist())
         if cap == "auto":
-            nc_lim, _ = O.nc_limit(res["alpha"], res["rho"], **cost_model_fp64(seq, min(1024, res["m"] - 1)))
+            nc_lim, _ = O.nc_limit(res["alpha"], res["rho"], eps=cfg["eps"],
+                                   **cost_model_fp64(seq, min(1024, res["m"] - 1)))
             cap = nc_lim
             rec["nc_lim"] = int(nc_lim)
         room = cap - C.shape[1]
@@ -106,11 +107,11 @@ def make(name: str) -> None:
             new = O.ritz_block(res["Z"], res["alpha"], res["rho"], sel, th_m)
             C = np.concatenate([C, new], axis=1)
         # the oracle's own sensitivity: the same solve with b perturbed at
-        # the rounding level (relative 1e-15, two draws); the spread of
+        # the rounding level (relative 1e-15, one draw); the spread of
         # these iteration counts is what rounding alone moves
         prng = np.random.default_rng(np.random.SeedSequence([13017530, 98, k]))
         pm = []
-        for _ in range(2):
+        for _ in range(1):
             bp = b * (1.0 + 1e-15 * prng.standard_normal(b.shape))
             pm.append(int(O.apcg(rp, ci, v, bp, "block3", C=C_solve, tol=1e-8, max_iter=cfg["max_iter"],
                                  direction="project_old")["m"]))

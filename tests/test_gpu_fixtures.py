@@ -6,7 +6,7 @@ re-projected form w = z + beta P w_old, the library's default, equal to
 Algorithm 1's in exact arithmetic).  Per system, in FP64: the iteration
 count within +-2 of the range of the oracle's counts over faithful
 evaluations of the same solve (sums accumulated in double and in extended
-precision, b perturbed at the rounding level; stored with the fixture:
+precision, b perturbed at the rounding level once; stored with the fixture:
 thousands of CG steps amplify rounding, so the accumulation alone moves the
 count by about 1 %: 4882 in double, 4803 in extended precision on the first
 40^3 system), the basis width the solve used and the columns appended
@@ -131,7 +131,7 @@ def test_elasticity40_auto_cap_against_fixture(gpu):
         from golden.make_fixtures import cost_model_fp64
 
         a, r = got[0]["alpha"], got[0]["rho"]
-        k_o, T = O.nc_limit(a, r, **cost_model_fp64(seq, min(1024, len(a) - 1)))
+        k_o, T = O.nc_limit(a, r, eps=fx["config"]["eps"], **cost_model_fp64(seq, min(1024, len(a) - 1)))
         assert k_o == lim
         assert abs(T[want] - T[lim]) <= 1e-3 * T[lim]
     _compare(fx, got)
