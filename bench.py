@@ -41,10 +41,12 @@ HBM_PEAK = 8.0e12  # MI355X HBM3E, bytes/s
 
 WORKLOADS = {
     "elasticity40": dict(kind="elasticity", size=40, n_systems=20, workload_id=2, max_basis=60, eps=1e-8),
-    # the whole Krylov run is kept (16000 x 3.06 M single-precision vectors,
-    # 196 GB): with a shorter history only the top of the spectrum stagnates
-    "elasticity100": dict(kind="elasticity", size=100, n_systems=30, workload_id=3, max_basis=200, eps=1e-8,
-                          history_cap=16000),
+    # the basis cap from the complexity analysis of the first solve
+    # (max_basis -1); the whole Krylov run is kept, in single precision
+    # (16000 x 3.06 M vectors, 196 GB): with a shorter history only the top
+    # of the spectrum stagnates
+    "elasticity100": dict(kind="elasticity", size=100, n_systems=30, workload_id=3, max_basis=-1, eps=1e-8,
+                          history_cap=16000, history="fp32"),
     "diffusion20": dict(kind="diffusion", size=(20, 20, 20), n_systems=8, workload_id=1, max_basis=0, eps=1e-14),
     # secant loop of a damaging cube: each matrix from the previous solution's strains
     "newton40": dict(kind="newton", size=40, n_systems=20, workload_id=6, max_basis=60, eps=1e-8),
@@ -80,14 +82,15 @@ def gen_systems(seq, ks, threads=16):
 KERNEL_NAMES = ("k_spmv_dot", "k_update_fused", "k_correct_dir")
 
 
-def kernel_bytes(seq, prec, n_c, hist, reuse):
+def kernel_bytes(seq, prec, n_c, hist, reuse, hist_bytes=None):
     """Algorithmic bytes of one launch of each per-iteration kernel.
 
     K1 q = A w and (w, q): the matrix values and block columns, w read, q
     written.  K3: x, w, r, q read, x, r, s written, the preconditioner, the
     rows of A C.  K5: s, w_old read, w written, z_j written to the history
     when one is kept, the basis C.  p: matrix value bytes, pb: basis and
-    preconditioner bytes, pw: Krylov vector bytes (x is always 8)."""
+    preconditioner bytes, pw: Krylov vector bytes (x is always 8);
+    ``hist_bytes``: bytes of a stored history element (default pb)."""
     p, pb, pw = prec["p"], prec["pb"], prec["pw"]
     n = seq.n
     nnz = seq.nnzb * seq.block * seq.block
@@ -95,7 +98,7 @@ def kernel_bytes(seq, prec, n_c, hist, reuse):
     BM = n * pb if seq.block == 1 else 3 * n * pb
     k1 = BA + 2 * n * pw
     k3 = n * (2 * 8 + 5 * pw) + BM + n * n_c * pb
-    k5 = n * 3 * pw + (n * pb if (hist and reuse == "selective") else 0) + n * n_c * pb
+    k5 = n * 3 * pw + (n * (hist_bytes or pb) if (hist and reuse == "selective") else 0) + n * n_c * pb
     return k1, k3, k5
 
 
@@ -118,6 +121,12 @@ def max_basis(args, wl):
     return int(args.max_basis) if args.max_basis else wl["max_basis"]
 
 
+def history_fp32(args, wl, precision):
+    """FP64 runs: whether the Krylov history is kept in single precision
+    (--history, else the workload's choice)."""
+    return precision == "fp64" and (args.history or wl.get("history", "fp64")) == "fp32"
+
+
 def run_sequence(K, ctx, seq, dev_sys, ks, precision, reuse, args, wl, timing=False, xs=None, label=""):
     """Systems ``ks`` of one sequence in order, from an empty basis, each
     through intake, rebuild, iterations and recycle.  Returns the wall time
@@ -132,7 +141,7 @@ def run_sequence(K, ctx, seq, dev_sys, ks, precision, reuse, args, wl, timing=Fa
                        cap_policy=args.cap_policy,
                        refine_drop=args.refine_drop, autotune=args.autotune, update_rows=args.update_rows,
                        eager=args.eager, separate_finalize=args.separate_finalize, spmv_variant=args.spmv_variant,
-                       history_fp32=args.history_fp32 and precision == "fp64")
+                       history_fp32=history_fp32(args, wl, precision))
     x_scratch = torch.empty(seq.n, dtype=torch.float64, device="cuda")
     recs = []
     try:
@@ -338,12 +347,15 @@ def run_sequence_workload(args, K, torch, wl):
     if plain_ks:
         _log(f"plain PCG: systems {plain_ks[0]}..{plain_ks[-1]} ({precision})")
         plain = run_sequence(K, ctx, seq, dev_sys, plain_ks, precision, "none", args, wl, label="plain")
-    cmp = None
-    if cmp_ks:
-        _log(f"{args.compare}: systems {cmp_ks[0]}..{cmp_ks[-1]} from an empty basis, errors against the {precision} run")
+    cmps = []
+    for cp in (args.compare if cmp_ks else []):
+        _log(f"{cp}: systems {cmp_ks[0]}..{cmp_ks[-1]} from an empty basis, errors against the {precision} run")
         xc = [torch.empty(seq.n, dtype=torch.float64, device="cuda") for _ in cmp_ks]
-        cmp = run_sequence(K, ctx, seq, dev_sys, cmp_ks, args.compare, reuse, args, wl, xs=xc, label=args.compare)
+        cmp = run_sequence(K, ctx, seq, dev_sys, cmp_ks, cp, reuse, args, wl, xs=xc, label=cp)
         cmp["err"] = [float(torch.linalg.norm(xc[i] - xs[i]) / torch.linalg.norm(xs[i])) for i in range(len(cmp_ks))]
+        cmp["precision"] = cp
+        cmps.append(cmp)
+        del xc
     ctx.close()
 
     infos = main["infos"]
@@ -367,7 +379,8 @@ def run_sequence_workload(args, K, torch, wl):
             # it: a full frozen basis, or a limit of 0 from the analysis
             lim = i["n_c_lim"]
             hist = not ((cap < 0 and lim == 0) or (args.cap_policy == "freeze" and lim > 0 and i["n_c_solve"] >= lim))
-            byt += kernel_bytes(seq, prec, i["n_c_solve"], hist, reuse)[j] * i["ktime"][j][0]
+            byt += kernel_bytes(seq, prec, i["n_c_solve"], hist, reuse,
+                                4 if history_fp32(args, wl, precision) else None)[j] * i["ktime"][j][0]
         kstat.append(dict(kernel=KERNEL_NAMES[j], launches_sampled=cnt, mean_us=1e3 * ms / cnt if cnt else None,
                           achieved_GBps=byt / (ms * 1e-3) / 1e9 if ms else None,
                           frac=byt / (ms * 1e-3) / HBM_PEAK if ms else None,
@@ -404,6 +417,9 @@ def run_sequence_workload(args, K, torch, wl):
             "tol": 1e-8,
             "precision": precision,
             "precision_detail": prec["detail"],
+            "krylov_history": ("fp32 (storage of the directions that form the recycled vectors; "
+                               "every iteration and the basis stay fp64)" if history_fp32(args, wl, precision)
+                               else prec["dtype"]),
         },
         "iters": iters,
         "phase_ms": [[round(i[k], 1) for k in ("t_rebuild_ms", "t_iter_ms", "t_recycle_ms")] + [round(1e3 * i["lat_s"], 1)]
@@ -444,18 +460,22 @@ def run_sequence_workload(args, K, torch, wl):
         same = len(plain_ks) / sum(infos[i]["lat_s"] for i in range(len(plain_ks)))
         out["plain_pcg"]["srks_value_same_systems"] = round(same, 4)
         out["speedup_vs_plain_pcg"] = value / pv
-    if cmp is not None:
-        ci = cmp["infos"]
-        out["compare"] = {
-            "precision": args.compare,
-            "detail": PRECISIONS[args.compare]["detail"],
-            "systems": f"0..{cmp_ks[-1]} from an empty basis",
-            "value": round(len(cmp_ks) / cmp["time"], 4),
-            "per_system": [dict(k=cmp_ks[i], iters=ci[i]["iters"], d_iters=ci[i]["iters"] - infos[i]["iters"],
-                                n_c=ci[i]["n_c_solve"], d_n_c=ci[i]["n_c_solve"] - infos[i]["n_c_solve"],
-                                rel_err_vs_fp64=cmp["err"][i], rel_res_true=ci[i]["rel_res_true"])
-                           for i in range(len(cmp_ks))],
-        }
+    if cmps:
+        out["compare"] = []
+        for cmp in cmps:
+            ci = cmp["infos"]
+            out["compare"].append({
+                "precision": cmp["precision"],
+                "detail": PRECISIONS[cmp["precision"]]["detail"],
+                "systems": f"0..{cmp_ks[-1]} from an empty basis",
+                "value": round(len(cmp_ks) / cmp["time"], 4),
+                "n_c_lim": ci[-1]["n_c_lim"],
+                "per_system": [dict(k=cmp_ks[i], iters=ci[i]["iters"], d_iters=ci[i]["iters"] - infos[i]["iters"],
+                                    n_c=ci[i]["n_c_solve"], d_n_c=ci[i]["n_c_solve"] - infos[i]["n_c_solve"],
+                                    rel_err_vs_fp64=cmp["err"][i], rel_res_true=ci[i]["rel_res_true"],
+                                    refinements=ci[i]["refinements"])
+                               for i in range(len(cmp_ks))],
+            })
     if args.cpu_baseline:
         _log("CPU baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline(seq, host, 0, float(np.mean(iters)), out["n_c_mean"], args.cpu_iters,
@@ -835,9 +855,9 @@ def main():
     ap.add_argument("--workload", default="elasticity100", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default=None, choices=sorted(PRECISIONS),
                     help="default: fp64 (elasticity, diffusion20), fp32basis (serving), mixed (batched diffusion)")
-    ap.add_argument("--compare", default="fp32basis", choices=sorted(PRECISIONS),
-                    help="second precision run on the first systems, with each solution's error against the "
-                         "headline run")
+    ap.add_argument("--compare", default="fp32basis,mixed", type=lambda v: [p for p in v.split(",") if p],
+                    help="further precisions (comma-separated) run on the first systems, with each solution's "
+                         "error against the headline run")
     ap.add_argument("--compare-systems", type=int, default=4)
     ap.add_argument("--no-compare", dest="compare", action="store_const", const=None)
     ap.add_argument("--cap-policy", default="freeze", choices=["freeze", "restart", "cost"])
@@ -861,8 +881,9 @@ def main():
                     help="block SpMV load schedule bits (0: the library's default, 8192 workgroups and "
                          "non-temporal loads for matrices over 256 MiB): 1 four blocks in flight, 2 non-temporal "
                          "matrix loads, 4/8/12 at most 2048/4096/8192 workgroups")
-    ap.add_argument("--history-fp32", action="store_true",
-                    help="fp64: keep the Krylov history (used only to form the recycled vectors) in single precision")
+    ap.add_argument("--history", default=None, choices=("fp64", "fp32"),
+                    help="fp64 runs: precision of the stored Krylov history, which only forms the recycled "
+                         "vectors (default: the workload's; single precision for elasticity100)")
     ap.add_argument("--separate-finalize", action="store_true",
                     help="run the end-of-step reduction as its own kernel")
     ap.add_argument("--clients", type=int, default=64, help="serving workload: clients (sequences)")
@@ -872,6 +893,9 @@ def main():
     ap.add_argument("--sweep", default="", help="serving workload: per-client arrival rates to sweep, e.g. 0.01,0.02")
     ap.add_argument("--window", type=float, default=60.0, help="serving sweep: seconds of arrivals per rate")
     args = ap.parse_args()
+    for cp in args.compare or []:
+        if cp not in PRECISIONS:
+            ap.error(f"--compare: unknown precision {cp!r} (one of {', '.join(sorted(PRECISIONS))})")
     if args.precision is None:
         args.precision = {"batched": "mixed", "serving": "fp32basis"}.get(args.workload, "fp64")
     if args.gpus != 1:

@@ -937,7 +937,8 @@ krs_status SeqImpl<V, W>::end_solve(double* x, bool device_x, krs_solve_info* in
 template <typename V, typename W>
 int64_t SeqImpl<V, W>::model_bytes_per_iter(bool padded) const {
     // Algorithmic bytes of one iteration: B_A + B_M + 10 n p_w + 2 n p_x
-    // (+ n p for the history column z_j when one is kept) + 2 n n_c p;
+    // (+ n p_z for the history column z_j when one is kept, p_z its storage
+    // size) + 2 n n_c p;
     // p: matrix / basis storage, p_w: Krylov vectors, p_x = 8.
     // `padded`: the cost cap's figure instead, which counts the padded rows
     // of A C that the update kernel streams and a z column for every
@@ -953,7 +954,7 @@ int64_t SeqImpl<V, W>::model_bytes_per_iter(bool padded) const {
         return BA + BM + vec + basis;
     }
     const bool z_kept = desc.reuse == KRS_REUSE_SELECTIVE && history_kept > 0;
-    const int64_t vec = 10 * n * pw + 2 * n * 8 + (z_kept ? n * p : 0);
+    const int64_t vec = 10 * n * pw + 2 * n * 8 + (z_kept ? n * hist_elem() : 0);
     return BA + BM + vec + 2 * n * (int64_t)nc * p;
 }
 
