@@ -6,7 +6,8 @@ comes from the HIP library.  Run from the repository root:
     python tests/golden/make_fixtures.py [name ...]
 
 Each fixture is a JSON file with, per system of an SRKS sequence (Algorithm
-3, 3x3 block-Jacobi, FP64, tol 1e-8; the direction update in the form
+3, 3x3 block-Jacobi, FP64, tol 1e-8, with or without full
+reorthogonalisation as the fixture states; the direction update in the form
 w = z + beta P w_old, which equals Algorithm 1's w = z + beta w_old in exact
 arithmetic and is the library's default): the iteration count, the
 basis width before the solve and after the recycle, the selected Ritz
@@ -42,6 +43,10 @@ FIXTURES = {
     # the 40^3 workload with n_c_lim from the complexity analysis of the
     # first solve (byte model of the library's FP64 iteration), freeze cap
     "elasticity40_auto_fp64": dict(E=40, workload_id=2, systems=4, cap="auto", eps=1e-8, max_iter=30000),
+    # the 40^3 workload's setup at 24^3 with full reorthogonalisation (the
+    # remark of Section 2.1, the setting of Section 5.1) at eps = 1e-14
+    "elasticity24_reorth_fp64": dict(E=24, workload_id=2, systems=3, cap=60, eps=1e-14, max_iter=4096,
+                                     reorth=True),
 }
 
 
@@ -82,8 +87,9 @@ def make(name: str) -> None:
     nc_lim = None
     for k in range(cfg["systems"]):
         rp, ci, v, b = seq.csr(k)
+        ro = cfg.get("reorth", False)
         res = O.apcg(rp, ci, v, b, "block3", C=C, tol=1e-8, max_iter=cfg["max_iter"], record_z=True,
-                     direction="project_old")
+                     direction="project_old", reorth=ro)
         nc_in = C.shape[1]
         if nc_in:
             C = C[:, res["kept"]]
@@ -114,12 +120,12 @@ def make(name: str) -> None:
         for _ in range(1):
             bp = b * (1.0 + 1e-15 * prng.standard_normal(b.shape))
             pm.append(int(O.apcg(rp, ci, v, bp, "block3", C=C_solve, tol=1e-8, max_iter=cfg["max_iter"],
-                                 direction="project_old")["m"]))
+                                 direction="project_old", reorth=ro)["m"]))
         rec["m_perturbed"] = pm
         # and with the products accumulated in extended precision: another
         # faithful rounding of the same arithmetic
         rec["m_extended"] = int(O.apcg(rp, ci, v, b, "block3", C=C_solve, tol=1e-8, max_iter=cfg["max_iter"],
-                                       direction="project_old", extended=True)["m"])
+                                       direction="project_old", extended=True, reorth=ro)["m"])
         rec["selected"] = [int(i) for i in sel]
         rec["nc_next"] = int(C.shape[1])
         rec["fingerprint"] = span_fingerprint(C, R).tolist()

@@ -57,7 +57,8 @@ def _run(gpu, fx, max_basis):
     assert seq.n == fx["n"]
     R = _probe(seq.n)
     s = K.sequence_for(gpu, seq, precision="fp64", reuse="selective", ritz_eps=cfg["eps"], max_basis=max_basis,
-                       cap_policy="freeze", tol=1e-8, max_iter=cfg["max_iter"], history_cap=cfg["max_iter"])
+                       cap_policy="freeze", tol=1e-8, max_iter=cfg["max_iter"], history_cap=cfg["max_iter"],
+                       reorth=cfg.get("reorth", False))
     out = []
     try:
         for k in range(cfg["systems"]):
@@ -135,3 +136,11 @@ def test_elasticity40_auto_cap_against_fixture(gpu):
         assert k_o == lim
         assert abs(T[want] - T[lim]) <= 1e-3 * T[lim]
     _compare(fx, got)
+
+
+def test_elasticity24_reorth_against_fixture(gpu):
+    """Full reorthogonalisation (Section 2.1, the setting of Section 5.1)
+    over three systems of the 40^3 workload's setup at 24^3, at the paper's
+    eps = 1e-14."""
+    fx = _fixture("elasticity24_reorth_fp64")
+    _compare(fx, _run(gpu, fx, fx["config"]["cap"]))
