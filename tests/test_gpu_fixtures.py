@@ -32,6 +32,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 def _fixture(name):
     path = os.path.join(HERE, "golden", name + ".json")
+    if not os.path.exists(path):
+        pytest.skip(f"fixture {name} not written yet (tests/golden/make_fixtures.py {name})")
     with open(path) as f:
         return json.load(f)
 
