@@ -937,103 +937,197 @@ __device__ __forceinline__ void update_reduce_body(const SysView<V, W>& v, int64
     bool have_a = mode != 0;
     const bool run = ((1u << st_status) & mask) != 0;
     if (pb >= pe && !run) return;
-    for (int64_t ps = pb; ps < pe; ps += T) {
-        const int64_t p = ps + tid;
-        double ri[B], wi[B], si[B];
+    if constexpr (B == 3) {
+        // One thread per unknown: in each of SUB sub-steps a wave takes 63
+        // consecutive unknowns (21 block rows; lane 63 idles), so the loads
+        // and stores of x, r, w, q and s are contiguous across the wave and
+        // a lane reads the 3 entries of its row of the 3x3 block M^-1
+        // (3 i .. 3 i + 2 for unknown i = 3 p + d).  The residual entries
+        // of the other rows of the block come from the neighbouring lanes.
+        constexpr int NWV = T / 64, BPW = 21, SUB = 3;
+        constexpr int SB = NWV * BPW * SUB;  // block rows per step
+        static_assert(SB * 3 <= T * B, "a step's s and w fit the LDS rows of the projection");
+        const int lane = tid & 63, wave = tid >> 6;
+        const int l0 = lane - lane % 3;
+        for (int64_t ps = pb; ps < pe; ps += SB) {
+            const int64_t pn = (ps + SB) < pe ? (ps + SB) : pe;
+            const int nloc = (int)((pn - ps) * 3);
+            int loc[SUB];
+            bool act[SUB];
+            W rv[SUB], qv[SUB];
+            double xv[SUB], wi[SUB];
+            V mv[SUB][3];
 #pragma unroll
-        for (int d = 0; d < B; ++d) {
-            ri[d] = 0.0;
-            wi[d] = 0.0;
-            si[d] = 0.0;
-        }
-        // the step's vector loads are issued before alpha is formed from
-        // the SpMV partials, so the two latencies overlap
-        W rv[B], qv[B];
-        double xv[B];
-        V mv[B * B];
-        if (p < pe) {
+            for (int k = 0; k < SUB; ++k) {
+                loc[k] = k * (NWV * BPW * 3) + wave * (BPW * 3) + lane;
+                act[k] = lane < 63 && loc[k] < nloc;
+                wi[k] = 0.0;
+                if (act[k]) {
+                    const int64_t i = ps * 3 + loc[k];
+                    rv[k] = v.r[i];
+                    if (mode != 1) wi[k] = (double)v.w[i];
+                    if (mode == 0) {
+                        qv[k] = v.q[i];
+                        xv[k] = v.x[i];
+                    }
 #pragma unroll
-            for (int d = 0; d < B; ++d) {
-                const int64_t i = p * B + d;
-                rv[d] = v.r[i];
-                if (mode != 1) wi[d] = (double)v.w[i];
-                if (mode == 0) {
-                    qv[d] = v.q[i];
-                    xv[d] = v.x[i];
+                    for (int e = 0; e < 3; ++e) mv[k][e] = v.minv[3 * i + e];
                 }
             }
+            // the status is tested once the first step's loads are issued
+            // (they are in bounds whatever it is), so the latencies overlap
+            if (ps == pb) {
+                if (!run) return;
+                tm = mode == 0 && st_kt && (st_iter & 31) == 1;
+                ktime_begin(v.kslots, 1, bid, tm);
+            }
+            if (!have_a) {
+                gam = sum_all(v.part1, v.geo.g1, red);
+                a = st_rho / gam;
+                have_a = true;
+            }
+            double si[SUB];
 #pragma unroll
-            for (int e = 0; e < B * B; ++e) mv[e] = v.minv[p * B * B + e];
-        }
-        // the status is tested once the first step's loads are issued (they
-        // are in bounds whatever it is), so the latencies overlap
-        if (ps == pb) {
-            if (!run) return;
-            tm = mode == 0 && st_kt && (st_iter & 31) == 1;
-            ktime_begin(v.kslots, 1, bid, tm);
-        }
-        if (!have_a) {
-            gam = sum_all(v.part1, v.geo.g1, red);
-            a = st_rho / gam;
-            have_a = true;
-        }
-        double xn[B];
-        W rn[B];
-        if (p < pe) {
-#pragma unroll
-            for (int d = 0; d < B; ++d) {
-                W r2 = rv[d];
-                if (mode == 0) {
-                    xn[d] = xv[d] + a * wi[d];
-                    r2 = (W)((double)r2 - a * (double)qv[d]);
+            for (int k = 0; k < SUB; ++k) {
+                W r2 = act[k] ? rv[k] : (W)0;
+                double xn = 0.0;
+                if (act[k] && mode == 0) {
+                    xn = xv[k] + a * wi[k];
+                    r2 = (W)((double)r2 - a * (double)qv[k]);
                 }
-                rn[d] = r2;
-                ri[d] = (double)r2;
-            }
-            if (B == 1) {
-                si[0] = (double)(W)((double)mv[0] * ri[0]);
-            } else {
-#pragma unroll
-                for (int d = 0; d < B; ++d)
-                    si[d] = (double)(W)((double)mv[3 * d] * ri[0] + (double)mv[3 * d + 1] * ri[1] +
-                                        (double)mv[3 * d + 2] * ri[2]);
-            }
-#pragma unroll
-            for (int d = 0; d < B; ++d) {
-                rr += ri[d] * ri[d];
-                rs += ri[d] * si[d];
-            }
-        }
-        // s and w go to LDS before the stores are issued, so the barrier
-        // does not wait for them (the previous step's projection ended with
-        // a barrier, so the buffers are free)
-        if (nc > 0) {
-#pragma unroll
-            for (int d = 0; d < B; ++d) {
-                ss[tid * B + d] = si[d];
-                ws[tid * B + d] = wi[d];
-            }
-            __syncthreads();
-        }
-        if (p < pe) {
-#pragma unroll
-            for (int d = 0; d < B; ++d) {
-                const int64_t i = p * B + d;
-                if (mode == 0) {
-                    v.x[i] = xn[d];
-                    v.r[i] = rn[d];
+                const double ri = (double)r2;
+                // the block's three residual entries (every lane takes part in the shuffles)
+                const double r0 = __shfl(ri, l0, 64), r1 = __shfl(ri, l0 + 1, 64), r2d = __shfl(ri, l0 + 2, 64);
+                si[k] = 0.0;
+                if (act[k]) {
+                    si[k] = (double)(W)((double)mv[k][0] * r0 + (double)mv[k][1] * r1 + (double)mv[k][2] * r2d);
+                    rr += ri * ri;
+                    rs += ri * si[k];
+                    const int64_t i = ps * 3 + loc[k];
+                    if (mode == 0) {
+                        v.x[i] = xn;
+                        v.r[i] = r2;
+                    }
+                    v.s[i] = (W)si[k];
                 }
-                v.s[i] = (W)si[d];
+            }
+            if (nc > 0) {
+                // s and w of the step to LDS for the projection (the previous
+                // step's projection ended with a barrier, so the rows are free)
+#pragma unroll
+                for (int k = 0; k < SUB; ++k)
+                    if (act[k]) {
+                        ss[loc[k]] = si[k];
+                        ws[loc[k]] = wi[k];
+                    }
+                __syncthreads();
+                if (SINGLE && v.ldac >= ProjSplit<V>::CW)
+                    project_rows<V, UR, true>(v.AC + ps * 3 * v.ldac, v.ldac, nloc, nc, ss, ws, tacc, vacc, cred,
+                                              pg);
+                else
+                    project_rows<V, UR, false>(v.AC + ps * 3 * v.ldac, v.ldac, nloc, nc, ss, ws, tacc, vacc, cred,
+                                               pg);
             }
         }
-        if (nc > 0) {
-            const int64_t pn = (ps + T) < pe ? (ps + T) : pe;
-            if (SINGLE && v.ldac >= ProjSplit<V>::CW)
-                project_rows<V, UR, true>(v.AC + ps * B * v.ldac, v.ldac, (int)((pn - ps) * B), nc, ss, ws, tacc,
-                                          vacc, cred, pg);
-            else
-                project_rows<V, UR, false>(v.AC + ps * B * v.ldac, v.ldac, (int)((pn - ps) * B), nc, ss, ws, tacc,
-                                           vacc, cred, pg);
+    } else {
+        for (int64_t ps = pb; ps < pe; ps += T) {
+            const int64_t p = ps + tid;
+            double ri[B], wi[B], si[B];
+#pragma unroll
+            for (int d = 0; d < B; ++d) {
+                ri[d] = 0.0;
+                wi[d] = 0.0;
+                si[d] = 0.0;
+            }
+            // the step's vector loads are issued before alpha is formed from
+            // the SpMV partials, so the two latencies overlap
+            W rv[B], qv[B];
+            double xv[B];
+            V mv[B * B];
+            if (p < pe) {
+#pragma unroll
+                for (int d = 0; d < B; ++d) {
+                    const int64_t i = p * B + d;
+                    rv[d] = v.r[i];
+                    if (mode != 1) wi[d] = (double)v.w[i];
+                    if (mode == 0) {
+                        qv[d] = v.q[i];
+                        xv[d] = v.x[i];
+                    }
+                }
+#pragma unroll
+                for (int e = 0; e < B * B; ++e) mv[e] = v.minv[p * B * B + e];
+            }
+            // the status is tested once the first step's loads are issued (they
+            // are in bounds whatever it is), so the latencies overlap
+            if (ps == pb) {
+                if (!run) return;
+                tm = mode == 0 && st_kt && (st_iter & 31) == 1;
+                ktime_begin(v.kslots, 1, bid, tm);
+            }
+            if (!have_a) {
+                gam = sum_all(v.part1, v.geo.g1, red);
+                a = st_rho / gam;
+                have_a = true;
+            }
+            double xn[B];
+            W rn[B];
+            if (p < pe) {
+#pragma unroll
+                for (int d = 0; d < B; ++d) {
+                    W r2 = rv[d];
+                    if (mode == 0) {
+                        xn[d] = xv[d] + a * wi[d];
+                        r2 = (W)((double)r2 - a * (double)qv[d]);
+                    }
+                    rn[d] = r2;
+                    ri[d] = (double)r2;
+                }
+                if (B == 1) {
+                    si[0] = (double)(W)((double)mv[0] * ri[0]);
+                } else {
+#pragma unroll
+                    for (int d = 0; d < B; ++d)
+                        si[d] = (double)(W)((double)mv[3 * d] * ri[0] + (double)mv[3 * d + 1] * ri[1] +
+                                            (double)mv[3 * d + 2] * ri[2]);
+                }
+#pragma unroll
+                for (int d = 0; d < B; ++d) {
+                    rr += ri[d] * ri[d];
+                    rs += ri[d] * si[d];
+                }
+            }
+            // s and w go to LDS before the stores are issued, so the barrier
+            // does not wait for them (the previous step's projection ended with
+            // a barrier, so the buffers are free)
+            if (nc > 0) {
+#pragma unroll
+                for (int d = 0; d < B; ++d) {
+                    ss[tid * B + d] = si[d];
+                    ws[tid * B + d] = wi[d];
+                }
+                __syncthreads();
+            }
+            if (p < pe) {
+#pragma unroll
+                for (int d = 0; d < B; ++d) {
+                    const int64_t i = p * B + d;
+                    if (mode == 0) {
+                        v.x[i] = xn[d];
+                        v.r[i] = rn[d];
+                    }
+                    v.s[i] = (W)si[d];
+                }
+            }
+            if (nc > 0) {
+                const int64_t pn = (ps + T) < pe ? (ps + T) : pe;
+                if (SINGLE && v.ldac >= ProjSplit<V>::CW)
+                    project_rows<V, UR, true>(v.AC + ps * B * v.ldac, v.ldac, (int)((pn - ps) * B), nc, ss, ws, tacc,
+                                              vacc, cred, pg);
+                else
+                    project_rows<V, UR, false>(v.AC + ps * B * v.ldac, v.ldac, (int)((pn - ps) * B), nc, ss, ws, tacc,
+                                               vacc, cred, pg);
+            }
         }
     }
     const int stride = 2 * nc + 2;
