@@ -448,7 +448,10 @@ __device__ __forceinline__ void ell_row3all(const V* __restrict__ val, const int
 // q = A w over sliced ELL; per-workgroup partial sums of (w, q) go to
 // part1[bid].  alpha = rho / (w, q) is formed from them by every workgroup
 // of the next kernel (a fixed-order sum, so all agree).
-template <typename V, typename W, int B>
+// VAR: the load schedule fixed at compile time (the single-system kernel,
+// one instantiation per schedule, so the registers are those of the one in
+// use), or -1 to take v.spmv_var at run time (the batch kernel).
+template <typename V, typename W, int B, int VAR = -1>
 __device__ __forceinline__ void spmv_dot_body(const SysView<V, W>& v, int64_t bid) {
     if (!gate(v.st, M_RUN)) return;
     const bool tm = ktime_sample(v.st, 0);
@@ -471,11 +474,12 @@ __device__ __forceinline__ void spmv_dot_body(const SysView<V, W>& v, int64_t bi
         }
     } else {
         // two slices per workgroup step, one per wave; a lane owns a block row
-        const int var = v.spmv_var;
+        const int var = VAR >= 0 ? VAR : v.spmv_var;
         for (int64_t sl = bid * 2 + wave; sl < v.nslices; sl += nblk * 2) {
             const int64_t k0 = v.slice_ptr[sl], k1 = v.slice_ptr[sl + 1];
             W acc[3];
-            if (v.op64) {
+            if (std::is_same<V, double>::value || v.op64) {
+                // (a double-precision basis always has the double-precision operator)
                 if ((var & 3) == 0) ell_row3all<double, W, 2, false>(v.val64, v.col, v.w, k0, k1, lane, acc);
                 else if ((var & 3) == 1) ell_row3all<double, W, 4, false>(v.val64, v.col, v.w, k0, k1, lane, acc);
                 else if ((var & 3) == 2) ell_row3all<double, W, 2, true>(v.val64, v.col, v.w, k0, k1, lane, acc);
@@ -1544,9 +1548,9 @@ __device__ __forceinline__ void coarse_correct_body(const SysView<V, W>& v, int6
 }
 
 // ------------------------------------------- single-system entry points
-template <typename V, typename W, int B>
+template <typename V, typename W, int B, int VAR>
 __global__ __launch_bounds__(256) void k_spmv_dot(SysView<V, W> v) {
-    spmv_dot_body<V, W, B>(v, blockIdx.x);
+    spmv_dot_body<V, W, B, VAR>(v, blockIdx.x);
 }
 template <typename V, typename W, int B>
 __global__ __launch_bounds__(kT3, 2) void k_update_reduce(SysView<V, W> v, int mode) {
@@ -2117,7 +2121,13 @@ int64_t partial_doubles(const Geometry& g, int nc) {
 template <typename V, typename W, int B>
 void launch_spmv_dot(const SysView<V, W>& v, hipStream_t stream) {
     const int threads = (B == 1) ? 256 : 128;
-    hipLaunchKernelGGL((k_spmv_dot<V, W, B>), dim3((unsigned)v.geo.g1), dim3(threads), 0, stream, v);
+    const dim3 grid((unsigned)v.geo.g1);
+    switch ((B == 3 && v.op64) ? (v.spmv_var & 3) : 0) {
+        case 1: hipLaunchKernelGGL((k_spmv_dot<V, W, B, 1>), grid, dim3(threads), 0, stream, v); break;
+        case 2: hipLaunchKernelGGL((k_spmv_dot<V, W, B, 2>), grid, dim3(threads), 0, stream, v); break;
+        case 3: hipLaunchKernelGGL((k_spmv_dot<V, W, B, 3>), grid, dim3(threads), 0, stream, v); break;
+        default: hipLaunchKernelGGL((k_spmv_dot<V, W, B, 0>), grid, dim3(threads), 0, stream, v); break;
+    }
 }
 
 template <typename V, typename W, int B>

