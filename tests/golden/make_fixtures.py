@@ -4,6 +4,7 @@ Calls only ``oracle`` (and the input generators of ``gen``); nothing here
 comes from the HIP library.  Run from the repository root:
 
     python tests/golden/make_fixtures.py [name ...]
+    python tests/golden/make_fixtures.py --draws name ...   (adds the sequence draws)
 
 Each fixture is a JSON file with, per system of an SRKS sequence (Algorithm
 3, 3x3 block-Jacobi, FP64, tol 1e-8, with or without full
@@ -139,6 +140,64 @@ def make(name: str) -> None:
         json.dump(out, f, indent=0)
 
 
+def draw(name: str, kind: str) -> dict:
+    """The whole sequence again under another faithful rounding of the same
+    arithmetic: every right-hand side perturbed at the rounding level
+    (relative 1e-15, seeded per system) or every product accumulated in
+    extended precision.  Per system: iterations, basis width at the solve,
+    columns appended and the span fingerprint.  Without reorthogonalisation
+    rounding moves long runs by about 1 %, and a different run selects a
+    slightly different set of Ritz vectors, which moves the later systems of
+    the sequence further: the spread over such draws is the oracle's own."""
+    cfg = FIXTURES[name]
+    seq = gen.config_elasticity(cfg["E"], cfg["systems"], cfg["workload_id"])
+    R = probe(seq.n)
+    ro = cfg.get("reorth", False)
+    C = np.zeros((seq.n, 0))
+    cap = cfg["cap"]
+    out = []
+    t = time.perf_counter()
+    for k in range(cfg["systems"]):
+        rp, ci, v, b = seq.csr(k)
+        if kind == "perturbed":
+            prng = np.random.default_rng(np.random.SeedSequence([13017530, 97, k]))
+            b = b * (1.0 + 1e-15 * prng.standard_normal(b.shape))
+        res = O.apcg(rp, ci, v, b, "block3", C=C, tol=1e-8, max_iter=cfg["max_iter"], record_z=True,
+                     direction="project_old", reorth=ro, extended=(kind == "extended"))
+        if C.shape[1]:
+            C = C[:, res["kept"]]
+        nc_solve = C.shape[1]
+        if cap == "auto":
+            cap, _ = O.nc_limit(res["alpha"], res["rho"], eps=cfg["eps"],
+                                **cost_model_fp64(seq, min(1024, res["m"] - 1)))
+        room = cap - C.shape[1]
+        sel = []
+        if res["m"] > 1 and room > 0:
+            th_m, th_m1 = O.ritz_values(res["alpha"], res["rho"])
+            sel = O.freeze_pick(O.srks_select(th_m, th_m1, cfg["eps"]), th_m, room)
+            C = np.concatenate([C, O.ritz_block(res["Z"], res["alpha"], res["rho"], sel, th_m)], axis=1)
+        out.append(dict(k=k, m=int(res["m"]), nc_solve=int(nc_solve), added=len(sel),
+                        fingerprint=span_fingerprint(C, R).tolist()))
+        del res
+        print(f"{name} draw {kind} system {k}: m={out[-1]['m']} n_c {nc_solve} (+{len(sel)})  "
+              f"[{time.perf_counter() - t:.0f} s]", flush=True)
+    return dict(kind=kind, systems=out)
+
+
+def add_draws(name: str) -> None:
+    path = os.path.join(HERE, name + ".json")
+    with open(path) as f:
+        fx = json.load(f)
+    fx["sequence_draws"] = [draw(name, kind) for kind in ("perturbed", "extended")]
+    with open(path, "w") as f:
+        json.dump(fx, f, indent=0)
+
+
 if __name__ == "__main__":
-    for nm in sys.argv[1:] or list(FIXTURES):
-        make(nm)
+    args = sys.argv[1:]
+    if args and args[0] == "--draws":
+        for nm in args[1:]:
+            add_draws(nm)
+    else:
+        for nm in args or list(FIXTURES):
+            make(nm)
