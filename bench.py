@@ -760,15 +760,17 @@ def run_batched(args, K, torch, data):
     torch.cuda.synchronize()
     ctx = K.Context(0)
     kw = dict(precision=args.precision, tol=1e-8, max_iter=args.max_iter, ritz_eps=args.eps or wl["eps"],
-              max_basis=wl["max_basis"], cap_policy=wl.get("cap_policy", "freeze"), history_cap=args.history_cap,
+              max_basis=max_basis(args, wl), cap_policy=args.cap_policy, history_cap=args.history_cap,
               refine_drop=args.refine_drop, separate_finalize=args.separate_finalize)
     fused_rows = args.update_rows
 
     def phase(reuse, fused):
+        kwr = dict(kw, max_basis=kw["max_basis"] if reuse == "selective" else 0)
         hs = [K.sequence_for(ctx, sq, reuse=reuse, update_rows=fused_rows if fused else 0,
-                             autotune=fused and not fused_rows, **kw) for sq in seqs]
+                             autotune=fused and not fused_rows, **kwr) for sq in seqs]
         xs = [torch.empty(sq.n, dtype=torch.float64, device="cuda") for sq in seqs]
         iters, t_steps, t_rec, ncs, tiles = [], [], [], [], []
+        lims = {}
         try:
             for step, k in enumerate(ks):
                 torch.cuda.synchronize()
@@ -793,6 +795,9 @@ def run_batched(args, K, torch, data):
                     iters.append([inf["iters"] for inf in infos])
                     tiles.append(sorted({inf["update_rows"] for inf in infos}))
                     ncs.append(float(np.mean([inf["n_c"] for inf in infos])))
+                    lims = {}
+                    for inf in infos:
+                        lims[int(inf["n_c_lim"])] = lims.get(int(inf["n_c_lim"]), 0) + 1
                     bad = [inf for inf in infos if inf["rel_res_true"] > 1e-8 or inf["status"] != 0]
                     if bad:
                         raise RuntimeError(f"{len(bad)} systems missed the tolerance: {bad[0]}")
@@ -802,12 +807,13 @@ def run_batched(args, K, torch, data):
         t = sum(t_steps)
         return dict(value=len(hs) * len(t_steps) / t, time=t, iters_mean=float(np.mean(iters)),
                     step_ms=[round(1e3 * x, 2) for x in t_steps], recycle_ms=[round(1e3 * x, 2) for x in t_rec],
-                    n_c_mean=[round(x, 2) for x in ncs], tiles=tiles)
+                    n_c_mean=[round(x, 2) for x in ncs], tiles=tiles,
+                    n_c_lim_last_step={str(k): v for k, v in sorted(lims.items())})
 
     _log("fused SRKS")
     fused = phase("selective", True)
     _log("sequential SRKS")
-    alone = phase("selective", False) if args.plain else None
+    alone = phase("selective", False) if args.plain and args.sequential else None
     _log("fused plain PCG")
     plain = phase("none", True) if args.plain else None
     ctx.close()
@@ -825,7 +831,8 @@ def run_batched(args, K, torch, data):
         "dtype": {"mixed": "f32+f64", "fp64": "f64", "fp32": "f32", "fp32basis": "f64+f32"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"batched: {len(seqs)} diffusion sequences, n ~ U[5e3, 2e5] (sum {n_tot}), "
-                               f"SRKS eps={kw['ritz_eps']:.0e} cap {wl['max_basis']} ({kw['cap_policy']}), "
+                               f"SRKS eps={kw['ritz_eps']:.0e} cap "
+                               f"{'auto' if kw['max_basis'] < 0 else kw['max_basis']} ({kw['cap_policy']}), "
                                f"fused launches",
                    "sequences": len(seqs), "sum_n": n_tot, "precision": args.precision,
                    "history_cap": args.history_cap,
@@ -835,6 +842,7 @@ def run_batched(args, K, torch, data):
         "step_ms": fused["step_ms"],
         "recycle_ms": fused["recycle_ms"],
         "n_c_mean_per_step": fused["n_c_mean"],
+        "n_c_lim_last_step": fused["n_c_lim_last_step"],
         "recycle_mode": "host Ritz work of each member started when it finishes, during the fused launches "
                         "(krs_batch_solve_recycle); recycle_ms is the part left after that call returns",
     }
@@ -860,10 +868,13 @@ def main():
                          "error against the headline run")
     ap.add_argument("--compare-systems", type=int, default=4)
     ap.add_argument("--no-compare", dest="compare", action="store_const", const=None)
-    ap.add_argument("--cap-policy", default="freeze", choices=["freeze", "restart", "cost"])
+    ap.add_argument("--cap-policy", default=None, choices=["freeze", "restart", "cost"],
+                    help="what happens at the basis cap (default: the workload's; freeze for most)")
     ap.add_argument("--max-iter", type=int, default=30000)
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--no-plain", dest="plain", action="store_false")
+    ap.add_argument("--no-sequential", dest="sequential", action="store_false",
+                    help="batched workload: skip the one-sequence-at-a-time comparison")
     ap.add_argument("--plain-systems", type=int, default=3, help="plain PCG on the first systems of the sequence")
     ap.add_argument("--cpu-iters", type=int, default=10, help="oracle iterations per timed sample")
     ap.add_argument("--cpu-nc", type=int, default=8, help="basis columns of the oracle's timed sample")
@@ -896,6 +907,8 @@ def main():
     for cp in args.compare or []:
         if cp not in PRECISIONS:
             ap.error(f"--compare: unknown precision {cp!r} (one of {', '.join(sorted(PRECISIONS))})")
+    if args.cap_policy is None:
+        args.cap_policy = WORKLOADS[args.workload].get("cap_policy", "freeze")
     if args.precision is None:
         args.precision = {"batched": "mixed", "serving": "fp32basis"}.get(args.workload, "fp64")
     if args.gpus != 1:

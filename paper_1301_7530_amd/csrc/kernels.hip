@@ -554,86 +554,151 @@ struct ProjSplit {
 
 // FULL: rows of at least one 128-byte chunk (the chunk geometry is then
 // known at compile time).
+//
+// project_acc: item (chunk ch, row phase ph) of one wave over `rows` rows,
+// added into the lane's sums at / av.
+template <typename V, int UR, bool FULL>
+__device__ __forceinline__ void project_acc(const V* __restrict__ ACt, int64_t ld, int rows, const double* ss,
+                                            const double* ws, int ch, int ph, double* at, double* av,
+                                            const ProjSplit<V>& g) {
+    using G = ProjSplit<V>;
+    constexpr int QW = G::QW;
+    const int CW = FULL ? G::CW : g.cw, RPW = FULL ? 64 / (G::CW / QW) : g.rpw;
+    const int q = g.q, rsub = g.rsub, step = g.step;
+    const V* base = ACt + ch * CW + q * QW;
+    for (int r0 = ph * RPW + rsub; r0 < rows; r0 += step * UR) {
+        // rows past the step are clamped to its last row (weight 0)
+        // so every load of the group is issued unconditionally
+        Vec16<V> a[UR];
+#pragma unroll
+        for (int u = 0; u < UR; ++u) {
+            const int rr = min(r0 + u * step, rows - 1);
+            a[u] = *reinterpret_cast<const Vec16<V>*>(base + (int64_t)rr * ld);
+        }
+#pragma unroll
+        for (int u = 0; u < UR; ++u) {
+            const int rr = r0 + u * step;
+            const bool ok = rr < rows;
+            const double sv = ok ? ss[rr] : 0.0, wv = ok ? ws[rr] : 0.0;
+#pragma unroll
+            for (int e = 0; e < QW; ++e) {
+                at[e] += (double)a[u].e[e] * sv;
+                av[e] += (double)a[u].e[e] * wv;
+            }
+        }
+    }
+}
+
+// project_flush: the lanes' sums of round k0 (items k0 .. k0 + NW - 1, one
+// per wave) added into tacc / vacc: lanes of equal column by shuffles, the
+// waves of a chunk in a fixed order through LDS.  Every thread of the
+// workgroup calls it (two barriers).
+template <typename V, bool FULL>
+__device__ __forceinline__ void project_flush(double* at, double* av, int k0, int nc, double* tacc, double* vacc,
+                                              double (*cred)[64], const ProjSplit<V>& g) {
+    using G = ProjSplit<V>;
+    constexpr int QW = G::QW, NW = G::NW;
+    const int CW = FULL ? G::CW : g.cw, LPR = FULL ? G::CW / QW : g.lpr;
+    const int wave = threadIdx.x >> 6;
+    const int q = g.q, rsub = g.rsub, nch = g.nch, P = g.P;
+    const bool act = k0 + wave < g.items;
+#pragma unroll
+    for (int e = 0; e < QW; ++e) {
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            if (off >= LPR) {
+                at[e] += __shfl_xor(at[e], off, 64);
+                av[e] += __shfl_xor(av[e], off, 64);
+            }
+        }
+    }
+    if (rsub == 0 && act) {
+#pragma unroll
+        for (int e = 0; e < QW; ++e) {
+            cred[wave][q * QW + e] = at[e];
+            cred[wave][32 + q * QW + e] = av[e];
+        }
+    }
+    __syncthreads();
+    // chunks of this round: all of them when there are fewer than waves
+    // (wave cl + p nch holds phase p of chunk cl), else NW of them
+    const int nchr = nch <= NW ? nch : min(NW, nch - k0);
+    const int t = threadIdx.x;
+    if (t < nchr * CW) {
+        const int cl = t / CW, e = t % CW;
+        const int c = (nch <= NW ? cl : k0 + cl) * CW + e;
+        if (c < nc) {
+            double ts = 0.0, vs = 0.0;
+            for (int p = 0; p < P; ++p) {
+                const int w = cl + p * nch;
+                ts += cred[w][e];
+                vs += cred[w][32 + e];
+            }
+            tacc[c] += ts;
+            vacc[c] += vs;
+        }
+    }
+    __syncthreads();
+}
+
 template <typename V, int UR, bool FULL>
 __device__ __forceinline__ void project_rows(const V* __restrict__ ACt, int64_t ld, int rows, int nc,
                                              const double* ss, const double* ws, double* tacc, double* vacc,
                                              double (*cred)[64], const ProjSplit<V>& g) {
-    using G = ProjSplit<V>;
-    constexpr int QW = G::QW, NW = G::NW;
-    const int CW = FULL ? G::CW : g.cw, LPR = FULL ? G::CW / QW : g.lpr, RPW = FULL ? 64 / (G::CW / QW) : g.rpw;
+    constexpr int QW = ProjSplit<V>::QW, NW = ProjSplit<V>::NW;
     const int wave = threadIdx.x >> 6;
-    const int q = g.q, rsub = g.rsub, nch = g.nch, P = g.P, items = g.items, step = g.step;
-    for (int k0 = 0; k0 < items; k0 += NW) {
+    for (int k0 = 0; k0 < g.items; k0 += NW) {
         const int it = k0 + wave;
-        const bool act = it < items;
-        const int ch = it % nch, ph = it / nch;
         double at[QW], av[QW];
 #pragma unroll
         for (int e = 0; e < QW; ++e) {
             at[e] = 0.0;
             av[e] = 0.0;
         }
-        if (act) {
-            const V* base = ACt + ch * CW + q * QW;
-            for (int r0 = ph * RPW + rsub; r0 < rows; r0 += step * UR) {
-                // rows past the step are clamped to its last row (weight 0)
-                // so every load of the group is issued unconditionally
-                Vec16<V> a[UR];
+        if (it < g.items) project_acc<V, UR, FULL>(ACt, ld, rows, ss, ws, it % g.nch, it / g.nch, at, av, g);
+        project_flush<V, FULL>(at, av, k0, nc, tacc, vacc, cred, g);
+    }
+}
+
+// Loads of A C issued ahead.  When the items do not outnumber the waves and
+// a step's rows take at most UF loads per lane, a wave's loads of the
+// step's rows of A C are issued together with the step's vector loads, so
+// that the two latencies overlap instead of following each other across
+// the barrier; the products follow the barrier.
+template <typename V, int UF>
+__device__ __forceinline__ bool proj_ahead_fits(int rows, const ProjSplit<V>& g) {
+    return g.items <= ProjSplit<V>::NW && rows <= g.step * UF;
+}
+template <typename V, int UF>
+__device__ __forceinline__ void proj_ahead_issue(const V* __restrict__ ACt, int64_t ld, int rows,
+                                                 const ProjSplit<V>& g, Vec16<V>* a) {
+    const int wave = threadIdx.x >> 6;
+    if (wave >= g.items) return;
+    const V* base = ACt + (wave % g.nch) * g.cw + g.q * ProjSplit<V>::QW;
+    const int r0 = (wave / g.nch) * g.rpw + g.rsub;
 #pragma unroll
-                for (int u = 0; u < UR; ++u) {
-                    const int rr = min(r0 + u * step, rows - 1);
-                    a[u] = *reinterpret_cast<const Vec16<V>*>(base + (int64_t)rr * ld);
-                }
+    for (int u = 0; u < UF; ++u) {
+        const int rr = min(r0 + u * g.step, rows - 1);
+        a[u] = *reinterpret_cast<const Vec16<V>*>(base + (int64_t)rr * ld);
+    }
+}
+template <typename V, int UF>
+__device__ __forceinline__ void proj_ahead_acc(const Vec16<V>* a, int rows, const double* ss, const double* ws,
+                                               double* at, double* av, const ProjSplit<V>& g) {
+    constexpr int QW = ProjSplit<V>::QW;
+    const int wave = threadIdx.x >> 6;
+    if (wave >= g.items) return;
+    const int r0 = (wave / g.nch) * g.rpw + g.rsub;
 #pragma unroll
-                for (int u = 0; u < UR; ++u) {
-                    const int rr = r0 + u * step;
-                    const bool ok = rr < rows;
-                    const double sv = ok ? ss[rr] : 0.0, wv = ok ? ws[rr] : 0.0;
-#pragma unroll
-                    for (int e = 0; e < QW; ++e) {
-                        at[e] += (double)a[u].e[e] * sv;
-                        av[e] += (double)a[u].e[e] * wv;
-                    }
-                }
-            }
-        }
+    for (int u = 0; u < UF; ++u) {
+        const int rr = r0 + u * g.step;
+        const bool ok = rr < rows;
+        const double sv = ok ? ss[rr] : 0.0, wv = ok ? ws[rr] : 0.0;
 #pragma unroll
         for (int e = 0; e < QW; ++e) {
-#pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                if (off >= LPR) {
-                    at[e] += __shfl_xor(at[e], off, 64);
-                    av[e] += __shfl_xor(av[e], off, 64);
-                }
-            }
+            at[e] += (double)a[u].e[e] * sv;
+            av[e] += (double)a[u].e[e] * wv;
         }
-        if (rsub == 0 && act) {
-#pragma unroll
-            for (int e = 0; e < QW; ++e) {
-                cred[wave][q * QW + e] = at[e];
-                cred[wave][32 + q * QW + e] = av[e];
-            }
-        }
-        __syncthreads();
-        // chunks of this round: all of them when there are fewer than waves
-        // (wave cl + p nch holds phase p of chunk cl), else NW of them
-        const int nchr = nch <= NW ? nch : min(NW, nch - k0);
-        const int t = threadIdx.x;
-        if (t < nchr * CW) {
-            const int cl = t / CW, e = t % CW;
-            const int c = (nch <= NW ? cl : k0 + cl) * CW + e;
-            if (c < nc) {
-                double ts = 0.0, vs = 0.0;
-                for (int p = 0; p < P; ++p) {
-                    const int w = cl + p * nch;
-                    ts += cred[w][e];
-                    vs += cred[w][32 + e];
-                }
-                tacc[c] += ts;
-                vacc[c] += vs;
-            }
-        }
-        __syncthreads();
     }
 }
 
@@ -935,6 +1000,26 @@ __device__ __forceinline__ void update_reduce_body(const SysView<V, W>& v, int64
     const int64_t pb = bid * v.geo.cb3;
     const int64_t pe = (pb + v.geo.cb3) < v.nb ? (pb + v.geo.cb3) : v.nb;
     const ProjSplit<V> pg(nc, v.ldac);
+    // With no more projection items than waves each wave keeps the running
+    // sums of its item over all the steps of the range and they are reduced
+    // across lanes and waves once, at the end; otherwise each step's sums
+    // are reduced after that step.
+    // This is done when, besides, a step's rows of A C take at most UF loads
+    // per lane: those loads are then issued together with the step's vector
+    // loads, so that the two latencies overlap instead of following each
+    // other across the step's barrier (a 3x3-block step is 1008 rows: four
+    // loads cover a basis of up to 4 double or 8 single columns; a scalar
+    // step is 512 rows: two loads cover 2 double or 8 single columns).
+    using PS = ProjSplit<V>;
+    constexpr int UF = (B == 3) ? 4 : 2;
+    constexpr int step_rows = (B == 3) ? 2 * 3 * 21 * (T / 64) : T * B;
+    const bool persist = nc > 0 && proj_ahead_fits<V, UF>(step_rows, pg);
+    double pat[PS::QW], pav[PS::QW];
+#pragma unroll
+    for (int e = 0; e < PS::QW; ++e) {
+        pat[e] = 0.0;
+        pav[e] = 0.0;
+    }
     bool tm = false;
     double rr = 0.0, rs = 0.0;
     double a = 0.0, gam = -1.0;
@@ -948,7 +1033,7 @@ __device__ __forceinline__ void update_reduce_body(const SysView<V, W>& v, int64
         // a lane reads the 3 entries of its row of the 3x3 block M^-1
         // (3 i .. 3 i + 2 for unknown i = 3 p + d).  The residual entries
         // of the other rows of the block come from the neighbouring lanes.
-        constexpr int NWV = T / 64, BPW = 21, SUB = 3;
+        constexpr int NWV = T / 64, BPW = 21, SUB = 2;
         constexpr int SB = NWV * BPW * SUB;  // block rows per step
         static_assert(SB * 3 <= T * B, "a step's s and w fit the LDS rows of the projection");
         const int lane = tid & 63, wave = tid >> 6;
@@ -978,6 +1063,8 @@ __device__ __forceinline__ void update_reduce_body(const SysView<V, W>& v, int64
                     for (int e = 0; e < 3; ++e) mv[k][e] = v.minv[3 * i + e];
                 }
             }
+            Vec16<V> ahead[UF];
+            if (persist) proj_ahead_issue<V, UF>(v.AC + ps * 3 * v.ldac, v.ldac, nloc, pg, ahead);
             // the status is tested once the first step's loads are issued
             // (they are in bounds whatever it is), so the latencies overlap
             if (ps == pb) {
@@ -1016,8 +1103,10 @@ __device__ __forceinline__ void update_reduce_body(const SysView<V, W>& v, int64
                 }
             }
             if (nc > 0) {
-                // s and w of the step to LDS for the projection (the previous
-                // step's projection ended with a barrier, so the rows are free)
+                // s and w of the step to LDS for the projection, once every
+                // wave is done with the previous step's rows (a per-step
+                // reduction ends with a barrier)
+                if (persist && ps != pb) __syncthreads();
 #pragma unroll
                 for (int k = 0; k < SUB; ++k)
                     if (act[k]) {
@@ -1025,7 +1114,9 @@ __device__ __forceinline__ void update_reduce_body(const SysView<V, W>& v, int64
                         ws[loc[k]] = wi[k];
                     }
                 __syncthreads();
-                if (SINGLE && v.ldac >= ProjSplit<V>::CW)
+                if (persist)
+                    proj_ahead_acc<V, UF>(ahead, nloc, ss, ws, pat, pav, pg);
+                else if (SINGLE && v.ldac >= ProjSplit<V>::CW)
                     project_rows<V, UR, true>(v.AC + ps * 3 * v.ldac, v.ldac, nloc, nc, ss, ws, tacc, vacc, cred,
                                               pg);
                 else
@@ -1062,6 +1153,10 @@ __device__ __forceinline__ void update_reduce_body(const SysView<V, W>& v, int64
 #pragma unroll
                 for (int e = 0; e < B * B; ++e) mv[e] = v.minv[p * B * B + e];
             }
+            const int64_t pn = (ps + T) < pe ? (ps + T) : pe;
+            const int rows = (int)((pn - ps) * B);
+            Vec16<V> ahead[UF];
+            if (persist) proj_ahead_issue<V, UF>(v.AC + ps * B * v.ldac, v.ldac, rows, pg, ahead);
             // the status is tested once the first step's loads are issued (they
             // are in bounds whatever it is), so the latencies overlap
             if (ps == pb) {
@@ -1105,6 +1200,7 @@ __device__ __forceinline__ void update_reduce_body(const SysView<V, W>& v, int64
             // does not wait for them (the previous step's projection ended with
             // a barrier, so the buffers are free)
             if (nc > 0) {
+                if (persist && ps != pb) __syncthreads();
 #pragma unroll
                 for (int d = 0; d < B; ++d) {
                     ss[tid * B + d] = si[d];
@@ -1124,16 +1220,16 @@ __device__ __forceinline__ void update_reduce_body(const SysView<V, W>& v, int64
                 }
             }
             if (nc > 0) {
-                const int64_t pn = (ps + T) < pe ? (ps + T) : pe;
-                if (SINGLE && v.ldac >= ProjSplit<V>::CW)
-                    project_rows<V, UR, true>(v.AC + ps * B * v.ldac, v.ldac, (int)((pn - ps) * B), nc, ss, ws, tacc,
-                                              vacc, cred, pg);
+                if (persist)
+                    proj_ahead_acc<V, UF>(ahead, rows, ss, ws, pat, pav, pg);
+                else if (SINGLE && v.ldac >= ProjSplit<V>::CW)
+                    project_rows<V, UR, true>(v.AC + ps * B * v.ldac, v.ldac, rows, nc, ss, ws, tacc, vacc, cred, pg);
                 else
-                    project_rows<V, UR, false>(v.AC + ps * B * v.ldac, v.ldac, (int)((pn - ps) * B), nc, ss, ws, tacc,
-                                               vacc, cred, pg);
+                    project_rows<V, UR, false>(v.AC + ps * B * v.ldac, v.ldac, rows, nc, ss, ws, tacc, vacc, cred, pg);
             }
         }
     }
+    if (persist) project_flush<V, false>(pat, pav, 0, nc, tacc, vacc, cred, pg);
     const int stride = 2 * nc + 2;
     double* myp = v.partials + bid * stride;
     double brr = rr, brs = rs;
@@ -1602,15 +1698,18 @@ __global__ __launch_bounds__(256) void kb_spmv_dot(const SysView<V, W>* __restri
     const int2 e = map[blockIdx.x];
     spmv_dot_body<V, W, B>(views[e.x], e.y);
 }
+// (__launch_bounds__' second argument: waves per SIMD, 4 = two workgroups
+// per compute unit within 128 registers; the 3x3-block body needs more and
+// runs one workgroup per compute unit.)
 template <typename V, typename W, int B>
-__global__ __launch_bounds__(kT3, 4) void kb_update_reduce(const SysView<V, W>* __restrict__ views,
+__global__ __launch_bounds__(kT3, B == 3 ? 2 : 4) void kb_update_reduce(const SysView<V, W>* __restrict__ views,
                                                         const int2* __restrict__ map, int mode) {
     __shared__ double pool[upd_pool<B>()];
     const int2 e = map[blockIdx.x];
     update_reduce_body<V, W, B, false, kUrBatch>(views[e.x], e.y, mode, pool);
 }
 template <typename V, typename W, int B>
-__global__ __launch_bounds__(kT3, 4) void kb_update_fused(const SysView<V, W>* __restrict__ views,
+__global__ __launch_bounds__(kT3, B == 3 ? 2 : 4) void kb_update_fused(const SysView<V, W>* __restrict__ views,
                                                        const int2* __restrict__ map, int mode) {
     __shared__ double pool[upd_pool<B>() > fin_pool() ? upd_pool<B>() : fin_pool()];
     const int2 e = map[blockIdx.x];

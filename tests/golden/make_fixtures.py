@@ -4,7 +4,7 @@ Calls only ``oracle`` (and the input generators of ``gen``); nothing here
 comes from the HIP library.  Run from the repository root:
 
     python tests/golden/make_fixtures.py [name ...]
-    python tests/golden/make_fixtures.py --draws name ...   (adds the sequence draws)
+    python tests/golden/make_fixtures.py --draws name [n_perturbed [workers]]
 
 Each fixture is a JSON file with, per system of an SRKS sequence (Algorithm
 3, 3x3 block-Jacobi, FP64, tol 1e-8, with or without full
@@ -140,7 +140,7 @@ def make(name: str) -> None:
         json.dump(out, f, indent=0)
 
 
-def draw(name: str, kind: str) -> dict:
+def draw(name: str, kind: str, seed: int = 0) -> dict:
     """The whole sequence again under another faithful rounding of the same
     arithmetic: every right-hand side perturbed at the rounding level
     (relative 1e-15, seeded per system) or every product accumulated in
@@ -160,7 +160,7 @@ def draw(name: str, kind: str) -> dict:
     for k in range(cfg["systems"]):
         rp, ci, v, b = seq.csr(k)
         if kind == "perturbed":
-            prng = np.random.default_rng(np.random.SeedSequence([13017530, 97, k]))
+            prng = np.random.default_rng(np.random.SeedSequence([13017530, 97, k, seed]))
             b = b * (1.0 + 1e-15 * prng.standard_normal(b.shape))
         res = O.apcg(rp, ci, v, b, "block3", C=C, tol=1e-8, max_iter=cfg["max_iter"], record_z=True,
                      direction="project_old", reorth=ro, extended=(kind == "extended"))
@@ -181,14 +181,28 @@ def draw(name: str, kind: str) -> dict:
         del res
         print(f"{name} draw {kind} system {k}: m={out[-1]['m']} n_c {nc_solve} (+{len(sel)})  "
               f"[{time.perf_counter() - t:.0f} s]", flush=True)
-    return dict(kind=kind, systems=out)
+    return dict(kind=kind, seed=seed, systems=out)
 
 
-def add_draws(name: str) -> None:
+def _draw_task(task):
+    return draw(*task)
+
+
+def add_draws(name: str, n_perturbed: int = 1, workers: int = 1) -> None:
+    """Reruns of the whole sequence: n_perturbed seeds of the perturbed
+    right-hand sides and one with extended-precision accumulation."""
+    tasks = [(name, "perturbed", i) for i in range(n_perturbed)] + [(name, "extended", 0)]
+    if workers > 1:
+        import multiprocessing as mp
+
+        with mp.get_context("fork").Pool(workers) as pool:
+            draws = pool.map(_draw_task, tasks)
+    else:
+        draws = [_draw_task(t) for t in tasks]
     path = os.path.join(HERE, name + ".json")
     with open(path) as f:
         fx = json.load(f)
-    fx["sequence_draws"] = [draw(name, kind) for kind in ("perturbed", "extended")]
+    fx["sequence_draws"] = draws
     with open(path, "w") as f:
         json.dump(fx, f, indent=0)
 
@@ -196,8 +210,8 @@ def add_draws(name: str) -> None:
 if __name__ == "__main__":
     args = sys.argv[1:]
     if args and args[0] == "--draws":
-        for nm in args[1:]:
-            add_draws(nm)
+        # --draws NAME [N_PERTURBED [WORKERS]]
+        add_draws(args[1], int(args[2]) if len(args) > 2 else 1, int(args[3]) if len(args) > 3 else 1)
     else:
         for nm in args or list(FIXTURES):
             make(nm)

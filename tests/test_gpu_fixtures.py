@@ -5,16 +5,20 @@ which calls only the oracle (SRKS, Algorithm 3; direction update in the
 re-projected form w = z + beta P w_old, the library's default, equal to
 Algorithm 1's in exact arithmetic).  Per system, in FP64: the iteration
 count within +-2 of the range of the oracle's counts over faithful
-evaluations of the same solve (sums accumulated in double and in extended
-precision, b perturbed at the rounding level once; stored with the fixture:
-thousands of CG steps amplify rounding, so the accumulation alone moves the
-count by about 1 %: 4882 in double, 4803 in extended precision on the first
-40^3 system), the basis width the solve used and the columns appended
-within the rank guard's and the stagnation threshold's slack (+-2), the
-first CG coefficients of a solve from an empty basis to 1e-9, the true
-residual <= 1e-8, and the span of the recycled basis through its
+evaluations (sums accumulated in double and in extended precision, b
+perturbed at the rounding level, both for the solve from the oracle's basis
+and for whole reruns of the sequence; stored with the fixture: thousands of
+CG steps amplify rounding, so the accumulation alone moves the count by
+about 1 %: 4882 in double, 4803 in extended precision on the first 40^3
+system, and the Ritz vectors such a run leaves differ in turn), the basis
+width the solve used and the columns appended within the same ranges
+(+-2), the first CG coefficients of a solve from an empty basis to 1e-9,
+the true residual <= 1e-8, and the span of the recycled basis through its
 fingerprint (Q^T R)^T (Q^T R) for a seeded probe R and Q an orthonormal
-basis of span(C), which any basis of the same span reproduces.
+basis of span(C), which any basis of the same span reproduces, within
+twice the largest deviation among the oracle's own reruns.  With full
+reorthogonalisation the oracle's counts do not move under these roundings
+and no reruns are needed.
 """
 import json
 import os
@@ -83,26 +87,39 @@ def _run(gpu, fx, max_basis):
 
 def _compare(fx, got):
     nco = fx["n_coef"]
+    draws = [d["systems"] for d in fx.get("sequence_draws", [])]
+    if not draws and not fx["config"].get("reorth", False):
+        pytest.skip(f"fixture {fx['name']} has no sequence draws yet (make_fixtures.py --draws {fx['name']})")
     for k, (g, w) in enumerate(zip(got, fx["systems"])):
         assert g["status"] == 0 and g["res"] <= 1e-8, (k, g["res"])
-        # +-2 around the counts of the oracle's faithful evaluations of the
-        # same solve: double accumulation, extended-precision accumulation,
-        # and b perturbed at the rounding level (long FP64 CG runs move by
-        # about 1 % between them)
-        ms = [w["m"], w["m_extended"], *w["m_perturbed"]]
-        print(f"system {k}: m {g['m']} vs oracle {w['m']} (extended {w['m_extended']}, "
-              f"perturbed {w['m_perturbed']})", flush=True)
+        # +-2 around the oracle's counts over faithful evaluations: the
+        # solve from the oracle's basis in double and extended accumulation
+        # and with b perturbed at the rounding level, and whole sequences
+        # rerun under each rounding (which also select slightly different
+        # Ritz vectors: long FP64 CG runs without reorthogonalisation move
+        # by about 1 % between roundings, and the basis they leave moves the
+        # next system's count further)
+        ms = [w["m"], w["m_extended"], *w["m_perturbed"]] + [d[k]["m"] for d in draws]
+        ncs = [w["nc_solve"]] + [d[k]["nc_solve"] for d in draws]
+        adds = [len(w["selected"])] + [d[k]["added"] for d in draws]
+        print(f"system {k}: m {g['m']} vs oracle {ms}; n_c {g['nc_solve']} vs {ncs}; +{g['added']} vs {adds}",
+              flush=True)
         assert min(ms) - 2 <= g["m"] <= max(ms) + 2, (k, g["m"], ms)
-        assert abs(g["nc_solve"] - w["nc_solve"]) <= 2, (k, g["nc_solve"], w["nc_solve"])
-        assert abs(g["added"] - len(w["selected"])) <= 2, (k, g["added"], len(w["selected"]))
+        assert min(ncs) - 2 <= g["nc_solve"] <= max(ncs) + 2, (k, g["nc_solve"], ncs)
+        assert min(adds) - 2 <= g["added"] <= max(adds) + 2, (k, g["added"], adds)
         if w["nc_solve"] == 0:
             assert np.allclose(g["alpha"][:nco], w["alpha"], rtol=1e-9, atol=0)
             assert np.allclose(g["rho"][:nco], w["rho"], rtol=1e-9, atol=0)
-        F, F0 = g["fp"], np.asarray(w["fingerprint"])
+        # the span of the recycled basis: within twice the largest deviation
+        # of the oracle's own draws from its base run (at least 0.05)
+        F0 = np.asarray(w["fingerprint"])
         scale = max(np.abs(F0).max(), 1.0)
-        dev = np.abs(F - F0).max() / scale
-        print(f"system {k}: span fingerprint deviation {dev:.2e}", flush=True)
-        assert dev <= 0.05, (k, dev)
+        dev = np.abs(g["fp"] - F0).max() / scale
+        dev_d = [np.abs(np.asarray(d[k]["fingerprint"]) - F0).max() / scale for d in draws]
+        bar = max(0.05, 2.0 * max(dev_d, default=0.0))
+        print(f"system {k}: span fingerprint deviation {dev:.2e} (oracle draws {[f'{x:.2e}' for x in dev_d]}, "
+              f"bar {bar:.2e})", flush=True)
+        assert dev <= bar, (k, dev, bar)
 
 
 def test_elasticity40_srks_against_fixture(gpu):
@@ -127,7 +144,10 @@ def test_elasticity40_auto_cap_against_fixture(gpu):
     fx = _fixture("elasticity40_auto_fp64")
     got = _run(gpu, fx, K.NC_LIM_AUTO)
     want = fx["systems"][0]["nc_lim"]
-    lim = got[0]["nc_lim"]
+    # the analysis runs in the recycle after system 0: the solves from
+    # system 1 on report the limit it set
+    assert got[0]["nc_lim"] == -1
+    lim = got[1]["nc_lim"]
     print(f"n_c_lim: library {lim}, oracle {want}", flush=True)
     if lim != want:
         seq = gen.config_elasticity(fx["config"]["E"], 1, fx["config"]["workload_id"])
