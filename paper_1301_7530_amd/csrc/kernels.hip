@@ -1740,13 +1740,10 @@ __global__ __launch_bounds__(256) void kb_correct_dir(const SysView<V, W>* __res
 // before any store: with thousands of small systems the per-workgroup
 // latency, not the bytes, set the time of the general kernel.
 template <typename V, typename W, int NC>
-__global__ __launch_bounds__(256) void kb_correct_dir_few(const SysView<V, W>* __restrict__ views,
-                                                          const int2* __restrict__ map, int first) {
+__device__ __forceinline__ void correct_dir_few_body(const SysView<V, W>& v, int64_t b0, int first) {
     constexpr int G = kDirFewGroup;
     static_assert(NC == 0 || NC == 4, "the general kernel's four waves hold one column each");
     constexpr int NA = NC > 0 ? NC : 1;
-    const int2 e = map[blockIdx.x];
-    const SysView<V, W>& v = views[e.x];
     const DevState* st = v.st;
     if (!gate(st, M_RUN)) return;
     if (first == 2 && st->pending_dir == 0) return;
@@ -1764,7 +1761,6 @@ __global__ __launch_bounds__(256) void kb_correct_dir_few(const SysView<V, W>* _
     const int tid = threadIdx.x;
     const int64_t nblk = (v.n + 255) / 256;
     const int64_t g5 = v.geo.g5;
-    const int64_t b0 = e.y;
     const int nb = (int)((b0 + G) < g5 ? G : g5 - b0);
     for (int u = 0; u < nb; ++u) ktime_begin(v.kslots, 2, b0 + u, tm);
     for (int64_t r0 = 0; r0 + b0 < nblk; r0 += g5) {
@@ -1814,6 +1810,17 @@ __global__ __launch_bounds__(256) void kb_correct_dir_few(const SysView<V, W>* _
         }
     }
     for (int u = 0; u < nb; ++u) ktime_end(v.kslots, 2, b0 + u, tm);
+}
+template <typename V, typename W, int NC>
+__global__ __launch_bounds__(256) void kb_correct_dir_few(const SysView<V, W>* __restrict__ views,
+                                                          const int2* __restrict__ map, int first) {
+    const int2 e = map[blockIdx.x];
+    correct_dir_few_body<V, W, NC>(views[e.x], e.y, first);
+}
+// the same for one system (kDirFewGroup ranges per workgroup)
+template <typename V, typename W, int NC>
+__global__ __launch_bounds__(256) void k_correct_dir_few(SysView<V, W> v, int first) {
+    correct_dir_few_body<V, W, NC>(v, (int64_t)blockIdx.x * kDirFewGroup, first);
 }
 template <typename V, typename W, int B>
 __global__ __launch_bounds__(256) void kb_true_resid(const SysView<V, W>* __restrict__ views,
@@ -2246,6 +2253,14 @@ void launch_update_reduce(const SysView<V, W>& v, int mode, hipStream_t stream) 
 
 template <typename V, typename W>
 void launch_correct_dir(const SysView<V, W>& v, int first, hipStream_t stream) {
+    // up to kDirFewCols columns (and no copy of z for the reorthogonalisation):
+    // the per-row kernel, same products in the same order
+    if (!v.zr && v.nc <= kDirFewCols) {
+        const dim3 grid((unsigned)((v.geo.g5 + kDirFewGroup - 1) / kDirFewGroup));
+        if (v.nc == 0) hipLaunchKernelGGL((k_correct_dir_few<V, W, 0>), grid, dim3(256), 0, stream, v, first);
+        else hipLaunchKernelGGL((k_correct_dir_few<V, W, kDirFewCols>), grid, dim3(256), 0, stream, v, first);
+        return;
+    }
     hipLaunchKernelGGL((k_correct_dir<V, W>), dim3((unsigned)v.geo.g5), dim3(256), 0, stream, v, first);
 }
 

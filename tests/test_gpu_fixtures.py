@@ -4,21 +4,21 @@ The fixtures under tests/golden/ are written by tests/golden/make_fixtures.py,
 which calls only the oracle (SRKS, Algorithm 3; direction update in the
 re-projected form w = z + beta P w_old, the library's default, equal to
 Algorithm 1's in exact arithmetic).  Per system, in FP64: the iteration
-count within +-2 of the range of the oracle's counts over faithful
-evaluations (sums accumulated in double and in extended precision, b
-perturbed at the rounding level, both for the solve from the oracle's basis
-and for whole reruns of the sequence; stored with the fixture: thousands of
-CG steps amplify rounding, so the accumulation alone moves the count by
-about 1 %: 4882 in double, 4803 in extended precision on the first 40^3
-system, and the Ritz vectors such a run leaves differ in turn), the basis
-width the solve used and the columns appended within the same ranges
-(+-2), the first CG coefficients of a solve from an empty basis to 1e-9,
-the true residual <= 1e-8, and the span of the recycled basis through its
+count, the basis width the solve used and the columns appended, each within
+the range of the oracle's values over faithful evaluations widened by 2 and
+by half its width (evaluations: sums accumulated in double and in extended
+precision and b perturbed at the rounding level, both for the solve from
+the oracle's basis and for whole reruns of the sequence, stored with the
+fixture; thousands of CG steps amplify rounding, so the accumulation alone
+moves the count by about 1 %: 4882 in double, 4803 in extended precision on
+the first 40^3 system, and the Ritz vectors such a run leaves differ in
+turn); the first CG coefficients of a solve from an empty basis to 1e-9;
+the true residual <= 1e-8; and the span of the recycled basis through its
 fingerprint (Q^T R)^T (Q^T R) for a seeded probe R and Q an orthonormal
 basis of span(C), which any basis of the same span reproduces, within
 twice the largest deviation among the oracle's own reruns.  With full
 reorthogonalisation the oracle's counts do not move under these roundings
-and no reruns are needed.
+and no reruns are needed (the bar is then +-2).
 """
 import json
 import os
@@ -85,6 +85,19 @@ def _run(gpu, fx, max_basis):
     return out
 
 
+def _within(x, vals):
+    """x within the range of the oracle's faithful evaluations, widened by 2
+    and by half the range's own width: the GPU run is one more such
+    evaluation, and one more draw falls outside the range of k stored ones
+    with probability about 2 / (k + 1), while the widened range holds it
+    with high probability (about 3 standard deviations either side for
+    eight normal draws).  With no spread (full reorthogonalisation) this is
+    +-2."""
+    lo, hi = min(vals), max(vals)
+    pad = 2 + (hi - lo) / 2
+    return lo - pad <= x <= hi + pad
+
+
 def _compare(fx, got):
     nco = fx["n_coef"]
     draws = [d["systems"] for d in fx.get("sequence_draws", [])]
@@ -92,21 +105,21 @@ def _compare(fx, got):
         pytest.skip(f"fixture {fx['name']} has no sequence draws yet (make_fixtures.py --draws {fx['name']})")
     for k, (g, w) in enumerate(zip(got, fx["systems"])):
         assert g["status"] == 0 and g["res"] <= 1e-8, (k, g["res"])
-        # +-2 around the oracle's counts over faithful evaluations: the
-        # solve from the oracle's basis in double and extended accumulation
-        # and with b perturbed at the rounding level, and whole sequences
-        # rerun under each rounding (which also select slightly different
-        # Ritz vectors: long FP64 CG runs without reorthogonalisation move
-        # by about 1 % between roundings, and the basis they leave moves the
+        # the oracle's counts over faithful evaluations: the solve from the
+        # oracle's basis in double and extended accumulation and with b
+        # perturbed at the rounding level, and whole sequences rerun under
+        # each rounding (which also select and keep slightly different Ritz
+        # vectors: long FP64 CG runs without reorthogonalisation move by
+        # about 1 % between roundings, and the basis they leave moves the
         # next system's count further)
         ms = [w["m"], w["m_extended"], *w["m_perturbed"]] + [d[k]["m"] for d in draws]
         ncs = [w["nc_solve"]] + [d[k]["nc_solve"] for d in draws]
         adds = [len(w["selected"])] + [d[k]["added"] for d in draws]
         print(f"system {k}: m {g['m']} vs oracle {ms}; n_c {g['nc_solve']} vs {ncs}; +{g['added']} vs {adds}",
               flush=True)
-        assert min(ms) - 2 <= g["m"] <= max(ms) + 2, (k, g["m"], ms)
-        assert min(ncs) - 2 <= g["nc_solve"] <= max(ncs) + 2, (k, g["nc_solve"], ncs)
-        assert min(adds) - 2 <= g["added"] <= max(adds) + 2, (k, g["added"], adds)
+        assert _within(g["m"], ms), (k, g["m"], ms)
+        assert _within(g["nc_solve"], ncs), (k, g["nc_solve"], ncs)
+        assert _within(g["added"], adds), (k, g["added"], adds)
         if w["nc_solve"] == 0:
             assert np.allclose(g["alpha"][:nco], w["alpha"], rtol=1e-9, atol=0)
             assert np.allclose(g["rho"][:nco], w["rho"], rtol=1e-9, atol=0)
