@@ -54,8 +54,10 @@ WORKLOADS = {
     # (the fused phases let the library's batch autotuner pick the update
     # tile; the one-at-a-time comparison keeps the default tile)
     "batched": dict(kind="batched", size=None, n_systems=10, workload_id=4, max_basis=60, eps=1e-8, cap_policy="cost"),
-    # clients with elasticity sequences (1e4..5e5 dofs) served with continuous batching
-    "serving": dict(kind="serving", size=None, n_systems=50, workload_id=5, max_basis=200, eps=1e-8),
+    # clients with elasticity sequences (1e4..5e5 dofs) served with continuous
+    # batching; each client's basis cap from the complexity analysis of its
+    # first solve (a few columns on these systems, far below 200)
+    "serving": dict(kind="serving", size=None, n_systems=50, workload_id=5, max_basis=-1, eps=1e-8),
     # calibration for hardware byte counters: device-to-device copies of a known size
     "copy": dict(kind="copy", size=None, n_systems=0, workload_id=0, max_basis=0, eps=0.0),
 }
@@ -549,7 +551,7 @@ def run_serving(args, K, torch, data):
     seqs, host = data
     ctx = K.Context(0)
     kw = dict(precision=args.precision, reuse="selective", tol=1e-8, max_iter=args.max_iter,
-              ritz_eps=args.eps or wl["eps"], max_basis=wl["max_basis"], cap_policy="freeze",
+              ritz_eps=args.eps or wl["eps"], max_basis=max_basis(args, wl), cap_policy="freeze",
               history_cap=args.history_cap, refine_drop=args.refine_drop)
     rng = np.random.default_rng(np.random.SeedSequence((13017530, 5, 1 << 21)))
     arrivals = []
@@ -617,7 +619,8 @@ def run_serving(args, K, torch, data):
         "data": "synthetic",
         "config": {"workload": f"serving: {len(seqs)} clients, Q1 elasticity "
                                f"{min(s.n for s in seqs)}..{max(s.n for s in seqs)} dofs, {args.systems} systems "
-                               f"each, Poisson arrivals {args.rate}/s per client, SRKS cap {wl['max_basis']}",
+                               f"each, Poisson arrivals {args.rate}/s per client, SRKS cap "
+                               f"{'auto' if max_basis(args, wl) < 0 else max_basis(args, wl)}",
                    "clients": len(seqs), "sum_n": n_tot, "rate_per_client": args.rate,
                    "hbm_budget_gib": args.hbm_budget, "precision": args.precision},
         "latency_ms": {"p50": cb["p50_ms"], "p99": cb["p99_ms"], "mean": cb["mean_ms"]},
@@ -676,7 +679,7 @@ def run_serving_sweep(args, K, torch):
         plans.append(arr)
     ctx = K.Context(0)
     kw = dict(precision=args.precision, reuse="selective", tol=1e-8, max_iter=args.max_iter,
-              ritz_eps=args.eps or wl["eps"], max_basis=wl["max_basis"], cap_policy="freeze",
+              ritz_eps=args.eps or wl["eps"], max_basis=max_basis(args, wl), cap_policy="freeze",
               history_cap=args.history_cap, refine_drop=args.refine_drop)
     hs = [K.sequence_for(ctx, sq, **kw) for sq in seqs]
     out_rates = []
@@ -741,7 +744,8 @@ def run_serving_sweep(args, K, torch):
         "vs_baseline": None, "dtype": PRECISIONS[args.precision]["dtype"], "data": "synthetic",
         "config": {"workload": f"serving sweep: {len(seqs)} clients, Q1 elasticity {min(s.n for s in seqs)}.."
                                f"{max(s.n for s in seqs)} dofs, up to {wl['n_systems']} systems each, Poisson "
-                               f"arrivals swept over {rates} per client, {args.window:.0f} s windows",
+                               f"arrivals swept over {rates} per client, {args.window:.0f} s windows, SRKS cap "
+                               f"{'auto' if max_basis(args, wl) < 0 else max_basis(args, wl)}",
                    "clients": len(seqs), "hbm_budget_gib": args.hbm_budget, "precision": args.precision},
         "latency_ms": {"p50": top["p50_ms"], "p99": top["p99_ms"]},
         "per_rate": out_rates,
