@@ -266,6 +266,9 @@ void SeqImpl<V, W>::destroy() {
     if (h_coef) (void)hipHostFree(h_coef);
     h_coef = nullptr;
     h_coef_cap = 0;
+    if (h_G) (void)hipHostFree(h_G);
+    h_G = nullptr;
+    h_G_cap = 0;
     for (auto& e : ev)
         if (e) (void)hipEventDestroy(e);
     graph_release();
@@ -275,6 +278,7 @@ void SeqImpl<V, W>::destroy() {
 
 template <typename V, typename W>
 krs_status SeqImpl<V, W>::submit(const double* values, const double* b, bool device) {
+    rb_done = false;  // a new matrix needs its own rebuild
     if (!values || !b) {
         set_error("values and b are required");
         return KRS_E_INVALID;
@@ -472,6 +476,16 @@ void SeqImpl<V, W>::graph_release() {
 // A C (double) for the current basis, and G = C^T A C on the host.
 template <typename V, typename W>
 krs_status SeqImpl<V, W>::coarse_pass(std::vector<double>& G) {
+    krs_status st = coarse_pass_enqueue();
+    if (st != KRS_OK) return st;
+    KRS_HIP(hipStreamSynchronize(stream));
+    coarse_pass_read(G);
+    return KRS_OK;
+}
+
+// The pass's kernels and the read-back of G into pinned memory, enqueued.
+template <typename V, typename W>
+krs_status SeqImpl<V, W>::coarse_pass_enqueue() {
     const size_t nn = (size_t)nc * nc;
     const bool need_v = !std::is_same<V, double>::value;
     ldac = ac_leading_dim(nc, sizeof(V));
@@ -490,16 +504,32 @@ krs_status SeqImpl<V, W>::coarse_pass(std::vector<double>& G) {
     launch_gram<V>((const V*)d_C.p, ldc, (const double*)d_AC64.p, ldac, n, nc, (double*)d_G.p,
                    (double*)d_partials.p + kPart1, (int64_t)(d_partials.bytes / sizeof(double)) - kPart1, stream);
     KRS_CHECK_LAUNCH();
-    G.resize(nn);
-    KRS_HIP(hipMemcpyAsync(G.data(), d_G.p, nn * sizeof(double), hipMemcpyDeviceToHost, stream));
-    KRS_HIP(hipStreamSynchronize(stream));
+    if (h_G_cap < nn) {
+        if (h_G) (void)hipHostFree(h_G);
+        h_G = nullptr;
+        h_G_cap = 0;
+        if (hipHostMalloc((void**)&h_G, nn * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+            h_G = nullptr;
+            set_error("pinned host allocation failed for C^T A C");
+            return KRS_E_OOM;
+        }
+        h_G_cap = nn;
+    }
+    KRS_HIP(hipMemcpyAsync(h_G, d_G.p, nn * sizeof(double), hipMemcpyDeviceToHost, stream));
+    return KRS_OK;
+}
+
+// G from the pinned read-back (after a wait), symmetrised.
+template <typename V, typename W>
+void SeqImpl<V, W>::coarse_pass_read(std::vector<double>& G) const {
+    const size_t nn = (size_t)nc * nc;
+    G.assign(h_G, h_G + nn);
     for (int a = 0; a < nc; ++a)
         for (int b = a + 1; b < nc; ++b) {
             const double s = 0.5 * (G[(size_t)a * nc + b] + G[(size_t)b * nc + a]);
             G[(size_t)a * nc + b] = s;
             G[(size_t)b * nc + a] = s;
         }
-    return KRS_OK;
 }
 
 // Rebuild of the coarse space for A^(k) (Algorithm 1, first step):
@@ -566,6 +596,115 @@ krs_status SeqImpl<V, W>::rebuild(int* dropped) {
         KRS_CHECK_LAUNCH();
         KRS_HIP(hipStreamSynchronize(stream));
         nc = nk;
+    }
+    set_error("coarse space did not stabilise under the rank guard");
+    return KRS_E_COARSE_SINGULAR;
+}
+
+// The same steps as rebuild(), split at its waits so that a batch waits once
+// per stage for all its members (each pass is the same kernels and host
+// arithmetic, so the result is the same as rebuild()'s).
+template <typename V, typename W>
+krs_status SeqImpl<V, W>::rebuild_stage(int stage, bool* more) {
+    *more = false;
+    if (stage == 0) {
+        rb_done = false;
+        rb_dropped = 0;
+        if (!submitted || nc > 1024) return KRS_OK;  // begin_solve reports these
+        // the start of the rebuild phase, which begin_solve leaves out when staged
+        for (auto& e : ev)
+            if (!e) KRS_HIP(hipEventCreate(&e));
+        KRS_HIP(hipEventRecord(ev[0], stream));
+        if (nc == 0) {
+            rb_done = true;
+            return KRS_OK;
+        }
+        krs_status st = coarse_pass_enqueue();
+        *more = st == KRS_OK;
+        return st;
+    }
+    std::vector<double> G;
+    coarse_pass_read(G);
+    if (stage == 1) {
+        // the carried basis made A^(k)-orthonormal, then the second pass
+        rb_up.assign((size_t)nc * nc, 0.0);
+        std::vector<uint8_t> kept(nc, 1);
+        const int nk = coarse_orthonormalizer(nc, G.data(), desc.rank_tol, rb_up.data(), kept.data());
+        rb_dropped += nc - nk;
+        if (nk == 0) {
+            nc = 0;
+            rb_done = true;
+            return KRS_OK;
+        }
+        if (!d_F.reserve(ctx, (size_t)nc * nk * sizeof(double)) ||
+            !d_Ctmp.reserve(ctx, (size_t)ldc * nk * sizeof(V))) {
+            set_error("device allocation failed for the basis change");
+            return KRS_E_OOM;
+        }
+        KRS_HIP(hipMemcpyAsync(d_F.p, rb_up.data(), (size_t)nc * nk * sizeof(double), hipMemcpyHostToDevice, stream));
+        launch_basis_combine<V>((const V*)d_C.p, ldc, nc, (const double*)d_F.p, nk, (V*)d_Ctmp.p, ldc, n, stream);
+        KRS_CHECK_LAUNCH();
+        KRS_HIP(hipMemcpyAsync(d_C.p, d_Ctmp.p, (size_t)ldc * nk * sizeof(V), hipMemcpyDeviceToDevice, stream));
+        nc = nk;
+        krs_status st = coarse_pass_enqueue();
+        *more = st == KRS_OK;
+        return st;
+    }
+    // stage 2: G^-1, or (a column vanished after the change of basis) the
+    // remaining passes of rebuild() on this member alone
+    const size_t nn = (size_t)nc * nc;
+    rb_up.assign(nn, 0.0);
+    std::vector<uint8_t> kept(nc, 1);
+    const int nk = coarse_factor(nc, G.data(), desc.rank_tol, rb_up.data(), kept.data());
+    if (nk == nc) {
+        KRS_HIP(hipMemcpyAsync(d_Ginv.p, rb_up.data(), nn * sizeof(double), hipMemcpyHostToDevice, stream));
+        rb_done = true;
+        return KRS_OK;
+    }
+    rb_dropped += nc - nk;
+    if (nk == 0) {
+        nc = 0;
+        rb_done = true;
+        return KRS_OK;
+    }
+    std::vector<int32_t> keep_map;
+    for (int c = 0; c < nc; ++c)
+        if (kept[c]) keep_map.push_back(c);
+    if (!d_tmp.reserve(ctx, std::max<size_t>(keep_map.size() * sizeof(int32_t), 64))) return KRS_E_OOM;
+    KRS_HIP(hipMemcpyAsync(d_tmp.p, keep_map.data(), keep_map.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                           stream));
+    launch_copy_columns<V>((const V*)d_C.p, ldc, (V*)d_C.p, ldc, n, (const int32_t*)d_tmp.p, nk, stream);
+    KRS_CHECK_LAUNCH();
+    KRS_HIP(hipStreamSynchronize(stream));
+    nc = nk;
+    for (int pass = 1; pass < 3; ++pass) {
+        krs_status st = coarse_pass(G);
+        if (st != KRS_OK) return st;
+        const size_t m2 = (size_t)nc * nc;
+        std::vector<double> Gi(m2);
+        std::vector<uint8_t> kp(nc, 1);
+        const int nk2 = coarse_factor(nc, G.data(), desc.rank_tol, Gi.data(), kp.data());
+        if (nk2 == nc) {
+            KRS_HIP(hipMemcpyAsync(d_Ginv.p, Gi.data(), m2 * sizeof(double), hipMemcpyHostToDevice, stream));
+            KRS_HIP(hipStreamSynchronize(stream));
+            rb_done = true;
+            return KRS_OK;
+        }
+        rb_dropped += nc - nk2;
+        if (nk2 == 0) {
+            nc = 0;
+            rb_done = true;
+            return KRS_OK;
+        }
+        std::vector<int32_t> km;
+        for (int c = 0; c < nc; ++c)
+            if (kp[c]) km.push_back(c);
+        if (!d_tmp.reserve(ctx, std::max<size_t>(km.size() * sizeof(int32_t), 64))) return KRS_E_OOM;
+        KRS_HIP(hipMemcpyAsync(d_tmp.p, km.data(), km.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+        launch_copy_columns<V>((const V*)d_C.p, ldc, (V*)d_C.p, ldc, n, (const int32_t*)d_tmp.p, nk2, stream);
+        KRS_CHECK_LAUNCH();
+        KRS_HIP(hipStreamSynchronize(stream));
+        nc = nk2;
     }
     set_error("coarse space did not stabilise under the rank guard");
     return KRS_E_COARSE_SINGULAR;
@@ -690,6 +829,9 @@ krs_status SeqImpl<V, W>::set_update_rows(int64_t rows) {
 
 template <typename V, typename W>
 krs_status SeqImpl<V, W>::begin_solve() {
+    // a staged rebuild counts for this begin only
+    const bool staged = rb_done;
+    rb_done = false;
     if (!submitted) {
         set_error("krs_seq_solve needs a submitted system");
         return KRS_E_STATE;
@@ -701,10 +843,16 @@ krs_status SeqImpl<V, W>::begin_solve() {
     solved = false;
     for (auto& e : ev)
         if (!e) KRS_HIP(hipEventCreate(&e));
-    KRS_HIP(hipEventRecord(ev[0], stream));
     int dropped = 0;
-    krs_status st = rebuild(&dropped);
-    if (st != KRS_OK) return st;
+    krs_status st = KRS_OK;
+    if (staged) {
+        // rebuilt in stages by the batch (ev[0] recorded at its first stage)
+        dropped = rb_dropped;
+    } else {
+        KRS_HIP(hipEventRecord(ev[0], stream));
+        st = rebuild(&dropped);
+        if (st != KRS_OK) return st;
+    }
     dropped_last = dropped;
     // histories
     const int max_iter = std::max(0, desc.max_iter);
@@ -1515,9 +1663,38 @@ krs_status batch_solve(krs_ctx* ctx, SeqBase* const* seqs, int count, double* co
             fn();  // no helper thread: plan here
         }
     };
+    // the members' coarse rebuilds in stages, one wait per stage for all
+    {
+        std::vector<char> more(count, 0);
+        bool any = false;
+        for (int i = 0; i < count; ++i) {
+            bool m = false;
+            out[i] = seqs[i]->rebuild_stage(0, &m);
+            more[i] = m;
+            any = any || m;
+        }
+        for (int stage = 1; stage <= 2 && any; ++stage) {
+            if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
+                set_error("device failure during the batched coarse rebuild");
+                return KRS_E_DEVICE;
+            }
+            any = false;
+            for (int i = 0; i < count; ++i) {
+                if (!more[i] || out[i] != KRS_OK) continue;
+                bool m = false;
+                out[i] = seqs[i]->rebuild_stage(stage, &m);
+                more[i] = m;
+                any = any || m;
+            }
+        }
+    }
     // begin every member; group the begun ones by type
     std::map<int, std::vector<int>> groups;
     for (int i = 0; i < count; ++i) {
+        if (out[i] != KRS_OK) {
+            ended[i] = 1;
+            continue;
+        }
         out[i] = seqs[i]->begin_solve();
         if (out[i] == KRS_OK) groups[seqs[i]->type_key()].push_back(i);
         else ended[i] = 1;

@@ -51,6 +51,13 @@ struct SeqBase {
     // solve() = begin_solve() + iterate() + end_solve(); a batch runs the
     // iterations of several begun systems in fused launches instead
     virtual krs_status begin_solve() = 0;
+    // The coarse rebuild of begin_solve in stages, for a batch whose members
+    // share one stream: stage 0 enqueues the first A C / Gram pass, stage 1
+    // (after the caller's wait) orthonormalises and enqueues the second,
+    // stage 2 factors and uploads G^-1 (or, if a column vanished, finishes
+    // the rebuild on its own).  *more: whether the member needs the next
+    // stage after a wait.  begin_solve then skips the rebuild.
+    virtual krs_status rebuild_stage(int stage, bool* more) = 0;
     // iter_hint: the solve's final iteration count when the caller has read
     // it from the device status (lets the coefficient read-back start
     // before the wait), or -1
@@ -201,7 +208,15 @@ struct SeqImpl : SeqBase {
     bool ensure_c_capacity(int cols);
     bool ensure_partials(int64_t extra);
     krs_status rebuild(int* dropped);
+    krs_status rebuild_stage(int stage, bool* more) override;
     krs_status coarse_pass(std::vector<double>& G);
+    krs_status coarse_pass_enqueue();
+    void coarse_pass_read(std::vector<double>& G) const;
+    bool rb_done = false;         // the staged rebuild has run for the submitted system
+    int rb_dropped = 0;
+    std::vector<double> rb_up;    // host source of the stage's upload (kept until the next wait)
+    double* h_G = nullptr;        // pinned read-back of C^T A C
+    size_t h_G_cap = 0;
     void k_spmv(const SysView<V, W>& v);
     void k_update(const SysView<V, W>& v, int mode);
     void k_resid(const SysView<V, W>& v, int final_only);
