@@ -248,6 +248,24 @@ def profile_traffic(name):
     return int(vals["traffic_bytes_per_launch"])
 
 
+def device_copy_rate(torch, nbytes=1 << 30, reps=10):
+    """A device-to-device copy of nbytes (read + write bytes over the time),
+    the practical streaming ceiling of the same GPU, for context beside the
+    8 TB/s peak."""
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
 def run_newton_workload(args, K, torch, wl):
     """Secant loop of a damaging cube (gen.NewtonSequence): system k+1 is
     assembled on the host from the strains of solution k, so inputs cannot
@@ -478,6 +496,7 @@ def run_sequence_workload(args, K, torch, wl):
                                     refinements=ci[i]["refinements"])
                                for i in range(len(cmp_ks))],
             })
+    out["device_copy_GBps"] = round(device_copy_rate(torch), 1)
     if args.cpu_baseline:
         _log("CPU baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline(seq, host, 0, float(np.mean(iters)), out["n_c_mean"], args.cpu_iters,
