@@ -338,3 +338,46 @@ def test_batched_full_size_sampled(gpu):
                 assert np.linalg.norm(b - O.spmv(rp, ci, v, xb)) / np.linalg.norm(b) <= 1e-8
         finally:
             s.close()
+
+
+def test_batch_staged_rebuild_with_dependent_columns(gpu):
+    """The members' coarse rebuilds run in stages across the batch (one wait
+    per stage); members whose initial basis C0 carries duplicated and zero
+    columns have them dropped by the rank guard as when solved alone, next
+    to members without a basis, and every result equals its solve alone bit
+    for bit."""
+    K = _K()
+    seqs = _sequences(1)
+    rng = np.random.default_rng(7)
+    C0s = []
+    for i, sq in enumerate(seqs):
+        if i % 2:
+            C0s.append(None)
+            continue
+        c = rng.standard_normal((sq.n, 3))
+        C0s.append(np.column_stack([c, 2.0 * c[:, :1], np.zeros(sq.n), c[:, 1:2] + c[:, 2:3]]))
+    kw = dict(precision="fp64", reuse="none", tol=1e-8, max_iter=3000)
+    alone = []
+    for sq, C0 in zip(seqs, C0s):
+        s = K.sequence_for(gpu, sq, C0=C0, **kw)
+        try:
+            s.submit(*sq.system(0))
+            x, info = s.solve()
+            alone.append((x, info))
+        finally:
+            s.close()
+    hs = [K.sequence_for(gpu, sq, C0=C0, **kw) for sq, C0 in zip(seqs, C0s)]
+    try:
+        for h, sq in zip(hs, seqs):
+            h.submit(*sq.system(0))
+        xs, infos = gpu.batch_solve(hs)
+    finally:
+        for h in hs:
+            h.close()
+    for i, ((xa, ia), xb, ib) in enumerate(zip(alone, xs, infos)):
+        want_nc, want_drop = (0, 0) if C0s[i] is None else (3, 3)
+        assert ia["status"] == ib["status"] == 0
+        assert (ia["n_c"], ia["dropped"]) == (ib["n_c"], ib["dropped"]) == (want_nc, want_drop), i
+        assert ia["iters"] == ib["iters"]
+        assert np.array_equal(xa, xb)
+        assert _relres(seqs[i].csr(0), xb) <= 1e-8
