@@ -351,9 +351,14 @@ def run_sequence_workload(args, K, torch, wl):
     t = time.perf_counter()
     host = gen_systems(seq, need)
     _log(f"generated in {time.perf_counter() - t:.1f} s")
-    dev_sys = {k: (torch.from_numpy(host[k][0]).to("cuda"), torch.from_numpy(host[k][1]).to("cuda")) for k in need}
-    if not args.cpu_baseline:
-        host = {}
+    if args.host_inputs:
+        # the systems handed over from host memory (copied over PCIe by each submit)
+        dev_sys = {k: (np.ascontiguousarray(host[k][0]), np.ascontiguousarray(host[k][1])) for k in need}
+    else:
+        dev_sys = {k: (torch.from_numpy(host[k][0]).to("cuda"), torch.from_numpy(host[k][1]).to("cuda"))
+                   for k in need}
+        if not args.cpu_baseline:
+            host = {}
     torch.cuda.synchronize()
     ctx = K.Context(0)
     if warm:
@@ -429,6 +434,7 @@ def run_sequence_workload(args, K, torch, wl):
             "n": seq.n,
             "nnz": seq.nnzb * seq.block * seq.block,
             "systems_timed": f"0..{args.steps - 1} of one sequence, in order, from an empty basis",
+            "inputs": "host memory, copied by each submit" if args.host_inputs else "resident in HBM",
             "warmup": f"systems 0..{args.warmup - 1} on a separate sequence handle, discarded",
             "reuse": f"SRKS eps={args.eps if args.eps else wl['eps']:.0e}" if wl["max_basis"] else "TRKS",
             "max_basis": cap if cap >= 0 else f"auto (complexity analysis): {infos[-1]['n_c_lim']}",
@@ -896,6 +902,9 @@ def main():
     ap.add_argument("--max-iter", type=int, default=30000)
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--no-plain", dest="plain", action="store_false")
+    ap.add_argument("--host-inputs", action="store_true",
+                    help="sequence workloads: submit every system from host memory (the PCIe-inclusive rate); "
+                         "by default the inputs are resident in HBM before the timed region")
     ap.add_argument("--no-sequential", dest="sequential", action="store_false",
                     help="batched workload: skip the one-sequence-at-a-time comparison")
     ap.add_argument("--plain-systems", type=int, default=3, help="plain PCG on the first systems of the sequence")
