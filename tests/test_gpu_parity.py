@@ -144,17 +144,40 @@ def test_srks_elasticity_sequence_fp64(gpu):
         s.close()
 
 
+class _PerturbedRhs:
+    """The same sequence with every right-hand side perturbed at the
+    rounding level (relative 1e-15, seeded): another faithful evaluation."""
+
+    def __init__(self, seq, seed):
+        self.seq, self.seed = seq, seed
+        self.n, self.block, self.n_systems = seq.n, seq.block, seq.n_systems
+
+    def csr(self, k):
+        rp, ci, v, b = self.seq.csr(k)
+        rng = np.random.default_rng(np.random.SeedSequence([13017530, 96, self.seed, k]))
+        return rp, ci, v, b * (1.0 + 1e-15 * rng.standard_normal(b.shape))
+
+
 def test_srks_sequence_drift_bounded(gpu):
-    """Whole sequence run independently on both sides: borderline Ritz
-    selections may flip and compound, so only a loose bound is asserted."""
+    """Whole sequence run independently on both sides: the library's counts
+    lie in the range of the oracle's own sequences under faithful
+    evaluations (both direction forms, right-hand sides perturbed at the
+    rounding level), widened by 2 and half its width, as for the fixtures:
+    Ritz values at the stagnation threshold (Section 4.1) may be selected on
+    one side and not the other, and the difference compounds."""
     seq = gen.config_elasticity(6, 4)
-    recs, _ = O.solve_sequence(seq, 4, reuse="srks", eps=1e-10, cap=24, cap_policy="freeze", tol=1e-8,
-                               max_iter=4000)
+    kw = dict(reuse="srks", eps=1e-10, cap=24, cap_policy="freeze", tol=1e-8, max_iter=4000)
+    runs = [O.solve_sequence(seq, 4, **kw)[0], O.solve_sequence(seq, 4, direction="project_old", **kw)[0]]
+    runs += [O.solve_sequence(_PerturbedRhs(seq, i), 4, direction="project_old", **kw)[0] for i in range(3)]
     res = _run_gpu(gpu, seq, 4, precision="fp64", reuse="selective", ritz_eps=1e-10, max_basis=24,
                    cap_policy="freeze", tol=1e-8, max_iter=4000)
     for k in range(4):
         assert res[k]["status"] == 0 and _relres(seq.csr(k), res[k]["x"]) <= 1e-8
-        assert abs(res[k]["iters"] - recs[k]["m"]) <= max(2, 0.1 * recs[k]["m"]), (k, res[k]["iters"], recs[k]["m"])
+        ms = [r[k]["m"] for r in runs]
+        lo, hi = min(ms), max(ms)
+        pad = 2 + (hi - lo) / 2
+        print(f"system {k}: library {res[k]['iters']}, oracle evaluations {ms}", flush=True)
+        assert lo - pad <= res[k]["iters"] <= hi + pad, (k, res[k]["iters"], ms)
 
 
 def _dense(csr):
