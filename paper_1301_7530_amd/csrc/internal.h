@@ -109,6 +109,7 @@ template <typename V, typename W>
 struct SysView {
     // sliced-ELL matrix (block size B known at compile time)
     const int32_t* col;        // [slots*64] block column per entry
+    const int16_t* col16;      // the same as (column - own block row) when every difference fits 16 bits, or null
     const int64_t* slice_ptr;  // [nslices+1] slot offsets
     const V* val;              // values in V precision (planar per slot)
     int32_t op64;              // 1: the SpMV streams val64 (double-precision operator)

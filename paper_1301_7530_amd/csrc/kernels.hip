@@ -401,9 +401,12 @@ __device__ __forceinline__ T ld_stream(const T* p) {
     return *p;
 }
 
-template <typename V, typename X, int UNR = 2, bool NT = false>
+// C16: the block columns come from col16 as differences from `base` (the
+// lane's block row, clamped to the last one), two bytes each.
+template <typename V, typename X, int UNR = 2, bool NT = false, bool C16 = false>
 __device__ __forceinline__ void ell_row3all(const V* __restrict__ val, const int32_t* __restrict__ col,
-                                            const X* __restrict__ x, int64_t k0, int64_t k1, int lane, X out[3]) {
+                                            const X* __restrict__ x, int64_t k0, int64_t k1, int lane, X out[3],
+                                            const int16_t* __restrict__ col16 = nullptr, int64_t base = 0) {
     X a0 = 0, a1 = 0, a2 = 0;
     int64_t k = k0;
     for (; k + UNR <= k1; k += UNR) {
@@ -411,7 +414,8 @@ __device__ __forceinline__ void ell_row3all(const V* __restrict__ val, const int
         V a[UNR][9];
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
-            cc[u] = ld_stream<int32_t, NT>(col + (k + u) * 64 + lane);
+            if (C16) cc[u] = (int32_t)(base + ld_stream<int16_t, NT>(col16 + (k + u) * 64 + lane));
+            else cc[u] = ld_stream<int32_t, NT>(col + (k + u) * 64 + lane);
             const V* vb = val + (k + u) * 9 * 64 + lane;
 #pragma unroll
             for (int e = 0; e < 9; ++e) a[u][e] = ld_stream<V, NT>(vb + e * 64);
@@ -432,7 +436,7 @@ __device__ __forceinline__ void ell_row3all(const V* __restrict__ val, const int
         }
     }
     for (; k < k1; ++k) {
-        const int64_t c = 3 * (int64_t)col[k * 64 + lane];
+        const int64_t c = 3 * (C16 ? base + (int64_t)col16[k * 64 + lane] : (int64_t)col[k * 64 + lane]);
         const V* vb = val + k * 9 * 64 + lane;
         const X x0 = x[c], x1 = x[c + 1], x2 = x[c + 2];
         a0 += (X)vb[0] * x0 + (X)vb[64] * x1 + (X)vb[128] * x2;
@@ -450,7 +454,8 @@ __device__ __forceinline__ void ell_row3all(const V* __restrict__ val, const int
 // of the next kernel (a fixed-order sum, so all agree).
 // VAR: the load schedule fixed at compile time (the single-system kernel,
 // one instantiation per schedule, so the registers are those of the one in
-// use), or -1 to take v.spmv_var at run time (the batch kernel).
+// use; 4 and 6 are schedules 0 and 2 with 16-bit relative block columns),
+// or -1 to take v.spmv_var at run time (the batch kernel).
 template <typename V, typename W, int B, int VAR = -1>
 __device__ __forceinline__ void spmv_dot_body(const SysView<V, W>& v, int64_t bid) {
     if (!gate(v.st, M_RUN)) return;
@@ -478,7 +483,13 @@ __device__ __forceinline__ void spmv_dot_body(const SysView<V, W>& v, int64_t bi
         for (int64_t sl = bid * 2 + wave; sl < v.nslices; sl += nblk * 2) {
             const int64_t k0 = v.slice_ptr[sl], k1 = v.slice_ptr[sl + 1];
             W acc[3];
-            if (std::is_same<V, double>::value || v.op64) {
+            const int64_t prow = sl * 64 + lane;
+            const int64_t base = prow < v.nb ? prow : v.nb - 1;
+            if (VAR == 4) {
+                ell_row3all<double, W, 2, false, true>(v.val64, v.col, v.w, k0, k1, lane, acc, v.col16, base);
+            } else if (VAR == 6) {
+                ell_row3all<double, W, 2, true, true>(v.val64, v.col, v.w, k0, k1, lane, acc, v.col16, base);
+            } else if (std::is_same<V, double>::value || v.op64) {
                 // (a double-precision basis always has the double-precision operator)
                 if ((var & 3) == 0) ell_row3all<double, W, 2, false>(v.val64, v.col, v.w, k0, k1, lane, acc);
                 else if ((var & 3) == 1) ell_row3all<double, W, 4, false>(v.val64, v.col, v.w, k0, k1, lane, acc);
@@ -2228,7 +2239,11 @@ template <typename V, typename W, int B>
 void launch_spmv_dot(const SysView<V, W>& v, hipStream_t stream) {
     const int threads = (B == 1) ? 256 : 128;
     const dim3 grid((unsigned)v.geo.g1);
-    switch ((B == 3 && v.op64) ? (v.spmv_var & 3) : 0) {
+    // 16-bit relative block columns (set with the default load schedule, 0 or 2)
+    const int c16 = (B == 3 && v.op64 && v.col16 && (v.spmv_var & 1) == 0) ? 4 : 0;
+    switch ((B == 3 && v.op64) ? (v.spmv_var & 3) | c16 : 0) {
+        case 4: hipLaunchKernelGGL((k_spmv_dot<V, W, B, 4>), grid, dim3(threads), 0, stream, v); break;
+        case 6: hipLaunchKernelGGL((k_spmv_dot<V, W, B, 6>), grid, dim3(threads), 0, stream, v); break;
         case 1: hipLaunchKernelGGL((k_spmv_dot<V, W, B, 1>), grid, dim3(threads), 0, stream, v); break;
         case 2: hipLaunchKernelGGL((k_spmv_dot<V, W, B, 2>), grid, dim3(threads), 0, stream, v); break;
         case 3: hipLaunchKernelGGL((k_spmv_dot<V, W, B, 3>), grid, dim3(threads), 0, stream, v); break;

@@ -118,6 +118,7 @@ struct SeqImpl : SeqBase {
     int coef_cap = 0;
     int trks_slots = 0;
     bool submitted = false, solved = false;
+    Buf d_col16;  // 16-bit relative block columns for the double-precision 3x3 SpMV, when they fit
     Buf d_col, d_slice_ptr, d_map, d_diag, d_val64, d_valV, d_minv, d_bad, d_in, d_b, d_x, d_r, d_s, d_w, d_q;
     Buf d_C, d_C0, d_AC64, d_ACv, d_G, d_Ginv, d_mu, d_Z, d_coef, d_partials, d_st, d_F, d_tmp, d_Ctmp, d_kslots;
     // full reorthogonalisation (kernel_flags bit 2): kept directions, their

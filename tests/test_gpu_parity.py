@@ -276,3 +276,22 @@ def test_fp32_vectors_mode_converges(gpu):
     for k in range(2):
         assert res[k]["status"] == 0
         assert _relres(seq.csr(k), res[k]["x"]) <= 1e-8 * 1.05
+
+
+@pytest.mark.parametrize("E,variant", [(16, 12), (100, 2)])
+def test_spmv_16bit_columns_same_bits(gpu, E, variant):
+    """With the default load schedule the double-precision 3x3 SpMV reads the
+    block columns as 16-bit differences from the lane's block row; an
+    explicit schedule (kernel_flags bits 3-6: the same workgroup count and
+    loads) reads the 32-bit columns.  Same columns, same sums: the CG
+    coefficients and the iterate agree bit for bit over 300 iterations (at
+    16^3 and at 100^3, where the default streams the matrix with
+    non-temporal loads)."""
+    seq = gen.config_elasticity(E, 1, 3)
+    kw = dict(precision="fp64", reuse="none", tol=1e-30, max_iter=300)
+    a = _run_gpu(gpu, seq, 1, **kw)[0]
+    b = _run_gpu(gpu, seq, 1, spmv_variant=variant, **kw)[0]
+    assert a["iters"] == b["iters"] == 300
+    assert np.array_equal(a["alpha"][:300], b["alpha"][:300])
+    assert np.array_equal(a["rho"][:300], b["rho"][:300])
+    assert np.array_equal(a["x"], b["x"])
