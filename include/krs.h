@@ -156,7 +156,7 @@ typedef struct {
                               of Section 5.1): each new direction is z made A-orthogonal to every kept
                               earlier direction, w = z - sum_i ((A w_i, z) / (w_i, A w_i)) w_i (classical
                               Gram-Schmidt in the A inner product); the first min(history_cap or max_iter,
-                              4096) directions and their products with A are kept (2 n doubles each).
+                              8192) directions and their products with A are kept (2 n doubles each).
                               KRS_FP64 only; not in fused batches or the server (KRS_E_INVALID).
                               bits 3-6: load schedule of the double-precision block SpMV (same results up
                               to the grouping of the (w, A w) partial sums): bit 3 four blocks of a row in

@@ -168,7 +168,7 @@ struct SysView {
     W* zr;            // z of the current step, written by the direction update
 };
 // largest number of directions a reorthogonalised solve keeps
-constexpr int kReorthMax = 4096;
+constexpr int kReorthMax = 8192;
 
 // Launch maps of a fused batch: map[k][i] = (system, workgroup) of launch
 // k's workgroup i; count[k] = total workgroups.

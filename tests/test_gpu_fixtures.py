@@ -210,3 +210,11 @@ def test_elasticity24_reorth_against_fixture(gpu):
     eps = 1e-14."""
     fx = _fixture("elasticity24_reorth_fp64")
     _compare(fx, _run(gpu, fx, fx["config"]["cap"]))
+
+
+def test_elasticity40_reorth_against_fixture(gpu):
+    """The 40^3 workload's first system with full reorthogonalisation at the
+    paper's eps = 1e-14 (the setting of Section 5.1): iterations +-2, the
+    first coefficients, and the span of the 60 recycled Ritz vectors."""
+    fx = _fixture("elasticity40_reorth_fp64")
+    _compare(fx, _run(gpu, fx, fx["config"]["cap"]))
