@@ -569,72 +569,29 @@ void SeqImpl<V, W>::coarse_pass_read(std::vector<double>& G) const {
 //     projector P and x0 depend on span(C) only, so the iteration is the
 //     same; the coarse matrix becomes ~I, which keeps the single-precision
 //     projector accurate;
-//  3. A C and G again for the new basis, G^{-1} for the iterations.
+//  3. A C and G again for the new basis, G^-1 for the iterations.
+// The stages of rebuild_stage with a wait after each: a batch runs the same
+// stages for all its members with one wait per stage.
 template <typename V, typename W>
 krs_status SeqImpl<V, W>::rebuild(int* dropped) {
     *dropped = 0;
-    if (nc == 0) return KRS_OK;
-    std::vector<double> G;
-    // source of an asynchronous upload: lives until the next pass has waited
-    std::vector<double> U;
-    krs_status st = coarse_pass(G);
-    if (st != KRS_OK) return st;
-    {
-        U.assign((size_t)nc * nc, 0.0);
-        std::vector<uint8_t> kept(nc, 1);
-        const int nk = coarse_orthonormalizer(nc, G.data(), desc.rank_tol, U.data(), kept.data());
-        *dropped += nc - nk;
-        if (nk == 0) {
-            nc = 0;
-            return KRS_OK;
-        }
-        if (!d_F.reserve(ctx, (size_t)nc * nk * sizeof(double)) ||
-            !d_Ctmp.reserve(ctx, (size_t)ldc * nk * sizeof(V))) {
-            set_error("device allocation failed for the basis change");
-            return KRS_E_OOM;
-        }
-        KRS_HIP(hipMemcpyAsync(d_F.p, U.data(), (size_t)nc * nk * sizeof(double), hipMemcpyHostToDevice, stream));
-        launch_basis_combine<V>((const V*)d_C.p, ldc, nc, (const double*)d_F.p, nk, (V*)d_Ctmp.p, ldc, n, stream);
-        KRS_CHECK_LAUNCH();
-        KRS_HIP(hipMemcpyAsync(d_C.p, d_Ctmp.p, (size_t)ldc * nk * sizeof(V), hipMemcpyDeviceToDevice, stream));
-        nc = nk;
-    }
-    for (int pass = 0; pass < 3; ++pass) {
-        st = coarse_pass(G);
-        if (st != KRS_OK) return st;
-        const size_t nn = (size_t)nc * nc;
-        std::vector<double> Gi(nn);
-        std::vector<uint8_t> kept(nc, 1);
-        const int nk = coarse_factor(nc, G.data(), desc.rank_tol, Gi.data(), kept.data());
-        if (nk == nc) {
-            KRS_HIP(hipMemcpyAsync(d_Ginv.p, Gi.data(), nn * sizeof(double), hipMemcpyHostToDevice, stream));
-            KRS_HIP(hipStreamSynchronize(stream));
-            return KRS_OK;
-        }
-        // a column vanished after the change of basis: compact and redo
-        *dropped += nc - nk;
-        if (nk == 0) {
-            nc = 0;
-            return KRS_OK;
-        }
-        std::vector<int32_t> keep_map;
-        for (int c = 0; c < nc; ++c)
-            if (kept[c]) keep_map.push_back(c);
-        if (!d_tmp.reserve(ctx, std::max<size_t>(keep_map.size() * sizeof(int32_t), 64))) return KRS_E_OOM;
-        KRS_HIP(hipMemcpyAsync(d_tmp.p, keep_map.data(), keep_map.size() * sizeof(int32_t), hipMemcpyHostToDevice,
-                               stream));
-        launch_copy_columns<V>((const V*)d_C.p, ldc, (V*)d_C.p, ldc, n, (const int32_t*)d_tmp.p, nk, stream);
-        KRS_CHECK_LAUNCH();
+    bool more = false;
+    krs_status st = rebuild_stage(0, &more);
+    for (int stage = 1; st == KRS_OK && more && stage <= 2; ++stage) {
         KRS_HIP(hipStreamSynchronize(stream));
-        nc = nk;
+        st = rebuild_stage(stage, &more);
     }
-    set_error("coarse space did not stabilise under the rank guard");
-    return KRS_E_COARSE_SINGULAR;
+    rb_done = false;
+    if (st != KRS_OK) return st;
+    *dropped = rb_dropped;
+    return KRS_OK;
 }
 
-// The same steps as rebuild(), split at its waits so that a batch waits once
-// per stage for all its members (each pass is the same kernels and host
-// arithmetic, so the result is the same as rebuild()'s).
+// The rebuild split at its waits (stage 0: the first A C / Gram pass;
+// stage 1, after a wait: the guarded orthonormalisation, the basis change
+// and the second pass; stage 2, after a wait: the guarded factorisation and
+// the upload of G^-1, or the remaining passes on this member alone when a
+// column vanished after the change of basis).
 template <typename V, typename W>
 krs_status SeqImpl<V, W>::rebuild_stage(int stage, bool* more) {
     *more = false;
