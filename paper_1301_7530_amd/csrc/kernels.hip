@@ -1040,10 +1040,11 @@ __device__ __forceinline__ void update_reduce_body(const SysView<V, W>& v, int64
     if constexpr (B == 3) {
         // One thread per unknown: in each of SUB sub-steps a wave takes 63
         // consecutive unknowns (21 block rows; lane 63 idles), so the loads
-        // and stores of x, r, w, q and s are contiguous across the wave and
-        // a lane reads the 3 entries of its row of the 3x3 block M^-1
-        // (3 i .. 3 i + 2 for unknown i = 3 p + d).  The residual entries
-        // of the other rows of the block come from the neighbouring lanes.
+        // and stores of x, r, w, q and s are contiguous across the wave, and
+        // so are the loads of the lane's row of the 3x3 block M^-1 (M^-1 is
+        // stored as three planes of columns: entry c of unknown i at c n + i).
+        // The residual entries of the other rows of the block come from the
+        // neighbouring lanes.
         constexpr int NWV = T / 64, BPW = 21, SUB = 2;
         constexpr int SB = NWV * BPW * SUB;  // block rows per step
         static_assert(SB * 3 <= T * B, "a step's s and w fit the LDS rows of the projection");
@@ -1071,7 +1072,7 @@ __device__ __forceinline__ void update_reduce_body(const SysView<V, W>& v, int64
                         xv[k] = v.x[i];
                     }
 #pragma unroll
-                    for (int e = 0; e < 3; ++e) mv[k][e] = v.minv[3 * i + e];
+                    for (int e = 0; e < 3; ++e) mv[k][e] = v.minv[(int64_t)e * (3 * v.nb) + i];
                 }
             }
             Vec16<V> ahead[UF];
@@ -2174,16 +2175,19 @@ __global__ void k_precond_setup(const double* in, const int64_t* diag_idx, int64
         const double m2 = a * e - b * d;
         if (!(a > 0.0) || !(m2 > 0.0) || !(det > 0.0)) atomicOr(bad, 1);
         const double id = 1.0 / det;
-        V* o = minv + p * 9;
-        o[0] = (V)(A * id);
-        o[1] = (V)(-(b * k - c * h) * id);
-        o[2] = (V)((b * f - c * e) * id);
-        o[3] = (V)(Bc * id);
-        o[4] = (V)((a * k - c * g) * id);
-        o[5] = (V)(-(a * f - c * d) * id);
-        o[6] = (V)(Cc * id);
-        o[7] = (V)(-(a * h - b * g) * id);
-        o[8] = (V)((a * e - b * d) * id);
+        // three planes of n = 3 nb entries: plane c holds column c of each
+        // block row, so that entry (3 p + r, c) sits at c n + 3 p + r and a
+        // lane per unknown reads its row with three contiguous loads
+        const int64_t n = 3 * nb, o = 3 * p;
+        minv[o] = (V)(A * id);
+        minv[n + o] = (V)(-(b * k - c * h) * id);
+        minv[2 * n + o] = (V)((b * f - c * e) * id);
+        minv[o + 1] = (V)(Bc * id);
+        minv[n + o + 1] = (V)((a * k - c * g) * id);
+        minv[2 * n + o + 1] = (V)(-(a * f - c * d) * id);
+        minv[o + 2] = (V)(Cc * id);
+        minv[n + o + 2] = (V)(-(a * h - b * g) * id);
+        minv[2 * n + o + 2] = (V)((a * e - b * d) * id);
     }
 }
 
