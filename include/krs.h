@@ -162,7 +162,9 @@ typedef struct {
                               to the grouping of the (w, A w) partial sums): bit 3 four blocks of a row in
                               flight instead of two, bit 4 non-temporal loads of the matrix, bits 5-6 the
                               cap on SpMV workgroups (0: 8192, 1: 2048, 2: 4096, 3: 8192).  With bits 3-6
-                              all zero, a matrix larger than 256 MiB streams with non-temporal loads.
+                              all zero, a matrix larger than 256 MiB streams with non-temporal loads, and
+                              the double-precision 3x3 SpMV reads the block columns as 16-bit differences
+                              from the row when every one fits (same columns, same results).
                               bit 7 (KRS_FP64 only): the Krylov history of z_j kept in single precision,
                               half the memory of a long run; it only forms the Ritz vectors of the
                               recycle (combined in double precision, then A-orthonormalised with the
