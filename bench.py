@@ -143,7 +143,8 @@ def run_sequence(K, ctx, seq, dev_sys, ks, precision, reuse, args, wl, timing=Fa
                        cap_policy=args.cap_policy,
                        refine_drop=args.refine_drop, autotune=args.autotune, update_rows=args.update_rows,
                        eager=args.eager, separate_finalize=args.separate_finalize, spmv_variant=args.spmv_variant,
-                       history_fp32=history_fp32(args, wl, precision))
+                       history_fp32=history_fp32(args, wl, precision),
+                       reorth=args.reorth and precision == "fp64" and reuse != "none")
     x_scratch = torch.empty(seq.n, dtype=torch.float64, device="cuda")
     recs = []
     try:
@@ -443,6 +444,7 @@ def run_sequence_workload(args, K, torch, wl):
             "tol": 1e-8,
             "precision": precision,
             "precision_detail": prec["detail"],
+            "reorthogonalisation": bool(args.reorth and precision == "fp64"),
             "krylov_history": ("fp32 (storage of the directions that form the recycled vectors; "
                                "every iteration and the basis stay fp64)" if history_fp32(args, wl, precision)
                                else prec["dtype"]),
@@ -902,6 +904,9 @@ def main():
     ap.add_argument("--max-iter", type=int, default=30000)
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--no-plain", dest="plain", action="store_false")
+    ap.add_argument("--reorth", action="store_true",
+                    help="fp64 sequence workloads: full reorthogonalisation of the SRKS solves (the setting of the "
+                         "paper's experiments; plain PCG stays without it)")
     ap.add_argument("--host-inputs", action="store_true",
                     help="sequence workloads: submit every system from host memory (the PCIe-inclusive rate); "
                          "by default the inputs are resident in HBM before the timed region")

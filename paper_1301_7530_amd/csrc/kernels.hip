@@ -1450,25 +1450,39 @@ __global__ __launch_bounds__(256) void k_reorth_dot(SysView<V, W> v) {
     const DevState* st = v.st;
     if (!gate(st, M_RUN)) return;
     const int jn = st->iter < v.rcap ? st->iter : v.rcap;
+    // workgroup = (row range g, chunk of 256 kept directions): chunks past
+    // the directions kept so far have nothing to do
+    const int nch = (v.rcap + 255) / 256;
+    const int chunk = (int)(blockIdx.x % nch);
+    const int64_t g = blockIdx.x / nch;
+    if (chunk * 256 >= jn) return;
     __shared__ double zs[256];
-    const int64_t per = (v.n + gridDim.x - 1) / gridDim.x;
-    const int64_t r0 = (int64_t)blockIdx.x * per;
+    const int64_t per = (v.n + v.gr - 1) / v.gr;
+    const int64_t r0 = g * per;
     const int64_t r1 = (r0 + per < v.n) ? r0 + per : v.n;
-    for (int i0 = 0; i0 < jn; i0 += 256) {
-        const int i = i0 + (int)threadIdx.x;
-        double acc = 0.0;
-        for (int64_t rb = r0; rb < r1; rb += 256) {
-            __syncthreads();
-            if (rb + threadIdx.x < r1) zs[threadIdx.x] = (double)v.zr[rb + threadIdx.x];
-            __syncthreads();
-            const int cnt = (r1 - rb < 256) ? (int)(r1 - rb) : 256;
-            if (i < jn) {
-                const W* q = v.Qr + rb * v.ldr + i;
-                for (int t = 0; t < cnt; ++t) acc += (double)q[(int64_t)t * v.ldr] * zs[t];
+    const int i = chunk * 256 + (int)threadIdx.x;
+    double acc = 0.0;
+    for (int64_t rb = r0; rb < r1; rb += 256) {
+        __syncthreads();
+        if (rb + threadIdx.x < r1) zs[threadIdx.x] = (double)v.zr[rb + threadIdx.x];
+        __syncthreads();
+        const int cnt = (r1 - rb < 256) ? (int)(r1 - rb) : 256;
+        if (i < jn) {
+            // four independent chains of loads and products per thread
+            const W* q = v.Qr + rb * v.ldr + i;
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+            int t = 0;
+            for (; t + 4 <= cnt; t += 4) {
+                a0 += (double)q[(int64_t)t * v.ldr] * zs[t];
+                a1 += (double)q[(int64_t)(t + 1) * v.ldr] * zs[t + 1];
+                a2 += (double)q[(int64_t)(t + 2) * v.ldr] * zs[t + 2];
+                a3 += (double)q[(int64_t)(t + 3) * v.ldr] * zs[t + 3];
             }
+            for (; t < cnt; ++t) a0 += (double)q[(int64_t)t * v.ldr] * zs[t];
+            acc += (a0 + a1) + (a2 + a3);
         }
-        if (i < jn) v.rpart[(int64_t)blockIdx.x * v.ldr + i] = acc;
     }
+    if (i < jn) v.rpart[g * v.ldr + i] = acc;
 }
 
 // coefficients c_i = (sum over row ranges, in order) / (w_i, A w_i)
@@ -1484,7 +1498,9 @@ __global__ __launch_bounds__(256) void k_reorth_reduce(SysView<V, W> v) {
     }
 }
 
-// w = z - sum_i c_i w_i: one wave per row, lanes over i, a fixed shuffle tree
+// w = z - sum_i c_i w_i: a wave takes four rows at a time, lanes over i
+// (each c_i read once from LDS serves the four rows: four independent
+// chains of loads and products), then a fixed shuffle tree per row
 template <typename V, typename W>
 __global__ __launch_bounds__(256) void k_reorth_apply(SysView<V, W> v) {
     const DevState* st = v.st;
@@ -1493,15 +1509,30 @@ __global__ __launch_bounds__(256) void k_reorth_apply(SysView<V, W> v) {
     __shared__ double cs[kReorthMax];
     for (int i = threadIdx.x; i < jn; i += 256) cs[i] = v.rc[i];
     __syncthreads();
+    constexpr int R = 4;
     const int lane = threadIdx.x & 63;
     const int64_t waves = (int64_t)gridDim.x * 4;
-    for (int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); row < v.n; row += waves) {
-        const W* wr = v.Wr + row * v.ldr;
-        double acc = 0.0;
-        for (int i = lane; i < jn; i += 64) acc += cs[i] * (double)wr[i];
+    for (int64_t row0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * R; row0 < v.n; row0 += waves * R) {
+        const W* wr[R];
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-        if (lane == 0) v.w[row] = (W)((double)v.zr[row] - acc);
+        for (int r = 0; r < R; ++r) wr[r] = v.Wr + ((row0 + r) < v.n ? (row0 + r) : (v.n - 1)) * v.ldr;
+        double acc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = 0.0;
+        for (int i = lane; i < jn; i += 64) {
+            const double c = cs[i];
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] += c * (double)wr[r][i];
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) acc[r] += __shfl_xor(acc[r], off);
+        if (lane == 0) {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (row0 + r < v.n) v.w[row0 + r] = (W)((double)v.zr[row0 + r] - acc[r]);
+        }
     }
 }
 
@@ -2479,9 +2510,12 @@ void launch_reorth_store(const SysView<V, W>& v, hipStream_t stream) {
 
 template <typename V, typename W>
 void launch_reorth(const SysView<V, W>& v, hipStream_t stream) {
-    hipLaunchKernelGGL((k_reorth_dot<V, W>), dim3(v.gr), dim3(256), 0, stream, v);
+    // row ranges x chunks of 256 kept directions (the ones past the
+    // current count exit at once)
+    hipLaunchKernelGGL((k_reorth_dot<V, W>), dim3((unsigned)(v.gr * ((v.rcap + 255) / 256))), dim3(256), 0, stream,
+                       v);
     hipLaunchKernelGGL((k_reorth_reduce<V, W>), dim3(cdiv(kReorthMax, 256)), dim3(256), 0, stream, v);
-    const int g = (int)std::min<int64_t>(cdiv(v.n, 4), 2048);
+    const int g = (int)std::min<int64_t>(cdiv(v.n, 16), 8192);
     hipLaunchKernelGGL((k_reorth_apply<V, W>), dim3(g), dim3(256), 0, stream, v);
 }
 

@@ -891,7 +891,9 @@ krs_status SeqImpl<V, W>::begin_solve() {
         rcap = std::min(std::min(max_iter + 1, kReorthMax), desc.history_cap > 0 ? desc.history_cap : kReorthMax);
         rcap = std::min(rcap, coef_cap);
         ldr = ((int64_t)rcap + 15) / 16 * 16;
-        rgr = (int)std::max<int64_t>(1, std::min<int64_t>(512, (n + 4095) / 4096));
+        // row ranges of about 1024 rows (at most 256): with the chunks of
+        // kept directions they give the coefficient pass thousands of workgroups
+        rgr = (int)std::max<int64_t>(1, std::min<int64_t>(256, (n + 1023) / 1024));
         if (!d_Wr.reserve(ctx, (size_t)n * ldr * sizeof(W)) || !d_Qr.reserve(ctx, (size_t)n * ldr * sizeof(W)) ||
             !d_rpart.reserve(ctx, (size_t)rgr * ldr * sizeof(double)) || !d_rc.reserve(ctx, (size_t)ldr * sizeof(double)) ||
             !d_zr.reserve(ctx, (size_t)n * sizeof(W))) {
