@@ -402,11 +402,16 @@ __device__ __forceinline__ T ld_stream(const T* p) {
 }
 
 // C16: the block columns come from col16 as differences from `base` (the
-// lane's block row, clamped to the last one), two bytes each.
-template <typename V, typename X, int UNR = 2, bool NT = false, bool C16 = false>
+// lane's block row, clamped to the last one), two bytes each.  OWN (with
+// C16): the lane's own three entries of x, gathered for the block whose
+// column is `base` (the diagonal block, or a padding slot), are kept in
+// own[] and *got is set, so that the caller need not load them again.
+template <typename V, typename X, int UNR = 2, bool NT = false, bool C16 = false, bool OWN = false>
 __device__ __forceinline__ void ell_row3all(const V* __restrict__ val, const int32_t* __restrict__ col,
                                             const X* __restrict__ x, int64_t k0, int64_t k1, int lane, X out[3],
-                                            const int16_t* __restrict__ col16 = nullptr, int64_t base = 0) {
+                                            const int16_t* __restrict__ col16 = nullptr, int64_t base = 0,
+                                            X* own = nullptr, bool* got = nullptr) {
+    static_assert(!OWN || C16, "own entries are recognised by the relative block column");
     X a0 = 0, a1 = 0, a2 = 0;
     int64_t k = k0;
     for (; k + UNR <= k1; k += UNR) {
@@ -430,15 +435,28 @@ __device__ __forceinline__ void ell_row3all(const V* __restrict__ val, const int
         }
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
+            if (OWN && cc[u] == base) {
+                own[0] = xs[u][0];
+                own[1] = xs[u][1];
+                own[2] = xs[u][2];
+                *got = true;
+            }
             a0 += (X)a[u][0] * xs[u][0] + (X)a[u][1] * xs[u][1] + (X)a[u][2] * xs[u][2];
             a1 += (X)a[u][3] * xs[u][0] + (X)a[u][4] * xs[u][1] + (X)a[u][5] * xs[u][2];
             a2 += (X)a[u][6] * xs[u][0] + (X)a[u][7] * xs[u][1] + (X)a[u][8] * xs[u][2];
         }
     }
     for (; k < k1; ++k) {
-        const int64_t c = 3 * (C16 ? base + (int64_t)col16[k * 64 + lane] : (int64_t)col[k * 64 + lane]);
+        const int64_t cb = C16 ? base + (int64_t)col16[k * 64 + lane] : (int64_t)col[k * 64 + lane];
+        const int64_t c = 3 * cb;
         const V* vb = val + k * 9 * 64 + lane;
         const X x0 = x[c], x1 = x[c + 1], x2 = x[c + 2];
+        if (OWN && cb == base) {
+            own[0] = x0;
+            own[1] = x1;
+            own[2] = x2;
+            *got = true;
+        }
         a0 += (X)vb[0] * x0 + (X)vb[64] * x1 + (X)vb[128] * x2;
         a1 += (X)vb[192] * x0 + (X)vb[256] * x1 + (X)vb[320] * x2;
         a2 += (X)vb[384] * x0 + (X)vb[448] * x1 + (X)vb[512] * x2;
@@ -483,12 +501,16 @@ __device__ __forceinline__ void spmv_dot_body(const SysView<V, W>& v, int64_t bi
         for (int64_t sl = bid * 2 + wave; sl < v.nslices; sl += nblk * 2) {
             const int64_t k0 = v.slice_ptr[sl], k1 = v.slice_ptr[sl + 1];
             W acc[3];
+            W own[3] = {0, 0, 0};
+            bool got = false;
             const int64_t prow = sl * 64 + lane;
             const int64_t base = prow < v.nb ? prow : v.nb - 1;
             if (VAR == 4) {
-                ell_row3all<double, W, 2, false, true>(v.val64, v.col, v.w, k0, k1, lane, acc, v.col16, base);
+                ell_row3all<double, W, 2, false, true, true>(v.val64, v.col, v.w, k0, k1, lane, acc, v.col16, base,
+                                                             own, &got);
             } else if (VAR == 6) {
-                ell_row3all<double, W, 2, true, true>(v.val64, v.col, v.w, k0, k1, lane, acc, v.col16, base);
+                ell_row3all<double, W, 2, true, true, true>(v.val64, v.col, v.w, k0, k1, lane, acc, v.col16, base,
+                                                            own, &got);
             } else if (std::is_same<V, double>::value || v.op64) {
                 // (a double-precision basis always has the double-precision operator)
                 if ((var & 3) == 0) ell_row3all<double, W, 2, false>(v.val64, v.col, v.w, k0, k1, lane, acc);
@@ -500,10 +522,16 @@ __device__ __forceinline__ void spmv_dot_body(const SysView<V, W>& v, int64_t bi
             }
             const int64_t p = sl * 64 + lane;
             if (p < v.nb) {
+                // the row's own entries of w: from the gather where the row
+                // stores its diagonal block (schedules 4 and 6), else loaded
+                if (!got) {
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) own[d] = v.w[3 * p + d];
+                }
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
                     v.q[3 * p + d] = acc[d];
-                    part += (double)v.w[3 * p + d] * (double)acc[d];
+                    part += (double)own[d] * (double)acc[d];
                 }
             }
         }

@@ -283,8 +283,10 @@ def test_spmv_16bit_columns_same_bits(gpu, E, variant):
     """With the default load schedule the double-precision 3x3 SpMV reads the
     block columns as 16-bit differences from the lane's block row; an
     explicit schedule (kernel_flags bits 3-6: the same workgroup count and
-    loads) reads the 32-bit columns.  Same columns, same sums: the CG
-    coefficients and the iterate agree bit for bit over 300 iterations (at
+    loads) reads the 32-bit columns.  Same columns, same sums (the row's
+    own entries of w in (w, A w) taken from the gather in the first, loaded
+    in the second): the CG coefficients and the iterate agree bit for bit
+    over 300 iterations (at
     16^3 and at 100^3, where the default streams the matrix with
     non-temporal loads)."""
     seq = gen.config_elasticity(E, 1, 3)
