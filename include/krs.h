@@ -168,7 +168,12 @@ typedef struct {
                               bit 7 (KRS_FP64 only): the Krylov history of z_j kept in single precision,
                               half the memory of a long run; it only forms the Ritz vectors of the
                               recycle (combined in double precision, then A-orthonormalised with the
-                              rest of the basis), so every solve still runs in double precision. */
+                              rest of the basis), so every solve still runs in double precision.
+                              With non-temporal matrix loads (bit 4, or the default for a matrix larger
+                              than 256 MiB) the vectors an iteration writes (A w; x, r, s; w and the
+                              Krylov history) go out with non-temporal stores, so that no dirty cache
+                              lines are left for the next kernel, which streams the matrix, to write back.
+                              bit 8: plain stores instead (the same values). */
     int32_t reselect;      /* SRKS: 0 = keep every Ritz vector that passed the stagnation test;
                               1 = KRS_RESELECT_CLUSTER: drop the central cluster of those values
                               ("clust", Section 4.4), before the cap */

@@ -368,7 +368,7 @@ class Sequence:
                  refine_every=0, history_cap=0, rank_tol=0.0, refine_drop=0.0, C0=None, eager=False,
                  update_rows=0, autotune=False, separate_finalize=False, literal_direction=False, reorth=False,
                  spmv_variant=0, history_fp32=False, reselect=None,
-                 cluster_min_frac=0.0):
+                 cluster_min_frac=0.0, plain_stores=False):
         self.ctx = ctx
         self.n = int(n)
         self.block = int(block)
@@ -399,7 +399,8 @@ class Sequence:
         d.update_rows = update_rows
         d.autotune = 1 if autotune else 0
         d.kernel_flags = ((1 if separate_finalize else 0) | (2 if literal_direction else 0) | (4 if reorth else 0)
-                          | ((int(spmv_variant) & 15) << 3) | (128 if history_fp32 else 0))
+                          | ((int(spmv_variant) & 15) << 3) | (128 if history_fp32 else 0)
+                          | (256 if plain_stores else 0))
         d.reselect = {None: 0, "none": 0, "cluster": 1}[reselect]
         d.cluster_min_frac = cluster_min_frac
         self.desc = d

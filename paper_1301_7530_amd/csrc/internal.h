@@ -128,7 +128,7 @@ struct SysView {
     W* q;
     // basis
     int32_t nc;      // columns of C in this solve
-    int32_t pad0;
+    int32_t nt_store;  // 1: the iteration's vector stores are non-temporal (set with the streaming schedule)
     const V* C;      // n x nc column-major, leading dim ldc (a multiple of 256 >= n)
     const V* AC;     // n x nc row-major, leading dim ldac = ac_leading_dim(nc, sizeof(V))
     int64_t ldc;

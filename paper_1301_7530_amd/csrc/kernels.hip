@@ -401,6 +401,16 @@ __device__ __forceinline__ T ld_stream(const T* p) {
     return *p;
 }
 
+// A store of an iteration vector: non-temporal with NT (written out at once
+// instead of left dirty in the caches for the next kernel to write back).
+// The value stored is the same either way.  NT is a compile-time choice: the
+// two forms of one store behind a run-time test are merged into a plain one.
+template <bool NT, typename T>
+__device__ __forceinline__ void st_vec(T* p, T v) {
+    if (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 // C16: the block columns come from col16 as differences from `base` (the
 // lane's block row, clamped to the last one), two bytes each.  OWN (with
 // C16): the lane's own three entries of x, gathered for the block whose
@@ -473,9 +483,13 @@ __device__ __forceinline__ void ell_row3all(const V* __restrict__ val, const int
 // VAR: the load schedule fixed at compile time (the single-system kernel,
 // one instantiation per schedule, so the registers are those of the one in
 // use; 4 and 6 are schedules 0 and 2 with 16-bit relative block columns),
-// or -1 to take v.spmv_var at run time (the batch kernel).
+// or -1 to take v.spmv_var at run time (the batch kernel); bit 3 added to a
+// schedule with non-temporal loads writes q with non-temporal stores.
 template <typename V, typename W, int B, int VAR = -1>
 __device__ __forceinline__ void spmv_dot_body(const SysView<V, W>& v, int64_t bid) {
+    // VAR bit 3: q goes out with non-temporal stores
+    constexpr bool NTS = VAR >= 0 && (VAR & 8) != 0;
+    constexpr int VS = VAR >= 0 ? (VAR & 7) : VAR;
     if (!gate(v.st, M_RUN)) return;
     const bool tm = ktime_sample(v.st, 0);
     ktime_begin(v.kslots, 0, bid, tm);
@@ -491,7 +505,7 @@ __device__ __forceinline__ void spmv_dot_body(const SysView<V, W>& v, int64_t bi
                                  : ell_row1<V, W>(v.val, v.col, v.w, k0, k1, lane);
             const int64_t row = sl * 64 + lane;
             if (row < v.n) {
-                v.q[row] = acc;
+                st_vec<NTS>(v.q + row, acc);
                 part += (double)v.w[row] * (double)acc;
             }
         }
@@ -505,10 +519,10 @@ __device__ __forceinline__ void spmv_dot_body(const SysView<V, W>& v, int64_t bi
             bool got = false;
             const int64_t prow = sl * 64 + lane;
             const int64_t base = prow < v.nb ? prow : v.nb - 1;
-            if (VAR == 4) {
+            if (VS == 4) {
                 ell_row3all<double, W, 2, false, true, true>(v.val64, v.col, v.w, k0, k1, lane, acc, v.col16, base,
                                                              own, &got);
-            } else if (VAR == 6) {
+            } else if (VS == 6) {
                 ell_row3all<double, W, 2, true, true, true>(v.val64, v.col, v.w, k0, k1, lane, acc, v.col16, base,
                                                             own, &got);
             } else if (std::is_same<V, double>::value || v.op64) {
@@ -530,7 +544,7 @@ __device__ __forceinline__ void spmv_dot_body(const SysView<V, W>& v, int64_t bi
                 }
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    v.q[3 * p + d] = acc[d];
+                    st_vec<NTS>(v.q + 3 * p + d, acc[d]);
                     part += (double)own[d] * (double)acc[d];
                 }
             }
@@ -1015,7 +1029,8 @@ constexpr int upd_pool() {
 
 // SINGLE: the single-system kernel, which also instantiates the projection
 // with compile-time chunk geometry (same lanes and order as the general one).
-template <typename V, typename W, int B, bool FUSE, int UR, bool SINGLE = false>
+// NTS: x, r and s go out with non-temporal stores.
+template <typename V, typename W, int B, bool FUSE, int UR, bool SINGLE = false, bool NTS = false>
 __device__ __forceinline__ void update_reduce_body(const SysView<V, W>& v, int64_t bid, int mode, double* pool) {
     DevState* st = v.st;
     const uint32_t mask = (mode == 2) ? M_REFINE : M_RUN;
@@ -1136,10 +1151,10 @@ __device__ __forceinline__ void update_reduce_body(const SysView<V, W>& v, int64
                     rs += ri * si[k];
                     const int64_t i = ps * 3 + loc[k];
                     if (mode == 0) {
-                        v.x[i] = xn;
-                        v.r[i] = r2;
+                        st_vec<NTS>(v.x + i, xn);
+                        st_vec<NTS>(v.r + i, (W)r2);
                     }
-                    v.s[i] = (W)si[k];
+                    st_vec<NTS>(v.s + i, (W)si[k]);
                 }
             }
             if (nc > 0) {
@@ -1253,10 +1268,10 @@ __device__ __forceinline__ void update_reduce_body(const SysView<V, W>& v, int64
                 for (int d = 0; d < B; ++d) {
                     const int64_t i = p * B + d;
                     if (mode == 0) {
-                        v.x[i] = xn[d];
-                        v.r[i] = rn[d];
+                        st_vec<NTS>(v.x + i, xn[d]);
+                        st_vec<NTS>(v.r + i, (W)rn[d]);
                     }
-                    v.s[i] = (W)si[d];
+                    st_vec<NTS>(v.s + i, (W)si[d]);
                 }
             }
             if (nc > 0) {
@@ -1354,7 +1369,7 @@ struct alignas(4 * sizeof(V)) Quad {
     V e[4];
 };
 
-template <typename V, typename W, int U>
+template <typename V, typename W, int U, bool NTS = false>
 __device__ __forceinline__ void correct_dir_body(const SysView<V, W>& v, int64_t bid, int first) {
     DevState* st = v.st;
     __shared__ double mu[1024];
@@ -1435,12 +1450,12 @@ __device__ __forceinline__ void correct_dir_body(const SysView<V, W>& v, int64_t
             const double s = (double)sv;
             const W zv = (W)(s - cz);
             const W wv = (first == 1) ? zv : (W)(s - cw + beta * (double)wv0);
-            v.w[i] = wv;
+            st_vec<NTS>(v.w + i, wv);
             if (v.zr) v.zr[i] = zv;
             if (j < hist_cap) {
-                if (v.zhist) v.zhist[(int64_t)j * v.ldh + i] = (V)zv;
-                if (v.zhist32) v.zhist32[(int64_t)j * v.ldh + i] = (float)zv;
-                if (v.whist) v.whist[(int64_t)j * v.ldh + i] = (V)wv;
+                if (v.zhist) st_vec<NTS>(v.zhist + (int64_t)j * v.ldh + i, (V)zv);
+                if (v.zhist32) st_vec<NTS>(v.zhist32 + (int64_t)j * v.ldh + i, (float)zv);
+                if (v.whist) st_vec<NTS>(v.whist + (int64_t)j * v.ldh + i, (V)wv);
             }
         }
     }
@@ -1724,19 +1739,19 @@ __global__ __launch_bounds__(kT3, 2) void k_update_reduce(SysView<V, W> v, int m
     __shared__ double pool[upd_pool<B>()];
     update_reduce_body<V, W, B, false, kUrOne, true>(v, blockIdx.x, mode, pool);
 }
-template <typename V, typename W, int B>
+template <typename V, typename W, int B, bool NTS>
 __global__ __launch_bounds__(kT3, 2) void k_update_fused(SysView<V, W> v, int mode) {
     __shared__ double pool[upd_pool<B>() > fin_pool() ? upd_pool<B>() : fin_pool()];
-    update_reduce_body<V, W, B, true, kUrOne, true>(v, blockIdx.x, mode, pool);
+    update_reduce_body<V, W, B, true, kUrOne, true, NTS>(v, blockIdx.x, mode, pool);
 }
 template <typename V, typename W>
 __global__ __launch_bounds__(kTF3) void k_finalize_update(SysView<V, W> v, int mode) {
     __shared__ double pool[fin_pool()];
     finalize_update_body<V, W, false>(v, mode, pool);
 }
-template <typename V, typename W>
+template <typename V, typename W, bool NTS>
 __global__ __launch_bounds__(256) void k_correct_dir(SysView<V, W> v, int first) {
-    correct_dir_body<V, W, 8>(v, blockIdx.x, first);
+    correct_dir_body<V, W, 8, NTS>(v, blockIdx.x, first);
 }
 template <typename V, typename W, int B>
 __global__ __launch_bounds__(256) void k_true_resid(SysView<V, W> v, int final_only) {
@@ -1810,7 +1825,7 @@ __global__ __launch_bounds__(256) void kb_correct_dir(const SysView<V, W>* __res
 // kernel's grid (blocks b, b + g5, ...) with every load of a round issued
 // before any store: with thousands of small systems the per-workgroup
 // latency, not the bytes, set the time of the general kernel.
-template <typename V, typename W, int NC>
+template <typename V, typename W, int NC, bool NTS = false>
 __device__ __forceinline__ void correct_dir_few_body(const SysView<V, W>& v, int64_t b0, int first) {
     constexpr int G = kDirFewGroup;
     static_assert(NC == 0 || NC == 4, "the general kernel's four waves hold one column each");
@@ -1871,11 +1886,11 @@ __device__ __forceinline__ void correct_dir_few_body(const SysView<V, W>& v, int
                 const double s = (double)sv[u];
                 const W zv = (W)(s - cz);
                 const W wv = (first == 1) ? zv : (W)(s - cw + beta * (double)wv0[u]);
-                v.w[i] = wv;
+                st_vec<NTS>(v.w + i, wv);
                 if (j < hist_cap) {
-                    if (v.zhist) v.zhist[(int64_t)j * v.ldh + i] = (V)zv;
-                    if (v.zhist32) v.zhist32[(int64_t)j * v.ldh + i] = (float)zv;
-                    if (v.whist) v.whist[(int64_t)j * v.ldh + i] = (V)wv;
+                    if (v.zhist) st_vec<NTS>(v.zhist + (int64_t)j * v.ldh + i, (V)zv);
+                    if (v.zhist32) st_vec<NTS>(v.zhist32 + (int64_t)j * v.ldh + i, (float)zv);
+                    if (v.whist) st_vec<NTS>(v.whist + (int64_t)j * v.ldh + i, (V)wv);
                 }
             }
         }
@@ -1889,9 +1904,9 @@ __global__ __launch_bounds__(256) void kb_correct_dir_few(const SysView<V, W>* _
     correct_dir_few_body<V, W, NC>(views[e.x], e.y, first);
 }
 // the same for one system (kDirFewGroup ranges per workgroup)
-template <typename V, typename W, int NC>
+template <typename V, typename W, int NC, bool NTS>
 __global__ __launch_bounds__(256) void k_correct_dir_few(SysView<V, W> v, int first) {
-    correct_dir_few_body<V, W, NC>(v, (int64_t)blockIdx.x * kDirFewGroup, first);
+    correct_dir_few_body<V, W, NC, NTS>(v, (int64_t)blockIdx.x * kDirFewGroup, first);
 }
 template <typename V, typename W, int B>
 __global__ __launch_bounds__(256) void kb_true_resid(const SysView<V, W>* __restrict__ views,
@@ -2302,11 +2317,16 @@ template <typename V, typename W, int B>
 void launch_spmv_dot(const SysView<V, W>& v, hipStream_t stream) {
     const int threads = (B == 1) ? 256 : 128;
     const dim3 grid((unsigned)v.geo.g1);
-    // 16-bit relative block columns (set with the default load schedule, 0 or 2)
+    // 16-bit relative block columns (set with the default load schedule, 0 or 2);
+    // non-temporal stores of q (bit 3) only with the non-temporal loads
     const int c16 = (B == 3 && v.op64 && v.col16 && (v.spmv_var & 1) == 0) ? 4 : 0;
-    switch ((B == 3 && v.op64) ? (v.spmv_var & 3) | c16 : 0) {
+    const int nts = (B == 3 && v.op64 && v.nt_store && (v.spmv_var & 2)) ? 8 : 0;
+    switch ((B == 3 && v.op64) ? (v.spmv_var & 3) | c16 | nts : 0) {
         case 4: hipLaunchKernelGGL((k_spmv_dot<V, W, B, 4>), grid, dim3(threads), 0, stream, v); break;
         case 6: hipLaunchKernelGGL((k_spmv_dot<V, W, B, 6>), grid, dim3(threads), 0, stream, v); break;
+        case 14: hipLaunchKernelGGL((k_spmv_dot<V, W, B, 14>), grid, dim3(threads), 0, stream, v); break;
+        case 10: hipLaunchKernelGGL((k_spmv_dot<V, W, B, 10>), grid, dim3(threads), 0, stream, v); break;
+        case 11: hipLaunchKernelGGL((k_spmv_dot<V, W, B, 11>), grid, dim3(threads), 0, stream, v); break;
         case 1: hipLaunchKernelGGL((k_spmv_dot<V, W, B, 1>), grid, dim3(threads), 0, stream, v); break;
         case 2: hipLaunchKernelGGL((k_spmv_dot<V, W, B, 2>), grid, dim3(threads), 0, stream, v); break;
         case 3: hipLaunchKernelGGL((k_spmv_dot<V, W, B, 3>), grid, dim3(threads), 0, stream, v); break;
@@ -2322,7 +2342,11 @@ void launch_update_only(const SysView<V, W>& v, int mode, hipStream_t stream) {
 template <typename V, typename W, int B>
 void launch_update_reduce(const SysView<V, W>& v, int mode, hipStream_t stream) {
     if (v.fused) {
-        hipLaunchKernelGGL((k_update_fused<V, W, B>), dim3((unsigned)v.geo.g3), dim3(kT3), 0, stream, v, mode);
+        if (v.nt_store)
+            hipLaunchKernelGGL((k_update_fused<V, W, B, true>), dim3((unsigned)v.geo.g3), dim3(kT3), 0, stream, v, mode);
+        else
+            hipLaunchKernelGGL((k_update_fused<V, W, B, false>), dim3((unsigned)v.geo.g3), dim3(kT3), 0, stream, v,
+                               mode);
         return;
     }
     hipLaunchKernelGGL((k_update_reduce<V, W, B>), dim3((unsigned)v.geo.g3), dim3(kT3), 0, stream, v, mode);
@@ -2335,11 +2359,18 @@ void launch_correct_dir(const SysView<V, W>& v, int first, hipStream_t stream) {
     // the per-row kernel, same products in the same order
     if (!v.zr && v.nc <= kDirFewCols) {
         const dim3 grid((unsigned)((v.geo.g5 + kDirFewGroup - 1) / kDirFewGroup));
-        if (v.nc == 0) hipLaunchKernelGGL((k_correct_dir_few<V, W, 0>), grid, dim3(256), 0, stream, v, first);
-        else hipLaunchKernelGGL((k_correct_dir_few<V, W, kDirFewCols>), grid, dim3(256), 0, stream, v, first);
+        const int k = (v.nc == 0 ? 0 : 1) | (v.nt_store ? 2 : 0);
+        if (k == 0) hipLaunchKernelGGL((k_correct_dir_few<V, W, 0, false>), grid, dim3(256), 0, stream, v, first);
+        if (k == 1)
+            hipLaunchKernelGGL((k_correct_dir_few<V, W, kDirFewCols, false>), grid, dim3(256), 0, stream, v, first);
+        if (k == 2) hipLaunchKernelGGL((k_correct_dir_few<V, W, 0, true>), grid, dim3(256), 0, stream, v, first);
+        if (k == 3)
+            hipLaunchKernelGGL((k_correct_dir_few<V, W, kDirFewCols, true>), grid, dim3(256), 0, stream, v, first);
         return;
     }
-    hipLaunchKernelGGL((k_correct_dir<V, W>), dim3((unsigned)v.geo.g5), dim3(256), 0, stream, v, first);
+    const dim3 grid((unsigned)v.geo.g5);
+    if (v.nt_store) hipLaunchKernelGGL((k_correct_dir<V, W, true>), grid, dim3(256), 0, stream, v, first);
+    else hipLaunchKernelGGL((k_correct_dir<V, W, false>), grid, dim3(256), 0, stream, v, first);
 }
 
 template <typename V, typename W, int B>

@@ -411,6 +411,11 @@ SysView<V, W> SeqImpl<V, W>::view() {
     v.spmv_var = (desc.kernel_flags >> 3) & 3;
     if (((desc.kernel_flags >> 3) & 15) == 0 && B == 3 && v.op64 && nslots * 64 * 9 * (int64_t)sizeof(double) > kNtBytes)
         v.spmv_var = 2;  // a matrix larger than the last-level cache streams with non-temporal loads
+    // With the streaming schedule the vectors an iteration writes (q; x, r,
+    // s; w and the history) go out with non-temporal stores: normal stores
+    // leave dirty lines in the caches whose write-back then falls inside
+    // the next kernel, which streams the matrix.
+    v.nt_store = ((v.spmv_var & 2) && !(desc.kernel_flags & 256)) ? 1 : 0;
     if (reorth() && rcap > 0) {
         v.Wr = (W*)d_Wr.p;
         v.Qr = (W*)d_Qr.p;

@@ -297,3 +297,34 @@ def test_spmv_16bit_columns_same_bits(gpu, E, variant):
     assert np.array_equal(a["alpha"][:300], b["alpha"][:300])
     assert np.array_equal(a["rho"][:300], b["rho"][:300])
     assert np.array_equal(a["x"], b["x"])
+
+
+def test_nontemporal_stores_same_bits(gpu):
+    """At 100^3 the default schedule writes the vectors of an iteration with
+    non-temporal stores; kernel_flags bit 8 keeps plain stores.  The values
+    stored are the same, so the CG coefficients and the iterate agree bit for
+    bit over 300 iterations, without a basis and with a four-column initial
+    basis (the update kernel's projection and the direction kernel with its
+    columns)."""
+    K = _K()
+    seq = gen.config_elasticity(100, 1, 3)
+    vals, b = seq.system(0)
+    C0 = np.random.default_rng(7).standard_normal((seq.n, 4))
+    for c0 in (None, C0):
+        out = []
+        for plain in (False, True):
+            s = K.sequence_for(gpu, seq, precision="fp64", reuse="none", tol=1e-30, max_iter=300, C0=c0,
+                               plain_stores=plain)
+            try:
+                s.submit(vals, b)
+                x, info = s.solve()
+                a, r, _ = s.coeffs()
+                out.append((info["iters"], info["n_c"], a, r, x))
+            finally:
+                s.close()
+        (ia, ca, aa, ra, xa), (ib, cb, ab, rb, xb) = out
+        assert ia == ib == 300
+        assert ca == cb == (0 if c0 is None else 4)
+        assert np.array_equal(aa[:300], ab[:300])
+        assert np.array_equal(ra[:300], rb[:300])
+        assert np.array_equal(xa, xb)
